@@ -1,0 +1,164 @@
+/*
+ * libd2 -- batched exact squared Mallows distances on one MI355X (gfx950).
+ *
+ * The paper (Zhang, Wang & Li, "Parallel D2-Clustering: Large-Scale
+ * Clustering of Discrete Distributions") works with discrete distributions,
+ * "bags of weighted vectors" v = {(v^(a), p^(a)) : a = 1..t} (Sec. 1.1 and
+ * Sec. 2.2), the squared Mallows distance between two of them -- the value of
+ * the transportation linear program of Eq. (1) once the centroid is fixed --
+ * and the labelling step C(i) = argmin_j D(v_i, z_j) (Alg. 2, Step 2), which
+ * it notes parallelises per point (Sec. 1.2).  This library computes those
+ * quantities exactly (FP64 optimum of the LP) for many pairs at once.
+ *
+ * For P = {(x_a, p_a)}_{a<t}, Q = {(y_b, q_b)}_{b<s} in R^d:
+ *
+ *     D^2(P,Q) = min_{w>=0} sum_ab w_ab |x_a - y_b|^2
+ *                s.t. sum_b w_ab = p_a, sum_a w_ab = q_b,
+ *
+ * where p and q are the caller's weights divided by their FP64 sums.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every pointer inside a d2_set and every output pointer is DEVICE memory
+ *    on the handle's device, owned by the caller.  The library never frees
+ *    caller memory and keeps no pointer past the completion of the stream
+ *    work a call enqueues.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls enqueue kernels on it and return without synchronising.
+ *  - A handle is not thread-safe; use one handle per host thread.
+ *  - Host-detectable problems are returned synchronously as a d2_status and
+ *    nothing is enqueued.  Problems found per pair on the device are written
+ *    to the per-pair (or per-row) status arrays (D2_PAIR_* codes); the
+ *    distance of a failed pair is NaN.
+ *  - The primary output is D^2 (the LP objective); opts->want_sqrt = 1
+ *    returns D = sqrt(D^2) instead.  Labels are 0-based; ties go to the lowest
+ *    centroid index; a row with any failed pair gets label -1.
+ *  - Supports of more than D2_MAX_SUPPORT atoms are not handled
+ *    (D2_EUNSUPPORTED when declared, D2_PAIR_TOO_LARGE when found on device).
+ */
+#ifndef D2_H
+#define D2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define D2_MAX_SUPPORT 64
+
+typedef enum {
+    D2_OK = 0,
+    D2_EINVAL = 1,       /* null pointer, negative count, bad dtype/mode/size   */
+    D2_EWORKSPACE = 2,   /* ws_bytes below d2_workspace_bytes() for the call     */
+    D2_EUNSUPPORTED = 3, /* declared max_support above D2_MAX_SUPPORT, etc.      */
+    D2_EHIP = 4,         /* a HIP runtime call or launch failed                  */
+    D2_ENOMEM = 5        /* host allocation failed (handle creation only)        */
+} d2_status;
+
+/* element type of d2_set.points and d2_set.weights (always both the same) */
+enum { D2_F64 = 0, D2_F32 = 1 };
+
+/* ground-cost arithmetic */
+enum {
+    D2_COST_F64_DIRECT = 0, /* C_ab = sum_k (x_ak - y_bk)^2 in FP64, k ascending   */
+    D2_COST_BF16_MFMA = 1   /* C_ab = max(0, |x|^2 + |y|^2 - 2 x.y): x.y by BF16   *
+                             * MFMA with FP32 accumulation, norms in FP32 from the *
+                             * same BF16-rounded values, result widened to FP64.  *
+                             * Approximate: not held to the FP64 tolerance.        */
+};
+
+/* starting basis of the transportation simplex */
+enum { D2_INIT_AUTO = 0, D2_INIT_NWC = 1, D2_INIT_VOGEL = 2 };
+
+/* per-pair status codes written by the device */
+enum {
+    D2_PAIR_OK = 0,
+    D2_PAIR_BAD_WEIGHTS = 1, /* a weight is NaN/inf/negative, or the sum is <= 0 */
+    D2_PAIR_TOO_LARGE = 2,   /* empty support or more than D2_MAX_SUPPORT atoms   */
+    D2_PAIR_PIVOT_CAP = 3,   /* pivot cap reached; the value is NaN               */
+    D2_PAIR_BAD_POINTS = 4   /* a ground cost is not finite (NaN/inf coordinates) */
+};
+
+/* A ragged set of n discrete distributions in R^d (device memory). */
+typedef struct {
+    int64_t n;               /* number of distributions (>= 0)                    */
+    int32_t d;               /* dimension (>= 1)                                  */
+    int32_t dtype;           /* D2_F64 or D2_F32                                  */
+    const int64_t *offsets;  /* [n+1]; atoms of object i: offsets[i]..offsets[i+1] */
+    const void *points;      /* [offsets[n]][d] row-major, dtype                  */
+    const void *weights;     /* [offsets[n]], dtype, any non-negative scale       */
+    int32_t max_support;     /* host-known upper bound on offsets[i+1]-offsets[i] */
+    int32_t reserved;        /* set to 0                                          */
+} d2_set;
+
+typedef struct {
+    int32_t cost_mode;  /* D2_COST_*                                               */
+    int32_t init;       /* D2_INIT_*                                               */
+    int32_t max_pivots; /* 0 = default cap max(50 t s, 100) per pair               */
+    int32_t want_sqrt;  /* 0 -> D^2, 1 -> D                                        */
+    double opt_tol;     /* 0 = default 1e-14; the simplex stops when every reduced *
+                         * cost is >= -opt_tol * max_ab C_ab                       */
+} d2_opts;
+
+typedef struct d2_handle d2_handle;
+
+/* Create a handle bound to HIP device `device`.  Allocates host memory only. */
+d2_status d2_create(d2_handle **h, int device);
+d2_status d2_destroy(d2_handle *h);
+const char *d2_status_string(int code);
+/* D2_MAX_SUPPORT and the library version, for binding self-checks. */
+int d2_max_support(void);
+const char *d2_version(void);
+
+/* Bytes of device workspace the call with these arguments needs (may be 0).
+ * `which` is 0 = d2_cost_tiles, 1 = d2_emd_batch, 2 = d2_assign,
+ * 3 = d2_pairwise; `npairs` is the pair count for 0 and 1, ignored otherwise;
+ * B may be NULL for d2_pairwise. */
+size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set *B,
+                          int64_t npairs, const d2_opts *opts);
+
+/* Ground-cost tiles (the t_i x s_j matrices |x_a - y_b|^2 inside Eq. (1)).
+ * pairs[npairs][2] (device int64): (i in A, j in B).  Tile k is written
+ * row-major (a over A's atoms, b over B's atoms) at tiles + tile_offsets[k];
+ * tile_offsets[npairs+1] (device int64) is supplied by the caller and must
+ * leave t_i*s_j doubles for pair k.  For testing and the precision study. */
+d2_status d2_cost_tiles(d2_handle *h, const d2_set *A, const d2_set *B, const int64_t *pairs,
+                        int64_t npairs, int32_t cost_mode, double *tiles,
+                        const int64_t *tile_offsets, void *ws, size_t ws_bytes, void *stream);
+
+/* D^2 for an explicit pair list: dist[k] = D^2(A_i, B_j) for pairs[k] = (i,j).
+ * plan_offsets, plan (nullable, both or neither): the optimal transport plan
+ * of pair k is written densely row-major (t_i x s_j doubles) at
+ * plan + plan_offsets[k].  duals (nullable): u[t_i] then v[s_j] at
+ * duals + dual_offsets[k] (dual_offsets[npairs+1], nullable with duals),
+ * satisfying u_a + v_b = C_ab on the plan's support and u_a + v_b <= C_ab +
+ * tol elsewhere.  pair_status[npairs] may be NULL. */
+d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int64_t *pairs,
+                       int64_t npairs, const d2_opts *opts, double *dist,
+                       const int64_t *plan_offsets, double *plan, const int64_t *dual_offsets,
+                       double *duals, int32_t *pair_status, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/* Nearest-centroid labelling (Alg. 2, Step 2) over the full cross product:
+ * for every object i of X, D^2 to every centroid j of Z, then
+ * labels[i] = argmin_j (ties: lowest j), best[i] = the minimum.  all[n][K]
+ * (nullable) receives every D^2; row_status[n] (nullable) the worst pair
+ * status of the row. */
+d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opts *opts,
+                    int32_t *labels, double *best, double *all, int32_t *row_status, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* All unordered pairs i<j of one set (one segment's pairwise matrix):
+ * condensed[k] for k = i*n - i*(i+1)/2 + (j-i-1), the order of
+ * scipy.spatial.distance.squareform.  pair_status (nullable) has the same
+ * shape. */
+d2_status d2_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double *condensed,
+                      int32_t *pair_status, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* D2_H */

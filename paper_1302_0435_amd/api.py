@@ -1,0 +1,225 @@
+"""Python binding of libd2 with the C ABI's names.
+
+Argument marshalling only: tensors are turned into device pointers and the
+current torch stream is passed down; every step of the computation runs in
+the HIP kernels.  Torch provides the device memory (outputs, workspace) and
+the stream.
+
+    h = Handle(0)
+    X = DeviceSet.from_ragged(ragged, device)          # offsets/points/weights on the GPU
+    labels, best, all_, status = d2_assign(h, X, Z)
+    dist, status = d2_emd_batch(h, A, B, pairs)[:2]
+    condensed, status = d2_pairwise(h, X)
+    tiles, tile_offsets = d2_cost_tiles(h, A, B, pairs)
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+import torch
+
+from . import _ffi
+from ._ffi import check
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclasses.dataclass
+class DeviceSet:
+    """A ragged set resident on the GPU (see d2_set in include/d2.h)."""
+    offsets: torch.Tensor   # int64 [n+1]
+    points: torch.Tensor    # float64|float32 [offsets[n], d]
+    weights: torch.Tensor   # same dtype [offsets[n]]
+    max_support: int
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets.shape[0]) - 1
+
+    @property
+    def d(self) -> int:
+        return int(self.points.shape[1])
+
+    @classmethod
+    def from_ragged(cls, s, device="cuda:0") -> "DeviceSet":
+        """From any object with numpy ``offsets``, ``points``, ``weights``."""
+        off = torch.as_tensor(s.offsets, dtype=torch.int64)
+        sizes = off[1:] - off[:-1]
+        ms = int(sizes.max()) if sizes.numel() else 1
+        pts = torch.as_tensor(s.points)
+        if pts.dtype not in (torch.float32, torch.float64):
+            pts = pts.to(torch.float64)
+        w = torch.as_tensor(s.weights).to(pts.dtype)
+        return cls(off.to(device), pts.reshape(off[-1].item() if off.numel() else 0, -1)
+                   .contiguous().to(device), w.contiguous().to(device), max(ms, 1))
+
+    def c(self) -> _ffi.d2_set:
+        if self.points.dtype == torch.float64:
+            dt = _ffi.D2_F64
+        elif self.points.dtype == torch.float32:
+            dt = _ffi.D2_F32
+        else:
+            raise TypeError("points must be float32 or float64")
+        if self.weights.dtype != self.points.dtype:
+            raise TypeError("weights and points must share a dtype")
+        for t in (self.offsets, self.points, self.weights):
+            if not t.is_contiguous():
+                raise ValueError("set tensors must be contiguous")
+        return _ffi.d2_set(self.n, self.d, dt, self.offsets.data_ptr(), self.points.data_ptr(),
+                           self.weights.data_ptr(), int(self.max_support), 0)
+
+
+@dataclasses.dataclass
+class Opts:
+    cost_mode: int = _ffi.D2_COST_F64_DIRECT
+    init: int = _ffi.D2_INIT_AUTO
+    max_pivots: int = 0
+    want_sqrt: int = 0
+    opt_tol: float = 0.0
+
+    def c(self) -> _ffi.d2_opts:
+        return _ffi.d2_opts(self.cost_mode, self.init, self.max_pivots, self.want_sqrt,
+                            self.opt_tol)
+
+
+class Handle:
+    """Owns a d2_handle bound to one GPU."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = ctypes.c_void_p()
+        check(_ffi.lib().d2_create(ctypes.byref(h), device), "d2_create")
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _ffi.lib().d2_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev(h: Handle) -> torch.device:
+    return torch.device("cuda", h.device)
+
+
+def d2_workspace_bytes(h: Handle, which: int, A: DeviceSet, B: Optional[DeviceSet] = None,
+                       npairs: int = 0, opts: Optional[Opts] = None) -> int:
+    a = A.c()
+    b = B.c() if B is not None else None
+    o = (opts or Opts()).c()
+    return int(_ffi.lib().d2_workspace_bytes(h.ptr, which, ctypes.byref(a),
+                                              ctypes.byref(b) if b is not None else None, npairs,
+                                              ctypes.byref(o)))
+
+
+def _workspace(h, which, A, B, npairs, opts):
+    nbytes = d2_workspace_bytes(h, which, A, B, npairs, opts)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=_dev(h))
+    return ws, nbytes
+
+
+def d2_assign(h: Handle, X: DeviceSet, Z: DeviceSet, opts: Optional[Opts] = None,
+              want_all: bool = False):
+    """labels[n] int32, best[n] f64, all[n,K] f64 or None, row_status[n] int32."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    n, K = X.n, Z.n
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    best = torch.empty(n, dtype=torch.float64, device=dev)
+    allv = torch.empty((n, K), dtype=torch.float64, device=dev) if want_all else None
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    ws, nbytes = _workspace(h, _ffi.WHICH_ASSIGN, X, Z, 0, opts)
+    x, z, o = X.c(), Z.c(), opts.c()
+    check(_ffi.lib().d2_assign(h.ptr, ctypes.byref(x), ctypes.byref(z), ctypes.byref(o),
+                               _ptr(labels), _ptr(best), _ptr(allv), _ptr(status), _ptr(ws),
+                               nbytes, _stream(dev)), "d2_assign")
+    return labels, best, allv, status
+
+
+def _pair_sizes(A: DeviceSet, B: DeviceSet, pairs: torch.Tensor):
+    sa = (A.offsets[1:] - A.offsets[:-1])[pairs[:, 0]]
+    sb = (B.offsets[1:] - B.offsets[:-1])[pairs[:, 1]]
+    return sa, sb
+
+
+def _offsets_of(sizes: torch.Tensor) -> torch.Tensor:
+    off = torch.zeros(sizes.numel() + 1, dtype=torch.int64, device=sizes.device)
+    off[1:] = torch.cumsum(sizes, 0)
+    return off
+
+
+def d2_emd_batch(h: Handle, A: DeviceSet, B: DeviceSet, pairs: torch.Tensor,
+                 opts: Optional[Opts] = None, want_plan: bool = False, want_duals: bool = False):
+    """dist[m], status[m], and (plan, plan_offsets), (duals, dual_offsets) when asked."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    pairs = pairs.to(device=dev, dtype=torch.int64).reshape(-1, 2).contiguous()
+    m = int(pairs.shape[0])
+    dist = torch.empty(m, dtype=torch.float64, device=dev)
+    status = torch.empty(m, dtype=torch.int32, device=dev)
+    plan = plan_off = duals = dual_off = None
+    if want_plan or want_duals:
+        sa, sb = _pair_sizes(A, B, pairs)
+        if want_plan:
+            plan_off = _offsets_of(sa * sb)
+            plan = torch.empty(int(plan_off[-1].item()) if m else 0, dtype=torch.float64,
+                               device=dev)
+        if want_duals:
+            dual_off = _offsets_of(sa + sb)
+            duals = torch.empty(int(dual_off[-1].item()) if m else 0, dtype=torch.float64,
+                                device=dev)
+    ws, nbytes = _workspace(h, _ffi.WHICH_EMD_BATCH, A, B, m, opts)
+    a, b, o = A.c(), B.c(), opts.c()
+    check(_ffi.lib().d2_emd_batch(h.ptr, ctypes.byref(a), ctypes.byref(b), _ptr(pairs), m,
+                                  ctypes.byref(o), _ptr(dist), _ptr(plan_off), _ptr(plan),
+                                  _ptr(dual_off), _ptr(duals), _ptr(status), _ptr(ws), nbytes,
+                                  _stream(dev)), "d2_emd_batch")
+    return dist, status, (plan, plan_off), (duals, dual_off)
+
+
+def d2_pairwise(h: Handle, X: DeviceSet, opts: Optional[Opts] = None):
+    """condensed[n(n-1)/2] f64 (squareform order), status (same shape)."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    m = X.n * (X.n - 1) // 2
+    out = torch.empty(m, dtype=torch.float64, device=dev)
+    status = torch.empty(m, dtype=torch.int32, device=dev)
+    ws, nbytes = _workspace(h, _ffi.WHICH_PAIRWISE, X, None, 0, opts)
+    x, o = X.c(), opts.c()
+    check(_ffi.lib().d2_pairwise(h.ptr, ctypes.byref(x), ctypes.byref(o), _ptr(out),
+                                 _ptr(status), _ptr(ws), nbytes, _stream(dev)), "d2_pairwise")
+    return out, status
+
+
+def d2_cost_tiles(h: Handle, A: DeviceSet, B: DeviceSet, pairs: torch.Tensor,
+                  cost_mode: int = _ffi.D2_COST_F64_DIRECT):
+    """tiles (ragged, row-major t_i x s_j per pair), tile_offsets[m+1]."""
+    dev = _dev(h)
+    pairs = pairs.to(device=dev, dtype=torch.int64).reshape(-1, 2).contiguous()
+    m = int(pairs.shape[0])
+    sa, sb = _pair_sizes(A, B, pairs)
+    off = _offsets_of(sa * sb)
+    tiles = torch.empty(int(off[-1].item()) if m else 0, dtype=torch.float64, device=dev)
+    ws, nbytes = _workspace(h, _ffi.WHICH_COST_TILES, A, B, m, None)
+    a, b = A.c(), B.c()
+    check(_ffi.lib().d2_cost_tiles(h.ptr, ctypes.byref(a), ctypes.byref(b), _ptr(pairs), m,
+                                   cost_mode, _ptr(tiles), _ptr(off), _ptr(ws), nbytes,
+                                   _stream(dev)), "d2_cost_tiles")
+    return tiles, off

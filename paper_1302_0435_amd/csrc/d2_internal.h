@@ -1,0 +1,65 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "d2.h"
+
+namespace d2 {
+
+// Options as the kernels see them (validated and defaulted on the host).
+struct KOpts {
+    int init;        // D2_INIT_NWC or D2_INIT_VOGEL (AUTO resolved on the host)
+    int max_pivots;  // 0 = max(50 t s, 100)
+    int want_sqrt;
+    int cost_mode;
+    double tol;      // relative optimality tolerance
+};
+
+// Device view of a ragged set.
+struct KSet {
+    const int64_t *off;
+    const void *pts;
+    const void *w;
+    int64_t n;
+    int d;
+    int dtype;
+};
+
+struct LaunchCtx {
+    hipStream_t stream;
+    int cu_count;
+};
+
+// Group width (lanes per pair) that covers supports up to `maxsup`.
+int group_width_for(int maxsup);
+
+// Work split of d2_assign: each (row, chunk) workgroup scans a chunk of the
+// centroids; partial minima go to the workspace when chunks > 1.
+struct AssignPlan {
+    int G;
+    int64_t chunks;
+    int64_t per_chunk;
+    size_t ws_bytes;
+};
+AssignPlan plan_assign(const KSet &X, const KSet &Z, int maxsup, int cu_count);
+
+hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
+                         const KOpts &o, int32_t *labels, double *best, double *all,
+                         int32_t *row_status, void *ws);
+
+hipError_t launch_emd_pairs(const LaunchCtx &c, int G, const KSet &A, const KSet &B,
+                            const int64_t *pairs, int64_t npairs, const KOpts &o, double *dist,
+                            const int64_t *plan_off, double *plan, const int64_t *dual_off,
+                            double *duals, int32_t *status);
+
+hipError_t launch_pairwise(const LaunchCtx &c, int G, const KSet &X, const KOpts &o,
+                           double *condensed, int32_t *status);
+
+hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
+                             const int64_t *pairs, int64_t npairs, int cost_mode, double *tiles,
+                             const int64_t *tile_off);
+
+}  // namespace d2
