@@ -8,51 +8,75 @@
 // basis, pricing r_ab = C_ab - u_a - v_b, and pivots around the cycle that
 // the entering cell closes in the basis spanning tree.
 //
-// GPU mapping.  A "group" of G lanes (G = 16, 32 or 64, so 64/G pairs per
+// GPU mapping.  A "group" of G lanes (G = 16, 32 or 64; 64/G pairs per
 // wavefront) owns one pair at a time.  The pair is oriented so that rows are
 // the larger support (D^2 is symmetric).  Lane l owns row node l and column
-// node l of the basis tree.  Every node stores its parent, the flow and cost
-// of the edge to its parent, its potential and its ancestor set as a bitmask
-// over the 2G nodes.  With ancestor masks a pivot needs no pointer chasing:
+// node l of the basis tree and keeps row l of the cost tile in registers.
+// Each node stores its parent, the flow and cost of its parent edge, its
+// potential and its ancestor set as a bitmask over the 2G nodes.  With
+// ancestor masks a pivot needs no pointer chasing:
 //   * the cycle of entering cell (r, c) is the tree path r..c, i.e. the nodes
 //     in anc(r) xor anc(c); the edges whose flow decreases are the row nodes
 //     on r's side and the column nodes on c's side;
 //   * the ratio test is a group min-reduction over those edges' flows;
-//   * the subtree cut off by the leaving edge is {x : L in anc(x)}, found by
-//     one ballot; it is re-hung below the entering cell, the edges on the
-//     path from the entering end up to L ("stem") change direction, and the
-//     new ancestor set of every moved node is anc(p) | (A xor stem) | {y},
-//     where A is its old ancestor set inside the subtree and y its deepest
-//     ancestor on the stem (looked up by position along the stem);
+//   * the subtree cut off by the leaving edge is {x : L in anc(x)}, one
+//     ballot; it is re-hung below the entering cell, the edges on the path
+//     from the entering end up to L ("stem") change direction, and the new
+//     ancestor set of every moved node is anc(p) | (A xor stem) | {y}, with A
+//     its old ancestor set inside the subtree and y its deepest ancestor on
+//     the stem (looked up by position along the stem);
 //   * potentials change only inside the moved subtree, by +-r_entering.
-// Potentials are recomputed from the tree by pointer jumping at the start
-// and once more before declaring optimality, so rounding drift in the
-// incremental updates cannot end the solve early.
+// Potentials are set from the tree as signed sums over ancestor sets at the
+// start and once more before optimality is declared, so rounding drift in
+// the incremental updates cannot end the solve early.
 //
-// All arithmetic that decides the result uses fixed orders that do not
-// depend on G (serial index-order sums, exact min/max reductions), so every
-// group width returns the same bits for the same pair.
+// Group communication: reductions are butterflies over DPP row permutations
+// (16 lanes), plus a swizzle (32) and a lane permute (64); broadcasts go
+// through a few LDS words.
+//
+// Every arithmetic step that decides the result runs in an order that does
+// not depend on G (index-order sums, exact min/max reductions), so all group
+// widths return the same bits for the same pair.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "d2_internal.h"
 
 namespace d2 {
 
 enum { kOk = 0, kBadWeights = 1, kTooLarge = 2, kPivotCap = 3, kBadPoints = 4 };
+constexpr int kNoKey = 0x7fffffff;
 
 // ------------------------------------------------------------------ masks
 
-// Node sets of one group's tree.  G <= 32: rows in bits [0,32), columns in
-// bits [32,64) of one word.  G = 64: one word each.
+// Node sets of one group's tree: rows are nodes 0..G-1, columns G..2G-1.
 template <int G>
-struct Mask {
+struct Mask;
+
+template <>
+struct Mask<16> {  // rows in bits [0,16), columns in [16,32)
+    uint32_t m;
+    __device__ static Mask none() { return {0u}; }
+    __device__ static Mask node(int id) { return {1u << id}; }
+    __device__ static Mask rows_only() { return {0x0000FFFFu}; }
+    __device__ static Mask cols_only() { return {0xFFFF0000u}; }
+    __device__ static Mask from_bits(uint64_t r, uint64_t c) { return {(uint32_t)r | ((uint32_t)c << 16)}; }
+    __device__ Mask operator|(Mask o) const { return {m | o.m}; }
+    __device__ Mask operator&(Mask o) const { return {m & o.m}; }
+    __device__ Mask operator^(Mask o) const { return {m ^ o.m}; }
+    __device__ Mask andnot(Mask o) const { return {m & ~o.m}; }
+    __device__ bool has(int id) const { return (m >> id) & 1u; }
+    __device__ int popc() const { return __popc(m); }
+};
+
+template <>
+struct Mask<32> {  // rows in bits [0,32), columns in [32,64)
     uint64_t m;
     __device__ static Mask none() { return {0ull}; }
-    __device__ static Mask row(int i) { return {1ull << i}; }
-    __device__ static Mask col(int j) { return {1ull << (32 + j)}; }
-    __device__ static Mask node(int id) { return id < G ? row(id) : col(id - G); }
+    __device__ static Mask node(int id) { return {1ull << id}; }
     __device__ static Mask rows_only() { return {0x00000000FFFFFFFFull}; }
     __device__ static Mask cols_only() { return {0xFFFFFFFF00000000ull}; }
     __device__ static Mask from_bits(uint64_t r, uint64_t c) { return {r | (c << 32)}; }
@@ -60,19 +84,15 @@ struct Mask {
     __device__ Mask operator&(Mask o) const { return {m & o.m}; }
     __device__ Mask operator^(Mask o) const { return {m ^ o.m}; }
     __device__ Mask andnot(Mask o) const { return {m & ~o.m}; }
-    __device__ bool has(int id) const { return id < G ? ((m >> id) & 1ull) : ((m >> (32 + id - G)) & 1ull); }
-    __device__ bool has_row(int i) const { return (m >> i) & 1ull; }
+    __device__ bool has(int id) const { return (m >> id) & 1ull; }
     __device__ int popc() const { return __popcll(m); }
-    __device__ Mask bcast(int src) const { return {__shfl(m, src, G)}; }
 };
 
 template <>
-struct Mask<64> {
+struct Mask<64> {  // one word for rows, one for columns
     uint64_t r, c;
     __device__ static Mask none() { return {0ull, 0ull}; }
-    __device__ static Mask row(int i) { return {1ull << i, 0ull}; }
-    __device__ static Mask col(int j) { return {0ull, 1ull << j}; }
-    __device__ static Mask node(int id) { return id < 64 ? row(id) : col(id - 64); }
+    __device__ static Mask node(int id) { return id < 64 ? Mask{1ull << id, 0ull} : Mask{0ull, 1ull << (id - 64)}; }
     __device__ static Mask rows_only() { return {~0ull, 0ull}; }
     __device__ static Mask cols_only() { return {0ull, ~0ull}; }
     __device__ static Mask from_bits(uint64_t rr, uint64_t cc) { return {rr, cc}; }
@@ -81,15 +101,10 @@ struct Mask<64> {
     __device__ Mask operator^(Mask o) const { return {r ^ o.r, c ^ o.c}; }
     __device__ Mask andnot(Mask o) const { return {r & ~o.r, c & ~o.c}; }
     __device__ bool has(int id) const { return id < 64 ? ((r >> id) & 1ull) : ((c >> (id - 64)) & 1ull); }
-    __device__ bool has_row(int i) const { return (r >> i) & 1ull; }
     __device__ int popc() const { return __popcll(r) + __popcll(c); }
-    __device__ Mask bcast(int src) const { return {__shfl(r, src, 64), __shfl(c, src, 64)}; }
 };
 
-template <int G>
-struct Log2 { static constexpr int v = G == 16 ? 4 : (G == 32 ? 5 : 6); };
-
-// Orders LDS traffic between lanes of one wavefront (hardware executes a
+// Orders LDS traffic between lanes of one wavefront (the hardware executes a
 // wavefront's LDS operations in order; this keeps the compiler from moving
 // loads above stores).
 __device__ __forceinline__ void wsync() {
@@ -98,21 +113,120 @@ __device__ __forceinline__ void wsync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ------------------------------------------------------- lane exchanges
+
+// Butterfly partner exchange, step k of an all-reduce over G lanes:
+// quad xor 1, quad xor 2, half-row mirror, row mirror (DPP), then xor 16
+// (swizzle, G >= 32) and xor 32 (lane permute, G = 64).  After log2(G)
+// steps with a commutative, associative combine every lane holds the result.
+template <int STEP>
+__device__ __forceinline__ int xchg(int v) {
+    if constexpr (STEP == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (STEP == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (STEP == 2) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+    else if constexpr (STEP == 3) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+    else if constexpr (STEP == 4) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+    else return __shfl_xor(v, 32, 64);
+}
+
+template <int STEP>
+__device__ __forceinline__ double xchg(double v) {
+    long long b = __double_as_longlong(v);
+    int lo = xchg<STEP>((int)(b & 0xffffffffll));
+    int hi = xchg<STEP>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int G>
+struct Steps { static constexpr int n = G == 16 ? 4 : (G == 32 ? 5 : 6); };
+
+// (value, key) minimum over the group, lowest key on equal values.
+template <int G, int STEP = 0>
+__device__ __forceinline__ void group_argmin(double &v, int &k) {
+    if constexpr (STEP < Steps<G>::n) {
+        double ov = xchg<STEP>(v);
+        int ok = xchg<STEP>(k);
+        bool take = (ov < v) || (ov == v && ok < k);
+        v = take ? ov : v;
+        k = take ? ok : k;
+        group_argmin<G, STEP + 1>(v, k);
+    }
+}
+
+template <int G, int STEP = 0>
+__device__ __forceinline__ double group_max(double v) {
+    if constexpr (STEP < Steps<G>::n) return group_max<G, STEP + 1>(fmax(v, xchg<STEP>(v)));
+    else return v;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_bits(bool p, int gbase) {
+    uint64_t b = __ballot(p);
+    const uint64_t gm = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    return (b >> gbase) & gm;
+}
+
+// Value of lane J of the group, to every lane of the group (J fixed at
+// compile time): DPP row broadcast for 16 lanes, lane reads otherwise.
+template <int G, int J>
+__device__ __forceinline__ int gbcast(int v, int gbase) {
+    if constexpr (G == 16) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x150 + J, 0xF, 0xF, false);
+    } else if constexpr (G == 32) {
+        const int a = __builtin_amdgcn_readlane(v, J);
+        const int b = __builtin_amdgcn_readlane(v, 32 + J);
+        return gbase ? b : a;
+    } else {
+        return __builtin_amdgcn_readlane(v, J);
+    }
+}
+
+template <int G, int J>
+__device__ __forceinline__ double gbcast_widen(float v, int gbase) {
+    return (double)__int_as_float(gbcast<G, J>(__float_as_int(v), gbase));
+}
+
+template <int G, int J>
+__device__ __forceinline__ double gbcast_widen(double v, int gbase) {
+    const long long b = __double_as_longlong(v);
+    const int lo = gbcast<G, J>((int)(b & 0xffffffffll), gbase);
+    const int hi = gbcast<G, J>((int)(b >> 32), gbase);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int J, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (J < N) {
+        f(std::integral_constant<int, J>{});
+        static_for<J + 1, N>(f);
+    }
+}
+
 // ------------------------------------------------------------ group memory
 
 template <int G>
 struct GroupMem {
-    double C[G][G + 1];  // cost tile, rows x columns (padded stride)
-    double vpot[G];      // column potentials, read by every row lane when pricing
+    double vpot[G];          // column potentials, read by every row lane when pricing
+    Mask<G> ancRm[G];        // ancestor masks of row nodes (mirror for broadcast)
+    Mask<G> ancCm[G];        // ancestor masks of column nodes
+    double bc_r, bc_c;       // entering cell: reduced cost and cost
     union {
-        struct { double pw[G]; double qw[G]; } w;  // weights / remaining supply and demand
-        struct { int jmp[2 * G]; Mask<G> anc[2 * G]; double val[2 * G]; } jump;
-        struct { int newpar[2 * G]; int stemtab[2 * G]; double newflow[2 * G]; double newcpar[2 * G]; } piv;
+        struct { double pw[G]; double qw[G]; double P[G]; double Q[G]; double colcpar[G];
+                 int colpar[G]; int kind[2 * G]; int lastpos[2 * G]; } init;
+        struct { int jmp[2 * G]; Mask<G> anc[2 * G]; } jump;
+        struct { double g[2 * G]; } pot;
+        struct { int newpar[2 * G]; int stemtab[2 * G]; double newflow[2 * G];
+                 double newcpar[2 * G]; } piv;
         struct { double obj[2 * G]; double colflow[G]; int colpar[G]; } fin;
     } u;
 };
 
-// Per-lane state: row node l and column node l.
+// Full cost tile, only for Vogel's start (it scans columns).
+template <int G>
+struct VogelTile { double C[G][G + 1]; };
+struct NoTile { char pad; };
+
+// Per-lane state: row node l, column node l, and row l of the cost tile.
 template <int G>
 struct NodeState {
     int parR, parC;          // parent index (a column / a row), -1 at the root
@@ -121,45 +235,12 @@ struct NodeState {
     double potR, potC;       // u_l, v_l
     Mask<G> ancR, ancC;      // ancestors including the node itself
     uint64_t bas;            // basic cells of row l, as a column bitmask
+    double crow[G];          // C[l][j], 0 beyond the columns
 };
 
 template <typename T>
 __device__ __forceinline__ double ldw(const void *p, int64_t i) {
     return (double)((const T *)p)[i];
-}
-
-// (value, index) minimum over the group, lowest index on equal values.
-template <int G>
-__device__ __forceinline__ void group_argmin(double &v, int &i) {
-#pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) {
-        double ov = __shfl_xor(v, off, G);
-        int oi = __shfl_xor(i, off, G);
-        bool take = (ov < v) || (ov == v && oi < i);
-        v = take ? ov : v;
-        i = take ? oi : i;
-    }
-}
-
-template <int G>
-__device__ __forceinline__ double group_max(double v) {
-#pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, G));
-    return v;
-}
-
-template <int G>
-__device__ __forceinline__ bool group_any(bool p, int gbase) {
-    uint64_t b = __ballot(p);
-    uint64_t gm = G == 64 ? ~0ull : ((1ull << G) - 1ull);
-    return ((b >> gbase) & gm) != 0ull;
-}
-
-template <int G>
-__device__ __forceinline__ uint64_t group_bits(bool p, int gbase) {
-    uint64_t b = __ballot(p);
-    uint64_t gm = G == 64 ? ~0ull : ((1ull << G) - 1ull);
-    return (b >> gbase) & gm;
 }
 
 // One oriented pair: rows = the larger support.
@@ -189,27 +270,60 @@ __device__ __forceinline__ PairView orient(const KSet &A, int64_t i, const KSet 
     return v;
 }
 
-// ---------------------------------------------------------- tree rebuild
-
-// Ancestor masks and potentials of every node from the parent pointers and
-// parent-edge costs, by pointer jumping (log2(2G) rounds).  The potential of
-// node x is sign(x) * sum over the path x..root of sign(n) * cpar(n) with
-// sign = (-1)^depth, which unrolls u_a + v_b = C_ab along the path.
 template <int G>
-__device__ void rebuild_tree(GroupMem<G> &M, NodeState<G> &N, int l, int T, int S) {
+__device__ __forceinline__ double pick(const double (&a)[G], int j) {
+    double r = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) r = (k == j) ? a[k] : r;
+    return r;
+}
+
+// ------------------------------------------------------------ potentials
+
+// u, v from the tree: with sign(n) = (-1)^depth(n), the potential of node x
+// is sign(x) * sum over its ancestors n != root of sign(n) * cpar(n), which
+// unrolls u_a + v_b = C_ab along the path to the root.  The sum runs over
+// node indices in order (rows, then columns).  Also refreshes the LDS
+// mirrors read when pricing and when broadcasting the entering cell.
+template <int G>
+__device__ void set_potentials(GroupMem<G> &M, NodeState<G> &N, int l, int T, int S) {
+    const bool hasR = l < T, hasC = l < S;
+    const double sR = ((N.ancR.popc() - 1) & 1) ? -1.0 : 1.0;
+    const double sC = ((N.ancC.popc() - 1) & 1) ? -1.0 : 1.0;
+    M.u.pot.g[l] = (hasR && N.parR >= 0) ? sR * N.cparR : 0.0;
+    M.u.pot.g[G + l] = (hasC && N.parC >= 0) ? sC * N.cparC : 0.0;
+    wsync();
+    double sumR = 0.0, sumC = 0.0;
+#pragma unroll 4
+    for (int n = 0; n < 2 * G; ++n) {
+        const double gv = M.u.pot.g[n];
+        sumR += N.ancR.has(n) ? gv : 0.0;
+        sumC += N.ancC.has(n) ? gv : 0.0;
+    }
+    N.potR = sR * sumR;
+    N.potC = sC * sumC;
+    if (hasC) M.vpot[l] = N.potC;
+    M.ancRm[l] = N.ancR;
+    M.ancCm[l] = N.ancC;
+    wsync();
+}
+
+// Ancestor masks from parent pointers by pointer jumping (Vogel's tree).
+template <int G>
+__device__ void anc_by_jumping(GroupMem<G> &M, NodeState<G> &N, int l, int T, int S) {
     const bool hasR = l < T, hasC = l < S;
     const int idR = l, idC = G + l;
     int jR = (hasR && N.parR >= 0) ? G + N.parR : idR;
     int jC = (hasC && N.parC >= 0) ? N.parC : idC;
-    Mask<G> aR = hasR ? Mask<G>::row(l) : Mask<G>::none();
-    Mask<G> aC = hasC ? Mask<G>::col(l) : Mask<G>::none();
+    Mask<G> aR = hasR ? Mask<G>::node(idR) : Mask<G>::none();
+    Mask<G> aC = hasC ? Mask<G>::node(idC) : Mask<G>::none();
     M.u.jump.jmp[idR] = jR;
     M.u.jump.jmp[idC] = jC;
     M.u.jump.anc[idR] = aR;
     M.u.jump.anc[idC] = aC;
     wsync();
 #pragma unroll 1
-    for (int k = 0; k < Log2<G>::v + 1; ++k) {
+    for (int k = 0; k < Steps<G>::n + 1; ++k) {
         int nR = M.u.jump.jmp[jR], nC = M.u.jump.jmp[jC];
         Mask<G> xR = M.u.jump.anc[jR], xC = M.u.jump.anc[jC];
         wsync();
@@ -225,36 +339,6 @@ __device__ void rebuild_tree(GroupMem<G> &M, NodeState<G> &N, int l, int T, int 
     }
     N.ancR = aR;
     N.ancC = aC;
-    const double sR = ((aR.popc() - 1) & 1) ? -1.0 : 1.0;
-    const double sC = ((aC.popc() - 1) & 1) ? -1.0 : 1.0;
-    double vR = (hasR && N.parR >= 0) ? sR * N.cparR : 0.0;
-    double vC = (hasC && N.parC >= 0) ? sC * N.cparC : 0.0;
-    jR = (hasR && N.parR >= 0) ? G + N.parR : idR;
-    jC = (hasC && N.parC >= 0) ? N.parC : idC;
-    M.u.jump.jmp[idR] = jR;
-    M.u.jump.jmp[idC] = jC;
-    M.u.jump.val[idR] = vR;
-    M.u.jump.val[idC] = vC;
-    wsync();
-#pragma unroll 1
-    for (int k = 0; k < Log2<G>::v + 1; ++k) {
-        int nR = M.u.jump.jmp[jR], nC = M.u.jump.jmp[jC];
-        double xR = M.u.jump.val[jR], xC = M.u.jump.val[jC];
-        wsync();
-        vR += xR;
-        vC += xC;
-        jR = nR;
-        jC = nC;
-        M.u.jump.jmp[idR] = jR;
-        M.u.jump.jmp[idC] = jC;
-        M.u.jump.val[idR] = vR;
-        M.u.jump.val[idC] = vC;
-        wsync();
-    }
-    N.potR = sR * vR;
-    N.potC = sC * vC;
-    if (hasC) M.vpot[l] = N.potC;
-    wsync();
 }
 
 // ------------------------------------------------------------ one solve
@@ -267,9 +351,9 @@ struct SolveOut {
 // Solve the LP of one oriented pair with the G lanes of this group.  On
 // return every lane holds the same SolveOut; N holds the optimal basis tree
 // and potentials (valid when status == kOk).
-template <int G, typename TIn>
-__device__ SolveOut solve_pair(GroupMem<G> &M, NodeState<G> &N, const PairView &pv, int d,
-                               const KOpts &o, int l, int gbase) {
+template <int G, typename TIn, bool VOGEL, typename TileT>
+__device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, const PairView &pv,
+                               int d, const KOpts &o, int l, int gbase) {
     SolveOut out{kOk, __builtin_nan("")};
     const int T = pv.T, S = pv.S;
     if (T < 1 || S < 1 || T > G || S > G) { out.status = kTooLarge; return out; }
@@ -278,80 +362,114 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, NodeState<G> &N, const PairView &
     // Weights: validated, then divided by their sum taken in index order.
     double pr = hasR ? ldw<TIn>(pv.wr, l) : 0.0;
     double pc = hasC ? ldw<TIn>(pv.wc, l) : 0.0;
-    bool badw = (hasR && !(isfinite(pr) && pr >= 0.0)) || (hasC && !(isfinite(pc) && pc >= 0.0));
-    M.u.w.pw[l] = pr;
-    M.u.w.qw[l] = pc;
+    const bool badw = (hasR && !(isfinite(pr) && pr >= 0.0)) || (hasC && !(isfinite(pc) && pc >= 0.0));
+    M.u.init.pw[l] = pr;
+    M.u.init.qw[l] = pc;
     wsync();
     double sumr = 0.0, sumc = 0.0;
-    for (int a = 0; a < T; ++a) sumr += M.u.w.pw[a];
-    for (int b = 0; b < S; ++b) sumc += M.u.w.qw[b];
-    badw = badw || !(sumr > 0.0) || !(sumc > 0.0) || !isfinite(sumr) || !isfinite(sumc);
-    if (group_any<G>(badw, gbase)) { out.status = kBadWeights; return out; }
+#pragma unroll 4
+    for (int a = 0; a < G; ++a) {
+        const double wp = M.u.init.pw[a], wq = M.u.init.qw[a];
+        sumr += wp;   // zeros beyond the support leave the sum unchanged
+        sumc += wq;
+    }
+    const bool badsum = !(sumr > 0.0) || !(sumc > 0.0) || !isfinite(sumr) || !isfinite(sumc);
+    if (group_bits<G>(badw || badsum, gbase) != 0ull) { out.status = kBadWeights; return out; }
     pr = pr / sumr;
     pc = pc / sumc;
-    wsync();
-    M.u.w.pw[l] = pr;
-    M.u.w.qw[l] = pc;
 
-    // Cost tile, direct form: C_ab = sum_k (x_ak - y_bk)^2.
+    // Cost row l, direct form: C_lj = sum_k (x_lk - y_jk)^2, k ascending.
+    // Lane l holds row point l and column point l; column point j reaches
+    // every lane of the group by a register broadcast.
+#pragma unroll
+    for (int j = 0; j < G; ++j) N.crow[j] = 0.0;
+    {
+        const TIn *xr = (const TIn *)pv.xr + (int64_t)l * d;
+        const TIn *yc = (const TIn *)pv.xc + (int64_t)l * d;
+        constexpr int KC = 4;
+        for (int k0 = 0; k0 < d; k0 += KC) {
+            TIn xv[KC], yv[KC];
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const bool in = k0 + kk < d;
+                xv[kk] = (hasR && in) ? xr[k0 + kk] : (TIn)0;
+                yv[kk] = (hasC && in) ? yc[k0 + kk] : (TIn)0;
+            }
+            static_for<0, G>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                if (j < S) {
+                    double acc = N.crow[j];
+#pragma unroll
+                    for (int kk = 0; kk < KC; ++kk) {
+                        if (k0 + kk < d) {
+                            const double diff = (double)xv[kk] - gbcast_widen<G, j>(yv[kk], gbase);
+                            acc = fma(diff, diff, acc);
+                        }
+                    }
+                    N.crow[j] = acc;
+                }
+            });
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) N.crow[j] = (hasR && j < S) ? N.crow[j] : 0.0;
+    }
     double cmax = 0.0;
     bool finite = true;
-    if (hasR) {
-        const TIn *xr = (const TIn *)pv.xr + (int64_t)l * d;
-        for (int j = 0; j < S; ++j) {
-            const TIn *yc = (const TIn *)pv.xc + (int64_t)j * d;
-            double acc = 0.0;
-            for (int k = 0; k < d; ++k) {
-                double diff = (double)xr[k] - (double)yc[k];
-                acc = fma(diff, diff, acc);
-            }
-            M.C[l][j] = acc;
-            finite = finite && isfinite(acc);
-            cmax = fmax(cmax, acc);
-        }
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        finite = finite && isfinite(N.crow[j]);
+        cmax = fmax(cmax, N.crow[j]);
     }
-    if (group_any<G>(!finite, gbase)) { out.status = kBadPoints; return out; }
+    if (group_bits<G>(!finite, gbase) != 0ull) { out.status = kBadPoints; return out; }
     cmax = group_max<G>(cmax);
     const double delta = o.tol * cmax;
-    wsync();
 
     // Starting basis: t+s-1 cells forming a spanning tree.
     N.parR = -1; N.parC = -1;
     N.flowR = 0.0; N.flowC = 0.0; N.cparR = 0.0; N.cparC = 0.0;
-    if (o.init == D2_INIT_VOGEL) {
+    wsync();
+    if constexpr (VOGEL) {
         // Vogel: close, one per round, the line whose two cheapest open cells
         // differ most (ties: rows first, lower index), filling its cheapest
         // open cell; the last open row (column) takes every open column's
         // remaining demand (row's remaining supply) and becomes the root.
+        M.u.init.pw[l] = pr;
+        M.u.init.qw[l] = pc;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (hasR && j < S) tile.C[l][j] = N.crow[j];
+        wsync();
         uint64_t rowon = (T == 64) ? ~0ull : ((1ull << T) - 1ull);
         uint64_t colon = (S == 64) ? ~0ull : ((1ull << S) - 1ull);
 #pragma unroll 1
         for (;;) {
-            int nr = __popcll(rowon), nc = __popcll(colon);
+            const int nr = __popcll(rowon), nc = __popcll(colon);
             if (nr == 1) {
-                int a = __ffsll((long long)rowon) - 1;
+                const int a = __ffsll((long long)rowon) - 1;
                 if (hasC && ((colon >> l) & 1ull)) {
-                    N.parC = a; N.flowC = M.u.w.qw[l]; N.cparC = M.C[a][l];
+                    N.parC = a; N.flowC = M.u.init.qw[l]; N.cparC = tile.C[a][l];
                 }
                 break;
             }
             if (nc == 1) {
-                int b = __ffsll((long long)colon) - 1;
+                const int b = __ffsll((long long)colon) - 1;
                 if (hasR && ((rowon >> l) & 1ull)) {
-                    N.parR = b; N.flowR = M.u.w.pw[l]; N.cparR = M.C[l][b];
+                    N.parR = b; N.flowR = M.u.init.pw[l]; N.cparR = tile.C[l][b];
                 }
                 break;
             }
             double pen = -1.0;
-            int key = 0x7fffffff, other = -1;
+            int key = kNoKey, other = -1;
             if (hasR && ((rowon >> l) & 1ull)) {
                 double m1 = INFINITY, m2 = INFINITY;
                 int j1 = -1;
-                for (int j = 0; j < S; ++j) {
-                    if (!((colon >> j) & 1ull)) continue;
-                    double c = M.C[l][j];
-                    if (c < m1) { m2 = m1; m1 = c; j1 = j; }
-                    else if (c < m2) m2 = c;
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    if (j < S && ((colon >> j) & 1ull)) {
+                        const double c = N.crow[j];
+                        if (c < m1) { m2 = m1; m1 = c; j1 = j; }
+                        else if (c < m2) m2 = c;
+                    }
                 }
                 pen = m2 - m1; key = l; other = j1;
             }
@@ -360,72 +478,142 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, NodeState<G> &N, const PairView &
                 int i1 = -1;
                 for (int a = 0; a < T; ++a) {
                     if (!((rowon >> a) & 1ull)) continue;
-                    double c = M.C[a][l];
+                    const double c = tile.C[a][l];
                     if (c < m1) { m2 = m1; m1 = c; i1 = a; }
                     else if (c < m2) m2 = c;
                 }
-                double pc2 = m2 - m1;
+                const double pc2 = m2 - m1;
                 if (pc2 > pen) { pen = pc2; key = 64 + l; other = i1; }
             }
-            // max penalty, then lowest key; carry `other`
-            double npen = -pen;
-            int packed = key * 128 + (other < 0 ? 127 : other);
+            double npen = key == kNoKey ? INFINITY : -pen;
+            int packed = key == kNoKey ? kNoKey : key * 128 + other;
             group_argmin<G>(npen, packed);
-            int bkey = packed >> 7, bother = packed & 127;
-            int a = bkey < 64 ? bkey : bother;
-            int b = bkey < 64 ? bother : bkey - 64;
-            double ra = M.u.w.pw[a], rb = M.u.w.qw[b];
-            double x = ra < rb ? ra : rb;
+            const int bkey = packed >> 7, bother = packed & 127;
+            const int a = bkey < 64 ? bkey : bother;
+            const int b = bkey < 64 ? bother : bkey - 64;
+            double ra = M.u.init.pw[a], rb = M.u.init.qw[b];
+            const double x = ra < rb ? ra : rb;
             ra -= x;
             rb -= x;
             wsync();
-            if (l == 0) { M.u.w.pw[a] = ra; M.u.w.qw[b] = rb; }
+            if (l == 0) { M.u.init.pw[a] = ra; M.u.init.qw[b] = rb; }
             if (ra <= rb) {
-                if (l == a) { N.parR = b; N.flowR = x; N.cparR = M.C[a][b]; }
+                if (l == a) { N.parR = b; N.flowR = x; N.cparR = tile.C[a][b]; }
                 rowon &= ~(1ull << a);
             } else {
-                if (l == b) { N.parC = a; N.flowC = x; N.cparC = M.C[a][b]; }
+                if (l == b) { N.parC = a; N.flowC = x; N.cparC = tile.C[a][b]; }
                 colon &= ~(1ull << b);
             }
             wsync();
         }
+        wsync();
+        M.u.init.colpar[l] = hasC ? N.parC : -1;
+        wsync();
+        N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0ull;
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+            if (hasR && c < S && M.u.init.colpar[c] == l) N.bas |= 1ull << c;
+        wsync();
+        anc_by_jumping<G>(M, N, l, T, S);
     } else {
-        // North-west corner; the last row takes each remaining column's
-        // demand, the last column each remaining row's supply; on a tie the
-        // walk moves down and keeps a zero cell.  Row 0 is the root.
-        int a = 0, b = 0, newer = G;  // first new node: column 0
-        double rs = M.u.w.pw[0], rd = M.u.w.qw[0];
-#pragma unroll 1
-        for (;;) {
-            double x = (a == T - 1) ? rd : ((b == S - 1) ? rs : (rs < rd ? rs : rd));
-            double c = M.C[a][b];
-            if (newer < G) {
-                if (l == newer) { N.parR = b; N.flowR = x; N.cparR = c; }
-            } else {
-                if (l == newer - G) { N.parC = a; N.flowC = x; N.cparC = c; }
-            }
-            rs -= x;
-            rd -= x;
-            if (a == T - 1 && b == S - 1) break;
-            if (a == T - 1) { b++; rd = M.u.w.qw[b]; newer = G + b; }
-            else if (b == S - 1) { a++; rs = M.u.w.pw[a]; newer = a; }
-            else if (rs <= rd) { a++; rs = M.u.w.pw[a]; newer = a; }
-            else { b++; rd = M.u.w.qw[b]; newer = G + b; }
+        // North-west corner, all nodes at once.  With inclusive prefix sums
+        // P_a of p and Q_b of q, the corner walk moves down after row a when
+        // P_a <= Q_b for the current column b (ties: down first).  So row a
+        // (a >= 1) hangs below column #{b <= S-2 : Q_b < P_{a-1}} and column b
+        // (b >= 1) below row #{a <= T-2 : P_a <= Q_{b-1}}; a cell's flow is the
+        // overlap of its row and column intervals, the last row and column
+        // extending to max(P_{T-1}, Q_{S-1}).  The walk visits nodes in the
+        // order row 0, column 0, then one node per move, so the depth of a
+        // node is its visiting position and its ancestors are the nodes
+        // visited before it.  Row 0 is the root.
+        M.u.init.pw[l] = pr;
+        M.u.init.qw[l] = pc;
+        wsync();
+        double Pl = 0.0, Ql = 0.0;
+#pragma unroll 4
+        for (int a = 0; a < G; ++a) {
+            const double wp = M.u.init.pw[a], wq = M.u.init.qw[a];
+            Pl += (a <= l) ? wp : 0.0;
+            Ql += (a <= l) ? wq : 0.0;
         }
+        M.u.init.P[l] = Pl;
+        M.u.init.Q[l] = Ql;
+        wsync();
+        const double END = fmax(M.u.init.P[T - 1], M.u.init.Q[S - 1]);
+        int idxR = 0x3fffffff, idxC = 0x3fffffff;
+        if (hasR && l >= 1) {
+            const double start = M.u.init.P[l - 1];
+            int b = 0;
+#pragma unroll 4
+            for (int j = 0; j < G - 1; ++j) {
+                const double qb = M.u.init.Q[j];
+                b += (j <= S - 2 && qb < start) ? 1 : 0;
+            }
+            const double er = (l == T - 1) ? END : Pl;
+            const double ec = (b == S - 1) ? END : M.u.init.Q[b];
+            N.parR = b;
+            N.flowR = fmin(er, ec) - start;
+            N.cparR = pick<G>(N.crow, b);
+            idxR = l + b + 1;
+        } else if (hasR) {
+            idxR = 0;
+        }
+        if (hasC) {
+            double start = 0.0;
+            int a = 0;
+            if (l >= 1) {
+                start = M.u.init.Q[l - 1];
+#pragma unroll 4
+                for (int i = 0; i < G - 1; ++i) {
+                    const double pa = M.u.init.P[i];
+                    a += (i <= T - 2 && pa <= start) ? 1 : 0;
+                }
+            }
+            const double ec = (l == S - 1) ? END : Ql;
+            const double er = (a == T - 1) ? END : M.u.init.P[a];
+            N.parC = a;
+            N.flowC = fmin(er, ec) - start;
+            idxC = l + a + 1;
+        }
+        // The walk's node sequence splits into runs of rows and runs of
+        // columns; a node hangs below the last node of the run before its
+        // own, so its ancestors are itself plus every run's last node visited
+        // before it.
+        M.u.init.colpar[l] = hasC ? N.parC : -1;
+        if (hasR) M.u.init.kind[idxR] = 0;
+        if (hasC) M.u.init.kind[idxC] = 1;
+        wsync();
+        // Basic cells of row l and the parent-edge costs of its child columns.
+        N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0ull;
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            if (hasR && c < S && M.u.init.colpar[c] == l) {
+                N.bas |= 1ull << c;
+                M.u.init.colcpar[c] = N.crow[c];
+            }
+        }
+        const int lastpos = T + S - 1;
+        const int nR = idxR + 1 < 2 * G ? idxR + 1 : 2 * G - 1;
+        const int nC = idxC + 1 < 2 * G ? idxC + 1 : 2 * G - 1;
+        const bool lastR = hasR && (idxR == lastpos || M.u.init.kind[nR] != 0);
+        const bool lastC = hasC && (idxC == lastpos || M.u.init.kind[nC] != 1);
+        M.u.init.lastpos[l] = lastR ? idxR : 0x3fffffff;
+        M.u.init.lastpos[G + l] = lastC ? idxC : 0x3fffffff;
+        wsync();
+        Mask<G> aR = Mask<G>::node(l), aC = Mask<G>::node(G + l);
+#pragma unroll 4
+        for (int n = 0; n < 2 * G; ++n) {
+            const int lp = M.u.init.lastpos[n];
+            if (lp < idxR) aR = aR | Mask<G>::node(n);
+            if (lp < idxC) aC = aC | Mask<G>::node(n);
+        }
+        N.ancR = hasR ? aR : Mask<G>::none();
+        N.ancC = hasC ? aC : Mask<G>::none();
+        if (hasC) N.cparC = M.u.init.colcpar[l];
+        wsync();
     }
-    wsync();
 
-    // Basic cells per row: the row's own parent edge plus the columns that
-    // hang below it.
-    M.u.fin.colpar[l] = hasC ? N.parC : -1;
-    wsync();
-    N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0ull;
-    if (hasR)
-        for (int c = 0; c < S; ++c)
-            if (M.u.fin.colpar[c] == l) N.bas |= 1ull << c;
-    wsync();
-
-    rebuild_tree<G>(M, N, l, T, S);
+    set_potentials<G>(M, N, l, T, S);
 
     const long long cap = o.max_pivots > 0 ? (long long)o.max_pivots
                                            : (50LL * T * S > 100 ? 50LL * T * S : 100LL);
@@ -436,35 +624,37 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, NodeState<G> &N, const PairView &
     for (;;) {
         // Pricing: most negative reduced cost (Bland: first negative cell).
         double best = -delta, bestC = 0.0;
-        int bidx = 0x7fffffff;
+        int bidx = kNoKey;
         if (hasR) {
             const double u = N.potR;
-            for (int j = 0; j < S; ++j) {
-                if ((N.bas >> j) & 1ull) continue;
-                double c = M.C[l][j];
-                double r = (c - u) - M.vpot[j];
-                if (r < best) {
-                    best = r; bestC = c; bidx = l * 64 + j;
-                    if (bland) break;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (j < S) {
+                    const double r = (N.crow[j] - u) - M.vpot[j];
+                    const bool cand = !((N.bas >> j) & 1ull) && r < best && !(bland && bidx != kNoKey);
+                    best = cand ? r : best;
+                    bestC = cand ? N.crow[j] : bestC;
+                    bidx = cand ? l * 64 + j : bidx;
                 }
             }
         }
         double key = bland ? 0.0 : best;
         int kidx = bidx;
         group_argmin<G>(key, kidx);
-        if (kidx == 0x7fffffff) {
+        if (kidx == kNoKey) {
             if (fresh) break;
-            // Refresh the potentials from the tree before concluding.
-            rebuild_tree<G>(M, N, l, T, S);
+            // Recompute the potentials from the tree before concluding.
+            set_potentials<G>(M, N, l, T, S);
             fresh = true;
             continue;
         }
         if (pivots >= cap) { out.status = kPivotCap; return out; }
         const int er = kidx >> 6, ec = kidx & 63;
-        const double re = __shfl(best, er, G);
-        const double Ce = __shfl(bestC, er, G);
-        const Mask<G> Ar = N.ancR.bcast(er);
-        const Mask<G> Ac = N.ancC.bcast(ec);
+        if (l == er) { M.bc_r = best; M.bc_c = bestC; }
+        wsync();
+        const double re = M.bc_r, Ce = M.bc_c;
+        const Mask<G> Ar = M.ancRm[er];
+        const Mask<G> Ac = M.ancCm[ec];
         // Edges whose flow decreases: rows on the entering row's side of the
         // path, columns on the entering column's side.
         const Mask<G> onR = Ar.andnot(Ac), onC = Ac.andnot(Ar);
@@ -472,10 +662,11 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, NodeState<G> &N, const PairView &
         const Mask<G> plus = (onR & Mask<G>::cols_only()) | (onC & Mask<G>::rows_only());
         // Ratio test: least flow on a decreasing edge, ties to the lowest cell.
         double th = INFINITY;
-        int tkey = 0x7fffffff;
-        if (hasR && minus.has(l)) { th = N.flowR; tkey = (l * 64 + N.parR) * 256 + l; }
-        if (hasC && minus.has(G + l)) {
-            int k2 = (N.parC * 64 + l) * 256 + (G + l);
+        int tkey = kNoKey;
+        const bool mR = hasR && minus.has(l), mC = hasC && minus.has(G + l);
+        if (mR) { th = N.flowR; tkey = (l * 64 + N.parR) * 256 + l; }
+        if (mC) {
+            const int k2 = (N.parC * 64 + l) * 256 + (G + l);
             if (N.flowC < th || (N.flowC == th && k2 < tkey)) { th = N.flowC; tkey = k2; }
         }
         group_argmin<G>(th, tkey);
@@ -483,11 +674,11 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, NodeState<G> &N, const PairView &
         const int Lnode = tkey & 255;
         const int lcell = tkey >> 8, lr = lcell >> 6, lc = lcell & 63;
         if (hasR) {
-            if (minus.has(l)) N.flowR -= theta;
+            if (mR) N.flowR -= theta;
             else if (plus.has(l)) N.flowR += theta;
         }
         if (hasC) {
-            if (minus.has(G + l)) N.flowC -= theta;
+            if (mC) N.flowC -= theta;
             else if (plus.has(G + l)) N.flowC += theta;
         }
         // Subtree cut off by the leaving edge, and the entering end inside it.
@@ -521,12 +712,15 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, NodeState<G> &N, const PairView &
             const int y = M.u.piv.stemtab[(A & stem).popc() - 1];
             N.ancR = Ap | (A ^ stem) | Mask<G>::node(y);
             N.potR += dU;
+            M.ancRm[l] = N.ancR;
         }
         if (inC) {
             const Mask<G> A = N.ancC & Sub;
             const int y = M.u.piv.stemtab[(A & stem).popc() - 1];
             N.ancC = Ap | (A ^ stem) | Mask<G>::node(y);
             N.potC += dV;
+            M.ancCm[l] = N.ancC;
+            M.vpot[l] = N.potC;
         }
         if (stR) {
             if (l == qnode) { N.parR = ec; N.flowR = theta; N.cparR = Ce; }
@@ -546,7 +740,6 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, NodeState<G> &N, const PairView &
         }
         if (l == er) N.bas |= 1ull << ec;
         if (l == lr) N.bas &= ~(1ull << lc);
-        if (inC) M.vpot[l] = N.potC;
         wsync();
         ++pivots;
         fresh = false;
@@ -563,8 +756,8 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, NodeState<G> &N, const PairView &
     M.u.fin.obj[G + l] = (hasC && N.parC >= 0) ? N.flowC * N.cparC : 0.0;
     wsync();
     double sum = 0.0;
-    for (int a = 0; a < T; ++a) sum += M.u.fin.obj[a];
-    for (int b = 0; b < S; ++b) sum += M.u.fin.obj[G + b];
+#pragma unroll 4
+    for (int n = 0; n < 2 * G; ++n) sum += M.u.fin.obj[n];
     out.d2 = o.want_sqrt ? sqrt(sum) : sum;
     wsync();
     return out;
@@ -585,13 +778,12 @@ __device__ void write_certificate(GroupMem<G> &M, const NodeState<G> &N, const P
             if (N.parR == j) w = N.flowR;
             else if (M.u.fin.colpar[j] == l) w = M.u.fin.colflow[j];
             // caller's frame: A side is t x s; rows here are A unless swapped
-            int64_t idx = pv.swapped ? ((int64_t)j * T + l) : ((int64_t)l * S + j);
+            const int64_t idx = pv.swapped ? ((int64_t)j * T + l) : ((int64_t)l * S + j);
             plan[idx] = w;
         }
     }
     if (duals) {
-        // u (A side) then v (B side)
-        const int tA = pv.swapped ? S : T;
+        const int tA = pv.swapped ? S : T;   // u (A side) then v (B side)
         if (!pv.swapped) {
             if (hasR) duals[l] = N.potR;
             if (hasC) duals[tA + l] = N.potC;
@@ -607,12 +799,15 @@ __device__ void write_certificate(GroupMem<G> &M, const NodeState<G> &N, const P
 
 template <int G>
 struct Cfg {
-    static constexpr int waves = G == 16 ? 4 : (G == 32 ? 2 : 1);
+    static constexpr int waves = G == 64 ? 2 : 4;
     static constexpr int threads = waves * 64;
     static constexpr int groups = threads / G;
 };
 
-template <int G, typename TIn>
+template <int G, bool VOGEL>
+using TileFor = typename std::conditional<VOGEL, VogelTile<G>, NoTile>::type;
+
+template <int G, typename TIn, bool VOGEL>
 __global__ __launch_bounds__(Cfg<G>::threads) void k_assign(KSet X, KSet Z, KOpts o, int64_t chunks,
                                                             int64_t per_chunk, int32_t *labels,
                                                             double *best, double *all,
@@ -620,6 +815,7 @@ __global__ __launch_bounds__(Cfg<G>::threads) void k_assign(KSet X, KSet Z, KOpt
                                                             int32_t *ws_label, int32_t *ws_status) {
     constexpr int NG = Cfg<G>::groups;
     __shared__ GroupMem<G> mem[NG];
+    __shared__ TileFor<G, VOGEL> tiles[NG];
     __shared__ double red_v[NG];
     __shared__ int red_i[NG], red_s[NG];
     const int tid = threadIdx.x;
@@ -631,11 +827,11 @@ __global__ __launch_bounds__(Cfg<G>::threads) void k_assign(KSet X, KSet Z, KOpt
         const int64_t j0 = ch * per_chunk;
         const int64_t j1 = j0 + per_chunk < K ? j0 + per_chunk : K;
         double bv = INFINITY;
-        int bj = 0x7fffffff, worst = kOk;
+        int bj = kNoKey, worst = kOk;
         for (int64_t j = j0 + g; j < j1; j += NG) {
             NodeState<G> N;
             PairView pv = orient(X, i, Z, j, (int)sizeof(TIn));
-            SolveOut r = solve_pair<G, TIn>(mem[g], N, pv, X.d, o, l, gbase);
+            SolveOut r = solve_pair<G, TIn, VOGEL>(mem[g], tiles[g], N, pv, X.d, o, l, gbase);
             if (r.status != kOk) {
                 worst = r.status > worst ? r.status : worst;
                 r.d2 = __builtin_nan("");
@@ -649,7 +845,7 @@ __global__ __launch_bounds__(Cfg<G>::threads) void k_assign(KSet X, KSet Z, KOpt
         __syncthreads();
         if (tid == 0) {
             double v = INFINITY;
-            int jj = 0x7fffffff, st = kOk;
+            int jj = kNoKey, st = kOk;
             for (int q = 0; q < NG; ++q) {
                 if (red_v[q] < v || (red_v[q] == v && red_i[q] < jj)) { v = red_v[q]; jj = red_i[q]; }
                 st = red_s[q] > st ? red_s[q] : st;
@@ -671,15 +867,15 @@ __global__ __launch_bounds__(Cfg<G>::threads) void k_assign(KSet X, KSet Z, KOpt
 __global__ void k_assign_reduce(int64_t n, int64_t chunks, const double *ws_best,
                                 const int32_t *ws_label, const int32_t *ws_status, int32_t *labels,
                                 double *best, int32_t *row_status) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double v = INFINITY;
-    int jj = 0x7fffffff, st = kOk;
+    int jj = kNoKey, st = kOk;
     for (int64_t c = 0; c < chunks; ++c) {
-        double bv = ws_best[i * chunks + c];
-        int bj = ws_label[i * chunks + c];
+        const double bv = ws_best[i * chunks + c];
+        const int bj = ws_label[i * chunks + c];
         if (bv < v || (bv == v && bj < jj)) { v = bv; jj = bj; }
-        int s = ws_status[i * chunks + c];
+        const int s = ws_status[i * chunks + c];
         st = s > st ? s : st;
     }
     labels[i] = st == kOk ? jj : -1;
@@ -687,7 +883,7 @@ __global__ void k_assign_reduce(int64_t n, int64_t chunks, const double *ws_best
     if (row_status) row_status[i] = st;
 }
 
-template <int G, typename TIn>
+template <int G, typename TIn, bool VOGEL>
 __global__ __launch_bounds__(Cfg<G>::threads) void k_emd_pairs(KSet A, KSet B, const int64_t *pairs,
                                                                int64_t npairs, KOpts o, double *dist,
                                                                const int64_t *plan_off, double *plan,
@@ -695,6 +891,7 @@ __global__ __launch_bounds__(Cfg<G>::threads) void k_emd_pairs(KSet A, KSet B, c
                                                                int32_t *status) {
     constexpr int NG = Cfg<G>::groups;
     __shared__ GroupMem<G> mem[NG];
+    __shared__ TileFor<G, VOGEL> tiles[NG];
     const int tid = threadIdx.x;
     const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
     const int64_t stride = (int64_t)gridDim.x * NG;
@@ -707,7 +904,7 @@ __global__ __launch_bounds__(Cfg<G>::threads) void k_emd_pairs(KSet A, KSet B, c
         } else {
             NodeState<G> N;
             PairView pv = orient(A, i, B, j, (int)sizeof(TIn));
-            SolveOut r = solve_pair<G, TIn>(mem[g], N, pv, A.d, o, l, gbase);
+            SolveOut r = solve_pair<G, TIn, VOGEL>(mem[g], tiles[g], N, pv, A.d, o, l, gbase);
             st = r.status;
             if (st == kOk) {
                 val = r.d2;
@@ -725,23 +922,23 @@ __global__ __launch_bounds__(Cfg<G>::threads) void k_emd_pairs(KSet A, KSet B, c
 
 // Row i of the strict upper triangle holds n-1-i pairs; k -> (i, j).
 __device__ __forceinline__ void condensed_ij(int64_t n, int64_t k, int64_t &i, int64_t &j) {
-    double nn = (double)n;
-    double disc = (2.0 * nn - 1.0) * (2.0 * nn - 1.0) - 8.0 * (double)k;
+    const double nn = (double)n;
+    const double disc = (2.0 * nn - 1.0) * (2.0 * nn - 1.0) - 8.0 * (double)k;
     int64_t r = (int64_t)floor(((2.0 * nn - 1.0) - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
     if (r < 0) r = 0;
     if (r > n - 2) r = n - 2;
-    // start(r) = r*n - r*(r+1)/2; fix rounding by stepping
     while (r > 0 && r * n - r * (r + 1) / 2 > k) --r;
     while (r + 1 <= n - 2 && (r + 1) * n - (r + 1) * (r + 2) / 2 <= k) ++r;
     i = r;
     j = k - (r * n - r * (r + 1) / 2) + r + 1;
 }
 
-template <int G, typename TIn>
+template <int G, typename TIn, bool VOGEL>
 __global__ __launch_bounds__(Cfg<G>::threads) void k_pairwise(KSet X, KOpts o, double *out,
                                                               int32_t *status) {
     constexpr int NG = Cfg<G>::groups;
     __shared__ GroupMem<G> mem[NG];
+    __shared__ TileFor<G, VOGEL> tiles[NG];
     const int tid = threadIdx.x;
     const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
     const int64_t m = X.n * (X.n - 1) / 2;
@@ -751,7 +948,7 @@ __global__ __launch_bounds__(Cfg<G>::threads) void k_pairwise(KSet X, KOpts o, d
         condensed_ij(X.n, k, i, j);
         NodeState<G> N;
         PairView pv = orient(X, i, X, j, (int)sizeof(TIn));
-        SolveOut r = solve_pair<G, TIn>(mem[g], N, pv, X.d, o, l, gbase);
+        SolveOut r = solve_pair<G, TIn, VOGEL>(mem[g], tiles[g], N, pv, X.d, o, l, gbase);
         if (l == 0) {
             out[k] = r.status == kOk ? r.d2 : __builtin_nan("");
             if (status) status[k] = r.status;
@@ -776,7 +973,7 @@ __global__ void k_cost_tiles_f64(KSet A, KSet B, const int64_t *pairs, int64_t n
             const int64_t a = c / s, b = c % s;
             double acc = 0.0;
             for (int q = 0; q < A.d; ++q) {
-                double diff = (double)x[a * A.d + q] - (double)y[b * B.d + q];
+                const double diff = (double)x[a * A.d + q] - (double)y[b * B.d + q];
                 acc = fma(diff, diff, acc);
             }
             dst[c] = acc;
@@ -812,7 +1009,7 @@ AssignPlan plan_assign(const KSet &X, const KSet &Z, int maxsup, int cu_count) {
     return p;
 }
 
-template <int G, typename TIn>
+template <int G, typename TIn, bool V>
 static hipError_t assign_t(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
                            const KOpts &o, int32_t *labels, double *best, double *all,
                            int32_t *row_status, void *ws) {
@@ -825,8 +1022,9 @@ static hipError_t assign_t(const LaunchCtx &c, const AssignPlan &p, const KSet &
         wsn = wl + X.n * p.chunks;
     }
     const int64_t grid = total < (1LL << 30) ? total : (1LL << 30);
-    hipLaunchKernelGGL((k_assign<G, TIn>), dim3((unsigned)grid), dim3(Cfg<G>::threads), 0, c.stream, X,
-                       Z, o, p.chunks, p.per_chunk, labels, best, all, row_status, wb, wl, wsn);
+    hipLaunchKernelGGL((k_assign<G, TIn, V>), dim3((unsigned)grid), dim3(Cfg<G>::threads), 0,
+                       c.stream, X, Z, o, p.chunks, p.per_chunk, labels, best, all, row_status, wb,
+                       wl, wsn);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || p.chunks == 1) return e;
     const int64_t blocks = (X.n + 255) / 256;
@@ -835,30 +1033,39 @@ static hipError_t assign_t(const LaunchCtx &c, const AssignPlan &p, const KSet &
     return hipGetLastError();
 }
 
+template <int G, bool V>
+static hipError_t assign_g(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
+                           const KOpts &o, int32_t *labels, double *best, double *all,
+                           int32_t *row_status, void *ws) {
+    return X.dtype == D2_F32 ? assign_t<G, float, V>(c, p, X, Z, o, labels, best, all, row_status, ws)
+                             : assign_t<G, double, V>(c, p, X, Z, o, labels, best, all, row_status, ws);
+}
+
 hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
                          const KOpts &o, int32_t *labels, double *best, double *all,
                          int32_t *row_status, void *ws) {
     if (X.n == 0) return hipSuccess;
-    const bool f32 = X.dtype == D2_F32;
+    const bool v = o.init == D2_INIT_VOGEL;
+#define D2_ASSIGN(GG)                                                                           \
+    return v ? assign_g<GG, true>(c, p, X, Z, o, labels, best, all, row_status, ws)             \
+             : assign_g<GG, false>(c, p, X, Z, o, labels, best, all, row_status, ws)
     switch (p.G) {
-    case 16: return f32 ? assign_t<16, float>(c, p, X, Z, o, labels, best, all, row_status, ws)
-                        : assign_t<16, double>(c, p, X, Z, o, labels, best, all, row_status, ws);
-    case 32: return f32 ? assign_t<32, float>(c, p, X, Z, o, labels, best, all, row_status, ws)
-                        : assign_t<32, double>(c, p, X, Z, o, labels, best, all, row_status, ws);
-    default: return f32 ? assign_t<64, float>(c, p, X, Z, o, labels, best, all, row_status, ws)
-                        : assign_t<64, double>(c, p, X, Z, o, labels, best, all, row_status, ws);
+    case 16: D2_ASSIGN(16);
+    case 32: D2_ASSIGN(32);
+    default: D2_ASSIGN(64);
     }
+#undef D2_ASSIGN
 }
 
-template <int G, typename TIn>
+template <int G, typename TIn, bool V>
 static hipError_t emd_pairs_t(const LaunchCtx &c, const KSet &A, const KSet &B, const int64_t *pairs,
                               int64_t npairs, const KOpts &o, double *dist, const int64_t *plan_off,
                               double *plan, const int64_t *dual_off, double *duals, int32_t *status) {
     const int NG = Cfg<G>::groups;
     int64_t grid = (npairs + NG - 1) / NG;
     if (grid > (1LL << 30)) grid = 1LL << 30;
-    hipLaunchKernelGGL((k_emd_pairs<G, TIn>), dim3((unsigned)grid), dim3(Cfg<G>::threads), 0, c.stream,
-                       A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status);
+    hipLaunchKernelGGL((k_emd_pairs<G, TIn, V>), dim3((unsigned)grid), dim3(Cfg<G>::threads), 0,
+                       c.stream, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status);
     return hipGetLastError();
 }
 
@@ -868,28 +1075,29 @@ hipError_t launch_emd_pairs(const LaunchCtx &c, int G, const KSet &A, const KSet
                             double *duals, int32_t *status) {
     if (npairs == 0) return hipSuccess;
     const bool f32 = A.dtype == D2_F32;
-#define D2_EMD(GG)                                                                                  \
-    return f32 ? emd_pairs_t<GG, float>(c, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off,  \
-                                        duals, status)                                              \
-               : emd_pairs_t<GG, double>(c, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, \
-                                         duals, status)
+    const bool v = o.init == D2_INIT_VOGEL;
+#define D2_EMD(GG, VV)                                                                                \
+    return f32 ? emd_pairs_t<GG, float, VV>(c, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, \
+                                            duals, status)                                            \
+               : emd_pairs_t<GG, double, VV>(c, A, B, pairs, npairs, o, dist, plan_off, plan,         \
+                                             dual_off, duals, status)
     switch (G) {
-    case 16: D2_EMD(16);
-    case 32: D2_EMD(32);
-    default: D2_EMD(64);
+    case 16: if (v) { D2_EMD(16, true); } else { D2_EMD(16, false); }
+    case 32: if (v) { D2_EMD(32, true); } else { D2_EMD(32, false); }
+    default: if (v) { D2_EMD(64, true); } else { D2_EMD(64, false); }
     }
 #undef D2_EMD
 }
 
-template <int G, typename TIn>
+template <int G, typename TIn, bool V>
 static hipError_t pairwise_t(const LaunchCtx &c, const KSet &X, const KOpts &o, double *out,
                              int32_t *status) {
     const int NG = Cfg<G>::groups;
     const int64_t m = X.n * (X.n - 1) / 2;
     int64_t grid = (m + NG - 1) / NG;
     if (grid > (1LL << 30)) grid = 1LL << 30;
-    hipLaunchKernelGGL((k_pairwise<G, TIn>), dim3((unsigned)grid), dim3(Cfg<G>::threads), 0, c.stream,
-                       X, o, out, status);
+    hipLaunchKernelGGL((k_pairwise<G, TIn, V>), dim3((unsigned)grid), dim3(Cfg<G>::threads), 0,
+                       c.stream, X, o, out, status);
     return hipGetLastError();
 }
 
@@ -897,14 +1105,16 @@ hipError_t launch_pairwise(const LaunchCtx &c, int G, const KSet &X, const KOpts
                            double *condensed, int32_t *status) {
     if (X.n < 2) return hipSuccess;
     const bool f32 = X.dtype == D2_F32;
+    const bool v = o.init == D2_INIT_VOGEL;
+#define D2_PW(GG, VV)                                                          \
+    return f32 ? pairwise_t<GG, float, VV>(c, X, o, condensed, status)         \
+               : pairwise_t<GG, double, VV>(c, X, o, condensed, status)
     switch (G) {
-    case 16: return f32 ? pairwise_t<16, float>(c, X, o, condensed, status)
-                        : pairwise_t<16, double>(c, X, o, condensed, status);
-    case 32: return f32 ? pairwise_t<32, float>(c, X, o, condensed, status)
-                        : pairwise_t<32, double>(c, X, o, condensed, status);
-    default: return f32 ? pairwise_t<64, float>(c, X, o, condensed, status)
-                        : pairwise_t<64, double>(c, X, o, condensed, status);
+    case 16: if (v) { D2_PW(16, true); } else { D2_PW(16, false); }
+    case 32: if (v) { D2_PW(32, true); } else { D2_PW(32, false); }
+    default: if (v) { D2_PW(64, true); } else { D2_PW(64, false); }
     }
+#undef D2_PW
 }
 
 hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
@@ -912,7 +1122,7 @@ hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
                              const int64_t *tile_off) {
     if (npairs == 0) return hipSuccess;
     (void)cost_mode;
-    int64_t grid = npairs < (1LL << 30) ? npairs : (1LL << 30);
+    const int64_t grid = npairs < (1LL << 30) ? npairs : (1LL << 30);
     if (A.dtype == D2_F32)
         hipLaunchKernelGGL(k_cost_tiles_f64<float>, dim3((unsigned)grid), dim3(256), 0, c.stream, A, B,
                            pairs, npairs, tiles, tile_off);
