@@ -121,10 +121,10 @@ __device__ __forceinline__ void wsync() {
 // steps with a commutative, associative combine every lane holds the result.
 template <int STEP>
 __device__ __forceinline__ int xchg(int v) {
-    if constexpr (STEP == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
-    else if constexpr (STEP == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
-    else if constexpr (STEP == 2) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
-    else if constexpr (STEP == 3) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+    if constexpr (STEP == 0) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+    else if constexpr (STEP == 1) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+    else if constexpr (STEP == 2) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);
+    else if constexpr (STEP == 3) return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);
     else if constexpr (STEP == 4) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
     else return __shfl_xor(v, 32, 64);
 }
@@ -140,17 +140,38 @@ __device__ __forceinline__ double xchg(double v) {
 template <int G>
 struct Steps { static constexpr int n = G == 16 ? 4 : (G == 32 ? 5 : 6); };
 
-// (value, key) minimum over the group, lowest key on equal values.
 template <int G, int STEP = 0>
+__device__ __forceinline__ double group_min(double v) {
+    if constexpr (STEP < Steps<G>::n) return group_min<G, STEP + 1>(fmin(v, xchg<STEP>(v)));
+    else return v;
+}
+
+template <int G, int STEP = 0>
+__device__ __forceinline__ int group_min_int(int v) {
+    if constexpr (STEP < Steps<G>::n) return group_min_int<G, STEP + 1>(min(v, xchg<STEP>(v)));
+    else return v;
+}
+
+// (value, key) minimum over the group, lowest key on equal values: the
+// exact minimum value first, then the least key among the lanes holding it.
+template <int G>
 __device__ __forceinline__ void group_argmin(double &v, int &k) {
-    if constexpr (STEP < Steps<G>::n) {
-        double ov = xchg<STEP>(v);
-        int ok = xchg<STEP>(k);
-        bool take = (ov < v) || (ov == v && ok < k);
-        v = take ? ov : v;
-        k = take ? ok : k;
-        group_argmin<G, STEP + 1>(v, k);
+    const double m = group_min<G>(v);
+    k = group_min_int<G>(v == m ? k : kNoKey);
+    v = m;
+}
+
+// Maximum of a group-uniform value over the whole wavefront (a scalar), so
+// loops bounded by it branch on the scalar unit.
+template <int G>
+__device__ __forceinline__ int wave_max(int v) {
+    int m = __builtin_amdgcn_readlane(v, 0);
+    if constexpr (G <= 32) m = max(m, __builtin_amdgcn_readlane(v, 32));
+    if constexpr (G == 16) {
+        m = max(m, __builtin_amdgcn_readlane(v, 16));
+        m = max(m, __builtin_amdgcn_readlane(v, 48));
     }
+    return m;
 }
 
 template <int G, int STEP = 0>
@@ -234,8 +255,8 @@ struct NodeState {
     double cparR, cparC;     // cost of the edge to the parent
     double potR, potC;       // u_l, v_l
     Mask<G> ancR, ancC;      // ancestors including the node itself
-    uint64_t bas;            // basic cells of row l, as a column bitmask
-    double crow[G];          // C[l][j], 0 beyond the columns
+    typename std::conditional<G == 64, uint64_t, uint32_t>::type bas;  // basic cells of row l
+    double crow[G];          // C[l][j]; +inf beyond the columns and on rows beyond the support
 };
 
 template <typename T>
@@ -378,6 +399,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
     pr = pr / sumr;
     pc = pc / sumc;
 
+    const int Sw = wave_max<G>(S);
     // Cost row l, direct form: C_lj = sum_k (x_lk - y_jk)^2, k ascending.
     // Lane l holds row point l and column point l; column point j reaches
     // every lane of the group by a register broadcast.
@@ -397,7 +419,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
             }
             static_for<0, G>([&](auto jc) {
                 constexpr int j = decltype(jc)::value;
-                if (j < S) {
+                if (j < Sw) {
                     double acc = N.crow[j];
 #pragma unroll
                     for (int kk = 0; kk < KC; ++kk) {
@@ -411,14 +433,15 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
             });
         }
 #pragma unroll
-        for (int j = 0; j < G; ++j) N.crow[j] = (hasR && j < S) ? N.crow[j] : 0.0;
+        for (int j = 0; j < G; ++j) N.crow[j] = (hasR && j < S) ? N.crow[j] : INFINITY;
     }
     double cmax = 0.0;
     bool finite = true;
 #pragma unroll
     for (int j = 0; j < G; ++j) {
-        finite = finite && isfinite(N.crow[j]);
-        cmax = fmax(cmax, N.crow[j]);
+        const bool live = hasR && j < S;
+        finite = finite & (!live | isfinite(N.crow[j]));
+        cmax = live ? fmax(cmax, N.crow[j]) : cmax;
     }
     if (group_bits<G>(!finite, gbase) != 0ull) { out.status = kBadPoints; return out; }
     cmax = group_max<G>(cmax);
@@ -509,7 +532,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         wsync();
         M.u.init.colpar[l] = hasC ? N.parC : -1;
         wsync();
-        N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0ull;
+        N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0u;
 #pragma unroll
         for (int c = 0; c < G; ++c)
             if (hasR && c < S && M.u.init.colpar[c] == l) N.bas |= 1ull << c;
@@ -584,7 +607,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         if (hasC) M.u.init.kind[idxC] = 1;
         wsync();
         // Basic cells of row l and the parent-edge costs of its child columns.
-        N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0ull;
+        N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0u;
 #pragma unroll
         for (int c = 0; c < G; ++c) {
             if (hasR && c < S && M.u.init.colpar[c] == l) {
@@ -623,15 +646,27 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
 #pragma unroll 1
     for (;;) {
         // Pricing: most negative reduced cost (Bland: first negative cell).
+        // Padding cells hold +inf, so every lane runs the same loop.
         double best = -delta, bestC = 0.0;
         int bidx = kNoKey;
-        if (hasR) {
-            const double u = N.potR;
+        const double u = N.potR;
+        if (!bland) {
 #pragma unroll
             for (int j = 0; j < G; ++j) {
-                if (j < S) {
+                if (j < Sw) {
                     const double r = (N.crow[j] - u) - M.vpot[j];
-                    const bool cand = !((N.bas >> j) & 1ull) && r < best && !(bland && bidx != kNoKey);
+                    const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < best);
+                    best = cand ? r : best;
+                    bestC = cand ? N.crow[j] : bestC;
+                    bidx = cand ? l * 64 + j : bidx;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = G - 1; j >= 0; --j) {
+                if (j < Sw) {
+                    const double r = (N.crow[j] - u) - M.vpot[j];
+                    const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < -delta);
                     best = cand ? r : best;
                     bestC = cand ? N.crow[j] : bestC;
                     bidx = cand ? l * 64 + j : bidx;
@@ -664,23 +699,20 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         double th = INFINITY;
         int tkey = kNoKey;
         const bool mR = hasR && minus.has(l), mC = hasC && minus.has(G + l);
-        if (mR) { th = N.flowR; tkey = (l * 64 + N.parR) * 256 + l; }
-        if (mC) {
+        th = mR ? N.flowR : th;
+        tkey = mR ? (l * 64 + N.parR) * 256 + l : tkey;
+        {
             const int k2 = (N.parC * 64 + l) * 256 + (G + l);
-            if (N.flowC < th || (N.flowC == th && k2 < tkey)) { th = N.flowC; tkey = k2; }
+            const bool takeC = mC & ((N.flowC < th) | ((N.flowC == th) & (k2 < tkey)));
+            th = takeC ? N.flowC : th;
+            tkey = takeC ? k2 : tkey;
         }
         group_argmin<G>(th, tkey);
         const double theta = th;
         const int Lnode = tkey & 255;
         const int lcell = tkey >> 8, lr = lcell >> 6, lc = lcell & 63;
-        if (hasR) {
-            if (mR) N.flowR -= theta;
-            else if (plus.has(l)) N.flowR += theta;
-        }
-        if (hasC) {
-            if (mC) N.flowC -= theta;
-            else if (plus.has(G + l)) N.flowC += theta;
-        }
+        N.flowR += mR ? -theta : ((hasR & plus.has(l)) ? theta : 0.0);
+        N.flowC += mC ? -theta : ((hasC & plus.has(G + l)) ? theta : 0.0);
         // Subtree cut off by the leaving edge, and the entering end inside it.
         const bool inR = hasR && N.ancR.has(Lnode);
         const bool inC = hasC && N.ancC.has(Lnode);
@@ -738,8 +770,8 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
                 N.cparC = M.u.piv.newcpar[G + l];
             }
         }
-        if (l == er) N.bas |= 1ull << ec;
-        if (l == lr) N.bas &= ~(1ull << lc);
+        if (l == er) N.bas |= (decltype(N.bas))1 << ec;
+        if (l == lr) N.bas &= ~((decltype(N.bas))1 << lc);
         wsync();
         ++pivots;
         fresh = false;
