@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_assign_16_f32_c2_100k_x512.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1302_0435_amd", "csrc", "d2_simplex.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
+               for f in ("d2_solver.h", "d2_kernels.hip")]
 
 
 def profile_counters():
@@ -42,7 +43,10 @@ def profile_counters():
             if "=" in line:
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+        h = hashlib.sha256()
+        for f in KERNEL_SRCS:
+            h.update(open(f, "rb").read())
+        sha = h.hexdigest()[:16]
     except OSError:
         return None
     if kv.get("kernel_source_sha256_16") != sha:

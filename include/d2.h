@@ -93,6 +93,13 @@ typedef struct {
     int32_t reserved;        /* set to 0                                          */
 } d2_set;
 
+/* work schedule (results are identical under every schedule) */
+enum {
+    D2_SCHED_AUTO = 0,  /* pairs grouped by support class, each class in the       *
+                         * narrowest group shape; persistent queue for pairwise    */
+    D2_SCHED_PLAIN = 1  /* one wavefront per pair, pairs in input order            */
+};
+
 typedef struct {
     int32_t cost_mode;  /* D2_COST_*                                               */
     int32_t init;       /* D2_INIT_*                                               */
@@ -100,11 +107,20 @@ typedef struct {
     int32_t want_sqrt;  /* 0 -> D^2, 1 -> D                                        */
     double opt_tol;     /* 0 = default 1e-14; the simplex stops when every reduced *
                          * cost is >= -opt_tol * max_ab C_ab                       */
+    int32_t schedule;   /* D2_SCHED_*                                              */
+    int32_t flags;      /* D2_FLAG_* bits, 0 by default                            */
 } d2_opts;
+
+/* D2_FLAG_EAGER: enqueue the kernels directly instead of recording the call
+ * once as a hipGraph and replaying it for later calls with the same
+ * arguments (the default for d2_assign and d2_pairwise). */
+#define D2_FLAG_EAGER 1
 
 typedef struct d2_handle d2_handle;
 
-/* Create a handle bound to HIP device `device`.  Allocates host memory only. */
+/* Create a handle bound to HIP device `device`.  It holds host memory, one
+ * private stream used only to record graphs, and the graph and schedule
+ * caches; it never allocates device memory. */
 d2_status d2_create(d2_handle **h, int device);
 d2_status d2_destroy(d2_handle *h);
 const char *d2_status_string(int code);
@@ -156,6 +172,16 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
  * shape. */
 d2_status d2_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double *condensed,
                       int32_t *pair_status, void *ws, size_t ws_bytes, void *stream);
+
+/* Schedule autotuner for d2_pairwise (synchronous: waits for the stream).
+ * Runs the call with each candidate schedule (persistent workgroups per CU x
+ * work-queue chunk), keeps the fastest for this workload shape (n, d, dtype,
+ * max_support, start rule) in the handle, and writes its time to *best_ms.
+ * Later d2_pairwise calls of the same shape use it.  Outputs are written as
+ * by d2_pairwise and do not depend on the schedule. */
+d2_status d2_tune_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double *condensed,
+                           int32_t *pair_status, void *ws, size_t ws_bytes, void *stream,
+                           double *best_ms);
 
 #ifdef __cplusplus
 }

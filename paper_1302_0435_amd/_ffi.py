@@ -15,12 +15,15 @@ D2_OK, D2_EINVAL, D2_EWORKSPACE, D2_EUNSUPPORTED, D2_EHIP, D2_ENOMEM = range(6)
 D2_F64, D2_F32 = 0, 1
 D2_COST_F64_DIRECT, D2_COST_BF16_MFMA = 0, 1
 D2_INIT_AUTO, D2_INIT_NWC, D2_INIT_VOGEL = 0, 1, 2
+D2_SCHED_AUTO, D2_SCHED_PLAIN = 0, 1
+D2_FLAG_EAGER = 1
 D2_PAIR_OK, D2_PAIR_BAD_WEIGHTS, D2_PAIR_TOO_LARGE, D2_PAIR_PIVOT_CAP, D2_PAIR_BAD_POINTS = range(5)
 WHICH_COST_TILES, WHICH_EMD_BATCH, WHICH_ASSIGN, WHICH_PAIRWISE = range(4)
 
 # Every function the header declares (checked against the header by the tests).
 EXPORTS = ["d2_create", "d2_destroy", "d2_status_string", "d2_max_support", "d2_version",
-           "d2_workspace_bytes", "d2_cost_tiles", "d2_emd_batch", "d2_assign", "d2_pairwise"]
+           "d2_workspace_bytes", "d2_cost_tiles", "d2_emd_batch", "d2_assign", "d2_pairwise",
+           "d2_tune_pairwise"]
 
 
 class d2_set(ctypes.Structure):
@@ -33,7 +36,8 @@ class d2_set(ctypes.Structure):
 class d2_opts(ctypes.Structure):
     _fields_ = [("cost_mode", ctypes.c_int32), ("init", ctypes.c_int32),
                 ("max_pivots", ctypes.c_int32), ("want_sqrt", ctypes.c_int32),
-                ("opt_tol", ctypes.c_double)]
+                ("opt_tol", ctypes.c_double), ("schedule", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
 
 
 class LibraryMissing(RuntimeError):
@@ -67,8 +71,9 @@ def lib():
     L.d2_emd_batch.argtypes = [P, S, S, P, I64, O, P, P, P, P, P, P, P, SZ, P]
     L.d2_assign.argtypes = [P, S, S, O, P, P, P, P, P, SZ, P]
     L.d2_pairwise.argtypes = [P, S, O, P, P, P, SZ, P]
+    L.d2_tune_pairwise.argtypes = [P, S, O, P, P, P, SZ, P, ctypes.POINTER(ctypes.c_double)]
     for name in ("d2_create", "d2_destroy", "d2_cost_tiles", "d2_emd_batch", "d2_assign",
-                 "d2_pairwise", "d2_max_support"):
+                 "d2_pairwise", "d2_max_support", "d2_tune_pairwise"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -84,10 +84,12 @@ class Opts:
     max_pivots: int = 0
     want_sqrt: int = 0
     opt_tol: float = 0.0
+    schedule: int = _ffi.D2_SCHED_AUTO
+    flags: int = 0
 
     def c(self) -> _ffi.d2_opts:
         return _ffi.d2_opts(self.cost_mode, self.init, self.max_pivots, self.want_sqrt,
-                            self.opt_tol)
+                            self.opt_tol, self.schedule, self.flags)
 
 
 class Handle:
@@ -206,6 +208,23 @@ def d2_pairwise(h: Handle, X: DeviceSet, opts: Optional[Opts] = None):
     check(_ffi.lib().d2_pairwise(h.ptr, ctypes.byref(x), ctypes.byref(o), _ptr(out),
                                  _ptr(status), _ptr(ws), nbytes, _stream(dev)), "d2_pairwise")
     return out, status
+
+
+def d2_tune_pairwise(h: Handle, X: DeviceSet, opts: Optional[Opts] = None):
+    """Autotune the pairwise schedule for this workload shape (synchronous).
+    Returns (condensed, status, best_ms) of the fastest run."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    m = X.n * (X.n - 1) // 2
+    out = torch.empty(m, dtype=torch.float64, device=dev)
+    status = torch.empty(m, dtype=torch.int32, device=dev)
+    ws, nbytes = _workspace(h, _ffi.WHICH_PAIRWISE, X, None, 0, opts)
+    x, o = X.c(), opts.c()
+    best = ctypes.c_double()
+    check(_ffi.lib().d2_tune_pairwise(h.ptr, ctypes.byref(x), ctypes.byref(o), _ptr(out),
+                                      _ptr(status), _ptr(ws), nbytes, _stream(dev),
+                                      ctypes.byref(best)), "d2_tune_pairwise")
+    return out, status, best.value
 
 
 def d2_cost_tiles(h: Handle, A: DeviceSet, B: DeviceSet, pairs: torch.Tensor,

@@ -1,24 +1,52 @@
 // Host side of the C ABI declared in include/d2.h: argument validation,
-// option defaults, work planning and kernel dispatch.  Nothing here
-// allocates device memory; every device buffer belongs to the caller.
+// option defaults, work planning, kernel dispatch, hipGraph capture/replay
+// and the schedule autotuner.  Nothing here allocates device memory; every
+// device buffer belongs to the caller.
 #include <hip/hip_runtime.h>
 #include <math.h>
-#include <new>
 #include <stdint.h>
 #include <string.h>
 
+#include <new>
+#include <vector>
+
 #include "d2.h"
 #include "d2_internal.h"
-
-struct d2_handle {
-    int device;
-    int cu_count;
-};
 
 namespace {
 
 using d2::KOpts;
 using d2::KSet;
+
+// One captured call: the arguments that fix its kernels and the executable.
+struct GraphEntry {
+    int which;
+    uint64_t key[24];
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+
+// Autotuned pairwise schedule for one workload shape.
+struct TuneEntry {
+    int64_t n;
+    int d, dtype, max_support, init;
+    d2::Schedule sch;
+};
+
+}  // namespace
+
+struct d2_handle {
+    int device;
+    int cu_count;
+    hipStream_t capture;            // private stream used only to record graphs
+    std::vector<GraphEntry> graphs;
+    std::vector<TuneEntry> tuned;
+    uint64_t clock;
+};
+
+namespace {
+
+constexpr size_t kMaxGraphs = 32;
 
 bool set_ok(const d2_set *s) {
     if (!s) return false;
@@ -40,15 +68,22 @@ KSet kset(const d2_set *s) {
     return k;
 }
 
+d2_opts defaults() {
+    d2_opts o;
+    memset(&o, 0, sizeof(o));
+    return o;
+}
+
 d2_status opts_ok(const d2_opts *o, KOpts &k) {
-    d2_opts def;
-    memset(&def, 0, sizeof(def));
+    static const d2_opts def = defaults();
     if (!o) o = &def;
     if (o->cost_mode != D2_COST_F64_DIRECT && o->cost_mode != D2_COST_BF16_MFMA) return D2_EINVAL;
     if (o->init != D2_INIT_AUTO && o->init != D2_INIT_NWC && o->init != D2_INIT_VOGEL) return D2_EINVAL;
     if (o->max_pivots < 0) return D2_EINVAL;
     if (o->want_sqrt != 0 && o->want_sqrt != 1) return D2_EINVAL;
     if (!(o->opt_tol >= 0.0) || !isfinite(o->opt_tol) || o->opt_tol >= 1.0) return D2_EINVAL;
+    if (o->schedule != D2_SCHED_AUTO && o->schedule != D2_SCHED_PLAIN) return D2_EINVAL;
+    if (o->flags & ~D2_FLAG_EAGER) return D2_EINVAL;
     k.init = o->init == D2_INIT_VOGEL ? D2_INIT_VOGEL : D2_INIT_NWC;
     k.max_pivots = o->max_pivots;
     k.want_sqrt = o->want_sqrt;
@@ -57,6 +92,9 @@ d2_status opts_ok(const d2_opts *o, KOpts &k) {
     return D2_OK;
 }
 
+int sched_of(const d2_opts *o) { return o ? o->schedule : D2_SCHED_AUTO; }
+bool eager_of(const d2_opts *o) { return o && (o->flags & D2_FLAG_EAGER); }
+
 d2_status pair_sets_ok(const d2_set *A, const d2_set *B) {
     if (!set_ok(A) || !set_ok(B)) return D2_EINVAL;
     if (A->d != B->d || A->dtype != B->dtype) return D2_EINVAL;
@@ -64,29 +102,93 @@ d2_status pair_sets_ok(const d2_set *A, const d2_set *B) {
     return D2_OK;
 }
 
-int maxsup(const d2_set *A, const d2_set *B) {
-    int m = A ? A->max_support : 1;
-    if (B && B->max_support > m) m = B->max_support;
-    return m < 1 ? 1 : m;
-}
+int ms(const d2_set *s) { return s && s->max_support > 0 ? s->max_support : 1; }
 
 d2_status bind_device(d2_handle *h) {
-    if (hipSetDevice(h->device) != hipSuccess) return D2_EHIP;
-    return D2_OK;
+    return hipSetDevice(h->device) == hipSuccess ? D2_OK : D2_EHIP;
 }
 
-d2::LaunchCtx ctx(d2_handle *h, void *stream) {
+d2::LaunchCtx ctx(d2_handle *h, hipStream_t s) {
     d2::LaunchCtx c;
-    c.stream = (hipStream_t)stream;
+    c.stream = s;
     c.cu_count = h->cu_count;
     return c;
+}
+
+void key_set(uint64_t *k, int &n, const d2_set *s) {
+    k[n++] = (uint64_t)s->n;
+    k[n++] = ((uint64_t)(uint32_t)s->d << 32) | (uint32_t)s->dtype;
+    k[n++] = (uint64_t)(uintptr_t)s->offsets;
+    k[n++] = (uint64_t)(uintptr_t)s->points;
+    k[n++] = (uint64_t)(uintptr_t)s->weights;
+    k[n++] = (uint64_t)s->max_support;
+}
+
+void key_opts(uint64_t *k, int &n, const KOpts &o) {
+    k[n++] = ((uint64_t)(uint32_t)o.init << 32) | (uint32_t)o.max_pivots;
+    k[n++] = ((uint64_t)(uint32_t)o.want_sqrt << 32) | (uint32_t)o.cost_mode;
+    uint64_t t;
+    memcpy(&t, &o.tol, sizeof(t));
+    k[n++] = t;
+}
+
+// Run `enqueue(stream)` either directly on the caller's stream or as a
+// hipGraph: recorded once on the handle's private stream, then replayed on
+// the caller's stream whenever a call with the same key comes again.
+template <typename F>
+d2_status run_graph(d2_handle *h, int which, const uint64_t *key, bool eager, hipStream_t stream,
+                    F &&enqueue) {
+    if (eager) return enqueue(stream) == hipSuccess ? D2_OK : D2_EHIP;
+    for (auto &g : h->graphs) {
+        if (g.which == which && memcmp(g.key, key, sizeof(g.key)) == 0) {
+            g.last_use = ++h->clock;
+            return hipGraphLaunch(g.exec, stream) == hipSuccess ? D2_OK : D2_EHIP;
+        }
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return D2_EHIP;
+    hipError_t e = enqueue(h->capture);
+    hipError_t e2 = hipStreamEndCapture(h->capture, &graph);
+    if (e != hipSuccess || e2 != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return D2_EHIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return D2_EHIP;
+    if (h->graphs.size() >= kMaxGraphs) {
+        size_t victim = 0;
+        for (size_t i = 1; i < h->graphs.size(); ++i)
+            if (h->graphs[i].last_use < h->graphs[victim].last_use) victim = i;
+        (void)hipGraphExecDestroy(h->graphs[victim].exec);
+        h->graphs.erase(h->graphs.begin() + victim);
+    }
+    GraphEntry g;
+    g.which = which;
+    memcpy(g.key, key, sizeof(g.key));
+    g.exec = exec;
+    g.last_use = ++h->clock;
+    h->graphs.push_back(g);
+    return hipGraphLaunch(exec, stream) == hipSuccess ? D2_OK : D2_EHIP;
+}
+
+d2::Schedule schedule_for(d2_handle *h, const d2_set *X, const KOpts &k) {
+    for (auto &t : h->tuned)
+        if (t.n == X->n && t.d == X->d && t.dtype == X->dtype && t.max_support == X->max_support &&
+            t.init == k.init)
+            return t.sch;
+    d2::Schedule s;
+    for (int c = 0; c < 4; ++c) { s.blocks_per_cu[c] = 4; s.chunk[c] = 4; }
+    return s;
 }
 
 }  // namespace
 
 extern "C" {
 
-const char *d2_version(void) { return "d2-mi355x 0.1"; }
+const char *d2_version(void) { return "d2-mi355x 0.2"; }
 
 int d2_max_support(void) { return D2_MAX_SUPPORT; }
 
@@ -110,15 +212,25 @@ d2_status d2_create(d2_handle **h, int device) {
     if (device < 0 || device >= count) return D2_EINVAL;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return D2_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return D2_EHIP;
     d2_handle *p = new (std::nothrow) d2_handle;
     if (!p) return D2_ENOMEM;
     p->device = device;
     p->cu_count = prop.multiProcessorCount;
+    p->clock = 0;
+    if (hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
+        delete p;
+        return D2_EHIP;
+    }
     *h = p;
     return D2_OK;
 }
 
 d2_status d2_destroy(d2_handle *h) {
+    if (!h) return D2_OK;
+    (void)hipSetDevice(h->device);
+    for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    (void)hipStreamDestroy(h->capture);
     delete h;
     return D2_OK;
 }
@@ -126,12 +238,13 @@ d2_status d2_destroy(d2_handle *h) {
 size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set *B,
                           int64_t npairs, const d2_opts *opts) {
     (void)npairs;
-    (void)opts;
-    if (!h || !A) return 0;
-    if (which == 2 && B) {
+    if (!h || !A || !set_ok(A)) return 0;
+    const int sched = sched_of(opts);
+    if (which == 2 && B && set_ok(B)) {
         KSet X = kset(A), Z = kset(B);
-        return d2::plan_assign(X, Z, maxsup(A, B), h->cu_count).ws_bytes;
+        return d2::plan_assign(X, Z, ms(A), ms(B), h->cu_count, sched).ws_bytes;
     }
+    if (which == 3) return d2::plan_pairwise(kset(A), ms(A), sched).ws_bytes;
     return 0;
 }
 
@@ -147,8 +260,8 @@ d2_status d2_cost_tiles(d2_handle *h, const d2_set *A, const d2_set *B, const in
     if (npairs > 0 && (!pairs || !tiles || !tile_offsets)) return D2_EINVAL;
     if (cost_mode == D2_COST_BF16_MFMA) return D2_EUNSUPPORTED;
     if ((st = bind_device(h)) != D2_OK) return st;
-    hipError_t e = d2::launch_cost_tiles(ctx(h, stream), kset(A), kset(B), pairs, npairs, cost_mode,
-                                         tiles, tile_offsets);
+    hipError_t e = d2::launch_cost_tiles(ctx(h, (hipStream_t)stream), kset(A), kset(B), pairs, npairs,
+                                         cost_mode, tiles, tile_offsets);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 
@@ -169,9 +282,10 @@ d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int
     if ((plan == nullptr) != (plan_offsets == nullptr)) return D2_EINVAL;
     if ((duals == nullptr) != (dual_offsets == nullptr)) return D2_EINVAL;
     if ((st = bind_device(h)) != D2_OK) return st;
-    hipError_t e = d2::launch_emd_pairs(ctx(h, stream), d2::group_width_for(maxsup(A, B)), kset(A),
-                                        kset(B), pairs, npairs, k, dist, plan_offsets, plan,
-                                        dual_offsets, duals, pair_status);
+    const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(ms(A), ms(B));
+    hipError_t e = d2::launch_emd_pairs(ctx(h, (hipStream_t)stream), cls, kset(A), kset(B), pairs,
+                                        npairs, k, dist, plan_offsets, plan, dual_offsets, duals,
+                                        pair_status);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 
@@ -188,17 +302,29 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
     if (X->n > 0 && Z->n < 1) return D2_EINVAL;
     if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
     KSet kx = kset(X), kz = kset(Z);
-    d2::AssignPlan p = d2::plan_assign(kx, kz, maxsup(X, Z), h->cu_count);
+    d2::AssignPlan p = d2::plan_assign(kx, kz, ms(X), ms(Z), h->cu_count, sched_of(opts));
     if (p.ws_bytes > 0 && (!ws || ws_bytes < p.ws_bytes)) return D2_EWORKSPACE;
     if ((st = bind_device(h)) != D2_OK) return st;
-    hipError_t e = d2::launch_assign(ctx(h, stream), p, kx, kz, k, labels, best, all, row_status, ws);
-    return e == hipSuccess ? D2_OK : D2_EHIP;
+    if (X->n == 0) return D2_OK;
+    uint64_t key[24];
+    memset(key, 0, sizeof(key));
+    int n = 0;
+    key_set(key, n, X);
+    key_set(key, n, Z);
+    key_opts(key, n, k);
+    key[n++] = (uint64_t)(uintptr_t)labels;
+    key[n++] = (uint64_t)(uintptr_t)best;
+    key[n++] = (uint64_t)(uintptr_t)all;
+    key[n++] = (uint64_t)(uintptr_t)row_status;
+    key[n++] = (uint64_t)(uintptr_t)ws;
+    key[n++] = (uint64_t)sched_of(opts);
+    return run_graph(h, 2, key, eager_of(opts), (hipStream_t)stream, [&](hipStream_t s) {
+        return d2::launch_assign(ctx(h, s), p, kx, kz, k, labels, best, all, row_status, ws);
+    });
 }
 
 d2_status d2_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double *condensed,
                       int32_t *pair_status, void *ws, size_t ws_bytes, void *stream) {
-    (void)ws;
-    (void)ws_bytes;
     if (!h) return D2_EINVAL;
     d2_status st = pair_sets_ok(X, X);
     if (st != D2_OK) return st;
@@ -206,10 +332,83 @@ d2_status d2_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double
     if ((st = opts_ok(opts, k)) != D2_OK) return st;
     if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
     if (X->n > 1 && !condensed) return D2_EINVAL;
+    KSet kx = kset(X);
+    d2::PairwisePlan p = d2::plan_pairwise(kx, ms(X), sched_of(opts));
+    if (p.ws_bytes > 0 && (!ws || ws_bytes < p.ws_bytes)) return D2_EWORKSPACE;
     if ((st = bind_device(h)) != D2_OK) return st;
-    hipError_t e = d2::launch_pairwise(ctx(h, stream), d2::group_width_for(maxsup(X, X)), kset(X), k,
-                                       condensed, pair_status);
-    return e == hipSuccess ? D2_OK : D2_EHIP;
+    if (X->n < 2) return D2_OK;
+    const d2::Schedule sch = schedule_for(h, X, k);
+    uint64_t key[24];
+    memset(key, 0, sizeof(key));
+    int n = 0;
+    key_set(key, n, X);
+    key_opts(key, n, k);
+    key[n++] = (uint64_t)(uintptr_t)condensed;
+    key[n++] = (uint64_t)(uintptr_t)pair_status;
+    key[n++] = (uint64_t)(uintptr_t)ws;
+    key[n++] = (uint64_t)sched_of(opts);
+    for (int c = 0; c < 4; ++c) key[n++] = ((uint64_t)(uint32_t)sch.blocks_per_cu[c] << 32) | (uint32_t)sch.chunk[c];
+    return run_graph(h, 3, key, eager_of(opts), (hipStream_t)stream, [&](hipStream_t s) {
+        return d2::launch_pairwise(ctx(h, s), p, kx, k, condensed, pair_status, ws, sch);
+    });
+}
+
+d2_status d2_tune_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double *condensed,
+                           int32_t *pair_status, void *ws, size_t ws_bytes, void *stream,
+                           double *best_ms) {
+    if (!h) return D2_EINVAL;
+    d2_status st = pair_sets_ok(X, X);
+    if (st != D2_OK) return st;
+    KOpts k;
+    if ((st = opts_ok(opts, k)) != D2_OK) return st;
+    if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
+    if (sched_of(opts) != D2_SCHED_AUTO) return D2_EINVAL;
+    if (X->n > 1 && !condensed) return D2_EINVAL;
+    KSet kx = kset(X);
+    d2::PairwisePlan p = d2::plan_pairwise(kx, ms(X), D2_SCHED_AUTO);
+    if (p.ws_bytes > 0 && (!ws || ws_bytes < p.ws_bytes)) return D2_EWORKSPACE;
+    if ((st = bind_device(h)) != D2_OK) return st;
+    if (X->n < 2) { if (best_ms) *best_ms = 0.0; return D2_OK; }
+    hipStream_t s = (hipStream_t)stream;
+    // Candidate schedules: persistent workgroups per CU x work-queue chunk;
+    // each candidate is applied to every class at once and timed as a whole.
+    static const int kBlocks[] = {2, 4, 8};
+    static const int kChunk[] = {1, 8};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return D2_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return D2_EHIP; }
+    float best = 1e30f;
+    d2::Schedule best_sch;
+    for (int c = 0; c < 4; ++c) { best_sch.blocks_per_cu[c] = 4; best_sch.chunk[c] = 4; }
+    hipError_t e = hipSuccess;
+    for (int bi = 0; bi < 3 && e == hipSuccess; ++bi) {
+        for (int ci = 0; ci < 2 && e == hipSuccess; ++ci) {
+            d2::Schedule sch;
+            for (int c = 0; c < 4; ++c) { sch.blocks_per_cu[c] = kBlocks[bi]; sch.chunk[c] = kChunk[ci]; }
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = d2::launch_pairwise(ctx(h, s), p, kx, k, condensed, pair_status, ws, sch);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms_ = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms_, e0, e1);
+            if (e == hipSuccess && ms_ < best) { best = ms_; best_sch = sch; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return D2_EHIP;
+    bool found = false;
+    for (auto &t : h->tuned)
+        if (t.n == X->n && t.d == X->d && t.dtype == X->dtype && t.max_support == X->max_support &&
+            t.init == k.init) { t.sch = best_sch; found = true; }
+    if (!found) {
+        TuneEntry t;
+        t.n = X->n; t.d = X->d; t.dtype = X->dtype; t.max_support = X->max_support; t.init = k.init;
+        t.sch = best_sch;
+        h->tuned.push_back(t);
+    }
+    if (best_ms) *best_ms = best;
+    return D2_OK;
 }
 
 }  // extern "C"

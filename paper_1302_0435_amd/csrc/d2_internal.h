@@ -33,30 +33,43 @@ struct LaunchCtx {
     int cu_count;
 };
 
-// Group width (lanes per pair) that covers supports up to `maxsup`.
-int group_width_for(int maxsup);
-
-// Work split of d2_assign: each (row, chunk) workgroup scans a chunk of the
-// centroids; partial minima go to the workspace when chunks > 1.
-struct AssignPlan {
-    int G;
-    int64_t chunks;
-    int64_t per_chunk;
-    size_t ws_bytes;
+// Persistent-kernel schedule per support class (chosen by the autotuner).
+struct Schedule {
+    int blocks_per_cu[4];
+    int chunk[4];
 };
-AssignPlan plan_assign(const KSet &X, const KSet &Z, int maxsup, int cu_count);
 
+// Support class of a pair with these (declared) maximum supports.
+int class_for(int maxsup_a, int maxsup_b);
+
+// d2_assign: rows, optionally sorted by support into classes, each
+// (row, centroid chunk) item handled by one workgroup; partial minima go to
+// the workspace when the centroids are split into chunks.
+struct AssignPlan {
+    bool plain, binned;
+    int single_class;
+    int zmax;
+    int64_t chunks, per_chunk;
+    size_t part_bytes, sort_bytes, ws_bytes;
+};
+AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_count, int schedule);
 hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
                          const KOpts &o, int32_t *labels, double *best, double *all,
                          int32_t *row_status, void *ws);
 
-hipError_t launch_emd_pairs(const LaunchCtx &c, int G, const KSet &A, const KSet &B,
+hipError_t launch_emd_pairs(const LaunchCtx &c, int cls, const KSet &A, const KSet &B,
                             const int64_t *pairs, int64_t npairs, const KOpts &o, double *dist,
                             const int64_t *plan_off, double *plan, const int64_t *dual_off,
                             double *duals, int32_t *status);
 
-hipError_t launch_pairwise(const LaunchCtx &c, int G, const KSet &X, const KOpts &o,
-                           double *condensed, int32_t *status);
+struct PairwisePlan {
+    bool plain, binned;
+    int plain_class;
+    size_t ws_bytes;
+};
+PairwisePlan plan_pairwise(const KSet &X, int xmax, int schedule);
+hipError_t launch_pairwise(const LaunchCtx &c, const PairwisePlan &p, const KSet &X, const KOpts &o,
+                           double *condensed, int32_t *status, void *ws, const Schedule &sch);
 
 hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
                              const int64_t *pairs, int64_t npairs, int cost_mode, double *tiles,

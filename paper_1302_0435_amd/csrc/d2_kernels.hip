@@ -1,0 +1,630 @@
+// Kernels and launchers: labelling (Alg. 2 Step 2), explicit pair lists,
+// one segment's pairwise matrix, and the cost tiles of Eq. (1).
+//
+// Pairs are grouped by support class so each runs in the narrowest group
+// shape that holds it (rows = the larger support, T; columns, S):
+//   class 0: T <= 16            -> 16 lanes, 16 columns, cost rows in registers
+//   class 1: 16 < T <= 32       -> 32 lanes, 32 columns, registers
+//   class 2: T > 32, S <= 32    -> 64 lanes, 32 columns, registers
+//   class 3: T > 32, S > 32     -> 64 lanes, 64 columns, cost tile in LDS
+// Objects are counting-sorted by support on the device, which makes every
+// class a contiguous range of rows (labelling) or of pair indices (pairwise
+// matrix); pairwise classes are drained by persistent workgroups through an
+// atomic work counter.  Results do not depend on the schedule: every shape
+// computes the same bits, and each pair is oriented by its own indices.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "d2_internal.h"
+#include "d2_solver.h"
+
+namespace d2 {
+
+// ------------------------------------------------------------------ shapes
+
+template <int CLS> struct Shape;
+template <> struct Shape<0> { static constexpr int G = 16, GS = 16, waves = 4; static constexpr bool LT = false; };
+template <> struct Shape<1> { static constexpr int G = 32, GS = 32, waves = 4; static constexpr bool LT = false; };
+template <> struct Shape<2> { static constexpr int G = 64, GS = 32, waves = 2; static constexpr bool LT = false; };
+template <> struct Shape<3> { static constexpr int G = 64, GS = 64, waves = 1; static constexpr bool LT = true; };
+
+template <int CLS>
+struct ShapeCfg {
+    static constexpr int G = Shape<CLS>::G, GS = Shape<CLS>::GS;
+    static constexpr bool LT = Shape<CLS>::LT;
+    static constexpr int threads = Shape<CLS>::waves * 64;
+    static constexpr int groups = threads / G;
+};
+
+template <int CLS, bool VOGEL>
+using TileOf = typename std::conditional<(Shape<CLS>::LT || VOGEL), Tile<Shape<CLS>::G, Shape<CLS>::GS>,
+                                         NoTile>::type;
+
+__host__ __device__ inline int class_of(int64_t T, int64_t S) {
+    if (T <= 16) return 0;
+    if (T <= 32) return 1;
+    return S <= 32 ? 2 : 3;
+}
+
+// Support-value bucket: 0..64, and 65 for anything larger (reported as too
+// large by the solver).
+__device__ __forceinline__ int support_bucket(const int64_t *off, int64_t i) {
+    const int64_t t = off[i + 1] - off[i];
+    return t < 0 ? 0 : (t > 64 ? 65 : (int)t);
+}
+
+// ------------------------------------------------------ support sorting
+
+// ws layout (all int64): hist[66] | cursor[66] | bounds[8] | counters[4] | perm[n]
+struct SortWS {
+    int64_t *hist, *cursor, *bounds;
+    unsigned long long *counters;
+    int64_t *perm;
+};
+
+__device__ __forceinline__ SortWS sort_ws(void *ws) {
+    int64_t *p = (int64_t *)ws;
+    SortWS s;
+    s.hist = p;
+    s.cursor = p + 66;
+    s.bounds = p + 132;
+    s.counters = (unsigned long long *)(p + 140);
+    s.perm = p + 144;
+    return s;
+}
+
+size_t sort_ws_bytes(int64_t n) { return (size_t)(144 + (n > 0 ? n : 0)) * sizeof(int64_t); }
+
+__global__ void k_sort_init(void *ws) {
+    SortWS s = sort_ws(ws);
+    const int t = threadIdx.x;
+    if (t < 66) { s.hist[t] = 0; s.cursor[t] = 0; }
+    if (t < 8) s.bounds[t] = 0;
+    if (t < 4) s.counters[t] = 0ull;
+}
+
+__global__ void k_sort_hist(KSet X, void *ws) {
+    SortWS s = sort_ws(ws);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < X.n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd((unsigned long long *)&s.hist[support_bucket(X.off, i)], 1ull);
+}
+
+// Exclusive prefix over buckets, and class boundaries: bounds[c] = number of
+// sorted objects whose class is <= c (class is monotone in the support).
+// mode 0 (pairwise): class by the support alone (<= 16, <= 32, larger).
+// mode 1 (labelling against centroids of support <= smax): class of the
+// pair (max(t, smax), min(t, smax)).
+__global__ void k_sort_scan(void *ws, int64_t n, int mode, int smax) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    SortWS s = sort_ws(ws);
+    int64_t acc = 0;
+    int64_t le[4] = {0, 0, 0, 0};
+    for (int t = 0; t < 66; ++t) {
+        s.cursor[t] = acc;
+        const int64_t T = t > smax ? t : smax, S = t < smax ? t : smax;
+        const int c = mode == 0 ? (t <= 16 ? 0 : (t <= 32 ? 1 : 2)) : class_of(T, S);
+        const int64_t h = s.hist[t];
+        acc += h;
+        for (int k = c; k < 4; ++k) le[k] += h;
+    }
+    for (int k = 0; k < 4; ++k) s.bounds[k] = le[k];
+}
+
+__global__ void k_sort_scatter(KSet X, void *ws) {
+    SortWS s = sort_ws(ws);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < X.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = support_bucket(X.off, i);
+        const int64_t pos = (int64_t)atomicAdd((unsigned long long *)&s.cursor[b], 1ull);
+        s.perm[pos] = i;
+    }
+}
+
+// ---------------------------------------------------------- labelling
+
+// Rows [row_lo, row_hi) of the (optionally permuted) row order, each against
+// centroid chunk c of `chunks`; one workgroup per (row, chunk) item.
+template <int CLS, typename TIn, bool VOGEL>
+__global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_assign(
+    KSet X, KSet Z, KOpts o, const int64_t *perm, const int64_t *bounds, int cls_lo_idx,
+    int64_t chunks, int64_t per_chunk, int32_t *labels, double *best, double *all,
+    int32_t *row_status, double *ws_best, int32_t *ws_label, int32_t *ws_status) {
+    constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
+    constexpr bool LT = ShapeCfg<CLS>::LT;
+    __shared__ GroupMem<G, GS> mem[NG];
+    __shared__ TileOf<CLS, VOGEL> tiles[NG];
+    __shared__ double red_v[NG];
+    __shared__ int red_i[NG], red_s[NG];
+    const int tid = threadIdx.x;
+    const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
+    int64_t row_lo = 0, row_hi = X.n;
+    if (bounds) {
+        row_lo = cls_lo_idx > 0 ? bounds[cls_lo_idx - 1] : 0;
+        row_hi = bounds[cls_lo_idx];
+    }
+    const int64_t total = (row_hi - row_lo) * chunks;
+    const int64_t K = Z.n;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int64_t r = row_lo + item / chunks, ch = item % chunks;
+        const int64_t i = perm ? perm[r] : r;
+        const int64_t j0 = ch * per_chunk;
+        const int64_t j1 = j0 + per_chunk < K ? j0 + per_chunk : K;
+        double bv = INFINITY;
+        int bj = kNoKey, worst = kOk;
+        for (int64_t j = j0 + g; j < j1; j += NG) {
+            NodeState<G, GS, LT> N;
+            PairView pv = orient(X, i, Z, j, (int)sizeof(TIn));
+            SolveOut res = solve_pair<G, GS, LT, TIn, VOGEL>(mem[g], tiles[g], N, pv, X.d, o, l, gbase);
+            if (res.status != kOk) {
+                worst = res.status > worst ? res.status : worst;
+                res.d2 = __builtin_nan("");
+            } else if (res.d2 < bv || (res.d2 == bv && (int)j < bj)) {
+                bv = res.d2;
+                bj = (int)j;
+            }
+            if (all && l == 0) all[i * K + j] = res.d2;
+        }
+        if (l == 0) { red_v[g] = bv; red_i[g] = bj; red_s[g] = worst; }
+        __syncthreads();
+        if (tid == 0) {
+            double v = INFINITY;
+            int jj = kNoKey, st = kOk;
+            for (int q = 0; q < NG; ++q) {
+                if (red_v[q] < v || (red_v[q] == v && red_i[q] < jj)) { v = red_v[q]; jj = red_i[q]; }
+                st = red_s[q] > st ? red_s[q] : st;
+            }
+            if (chunks == 1) {
+                labels[i] = st == kOk ? jj : -1;
+                best[i] = st == kOk ? v : __builtin_nan("");
+                if (row_status) row_status[i] = st;
+            } else {
+                ws_best[i * chunks + ch] = v;
+                ws_label[i * chunks + ch] = jj;
+                ws_status[i * chunks + ch] = st;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_assign_reduce(int64_t n, int64_t chunks, const double *ws_best,
+                                const int32_t *ws_label, const int32_t *ws_status, int32_t *labels,
+                                double *best, int32_t *row_status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = INFINITY;
+    int jj = kNoKey, st = kOk;
+    for (int64_t c = 0; c < chunks; ++c) {
+        const double bv = ws_best[i * chunks + c];
+        const int bj = ws_label[i * chunks + c];
+        if (bv < v || (bv == v && bj < jj)) { v = bv; jj = bj; }
+        const int s = ws_status[i * chunks + c];
+        st = s > st ? s : st;
+    }
+    labels[i] = st == kOk ? jj : -1;
+    best[i] = st == kOk ? v : __builtin_nan("");
+    if (row_status) row_status[i] = st;
+}
+
+// ------------------------------------------------------- explicit pairs
+
+template <int CLS, typename TIn, bool VOGEL>
+__global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_emd_pairs(
+    KSet A, KSet B, const int64_t *pairs, int64_t npairs, KOpts o, double *dist,
+    const int64_t *plan_off, double *plan, const int64_t *dual_off, double *duals, int32_t *status) {
+    constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
+    constexpr bool LT = ShapeCfg<CLS>::LT;
+    __shared__ GroupMem<G, GS> mem[NG];
+    __shared__ TileOf<CLS, VOGEL> tiles[NG];
+    const int tid = threadIdx.x;
+    const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
+    const int64_t stride = (int64_t)gridDim.x * NG;
+    for (int64_t k = (int64_t)blockIdx.x * NG + g; k < npairs; k += stride) {
+        const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+        int st;
+        double val = __builtin_nan("");
+        if (i < 0 || i >= A.n || j < 0 || j >= B.n) {
+            st = kTooLarge;
+        } else {
+            NodeState<G, GS, LT> N;
+            PairView pv = orient(A, i, B, j, (int)sizeof(TIn));
+            SolveOut r = solve_pair<G, GS, LT, TIn, VOGEL>(mem[g], tiles[g], N, pv, A.d, o, l, gbase);
+            st = r.status;
+            if (st == kOk) {
+                val = r.d2;
+                if (plan || duals)
+                    write_certificate<G, GS, LT>(mem[g], N, pv, l, plan ? plan + plan_off[k] : nullptr,
+                                                 duals ? duals + dual_off[k] : nullptr);
+            }
+        }
+        if (l == 0) {
+            dist[k] = val;
+            if (status) status[k] = st;
+        }
+    }
+}
+
+// ------------------------------------------------------------ pairwise
+
+// Position of pair (i, j), i < j, in the condensed row-major order.
+__device__ __forceinline__ int64_t condensed_index(int64_t n, int64_t i, int64_t j) {
+    return i * n - i * (i + 1) / 2 + (j - i - 1);
+}
+
+// k -> (a, b), a < b, in column-major order over a triangle: b(b-1)/2 + a.
+__device__ __forceinline__ void tri_colmajor(int64_t k, int64_t &a, int64_t &b) {
+    int64_t bb = (int64_t)floor((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
+    while (bb * (bb - 1) / 2 > k) --bb;
+    while ((bb + 1) * bb / 2 <= k) ++bb;
+    b = bb;
+    a = k - bb * (bb - 1) / 2;
+}
+
+// Pair items of one support class, in sorted-object positions (a < b):
+//   class 0: triangle over [0, n16); class 1: b in [n16, n32), a < b;
+//   class 2: a in [0, n32), b in [n32, n); class 3: triangle over [n32, n).
+__device__ __forceinline__ int64_t class_items(int cls, int64_t n16, int64_t n32, int64_t n) {
+    switch (cls) {
+    case 0: return n16 * (n16 - 1) / 2;
+    case 1: return n32 * (n32 - 1) / 2 - n16 * (n16 - 1) / 2;
+    case 2: return n32 * (n - n32);
+    default: return (n - n32) * (n - n32 - 1) / 2;
+    }
+}
+
+__device__ __forceinline__ void class_item(int cls, int64_t k, int64_t n16, int64_t n32, int64_t &a,
+                                           int64_t &b) {
+    switch (cls) {
+    case 0: tri_colmajor(k, a, b); break;
+    case 1: tri_colmajor(k + n16 * (n16 - 1) / 2, a, b); break;
+    case 2: b = n32 + k / n32; a = k % n32; break;
+    default: tri_colmajor(k, a, b); a += n32; b += n32; break;
+    }
+}
+
+template <int CLS, typename TIn, bool VOGEL>
+__global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_pairwise_q(
+    KSet X, KOpts o, void *ws, int cls, int chunk, double *out, int32_t *status) {
+    constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
+    constexpr bool LT = ShapeCfg<CLS>::LT;
+    __shared__ GroupMem<G, GS> mem[NG];
+    __shared__ TileOf<CLS, VOGEL> tiles[NG];
+    const int tid = threadIdx.x;
+    const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
+    SortWS s = sort_ws(ws);
+    const int64_t n = X.n, n16 = s.bounds[0], n32 = s.bounds[1];
+    const int64_t items = class_items(cls, n16, n32, n);
+    GroupMem<G, GS> &M = mem[g];
+#pragma unroll 1
+    for (;;) {
+        if (l == 0) M.grab = (long long)atomicAdd(&s.counters[cls], (unsigned long long)chunk);
+        wsync();
+        const int64_t base = M.grab;
+        wsync();
+        if (base >= items) break;
+        const int64_t end = base + chunk < items ? base + chunk : items;
+        for (int64_t k = base; k < end; ++k) {
+            int64_t a, b;
+            class_item(cls, k, n16, n32, a, b);
+            const int64_t pi = s.perm[a], pj = s.perm[b];
+            const int64_t lo = pi < pj ? pi : pj, hi = pi < pj ? pj : pi;
+            NodeState<G, GS, LT> N;
+            PairView pv = orient(X, lo, X, hi, (int)sizeof(TIn));
+            SolveOut r = solve_pair<G, GS, LT, TIn, VOGEL>(M, tiles[g], N, pv, X.d, o, l, gbase);
+            if (l == 0) {
+                const int64_t idx = condensed_index(n, lo, hi);
+                out[idx] = r.status == kOk ? r.d2 : __builtin_nan("");
+                if (status) status[idx] = r.status;
+            }
+        }
+    }
+}
+
+// Row i of the strict upper triangle holds n-1-i pairs; k -> (i, j).
+__device__ __forceinline__ void condensed_ij(int64_t n, int64_t k, int64_t &i, int64_t &j) {
+    const double nn = (double)n;
+    const double disc = (2.0 * nn - 1.0) * (2.0 * nn - 1.0) - 8.0 * (double)k;
+    int64_t r = (int64_t)floor(((2.0 * nn - 1.0) - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
+    if (r < 0) r = 0;
+    if (r > n - 2) r = n - 2;
+    while (r > 0 && r * n - r * (r + 1) / 2 > k) --r;
+    while (r + 1 <= n - 2 && (r + 1) * n - (r + 1) * (r + 2) / 2 <= k) ++r;
+    i = r;
+    j = k - (r * n - r * (r + 1) / 2) + r + 1;
+}
+
+// Plain schedule: one shape for every pair, pairs in input order.
+template <int CLS, typename TIn, bool VOGEL>
+__global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_pairwise_plain(KSet X, KOpts o, double *out,
+                                                                           int32_t *status) {
+    constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
+    constexpr bool LT = ShapeCfg<CLS>::LT;
+    __shared__ GroupMem<G, GS> mem[NG];
+    __shared__ TileOf<CLS, VOGEL> tiles[NG];
+    const int tid = threadIdx.x;
+    const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
+    const int64_t m = X.n * (X.n - 1) / 2;
+    const int64_t stride = (int64_t)gridDim.x * NG;
+    for (int64_t k = (int64_t)blockIdx.x * NG + g; k < m; k += stride) {
+        int64_t i, j;
+        condensed_ij(X.n, k, i, j);
+        NodeState<G, GS, LT> N;
+        PairView pv = orient(X, i, X, j, (int)sizeof(TIn));
+        SolveOut r = solve_pair<G, GS, LT, TIn, VOGEL>(mem[g], tiles[g], N, pv, X.d, o, l, gbase);
+        if (l == 0) {
+            out[k] = r.status == kOk ? r.d2 : __builtin_nan("");
+            if (status) status[k] = r.status;
+        }
+    }
+}
+
+// ------------------------------------------------------------ cost tiles
+
+template <typename TIn>
+__global__ void k_cost_tiles_f64(KSet A, KSet B, const int64_t *pairs, int64_t npairs,
+                                 double *tiles, const int64_t *tile_off) {
+    for (int64_t k = blockIdx.x; k < npairs; k += gridDim.x) {
+        const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+        if (i < 0 || i >= A.n || j < 0 || j >= B.n) continue;
+        const int64_t a0 = A.off[i], t = A.off[i + 1] - a0;
+        const int64_t b0 = B.off[j], s = B.off[j + 1] - b0;
+        if (t < 1 || s < 1 || t > D2_MAX_SUPPORT || s > D2_MAX_SUPPORT) continue;
+        const TIn *x = (const TIn *)A.pts + a0 * A.d;
+        const TIn *y = (const TIn *)B.pts + b0 * B.d;
+        double *dst = tiles + tile_off[k];
+        for (int64_t c = threadIdx.x; c < t * s; c += blockDim.x) {
+            const int64_t a = c / s, b = c % s;
+            double acc = 0.0;
+            for (int q = 0; q < A.d; ++q) {
+                const double diff = (double)x[a * A.d + q] - (double)y[b * B.d + q];
+                acc = fma(diff, diff, acc);
+            }
+            dst[c] = acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+template <typename F>
+static hipError_t dispatch_class(int cls, bool f32, bool vogel, F &&f) {
+#define D2_CASE(C)                                                                      \
+    case C:                                                                             \
+        if (f32) return vogel ? f.template run<C, float, true>() : f.template run<C, float, false>(); \
+        return vogel ? f.template run<C, double, true>() : f.template run<C, double, false>();
+    switch (cls) {
+        D2_CASE(0)
+        D2_CASE(1)
+        D2_CASE(2)
+        default: D2_CASE(3)
+    }
+#undef D2_CASE
+}
+
+int class_for(int maxsup_a, int maxsup_b) {
+    const int T = maxsup_a > maxsup_b ? maxsup_a : maxsup_b;
+    const int S = maxsup_a < maxsup_b ? maxsup_a : maxsup_b;
+    return class_of(T, S);
+}
+
+int class_groups(int cls) {
+    switch (cls) {
+    case 0: return ShapeCfg<0>::groups;
+    case 1: return ShapeCfg<1>::groups;
+    case 2: return ShapeCfg<2>::groups;
+    default: return ShapeCfg<3>::groups;
+    }
+}
+
+int class_threads(int cls) {
+    switch (cls) {
+    case 0: return ShapeCfg<0>::threads;
+    case 1: return ShapeCfg<1>::threads;
+    case 2: return ShapeCfg<2>::threads;
+    default: return ShapeCfg<3>::threads;
+    }
+}
+
+// ---- labelling
+
+AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_count, int schedule) {
+    AssignPlan p;
+    p.plain = schedule == D2_SCHED_PLAIN;
+    // classes the rows can fall in: rows of support 1..xmax against zmax
+    const int cmin = class_for(1, zmax), cmax = class_for(xmax, zmax);
+    p.binned = !p.plain && cmin != cmax;
+    p.single_class = p.plain ? 3 : cmax;
+    const int NG = class_groups(p.single_class);
+    const int64_t K = Z.n > 0 ? Z.n : 1;
+    const int64_t target = (int64_t)(cu_count > 0 ? cu_count : 256) * 8;
+    int64_t chunks = X.n > 0 ? (target + X.n - 1) / X.n : 1;
+    const int64_t max_chunks = (K + NG - 1) / NG;
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks < 1) chunks = 1;
+    p.chunks = chunks;
+    p.per_chunk = (K + chunks - 1) / chunks;
+    p.part_bytes = chunks > 1 ? (size_t)X.n * chunks * (sizeof(double) + 2 * sizeof(int32_t)) : 0;
+    p.sort_bytes = p.binned ? sort_ws_bytes(X.n) : 0;
+    p.ws_bytes = p.part_bytes + p.sort_bytes;
+    p.zmax = zmax;
+    return p;
+}
+
+struct AssignRun {
+    const LaunchCtx &c;
+    const AssignPlan &p;
+    const KSet &X, &Z;
+    const KOpts &o;
+    int32_t *labels; double *best; double *all; int32_t *row_status;
+    double *wb; int32_t *wl, *wsn;
+    const int64_t *perm, *bounds;
+    int cls_idx;
+    int64_t grid;
+    template <int C, typename TIn, bool V>
+    hipError_t run() {
+        hipLaunchKernelGGL((k_assign<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
+                           c.stream, X, Z, o, perm, bounds, cls_idx, p.chunks, p.per_chunk, labels,
+                           best, all, row_status, wb, wl, wsn);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
+                         const KOpts &o, int32_t *labels, double *best, double *all,
+                         int32_t *row_status, void *ws) {
+    if (X.n == 0) return hipSuccess;
+    const bool f32 = X.dtype == D2_F32, vogel = o.init == D2_INIT_VOGEL;
+    double *wb = nullptr;
+    int32_t *wl = nullptr, *wsn = nullptr;
+    if (p.chunks > 1) {
+        wb = (double *)ws;
+        wl = (int32_t *)(wb + X.n * p.chunks);
+        wsn = wl + X.n * p.chunks;
+    }
+    hipError_t e = hipSuccess;
+    const int64_t items = X.n * p.chunks;
+    if (!p.binned) {
+        const int64_t grid = items < (1LL << 30) ? items : (1LL << 30);
+        AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, nullptr, nullptr, 0, grid};
+        e = dispatch_class(p.single_class, f32, vogel, r);
+    } else {
+        void *sws = (char *)ws + p.part_bytes;
+        SortWS hs;  // host view of the device pointers
+        {
+            int64_t *q = (int64_t *)sws;
+            hs.hist = q; hs.cursor = q + 66; hs.bounds = q + 132;
+            hs.counters = (unsigned long long *)(q + 140); hs.perm = q + 144;
+        }
+        const int sb = (int)((X.n + 255) / 256 < 1024 ? (X.n + 255) / 256 : 1024);
+        hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(128), 0, c.stream, sws);
+        hipLaunchKernelGGL(k_sort_hist, dim3(sb), dim3(256), 0, c.stream, X, sws);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, c.stream, sws, X.n, 1, p.zmax);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(sb), dim3(256), 0, c.stream, X, sws);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // every class a row can fall in; kernels of empty classes exit at once
+        for (int cls = class_for(1, p.zmax); cls < 4 && e == hipSuccess; ++cls) {
+            const int64_t grid = (int64_t)(c.cu_count > 0 ? c.cu_count : 256) * 16;
+            const int64_t g2 = items < grid ? (items > 0 ? items : 1) : grid;
+            AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, hs.perm, hs.bounds,
+                        cls, g2};
+            e = dispatch_class(cls, f32, vogel, r);
+        }
+    }
+    if (e != hipSuccess || p.chunks == 1) return e;
+    const int64_t blocks = (X.n + 255) / 256;
+    hipLaunchKernelGGL(k_assign_reduce, dim3((unsigned)blocks), dim3(256), 0, c.stream, X.n, p.chunks,
+                       wb, wl, wsn, labels, best, row_status);
+    return hipGetLastError();
+}
+
+// ---- explicit pairs
+
+struct EmdRun {
+    const LaunchCtx &c;
+    const KSet &A, &B;
+    const int64_t *pairs; int64_t npairs;
+    const KOpts &o;
+    double *dist; const int64_t *plan_off; double *plan; const int64_t *dual_off; double *duals;
+    int32_t *status;
+    template <int C, typename TIn, bool V>
+    hipError_t run() {
+        const int NG = ShapeCfg<C>::groups;
+        int64_t grid = (npairs + NG - 1) / NG;
+        if (grid > (1LL << 30)) grid = 1LL << 30;
+        hipLaunchKernelGGL((k_emd_pairs<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
+                           c.stream, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_emd_pairs(const LaunchCtx &c, int cls, const KSet &A, const KSet &B,
+                            const int64_t *pairs, int64_t npairs, const KOpts &o, double *dist,
+                            const int64_t *plan_off, double *plan, const int64_t *dual_off,
+                            double *duals, int32_t *status) {
+    if (npairs == 0) return hipSuccess;
+    EmdRun r{c, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status};
+    return dispatch_class(cls, A.dtype == D2_F32, o.init == D2_INIT_VOGEL, r);
+}
+
+// ---- pairwise
+
+PairwisePlan plan_pairwise(const KSet &X, int xmax, int schedule) {
+    PairwisePlan p;
+    p.plain = schedule == D2_SCHED_PLAIN;
+    p.plain_class = p.plain ? 3 : class_for(xmax, xmax);
+    p.binned = !p.plain && class_for(xmax, xmax) != 0;
+    p.ws_bytes = p.plain ? 0 : sort_ws_bytes(X.n);
+    return p;
+}
+
+struct PairwisePlainRun {
+    const LaunchCtx &c;
+    const KSet &X; const KOpts &o; double *out; int32_t *status;
+    template <int C, typename TIn, bool V>
+    hipError_t run() {
+        const int NG = ShapeCfg<C>::groups;
+        const int64_t m = X.n * (X.n - 1) / 2;
+        int64_t grid = (m + NG - 1) / NG;
+        if (grid > (1LL << 30)) grid = 1LL << 30;
+        hipLaunchKernelGGL((k_pairwise_plain<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads),
+                           0, c.stream, X, o, out, status);
+        return hipGetLastError();
+    }
+};
+
+struct PairwiseQRun {
+    const LaunchCtx &c;
+    const KSet &X; const KOpts &o; void *ws; int cls; int chunk; int64_t grid;
+    double *out; int32_t *status;
+    template <int C, typename TIn, bool V>
+    hipError_t run() {
+        hipLaunchKernelGGL((k_pairwise_q<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
+                           c.stream, X, o, ws, cls, chunk, out, status);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_pairwise(const LaunchCtx &c, const PairwisePlan &p, const KSet &X, const KOpts &o,
+                           double *condensed, int32_t *status, void *ws, const Schedule &sch) {
+    if (X.n < 2) return hipSuccess;
+    const bool f32 = X.dtype == D2_F32, vogel = o.init == D2_INIT_VOGEL;
+    if (p.plain) {
+        PairwisePlainRun r{c, X, o, condensed, status};
+        return dispatch_class(p.plain_class, f32, vogel, r);
+    }
+    const int sb = (int)((X.n + 255) / 256 < 1024 ? (X.n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(128), 0, c.stream, ws);
+    hipLaunchKernelGGL(k_sort_hist, dim3(sb), dim3(256), 0, c.stream, X, ws);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, c.stream, ws, X.n, 0, 0);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(sb), dim3(256), 0, c.stream, X, ws);
+    hipError_t e = hipGetLastError();
+    // classes 0..3; empty ones exit at once
+    for (int cls = 0; cls < 4 && e == hipSuccess; ++cls) {
+        const int per_cu = sch.blocks_per_cu[cls] > 0 ? sch.blocks_per_cu[cls] : 4;
+        const int64_t grid = (int64_t)(c.cu_count > 0 ? c.cu_count : 256) * per_cu;
+        PairwiseQRun r{c, X, o, ws, cls, sch.chunk[cls] > 0 ? sch.chunk[cls] : 4, grid, condensed, status};
+        e = dispatch_class(cls, f32, vogel, r);
+    }
+    return e;
+}
+
+// ---- cost tiles
+
+hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
+                             const int64_t *pairs, int64_t npairs, int cost_mode, double *tiles,
+                             const int64_t *tile_off) {
+    if (npairs == 0) return hipSuccess;
+    (void)cost_mode;
+    const int64_t grid = npairs < (1LL << 30) ? npairs : (1LL << 30);
+    if (A.dtype == D2_F32)
+        hipLaunchKernelGGL(k_cost_tiles_f64<float>, dim3((unsigned)grid), dim3(256), 0, c.stream, A, B,
+                           pairs, npairs, tiles, tile_off);
+    else
+        hipLaunchKernelGGL(k_cost_tiles_f64<double>, dim3((unsigned)grid), dim3(256), 0, c.stream, A, B,
+                           pairs, npairs, tiles, tile_off);
+    return hipGetLastError();
+}
+
+}  // namespace d2

@@ -10,11 +10,12 @@
 //
 // GPU mapping.  A "group" of G lanes (G = 16, 32 or 64; 64/G pairs per
 // wavefront) owns one pair at a time.  The pair is oriented so that rows are
-// the larger support (D^2 is symmetric).  Lane l owns row node l and column
-// node l of the basis tree and keeps row l of the cost tile in registers.
+// the larger support (D^2 is symmetric); the column count is at most GS.
+// Lane l owns row node l and column node l of the basis tree, and row l of
+// the cost tile (in registers, or in an LDS tile for the widest shape).
 // Each node stores its parent, the flow and cost of its parent edge, its
-// potential and its ancestor set as a bitmask over the 2G nodes.  With
-// ancestor masks a pivot needs no pointer chasing:
+// potential and its ancestor set as a bitmask.  With ancestor masks a pivot
+// needs no pointer chasing:
 //   * the cycle of entering cell (r, c) is the tree path r..c, i.e. the nodes
 //     in anc(r) xor anc(c); the edges whose flow decreases are the row nodes
 //     on r's side and the column nodes on c's side;
@@ -35,8 +36,10 @@
 // through a few LDS words.
 //
 // Every arithmetic step that decides the result runs in an order that does
-// not depend on G (index-order sums, exact min/max reductions), so all group
-// widths return the same bits for the same pair.
+// not depend on the shape (index-order sums, exact min/max reductions), so
+// all shapes return the same bits for the same pair.
+#pragma once
+
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -152,6 +155,12 @@ __device__ __forceinline__ int group_min_int(int v) {
     else return v;
 }
 
+template <int G, int STEP = 0>
+__device__ __forceinline__ double group_max(double v) {
+    if constexpr (STEP < Steps<G>::n) return group_max<G, STEP + 1>(fmax(v, xchg<STEP>(v)));
+    else return v;
+}
+
 // (value, key) minimum over the group, lowest key on equal values: the
 // exact minimum value first, then the least key among the lanes holding it.
 template <int G>
@@ -172,12 +181,6 @@ __device__ __forceinline__ int wave_max(int v) {
         m = max(m, __builtin_amdgcn_readlane(v, 48));
     }
     return m;
-}
-
-template <int G, int STEP = 0>
-__device__ __forceinline__ double group_max(double v) {
-    if constexpr (STEP < Steps<G>::n) return group_max<G, STEP + 1>(fmax(v, xchg<STEP>(v)));
-    else return v;
 }
 
 template <int G>
@@ -225,38 +228,40 @@ __device__ __forceinline__ void static_for(F &&f) {
 
 // ------------------------------------------------------------ group memory
 
-template <int G>
+template <int G, int GS>
 struct GroupMem {
-    double vpot[G];          // column potentials, read by every row lane when pricing
+    double vpot[GS];         // column potentials, read by every row lane when pricing
     Mask<G> ancRm[G];        // ancestor masks of row nodes (mirror for broadcast)
-    Mask<G> ancCm[G];        // ancestor masks of column nodes
+    Mask<G> ancCm[GS];       // ancestor masks of column nodes
     double bc_r, bc_c;       // entering cell: reduced cost and cost
+    long long grab;          // work-queue slot broadcast
     union {
-        struct { double pw[G]; double qw[G]; double P[G]; double Q[G]; double colcpar[G];
-                 int colpar[G]; int kind[2 * G]; int lastpos[2 * G]; } init;
+        struct { double pw[G]; double qw[GS]; double P[G]; double Q[GS]; double colcpar[GS];
+                 int colpar[GS]; int kind[2 * G]; int lastpos[2 * G]; } init;
         struct { int jmp[2 * G]; Mask<G> anc[2 * G]; } jump;
         struct { double g[2 * G]; } pot;
         struct { int newpar[2 * G]; int stemtab[2 * G]; double newflow[2 * G];
                  double newcpar[2 * G]; } piv;
-        struct { double obj[2 * G]; double colflow[G]; int colpar[G]; } fin;
+        struct { double obj[2 * G]; double colflow[GS]; int colpar[GS]; } fin;
     } u;
 };
 
-// Full cost tile, only for Vogel's start (it scans columns).
-template <int G>
-struct VogelTile { double C[G][G + 1]; };
+// Cost tile, column-major C[b][a], for the widest shape and for Vogel's
+// start (which scans columns).
+template <int G, int GS>
+struct Tile { double C[GS][G + 1]; };
 struct NoTile { char pad; };
 
 // Per-lane state: row node l, column node l, and row l of the cost tile.
-template <int G>
+template <int G, int GS, bool LT>
 struct NodeState {
     int parR, parC;          // parent index (a column / a row), -1 at the root
     double flowR, flowC;     // flow on the edge to the parent
     double cparR, cparC;     // cost of the edge to the parent
     double potR, potC;       // u_l, v_l
     Mask<G> ancR, ancC;      // ancestors including the node itself
-    typename std::conditional<G == 64, uint64_t, uint32_t>::type bas;  // basic cells of row l
-    double crow[G];          // C[l][j]; +inf beyond the columns and on rows beyond the support
+    typename std::conditional<GS == 64, uint64_t, uint32_t>::type bas;  // basic cells of row l
+    double crow[LT ? 1 : GS];  // C[l][j]; +inf beyond the columns and on rows beyond the support
 };
 
 template <typename T>
@@ -291,12 +296,24 @@ __device__ __forceinline__ PairView orient(const KSet &A, int64_t i, const KSet 
     return v;
 }
 
-template <int G>
-__device__ __forceinline__ double pick(const double (&a)[G], int j) {
-    double r = 0.0;
+// Cost of cell (l, j) from the lane's registers or the LDS tile; in
+// register mode j must be a compile-time index.
+template <int G, int GS, bool LT, typename TileT>
+__device__ __forceinline__ double cost_at(const NodeState<G, GS, LT> &N, const TileT &tile, int l, int j) {
+    if constexpr (LT) return tile.C[j][l];
+    else return N.crow[j];
+}
+
+template <int G, int GS, bool LT, typename TileT>
+__device__ __forceinline__ double cost_pick(const NodeState<G, GS, LT> &N, const TileT &tile, int l, int j) {
+    if constexpr (LT) {
+        return tile.C[j][l];
+    } else {
+        double r = 0.0;
 #pragma unroll
-    for (int k = 0; k < G; ++k) r = (k == j) ? a[k] : r;
-    return r;
+        for (int k = 0; k < GS; ++k) r = (k == j) ? N.crow[k] : r;
+        return r;
+    }
 }
 
 // ------------------------------------------------------------ potentials
@@ -306,32 +323,34 @@ __device__ __forceinline__ double pick(const double (&a)[G], int j) {
 // unrolls u_a + v_b = C_ab along the path to the root.  The sum runs over
 // node indices in order (rows, then columns).  Also refreshes the LDS
 // mirrors read when pricing and when broadcasting the entering cell.
-template <int G>
-__device__ void set_potentials(GroupMem<G> &M, NodeState<G> &N, int l, int T, int S) {
+template <int G, int GS, bool LT>
+__device__ void set_potentials(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int l, int T, int S) {
     const bool hasR = l < T, hasC = l < S;
     const double sR = ((N.ancR.popc() - 1) & 1) ? -1.0 : 1.0;
     const double sC = ((N.ancC.popc() - 1) & 1) ? -1.0 : 1.0;
     M.u.pot.g[l] = (hasR && N.parR >= 0) ? sR * N.cparR : 0.0;
-    M.u.pot.g[G + l] = (hasC && N.parC >= 0) ? sC * N.cparC : 0.0;
+    if (l < GS) M.u.pot.g[G + l] = (hasC && N.parC >= 0) ? sC * N.cparC : 0.0;
     wsync();
     double sumR = 0.0, sumC = 0.0;
 #pragma unroll 4
-    for (int n = 0; n < 2 * G; ++n) {
+    for (int n = 0; n < G + GS; ++n) {
         const double gv = M.u.pot.g[n];
         sumR += N.ancR.has(n) ? gv : 0.0;
         sumC += N.ancC.has(n) ? gv : 0.0;
     }
     N.potR = sR * sumR;
     N.potC = sC * sumC;
-    if (hasC) M.vpot[l] = N.potC;
     M.ancRm[l] = N.ancR;
-    M.ancCm[l] = N.ancC;
+    if (l < GS) {
+        if (hasC) M.vpot[l] = N.potC;
+        M.ancCm[l] = N.ancC;
+    }
     wsync();
 }
 
 // Ancestor masks from parent pointers by pointer jumping (Vogel's tree).
-template <int G>
-__device__ void anc_by_jumping(GroupMem<G> &M, NodeState<G> &N, int l, int T, int S) {
+template <int G, int GS, bool LT>
+__device__ void anc_by_jumping(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int l, int T, int S) {
     const bool hasR = l < T, hasC = l < S;
     const int idR = l, idC = G + l;
     int jR = (hasR && N.parR >= 0) ? G + N.parR : idR;
@@ -372,12 +391,12 @@ struct SolveOut {
 // Solve the LP of one oriented pair with the G lanes of this group.  On
 // return every lane holds the same SolveOut; N holds the optimal basis tree
 // and potentials (valid when status == kOk).
-template <int G, typename TIn, bool VOGEL, typename TileT>
-__device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, const PairView &pv,
-                               int d, const KOpts &o, int l, int gbase) {
+template <int G, int GS, bool LT, typename TIn, bool VOGEL, typename TileT>
+__device__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS, LT> &N,
+                               const PairView &pv, int d, const KOpts &o, int l, int gbase) {
     SolveOut out{kOk, __builtin_nan("")};
     const int T = pv.T, S = pv.S;
-    if (T < 1 || S < 1 || T > G || S > G) { out.status = kTooLarge; return out; }
+    if (T < 1 || S < 1 || T > G || S > GS) { out.status = kTooLarge; return out; }
     const bool hasR = l < T, hasC = l < S;
 
     // Weights: validated, then divided by their sum taken in index order.
@@ -385,63 +404,77 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
     double pc = hasC ? ldw<TIn>(pv.wc, l) : 0.0;
     const bool badw = (hasR && !(isfinite(pr) && pr >= 0.0)) || (hasC && !(isfinite(pc) && pc >= 0.0));
     M.u.init.pw[l] = pr;
-    M.u.init.qw[l] = pc;
+    if (l < GS) M.u.init.qw[l] = pc;
     wsync();
     double sumr = 0.0, sumc = 0.0;
 #pragma unroll 4
-    for (int a = 0; a < G; ++a) {
-        const double wp = M.u.init.pw[a], wq = M.u.init.qw[a];
-        sumr += wp;   // zeros beyond the support leave the sum unchanged
-        sumc += wq;
-    }
+    for (int a = 0; a < G; ++a) sumr += M.u.init.pw[a];   // zeros beyond the support add nothing
+#pragma unroll 4
+    for (int b = 0; b < GS; ++b) sumc += M.u.init.qw[b];
     const bool badsum = !(sumr > 0.0) || !(sumc > 0.0) || !isfinite(sumr) || !isfinite(sumc);
     if (group_bits<G>(badw || badsum, gbase) != 0ull) { out.status = kBadWeights; return out; }
     pr = pr / sumr;
     pc = pc / sumc;
 
-    const int Sw = wave_max<G>(S);
     // Cost row l, direct form: C_lj = sum_k (x_lk - y_jk)^2, k ascending.
     // Lane l holds row point l and column point l; column point j reaches
-    // every lane of the group by a register broadcast.
-#pragma unroll
-    for (int j = 0; j < G; ++j) N.crow[j] = 0.0;
+    // every lane of the group by a register broadcast.  Columns go in blocks
+    // of 16 to bound the registers in flight.
+    const int Sw = wave_max<G>(S);
     {
         const TIn *xr = (const TIn *)pv.xr + (int64_t)l * d;
         const TIn *yc = (const TIn *)pv.xc + (int64_t)l * d;
         constexpr int KC = 4;
-        for (int k0 = 0; k0 < d; k0 += KC) {
-            TIn xv[KC], yv[KC];
+        static_for<0, (GS + 15) / 16>([&](auto bc) {
+            constexpr int jb = decltype(bc)::value * 16;
+            if (jb < Sw) {
+                double acc[16];
 #pragma unroll
-            for (int kk = 0; kk < KC; ++kk) {
-                const bool in = k0 + kk < d;
-                xv[kk] = (hasR && in) ? xr[k0 + kk] : (TIn)0;
-                yv[kk] = (hasC && in) ? yc[k0 + kk] : (TIn)0;
-            }
-            static_for<0, G>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                if (j < Sw) {
-                    double acc = N.crow[j];
+                for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+                for (int k0 = 0; k0 < d; k0 += KC) {
+                    TIn xv[KC], yv[KC];
 #pragma unroll
                     for (int kk = 0; kk < KC; ++kk) {
-                        if (k0 + kk < d) {
-                            const double diff = (double)xv[kk] - gbcast_widen<G, j>(yv[kk], gbase);
-                            acc = fma(diff, diff, acc);
-                        }
+                        const bool in = k0 + kk < d;
+                        xv[kk] = (hasR && in) ? xr[k0 + kk] : (TIn)0;
+                        yv[kk] = (hasC && in) ? yc[k0 + kk] : (TIn)0;
                     }
-                    N.crow[j] = acc;
-                }
-            });
-        }
+                    static_for<0, 16>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        if (jb + j < Sw) {
 #pragma unroll
-        for (int j = 0; j < G; ++j) N.crow[j] = (hasR && j < S) ? N.crow[j] : INFINITY;
+                            for (int kk = 0; kk < KC; ++kk) {
+                                if (k0 + kk < d) {
+                                    const double diff = (double)xv[kk] - gbcast_widen<G, jb + j>(yv[kk], gbase);
+                                    acc[j] = fma(diff, diff, acc[j]);
+                                }
+                            }
+                        }
+                    });
+                }
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const double c = (hasR && jb + j < S) ? acc[j] : INFINITY;
+                    if constexpr (LT) tile.C[jb + j][l] = c;
+                    else N.crow[jb + j] = c;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    if constexpr (LT) tile.C[jb + j][l] = INFINITY;
+                    else N.crow[jb + j] = INFINITY;
+                }
+            }
+        });
     }
     double cmax = 0.0;
     bool finite = true;
 #pragma unroll
-    for (int j = 0; j < G; ++j) {
+    for (int j = 0; j < GS; ++j) {
         const bool live = hasR && j < S;
-        finite = finite & (!live | isfinite(N.crow[j]));
-        cmax = live ? fmax(cmax, N.crow[j]) : cmax;
+        const double c = cost_at<G, GS, LT>(N, tile, l, j);
+        finite = finite & (!live | isfinite(c));
+        cmax = live ? fmax(cmax, c) : cmax;
     }
     if (group_bits<G>(!finite, gbase) != 0ull) { out.status = kBadPoints; return out; }
     cmax = group_max<G>(cmax);
@@ -457,10 +490,11 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         // open cell; the last open row (column) takes every open column's
         // remaining demand (row's remaining supply) and becomes the root.
         M.u.init.pw[l] = pr;
-        M.u.init.qw[l] = pc;
+        if (l < GS) M.u.init.qw[l] = pc;
+        if constexpr (!LT) {
 #pragma unroll
-        for (int j = 0; j < G; ++j)
-            if (hasR && j < S) tile.C[l][j] = N.crow[j];
+            for (int j = 0; j < GS; ++j) tile.C[j][l] = N.crow[j];
+        }
         wsync();
         uint64_t rowon = (T == 64) ? ~0ull : ((1ull << T) - 1ull);
         uint64_t colon = (S == 64) ? ~0ull : ((1ull << S) - 1ull);
@@ -470,14 +504,14 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
             if (nr == 1) {
                 const int a = __ffsll((long long)rowon) - 1;
                 if (hasC && ((colon >> l) & 1ull)) {
-                    N.parC = a; N.flowC = M.u.init.qw[l]; N.cparC = tile.C[a][l];
+                    N.parC = a; N.flowC = M.u.init.qw[l]; N.cparC = tile.C[l][a];
                 }
                 break;
             }
             if (nc == 1) {
                 const int b = __ffsll((long long)colon) - 1;
                 if (hasR && ((rowon >> l) & 1ull)) {
-                    N.parR = b; N.flowR = M.u.init.pw[l]; N.cparR = tile.C[l][b];
+                    N.parR = b; N.flowR = M.u.init.pw[l]; N.cparR = tile.C[b][l];
                 }
                 break;
             }
@@ -486,13 +520,11 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
             if (hasR && ((rowon >> l) & 1ull)) {
                 double m1 = INFINITY, m2 = INFINITY;
                 int j1 = -1;
-#pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    if (j < S && ((colon >> j) & 1ull)) {
-                        const double c = N.crow[j];
-                        if (c < m1) { m2 = m1; m1 = c; j1 = j; }
-                        else if (c < m2) m2 = c;
-                    }
+                for (int j = 0; j < S; ++j) {
+                    if (!((colon >> j) & 1ull)) continue;
+                    const double c = tile.C[j][l];
+                    if (c < m1) { m2 = m1; m1 = c; j1 = j; }
+                    else if (c < m2) m2 = c;
                 }
                 pen = m2 - m1; key = l; other = j1;
             }
@@ -501,7 +533,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
                 int i1 = -1;
                 for (int a = 0; a < T; ++a) {
                     if (!((rowon >> a) & 1ull)) continue;
-                    const double c = tile.C[a][l];
+                    const double c = tile.C[l][a];
                     if (c < m1) { m2 = m1; m1 = c; i1 = a; }
                     else if (c < m2) m2 = c;
                 }
@@ -521,23 +553,23 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
             wsync();
             if (l == 0) { M.u.init.pw[a] = ra; M.u.init.qw[b] = rb; }
             if (ra <= rb) {
-                if (l == a) { N.parR = b; N.flowR = x; N.cparR = tile.C[a][b]; }
+                if (l == a) { N.parR = b; N.flowR = x; N.cparR = tile.C[b][a]; }
                 rowon &= ~(1ull << a);
             } else {
-                if (l == b) { N.parC = a; N.flowC = x; N.cparC = tile.C[a][b]; }
+                if (l == b) { N.parC = a; N.flowC = x; N.cparC = tile.C[b][a]; }
                 colon &= ~(1ull << b);
             }
             wsync();
         }
         wsync();
-        M.u.init.colpar[l] = hasC ? N.parC : -1;
+        if (l < GS) M.u.init.colpar[l] = hasC ? N.parC : -1;
         wsync();
         N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0u;
 #pragma unroll
-        for (int c = 0; c < G; ++c)
-            if (hasR && c < S && M.u.init.colpar[c] == l) N.bas |= 1ull << c;
+        for (int c = 0; c < GS; ++c)
+            if (hasR && c < S && M.u.init.colpar[c] == l) N.bas |= (decltype(N.bas))1 << c;
         wsync();
-        anc_by_jumping<G>(M, N, l, T, S);
+        anc_by_jumping<G, GS, LT>(M, N, l, T, S);
     } else {
         // North-west corner, all nodes at once.  With inclusive prefix sums
         // P_a of p and Q_b of q, the corner walk moves down after row a when
@@ -545,22 +577,17 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         // (a >= 1) hangs below column #{b <= S-2 : Q_b < P_{a-1}} and column b
         // (b >= 1) below row #{a <= T-2 : P_a <= Q_{b-1}}; a cell's flow is the
         // overlap of its row and column intervals, the last row and column
-        // extending to max(P_{T-1}, Q_{S-1}).  The walk visits nodes in the
-        // order row 0, column 0, then one node per move, so the depth of a
-        // node is its visiting position and its ancestors are the nodes
-        // visited before it.  Row 0 is the root.
+        // extending to max(P_{T-1}, Q_{S-1}).  Row 0 is the root.
         M.u.init.pw[l] = pr;
-        M.u.init.qw[l] = pc;
+        if (l < GS) M.u.init.qw[l] = pc;
         wsync();
         double Pl = 0.0, Ql = 0.0;
 #pragma unroll 4
-        for (int a = 0; a < G; ++a) {
-            const double wp = M.u.init.pw[a], wq = M.u.init.qw[a];
-            Pl += (a <= l) ? wp : 0.0;
-            Ql += (a <= l) ? wq : 0.0;
-        }
+        for (int a = 0; a < G; ++a) Pl += (a <= l) ? M.u.init.pw[a] : 0.0;
+#pragma unroll 4
+        for (int b = 0; b < GS; ++b) Ql += (b <= l) ? M.u.init.qw[b] : 0.0;
         M.u.init.P[l] = Pl;
-        M.u.init.Q[l] = Ql;
+        if (l < GS) M.u.init.Q[l] = Ql;
         wsync();
         const double END = fmax(M.u.init.P[T - 1], M.u.init.Q[S - 1]);
         int idxR = 0x3fffffff, idxC = 0x3fffffff;
@@ -568,7 +595,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
             const double start = M.u.init.P[l - 1];
             int b = 0;
 #pragma unroll 4
-            for (int j = 0; j < G - 1; ++j) {
+            for (int j = 0; j < GS - 1; ++j) {
                 const double qb = M.u.init.Q[j];
                 b += (j <= S - 2 && qb < start) ? 1 : 0;
             }
@@ -576,7 +603,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
             const double ec = (b == S - 1) ? END : M.u.init.Q[b];
             N.parR = b;
             N.flowR = fmin(er, ec) - start;
-            N.cparR = pick<G>(N.crow, b);
+            N.cparR = cost_pick<G, GS, LT>(N, tile, l, b);
             idxR = l + b + 1;
         } else if (hasR) {
             idxR = 0;
@@ -602,17 +629,17 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         // columns; a node hangs below the last node of the run before its
         // own, so its ancestors are itself plus every run's last node visited
         // before it.
-        M.u.init.colpar[l] = hasC ? N.parC : -1;
+        if (l < GS) M.u.init.colpar[l] = hasC ? N.parC : -1;
         if (hasR) M.u.init.kind[idxR] = 0;
         if (hasC) M.u.init.kind[idxC] = 1;
         wsync();
         // Basic cells of row l and the parent-edge costs of its child columns.
         N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0u;
 #pragma unroll
-        for (int c = 0; c < G; ++c) {
+        for (int c = 0; c < GS; ++c) {
             if (hasR && c < S && M.u.init.colpar[c] == l) {
-                N.bas |= 1ull << c;
-                M.u.init.colcpar[c] = N.crow[c];
+                N.bas |= (decltype(N.bas))1 << c;
+                M.u.init.colcpar[c] = cost_at<G, GS, LT>(N, tile, l, c);
             }
         }
         const int lastpos = T + S - 1;
@@ -625,7 +652,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         wsync();
         Mask<G> aR = Mask<G>::node(l), aC = Mask<G>::node(G + l);
 #pragma unroll 4
-        for (int n = 0; n < 2 * G; ++n) {
+        for (int n = 0; n < G + GS; ++n) {
             const int lp = M.u.init.lastpos[n];
             if (lp < idxR) aR = aR | Mask<G>::node(n);
             if (lp < idxC) aC = aC | Mask<G>::node(n);
@@ -636,7 +663,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         wsync();
     }
 
-    set_potentials<G>(M, N, l, T, S);
+    set_potentials<G, GS, LT>(M, N, l, T, S);
 
     const long long cap = o.max_pivots > 0 ? (long long)o.max_pivots
                                            : (50LL * T * S > 100 ? 50LL * T * S : 100LL);
@@ -652,23 +679,25 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         const double u = N.potR;
         if (!bland) {
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
+            for (int j = 0; j < GS; ++j) {
                 if (j < Sw) {
-                    const double r = (N.crow[j] - u) - M.vpot[j];
+                    const double c = cost_at<G, GS, LT>(N, tile, l, j);
+                    const double r = (c - u) - M.vpot[j];
                     const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < best);
                     best = cand ? r : best;
-                    bestC = cand ? N.crow[j] : bestC;
+                    bestC = cand ? c : bestC;
                     bidx = cand ? l * 64 + j : bidx;
                 }
             }
         } else {
 #pragma unroll
-            for (int j = G - 1; j >= 0; --j) {
+            for (int j = GS - 1; j >= 0; --j) {
                 if (j < Sw) {
-                    const double r = (N.crow[j] - u) - M.vpot[j];
+                    const double c = cost_at<G, GS, LT>(N, tile, l, j);
+                    const double r = (c - u) - M.vpot[j];
                     const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < -delta);
                     best = cand ? r : best;
-                    bestC = cand ? N.crow[j] : bestC;
+                    bestC = cand ? c : bestC;
                     bidx = cand ? l * 64 + j : bidx;
                 }
             }
@@ -679,7 +708,7 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
         if (kidx == kNoKey) {
             if (fresh) break;
             // Recompute the potentials from the tree before concluding.
-            set_potentials<G>(M, N, l, T, S);
+            set_potentials<G, GS, LT>(M, N, l, T, S);
             fresh = true;
             continue;
         }
@@ -789,20 +818,22 @@ __device__ SolveOut solve_pair(GroupMem<G> &M, TileT &tile, NodeState<G> &N, con
     wsync();
     double sum = 0.0;
 #pragma unroll 4
-    for (int n = 0; n < 2 * G; ++n) sum += M.u.fin.obj[n];
+    for (int n = 0; n < G + GS; ++n) sum += M.u.fin.obj[n];
     out.d2 = o.want_sqrt ? sqrt(sum) : sum;
     wsync();
     return out;
 }
 
 // Dense plan (caller's orientation) and duals of a solved pair.
-template <int G>
-__device__ void write_certificate(GroupMem<G> &M, const NodeState<G> &N, const PairView &pv, int l,
-                                  double *plan, double *duals) {
+template <int G, int GS, bool LT>
+__device__ void write_certificate(GroupMem<G, GS> &M, const NodeState<G, GS, LT> &N,
+                                  const PairView &pv, int l, double *plan, double *duals) {
     const int T = pv.T, S = pv.S;
     const bool hasR = l < T, hasC = l < S;
-    M.u.fin.colflow[l] = hasC ? N.flowC : 0.0;
-    M.u.fin.colpar[l] = hasC ? N.parC : -1;
+    if (l < GS) {
+        M.u.fin.colflow[l] = hasC ? N.flowC : 0.0;
+        M.u.fin.colpar[l] = hasC ? N.parC : -1;
+    }
     wsync();
     if (plan && hasR) {
         for (int j = 0; j < S; ++j) {
@@ -825,343 +856,6 @@ __device__ void write_certificate(GroupMem<G> &M, const NodeState<G> &N, const P
         }
     }
     wsync();
-}
-
-// -------------------------------------------------------------- kernels
-
-template <int G>
-struct Cfg {
-    static constexpr int waves = G == 64 ? 2 : 4;
-    static constexpr int threads = waves * 64;
-    static constexpr int groups = threads / G;
-};
-
-template <int G, bool VOGEL>
-using TileFor = typename std::conditional<VOGEL, VogelTile<G>, NoTile>::type;
-
-template <int G, typename TIn, bool VOGEL>
-__global__ __launch_bounds__(Cfg<G>::threads) void k_assign(KSet X, KSet Z, KOpts o, int64_t chunks,
-                                                            int64_t per_chunk, int32_t *labels,
-                                                            double *best, double *all,
-                                                            int32_t *row_status, double *ws_best,
-                                                            int32_t *ws_label, int32_t *ws_status) {
-    constexpr int NG = Cfg<G>::groups;
-    __shared__ GroupMem<G> mem[NG];
-    __shared__ TileFor<G, VOGEL> tiles[NG];
-    __shared__ double red_v[NG];
-    __shared__ int red_i[NG], red_s[NG];
-    const int tid = threadIdx.x;
-    const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
-    const int64_t total = X.n * chunks;
-    const int64_t K = Z.n;
-    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const int64_t i = item / chunks, ch = item % chunks;
-        const int64_t j0 = ch * per_chunk;
-        const int64_t j1 = j0 + per_chunk < K ? j0 + per_chunk : K;
-        double bv = INFINITY;
-        int bj = kNoKey, worst = kOk;
-        for (int64_t j = j0 + g; j < j1; j += NG) {
-            NodeState<G> N;
-            PairView pv = orient(X, i, Z, j, (int)sizeof(TIn));
-            SolveOut r = solve_pair<G, TIn, VOGEL>(mem[g], tiles[g], N, pv, X.d, o, l, gbase);
-            if (r.status != kOk) {
-                worst = r.status > worst ? r.status : worst;
-                r.d2 = __builtin_nan("");
-            } else if (r.d2 < bv || (r.d2 == bv && (int)j < bj)) {
-                bv = r.d2;
-                bj = (int)j;
-            }
-            if (all && l == 0) all[i * K + j] = r.d2;
-        }
-        if (l == 0) { red_v[g] = bv; red_i[g] = bj; red_s[g] = worst; }
-        __syncthreads();
-        if (tid == 0) {
-            double v = INFINITY;
-            int jj = kNoKey, st = kOk;
-            for (int q = 0; q < NG; ++q) {
-                if (red_v[q] < v || (red_v[q] == v && red_i[q] < jj)) { v = red_v[q]; jj = red_i[q]; }
-                st = red_s[q] > st ? red_s[q] : st;
-            }
-            if (chunks == 1) {
-                labels[i] = st == kOk ? jj : -1;
-                best[i] = st == kOk ? v : __builtin_nan("");
-                if (row_status) row_status[i] = st;
-            } else {
-                ws_best[item] = v;
-                ws_label[item] = jj;
-                ws_status[item] = st;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-__global__ void k_assign_reduce(int64_t n, int64_t chunks, const double *ws_best,
-                                const int32_t *ws_label, const int32_t *ws_status, int32_t *labels,
-                                double *best, int32_t *row_status) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double v = INFINITY;
-    int jj = kNoKey, st = kOk;
-    for (int64_t c = 0; c < chunks; ++c) {
-        const double bv = ws_best[i * chunks + c];
-        const int bj = ws_label[i * chunks + c];
-        if (bv < v || (bv == v && bj < jj)) { v = bv; jj = bj; }
-        const int s = ws_status[i * chunks + c];
-        st = s > st ? s : st;
-    }
-    labels[i] = st == kOk ? jj : -1;
-    best[i] = st == kOk ? v : __builtin_nan("");
-    if (row_status) row_status[i] = st;
-}
-
-template <int G, typename TIn, bool VOGEL>
-__global__ __launch_bounds__(Cfg<G>::threads) void k_emd_pairs(KSet A, KSet B, const int64_t *pairs,
-                                                               int64_t npairs, KOpts o, double *dist,
-                                                               const int64_t *plan_off, double *plan,
-                                                               const int64_t *dual_off, double *duals,
-                                                               int32_t *status) {
-    constexpr int NG = Cfg<G>::groups;
-    __shared__ GroupMem<G> mem[NG];
-    __shared__ TileFor<G, VOGEL> tiles[NG];
-    const int tid = threadIdx.x;
-    const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
-    const int64_t stride = (int64_t)gridDim.x * NG;
-    for (int64_t k = (int64_t)blockIdx.x * NG + g; k < npairs; k += stride) {
-        const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
-        int st;
-        double val = __builtin_nan("");
-        if (i < 0 || i >= A.n || j < 0 || j >= B.n) {
-            st = kTooLarge;
-        } else {
-            NodeState<G> N;
-            PairView pv = orient(A, i, B, j, (int)sizeof(TIn));
-            SolveOut r = solve_pair<G, TIn, VOGEL>(mem[g], tiles[g], N, pv, A.d, o, l, gbase);
-            st = r.status;
-            if (st == kOk) {
-                val = r.d2;
-                if (plan || duals)
-                    write_certificate<G>(mem[g], N, pv, l, plan ? plan + plan_off[k] : nullptr,
-                                         duals ? duals + dual_off[k] : nullptr);
-            }
-        }
-        if (l == 0) {
-            dist[k] = val;
-            if (status) status[k] = st;
-        }
-    }
-}
-
-// Row i of the strict upper triangle holds n-1-i pairs; k -> (i, j).
-__device__ __forceinline__ void condensed_ij(int64_t n, int64_t k, int64_t &i, int64_t &j) {
-    const double nn = (double)n;
-    const double disc = (2.0 * nn - 1.0) * (2.0 * nn - 1.0) - 8.0 * (double)k;
-    int64_t r = (int64_t)floor(((2.0 * nn - 1.0) - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
-    if (r < 0) r = 0;
-    if (r > n - 2) r = n - 2;
-    while (r > 0 && r * n - r * (r + 1) / 2 > k) --r;
-    while (r + 1 <= n - 2 && (r + 1) * n - (r + 1) * (r + 2) / 2 <= k) ++r;
-    i = r;
-    j = k - (r * n - r * (r + 1) / 2) + r + 1;
-}
-
-template <int G, typename TIn, bool VOGEL>
-__global__ __launch_bounds__(Cfg<G>::threads) void k_pairwise(KSet X, KOpts o, double *out,
-                                                              int32_t *status) {
-    constexpr int NG = Cfg<G>::groups;
-    __shared__ GroupMem<G> mem[NG];
-    __shared__ TileFor<G, VOGEL> tiles[NG];
-    const int tid = threadIdx.x;
-    const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
-    const int64_t m = X.n * (X.n - 1) / 2;
-    const int64_t stride = (int64_t)gridDim.x * NG;
-    for (int64_t k = (int64_t)blockIdx.x * NG + g; k < m; k += stride) {
-        int64_t i, j;
-        condensed_ij(X.n, k, i, j);
-        NodeState<G> N;
-        PairView pv = orient(X, i, X, j, (int)sizeof(TIn));
-        SolveOut r = solve_pair<G, TIn, VOGEL>(mem[g], tiles[g], N, pv, X.d, o, l, gbase);
-        if (l == 0) {
-            out[k] = r.status == kOk ? r.d2 : __builtin_nan("");
-            if (status) status[k] = r.status;
-        }
-    }
-}
-
-template <typename TIn>
-__global__ void k_cost_tiles_f64(KSet A, KSet B, const int64_t *pairs, int64_t npairs,
-                                 double *tiles, const int64_t *tile_off) {
-    // one workgroup per pair, threads over cells
-    for (int64_t k = blockIdx.x; k < npairs; k += gridDim.x) {
-        const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
-        if (i < 0 || i >= A.n || j < 0 || j >= B.n) continue;
-        const int64_t a0 = A.off[i], t = A.off[i + 1] - a0;
-        const int64_t b0 = B.off[j], s = B.off[j + 1] - b0;
-        if (t < 1 || s < 1 || t > D2_MAX_SUPPORT || s > D2_MAX_SUPPORT) continue;
-        const TIn *x = (const TIn *)A.pts + a0 * A.d;
-        const TIn *y = (const TIn *)B.pts + b0 * B.d;
-        double *dst = tiles + tile_off[k];
-        for (int64_t c = threadIdx.x; c < t * s; c += blockDim.x) {
-            const int64_t a = c / s, b = c % s;
-            double acc = 0.0;
-            for (int q = 0; q < A.d; ++q) {
-                const double diff = (double)x[a * A.d + q] - (double)y[b * B.d + q];
-                acc = fma(diff, diff, acc);
-            }
-            dst[c] = acc;
-        }
-    }
-}
-
-// ------------------------------------------------------------ launchers
-
-int group_width_for(int maxsup) {
-    if (maxsup <= 16) return 16;
-    if (maxsup <= 32) return 32;
-    return 64;
-}
-
-static int groups_per_block(int G) {
-    return G == 16 ? Cfg<16>::groups : (G == 32 ? Cfg<32>::groups : Cfg<64>::groups);
-}
-
-AssignPlan plan_assign(const KSet &X, const KSet &Z, int maxsup, int cu_count) {
-    AssignPlan p;
-    p.G = group_width_for(maxsup);
-    const int NG = groups_per_block(p.G);
-    const int64_t K = Z.n > 0 ? Z.n : 1;
-    const int64_t target = (int64_t)(cu_count > 0 ? cu_count : 256) * 8;
-    int64_t chunks = X.n > 0 ? (target + X.n - 1) / X.n : 1;
-    const int64_t max_chunks = (K + NG - 1) / NG;
-    if (chunks > max_chunks) chunks = max_chunks;
-    if (chunks < 1) chunks = 1;
-    p.chunks = chunks;
-    p.per_chunk = (K + chunks - 1) / chunks;
-    p.ws_bytes = chunks > 1 ? (size_t)X.n * chunks * (sizeof(double) + 2 * sizeof(int32_t)) : 0;
-    return p;
-}
-
-template <int G, typename TIn, bool V>
-static hipError_t assign_t(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
-                           const KOpts &o, int32_t *labels, double *best, double *all,
-                           int32_t *row_status, void *ws) {
-    const int64_t total = X.n * p.chunks;
-    double *wb = nullptr;
-    int32_t *wl = nullptr, *wsn = nullptr;
-    if (p.chunks > 1) {
-        wb = (double *)ws;
-        wl = (int32_t *)(wb + X.n * p.chunks);
-        wsn = wl + X.n * p.chunks;
-    }
-    const int64_t grid = total < (1LL << 30) ? total : (1LL << 30);
-    hipLaunchKernelGGL((k_assign<G, TIn, V>), dim3((unsigned)grid), dim3(Cfg<G>::threads), 0,
-                       c.stream, X, Z, o, p.chunks, p.per_chunk, labels, best, all, row_status, wb,
-                       wl, wsn);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || p.chunks == 1) return e;
-    const int64_t blocks = (X.n + 255) / 256;
-    hipLaunchKernelGGL(k_assign_reduce, dim3((unsigned)blocks), dim3(256), 0, c.stream, X.n, p.chunks,
-                       wb, wl, wsn, labels, best, row_status);
-    return hipGetLastError();
-}
-
-template <int G, bool V>
-static hipError_t assign_g(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
-                           const KOpts &o, int32_t *labels, double *best, double *all,
-                           int32_t *row_status, void *ws) {
-    return X.dtype == D2_F32 ? assign_t<G, float, V>(c, p, X, Z, o, labels, best, all, row_status, ws)
-                             : assign_t<G, double, V>(c, p, X, Z, o, labels, best, all, row_status, ws);
-}
-
-hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
-                         const KOpts &o, int32_t *labels, double *best, double *all,
-                         int32_t *row_status, void *ws) {
-    if (X.n == 0) return hipSuccess;
-    const bool v = o.init == D2_INIT_VOGEL;
-#define D2_ASSIGN(GG)                                                                           \
-    return v ? assign_g<GG, true>(c, p, X, Z, o, labels, best, all, row_status, ws)             \
-             : assign_g<GG, false>(c, p, X, Z, o, labels, best, all, row_status, ws)
-    switch (p.G) {
-    case 16: D2_ASSIGN(16);
-    case 32: D2_ASSIGN(32);
-    default: D2_ASSIGN(64);
-    }
-#undef D2_ASSIGN
-}
-
-template <int G, typename TIn, bool V>
-static hipError_t emd_pairs_t(const LaunchCtx &c, const KSet &A, const KSet &B, const int64_t *pairs,
-                              int64_t npairs, const KOpts &o, double *dist, const int64_t *plan_off,
-                              double *plan, const int64_t *dual_off, double *duals, int32_t *status) {
-    const int NG = Cfg<G>::groups;
-    int64_t grid = (npairs + NG - 1) / NG;
-    if (grid > (1LL << 30)) grid = 1LL << 30;
-    hipLaunchKernelGGL((k_emd_pairs<G, TIn, V>), dim3((unsigned)grid), dim3(Cfg<G>::threads), 0,
-                       c.stream, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status);
-    return hipGetLastError();
-}
-
-hipError_t launch_emd_pairs(const LaunchCtx &c, int G, const KSet &A, const KSet &B,
-                            const int64_t *pairs, int64_t npairs, const KOpts &o, double *dist,
-                            const int64_t *plan_off, double *plan, const int64_t *dual_off,
-                            double *duals, int32_t *status) {
-    if (npairs == 0) return hipSuccess;
-    const bool f32 = A.dtype == D2_F32;
-    const bool v = o.init == D2_INIT_VOGEL;
-#define D2_EMD(GG, VV)                                                                                \
-    return f32 ? emd_pairs_t<GG, float, VV>(c, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, \
-                                            duals, status)                                            \
-               : emd_pairs_t<GG, double, VV>(c, A, B, pairs, npairs, o, dist, plan_off, plan,         \
-                                             dual_off, duals, status)
-    switch (G) {
-    case 16: if (v) { D2_EMD(16, true); } else { D2_EMD(16, false); }
-    case 32: if (v) { D2_EMD(32, true); } else { D2_EMD(32, false); }
-    default: if (v) { D2_EMD(64, true); } else { D2_EMD(64, false); }
-    }
-#undef D2_EMD
-}
-
-template <int G, typename TIn, bool V>
-static hipError_t pairwise_t(const LaunchCtx &c, const KSet &X, const KOpts &o, double *out,
-                             int32_t *status) {
-    const int NG = Cfg<G>::groups;
-    const int64_t m = X.n * (X.n - 1) / 2;
-    int64_t grid = (m + NG - 1) / NG;
-    if (grid > (1LL << 30)) grid = 1LL << 30;
-    hipLaunchKernelGGL((k_pairwise<G, TIn, V>), dim3((unsigned)grid), dim3(Cfg<G>::threads), 0,
-                       c.stream, X, o, out, status);
-    return hipGetLastError();
-}
-
-hipError_t launch_pairwise(const LaunchCtx &c, int G, const KSet &X, const KOpts &o,
-                           double *condensed, int32_t *status) {
-    if (X.n < 2) return hipSuccess;
-    const bool f32 = X.dtype == D2_F32;
-    const bool v = o.init == D2_INIT_VOGEL;
-#define D2_PW(GG, VV)                                                          \
-    return f32 ? pairwise_t<GG, float, VV>(c, X, o, condensed, status)         \
-               : pairwise_t<GG, double, VV>(c, X, o, condensed, status)
-    switch (G) {
-    case 16: if (v) { D2_PW(16, true); } else { D2_PW(16, false); }
-    case 32: if (v) { D2_PW(32, true); } else { D2_PW(32, false); }
-    default: if (v) { D2_PW(64, true); } else { D2_PW(64, false); }
-    }
-#undef D2_PW
-}
-
-hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
-                             const int64_t *pairs, int64_t npairs, int cost_mode, double *tiles,
-                             const int64_t *tile_off) {
-    if (npairs == 0) return hipSuccess;
-    (void)cost_mode;
-    const int64_t grid = npairs < (1LL << 30) ? npairs : (1LL << 30);
-    if (A.dtype == D2_F32)
-        hipLaunchKernelGGL(k_cost_tiles_f64<float>, dim3((unsigned)grid), dim3(256), 0, c.stream, A, B,
-                           pairs, npairs, tiles, tile_off);
-    else
-        hipLaunchKernelGGL(k_cost_tiles_f64<double>, dim3((unsigned)grid), dim3(256), 0, c.stream, A, B,
-                           pairs, npairs, tiles, tile_off);
-    return hipGetLastError();
 }
 
 }  // namespace d2

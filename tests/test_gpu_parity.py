@@ -303,3 +303,88 @@ def test_cost_tiles_match_direct_form(d2, h):
         x, _ = A.bag(i); y, _ = B.bag(j)
         C = ((x.astype(np.float64)[:, None] - y.astype(np.float64)[None]) ** 2).sum(-1)
         assert np.allclose(tiles[off[k]:off[k + 1]].reshape(C.shape), C, rtol=1e-15, atol=0)
+
+
+def mixed_support_set(seed, n, d=6):
+    """Supports spread over every support class (1..64), log-uniform."""
+    rng = np.random.default_rng(seed)
+    bags = []
+    for _ in range(n):
+        t = int(min(64, np.floor(np.exp(rng.uniform(0, np.log(65))))))
+        bags.append((rng.normal(size=(t, d)) * 2 + rng.normal(size=d), rng.dirichlet(np.full(t, 0.5))))
+    return synth.from_bags(bags)
+
+
+def test_pairwise_binned_all_classes(d2, h):
+    X = mixed_support_set(91, 90)
+    sizes = np.diff(X.offsets)
+    assert (sizes <= 16).any() and ((sizes > 16) & (sizes <= 32)).any() and (sizes > 32).sum() >= 2
+    out, st = d2.d2_pairwise(h, dev(d2, X))
+    torch.cuda.synchronize()
+    o, o_st, _ = oracle.pairwise(X)
+    assert st.cpu().numpy().max() == 0
+    n = X.n
+    pairs = np.array([(i, j) for i in range(n) for j in range(i + 1, n)])
+    assert_close(out.cpu().numpy(), o, pair_tolerance(X, X, pairs))
+
+
+def test_schedules_and_graph_replays_are_bitwise_identical(d2, h):
+    """Plain one-wavefront-per-pair, binned eager, and several graph replays
+    (with other eager work and synchronisations in between) give the same
+    bits."""
+    X = mixed_support_set(92, 70)
+    Xd = dev(d2, X)
+    ref, st = d2.d2_pairwise(h, Xd, d2.Opts(schedule=d2.D2_SCHED_PLAIN, flags=d2.D2_FLAG_EAGER))
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    eager, _ = d2.d2_pairwise(h, Xd, d2.Opts(flags=d2.D2_FLAG_EAGER))
+    torch.cuda.synchronize()
+    assert np.array_equal(eager.cpu().numpy(), ref)
+    # graph path: same output buffers every call so the recorded graph replays
+    m = X.n * (X.n - 1) // 2
+    out = torch.full((m,), -1.0, dtype=torch.float64, device=DEV)
+    status = torch.empty(m, dtype=torch.int32, device=DEV)
+    nbytes = d2.d2_workspace_bytes(h, 3, Xd)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=DEV)
+    import ctypes
+    from paper_1302_0435_amd import _ffi
+    x = Xd.c()
+    o = d2.Opts().c()
+    for rep in range(4):
+        out.fill_(-1.0)
+        _ = torch.ones(1000, device=DEV).sum()      # unrelated eager work
+        rc = _ffi.lib().d2_pairwise(h.ptr, ctypes.byref(x), ctypes.byref(o),
+                                    ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(status.data_ptr()),
+                                    ctypes.c_void_p(ws.data_ptr()), nbytes,
+                                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), f"replay {rep}"
+
+
+def test_assign_plain_and_binned_agree(d2, h):
+    X = mixed_support_set(93, 40, d=5)
+    Z = mixed_support_set(94, 33, d=5)
+    a = d2.d2_assign(h, dev(d2, X), dev(d2, Z), d2.Opts(schedule=d2.D2_SCHED_PLAIN), want_all=True)
+    b = d2.d2_assign(h, dev(d2, X), dev(d2, Z), d2.Opts(), want_all=True)
+    torch.cuda.synchronize()
+    for u, v in zip(a, b):
+        assert np.array_equal(u.cpu().numpy(), v.cpu().numpy())
+    o_lab, o_best, o_all, _, _ = oracle.assign(X, Z)
+    assert_close(b[2].cpu().numpy(), o_all, full_floor(X, Z))
+
+
+def test_autotuned_pairwise_matches(d2, h):
+    X = mixed_support_set(95, 60)
+    Xd = dev(d2, X)
+    out, st, best_ms = d2.d2_tune_pairwise(h, Xd)
+    torch.cuda.synchronize()
+    assert best_ms > 0.0
+    again, _ = d2.d2_pairwise(h, Xd)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), again.cpu().numpy())
+    o, _, _ = oracle.pairwise(X)
+    n = X.n
+    pairs = np.array([(i, j) for i in range(n) for j in range(i + 1, n)])
+    assert_close(again.cpu().numpy(), o, pair_tolerance(X, X, pairs))
