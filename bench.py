@@ -1,13 +1,16 @@
 """Throughput of the batched exact Mallows-distance path on one MI355X.
 
-One step = one d2_assign over the whole workload: every object against every
-centroid (one transportation LP each, FP64 simplex), reduced to the nearest
-centroid (Alg. 2, Step 2 of the paper).  Inputs are resident in HBM before the
-timed region.  Prints one JSON line.
+Default (configuration 2): one step = one d2_assign over the whole workload
+-- every object against every centroid (one transportation LP each, FP64
+simplex) reduced to the nearest centroid (Alg. 2, Step 2 of the paper):
+100,000 distributions (d=8, supports 1..16, 20-component Gaussian mixture,
+Dirichlet(0.5) weights, FP32 storage) against 512 centroids of support 16,
+51.2M LPs per step.  Inputs are resident in HBM before the timed region.
+Prints one JSON line.
 
-Default workload: 100,000 distributions (d=8, supports 1..16, 20-component
-Gaussian mixture, Dirichlet(0.5) weights, FP32 storage) against 512 centroids
-of support 16: 51.2M LPs per step.
+Other workloads: --config 1 (200 x 10, d=3), --config 3 (50,000 x 256,
+d=128), --config 4 (one segment's pairwise matrix, 4,096 objects, d=16,
+8.4M pairs); --config 5 runs the serving loop (see paper_1302_0435_amd.serve).
 """
 from __future__ import annotations
 
@@ -25,28 +28,34 @@ if ROOT not in sys.path:
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
-
-
-PROFILE = os.path.join(ROOT, "profiles", "k_assign_16_f32_c2_100k_x512.txt")
+PROFILES = {
+    2: os.path.join(ROOT, "profiles", "k_assign_16_f32_c2_100k_x512.txt"),
+}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
                for f in ("d2_solver.h", "d2_kernels.hip")]
 
 
-def profile_counters():
-    """HBM bytes and VALU busy of the dominant kernel from the committed
-    rocprofv3 summary, valid only while the kernel source is unchanged."""
+def kernel_sha() -> str:
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profile_counters(cfg: int):
+    """HBM bytes and VALU busy of the dominant kernel from the committed
+    rocprofv3 summary, valid only while the kernel sources are unchanged."""
+    if cfg not in PROFILES:
+        return None
     try:
         kv = {}
-        for line in open(PROFILE):
+        for line in open(PROFILES[cfg]):
             line = line.split("#", 1)[0].strip()
             if "=" in line:
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-        h = hashlib.sha256()
-        for f in KERNEL_SRCS:
-            h.update(open(f, "rb").read())
-        sha = h.hexdigest()[:16]
+        sha = kernel_sha()
     except OSError:
         return None
     if kv.get("kernel_source_sha256_16") != sha:
@@ -54,57 +63,6 @@ def profile_counters():
     return {"traffic": float(kv["hbm_bytes_per_dispatch"]),
             "valu_issue_busy": float(kv["valu_issue_busy_fraction"]),
             "profile_avg_ms": float(kv["avg_duration_ns"]) / 1e6}
-
-
-def algorithmic_flops(X, Z) -> float:
-    """Pivot-free work per step: for every pair, the ground-cost tile
-    (t*s*d differences, squares and adds: 3 t s d) plus one certifying pricing
-    pass (r = C - u - v and its comparison: 3 t s)."""
-    ts = np.diff(X.offsets).astype(np.float64)
-    ss = np.diff(Z.offsets).astype(np.float64)
-    d = X.points.shape[1]
-    return float(ts.sum() * ss.sum() * (3 * d + 3))
-
-
-def algorithmic_bytes(X, Z) -> float:
-    """Bytes the step must move: read X and Z once, write a label and a best."""
-    return float(X.points.nbytes + X.weights.nbytes + X.offsets.nbytes + Z.points.nbytes +
-                 Z.weights.nbytes + Z.offsets.nbytes + (X.offsets.shape[0] - 1) * (4 + 8))
-
-
-def cpu_baseline(X, Z, g_labels, g_best, target_s: float, init: int):
-    """The oracle timed on this host's cores on a bounded sample of rows (all
-    centroids per row); also checks the device results for those rows."""
-    import oracle
-    import synth
-    from tests.parity import coupling_cost
-    threads = oracle.default_threads()
-    rows = synth.sample_rows(2, X.n, 64, tag=1)
-    t0 = time.perf_counter()
-    oracle.assign(X.subset(rows), Z, init=init, threads=threads, want_all=False)
-    rate = len(rows) * Z.n / max(time.perf_counter() - t0, 1e-6)
-    n_rows = int(min(X.n, max(64, target_s * rate / Z.n)))
-    rows = synth.sample_rows(2, X.n, n_rows, tag=2)
-    sub = X.subset(rows)
-    t0 = time.perf_counter()
-    o_lab, o_best, _, o_st, _ = oracle.assign(sub, Z, init=init, threads=threads, want_all=False)
-    dt = time.perf_counter() - t0
-    # parity of the sampled rows: best within tolerance, labels equal unless a near-tie
-    fails = 0
-    for k, i in enumerate(rows):
-        ob, gb = o_best[k], g_best[i]
-        if o_lab[k] == g_labels[i] and abs(gb - ob) <= 1e-10 * abs(ob):
-            continue
-        floor = 1e-14 * coupling_cost(*sub.bag(k), *Z.bag(int(o_lab[k])))
-        if abs(gb - ob) > max(1e-10 * abs(ob), floor):
-            fails += 1
-    return {
-        "value": len(rows) * Z.n / dt, "unit": "distances/s", "cores": threads, "kind": "oracle",
-        "sample": f"{len(rows)} seeded rows x all {Z.n} centroids ({len(rows) * Z.n} LPs), "
-                  f"{dt:.1f} s, same start rule",
-        "parity_checked_rows": len(rows), "parity_failures": fails,
-        "cpu_model": _cpu_model(),
-    }
 
 
 def _cpu_model() -> str:
@@ -132,46 +90,253 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+# ------------------------------------------------------------- workloads
+
+class AssignWorkload:
+    """d2_assign of a configuration's objects against its centroids."""
+
+    def __init__(self, cfg, d2, dev, init, schedule, n=None):
+        import synth
+        self.cfg = cfg
+        self.spec = synth.CONFIGS[cfg]
+        self.X = synth.make_data(cfg, n=n)
+        self.Z = synth.make_centroids(cfg)
+        self.d2 = d2
+        self.h = d2.Handle(0)
+        self.Xd = d2.DeviceSet.from_ragged(self.X, dev)
+        self.Zd = d2.DeviceSet.from_ragged(self.Z, dev)
+        self.opts = d2.Opts(init=init, schedule=schedule)
+        self.pairs = self.X.n * self.Z.n
+        self.out = None
+
+    def step(self):
+        self.out = self.d2.d2_assign(self.h, self.Xd, self.Zd, self.opts)
+
+    def flops(self):
+        """Pivot-free work: per pair the ground-cost tile (3 t s d: difference,
+        square, add) plus one certifying pricing pass (3 t s)."""
+        ts = np.diff(self.X.offsets).astype(np.float64)
+        ss = np.diff(self.Z.offsets).astype(np.float64)
+        return float(ts.sum() * ss.sum() * (3 * self.X.points.shape[1] + 3))
+
+    def bytes(self):
+        X, Z = self.X, self.Z
+        return float(X.points.nbytes + X.weights.nbytes + X.offsets.nbytes + Z.points.nbytes +
+                     Z.weights.nbytes + Z.offsets.nbytes + X.n * (4 + 8))
+
+    def failed(self):
+        return int((self.out[3].cpu().numpy() != 0).sum())
+
+    def config(self):
+        s = self.spec
+        return {"workload": s["name"], "n": self.X.n, "k": self.Z.n, "d": self.X.points.shape[1],
+                "t_range": list(s["t_range"]), "s": s["s"], "inputs": s["dtype"],
+                "pairs_per_step": self.pairs}
+
+    def cpu_baseline(self, target_s, init_oracle):
+        """The oracle timed on this host's cores on a bounded sample of rows
+        (all centroids per row); also checks the device results for those rows."""
+        import oracle
+        import synth
+        from tests.parity import coupling_cost
+        X, Z = self.X, self.Z
+        g_labels = self.out[0].cpu().numpy()
+        g_best = self.out[1].cpu().numpy()
+        threads = oracle.default_threads()
+        rows = synth.sample_rows(self.cfg, X.n, min(64, X.n), tag=1)
+        t0 = time.perf_counter()
+        oracle.assign(X.subset(rows), Z, init=init_oracle, threads=threads, want_all=False)
+        rate = len(rows) * Z.n / max(time.perf_counter() - t0, 1e-6)
+        n_rows = int(min(X.n, max(16, target_s * rate / Z.n)))
+        rows = synth.sample_rows(self.cfg, X.n, n_rows, tag=2)
+        sub = X.subset(rows)
+        t0 = time.perf_counter()
+        o_lab, o_best, _, o_st, _ = oracle.assign(sub, Z, init=init_oracle, threads=threads,
+                                                  want_all=False)
+        dt = time.perf_counter() - t0
+        fails = 0
+        for k, i in enumerate(rows):
+            ob, gb = o_best[k], g_best[i]
+            if o_lab[k] == g_labels[i] and abs(gb - ob) <= 1e-10 * abs(ob):
+                continue
+            floor = 1e-14 * coupling_cost(*sub.bag(k), *Z.bag(int(o_lab[k])))
+            if abs(gb - ob) > max(1e-10 * abs(ob), floor):
+                fails += 1
+        return {"value": len(rows) * Z.n / dt, "unit": "distances/s", "cores": threads,
+                "kind": "oracle",
+                "sample": f"{len(rows)} seeded rows x all {Z.n} centroids ({len(rows) * Z.n} LPs), "
+                          f"{dt:.1f} s, same start rule",
+                "parity_checked": len(rows), "parity_failures": fails, "cpu_model": _cpu_model()}
+
+
+class PairwiseWorkload:
+    """d2_pairwise over one segment (configuration 4)."""
+
+    def __init__(self, cfg, d2, dev, init, schedule, n=None, tune=False):
+        import synth
+        self.cfg = cfg
+        self.spec = synth.CONFIGS[cfg]
+        self.X = synth.make_data(cfg, n=n)
+        self.d2 = d2
+        self.h = d2.Handle(0)
+        self.Xd = d2.DeviceSet.from_ragged(self.X, dev)
+        self.opts = d2.Opts(init=init, schedule=schedule)
+        self.pairs = self.X.n * (self.X.n - 1) // 2
+        self.tuned_ms = None
+        if tune and schedule == d2.D2_SCHED_AUTO:
+            _, _, self.tuned_ms = d2.d2_tune_pairwise(self.h, self.Xd, self.opts)
+        self.out = None
+
+    def step(self):
+        self.out = self.d2.d2_pairwise(self.h, self.Xd, self.opts)
+
+    def flops(self):
+        ts = np.diff(self.X.offsets).astype(np.float64)
+        return float((ts.sum() ** 2 - (ts ** 2).sum()) / 2 * (3 * self.X.points.shape[1] + 3))
+
+    def bytes(self):
+        X = self.X
+        return float(X.points.nbytes + X.weights.nbytes + X.offsets.nbytes + self.pairs * 8)
+
+    def failed(self):
+        return int((self.out[1].cpu().numpy() != 0).sum())
+
+    def config(self):
+        s = self.spec
+        return {"workload": s["name"], "n": self.X.n, "d": self.X.points.shape[1],
+                "t_range": list(s["t_range"]), "single_atom": s["single_atom"],
+                "inputs": s["dtype"], "pairs_per_step": self.pairs,
+                "autotuned_ms": self.tuned_ms}
+
+    def cpu_baseline(self, target_s, init_oracle):
+        import oracle
+        import synth
+        from tests.parity import pair_tolerance
+        X = self.X
+        g = self.out[0].cpu().numpy()
+        threads = oracle.default_threads()
+        n = X.n
+
+        def sample(count, tag):
+            p = synth.sample_pairs(self.cfg, n, n, count * 3, tag=tag)
+            return p[p[:, 0] < p[:, 1]][:count]
+        p = sample(2000, 1)
+        t0 = time.perf_counter()
+        oracle.emd_batch(X, X, p, init=init_oracle, threads=threads)
+        rate = len(p) / max(time.perf_counter() - t0, 1e-6)
+        p = sample(int(max(1000, target_s * rate)), 2)
+        t0 = time.perf_counter()
+        o, o_st, _ = oracle.emd_batch(X, X, p, init=init_oracle, threads=threads)
+        dt = time.perf_counter() - t0
+        idx = p[:, 0] * n - p[:, 0] * (p[:, 0] + 1) // 2 + (p[:, 1] - p[:, 0] - 1)
+        tol = np.maximum(1e-10 * np.abs(o), pair_tolerance(X, X, p))
+        fails = int((~(np.abs(g[idx] - o) <= tol)).sum())
+        return {"value": len(p) / dt, "unit": "distances/s", "cores": threads, "kind": "oracle",
+                "sample": f"{len(p)} seeded pairs i<j, {dt:.1f} s, same start rule",
+                "parity_checked": len(p), "parity_failures": fails, "cpu_model": _cpu_model()}
+
+
+def make_pool(n_pool: int):
+    """Query pool for the serving workload (configuration 5, stream 1)."""
+    import synth
+    from paper_1302_0435_amd import serve
+    q = synth.make_data(5, n=n_pool)
+    return serve.QueryPool(q.offsets, q.points.astype(np.float64), q.weights.astype(np.float64))
+
+
+def run_serving(argv) -> int:
+    """Configuration 5: Poisson query streams against 1,024 resident centroids
+    of support 32 (d=32), one run per rate; reports p50/p99 latency and
+    distances/sec per rate, and as `value` the distances/sec of the highest
+    rate served in full with p99 under one second."""
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--rates", default="2000,10000,50000")
+    ap.add_argument("--duration", type=float, default=10.0, help="seconds per rate")
+    ap.add_argument("--pool", type=int, default=20000, help="distinct queries (reused cyclically)")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=512)
+    ap.add_argument("--budget-mib", type=float, default=256.0)
+    args = ap.parse_args(argv)
+    import torch
+    import synth
+    import paper_1302_0435_amd as d2
+    from paper_1302_0435_amd import serve
+
+    spec = synth.CONFIGS[5]
+    Z = synth.make_centroids(5)
+    Zd = d2.DeviceSet.from_ragged(Z, "cuda:0")
+    pool = make_pool(args.pool)
+    results = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        arrivals = synth.arrivals(5, rate, args.duration)
+        req_idx = np.arange(arrivals.size) % pool.n
+        ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, args.slots, args.max_batch)
+        sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n,
+                              int(args.budget_mib * 2**20), args.max_batch, args.slots)
+        sch.run(np.array([0.0]))          # warm the kernels outside the measured run
+        st = sch.run(arrivals)
+        summ = st.summary(Z.n)
+        summ["rate_qps"] = rate
+        results.append(summ)
+        print(json.dumps({"serve_rate": rate, **summ}), file=sys.stderr, flush=True)
+        del ex
+        torch.cuda.synchronize()
+    sustained = [r for r in results if r["completed"] == r["requests"] and r["p99_ms"] is not None
+                 and r["p99_ms"] < 1000.0]
+    top = max(sustained, key=lambda r: r["rate_qps"]) if sustained else results[-1]
+    print(json.dumps({
+        "metric": "exact Mallows distances/sec at <=1e-10 rel err vs FP64 oracle; p99 query latency",
+        "value": top["distances_per_s"], "unit": "distances/s", "n_gpus": 1,
+        "steps": len(results), "warmup": 1, "ms_per_step": args.duration * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": spec["name"], "k": Z.n, "s": spec["s"], "d": spec["d"],
+                   "t_range": list(spec["t_range"]), "duration_s": args.duration,
+                   "slots": args.slots, "max_batch": args.max_batch,
+                   "budget_mib": args.budget_mib},
+        "p99_ms": top["p99_ms"], "rates": results}), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--init", choices=["nwc", "vogel"], default="nwc")
+    ap.add_argument("--schedule", choices=["auto", "plain"], default="auto")
+    ap.add_argument("--tune", action="store_true", help="autotune the pairwise schedule first")
     ap.add_argument("--n", type=int, default=None, help="override object count (testing)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling the "
                          "HBM byte counters), then exit")
-    args = ap.parse_args(argv)
+    args, rest = ap.parse_known_args(argv)
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the path on a single MI355X; "
               "multi-GPU sharding is a design note, not a measured mode.", file=sys.stderr)
         return 2
+    if args.config == 5:
+        return run_serving(rest)
 
     import torch
-    import synth
     import paper_1302_0435_amd as d2
 
-    cfg = 2
-    spec = synth.CONFIGS[cfg]
-    X = synth.make_data(cfg, n=args.n)
-    Z = synth.make_centroids(cfg)
     dev = "cuda:0"
-    h = d2.Handle(0)
-    Xd = d2.DeviceSet.from_ragged(X, dev)
-    Zd = d2.DeviceSet.from_ragged(Z, dev)
     init = d2.D2_INIT_VOGEL if args.init == "vogel" else d2.D2_INIT_NWC
-    opts = d2.Opts(init=init)
-    npairs = X.n * Z.n
+    schedule = d2.D2_SCHED_PLAIN if args.schedule == "plain" else d2.D2_SCHED_AUTO
+    if args.config == 4:
+        w = PairwiseWorkload(4, d2, dev, init, schedule, n=args.n, tune=args.tune)
+    else:
+        w = AssignWorkload(args.config, d2, dev, init, schedule, n=args.n)
 
     for _ in range(args.warmup):
-        d2.d2_assign(h, Xd, Zd, opts)
+        w.step()
     torch.cuda.synchronize()
-
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
@@ -179,24 +344,22 @@ def main(argv=None) -> int:
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record(stream)
-        labels, best, _, status = d2.d2_assign(h, Xd, Zd, opts)
+        w.step()
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = [a.elapsed_time(b) for a, b in ev]
 
-    g_labels = labels.cpu().numpy()
-    g_best = best.cpu().numpy()
-    failed = int((status.cpu().numpy() != 0).sum())
-
-    value = npairs * args.steps / wall
     kernel_s = float(np.mean(kern_ms)) / 1e3
-    flops = algorithmic_flops(X, Z)
+    flops = w.flops()
     achieved = flops / kernel_s / 1e12
-    prof = profile_counters() if args.n is None else None
+    prof = profile_counters(args.config) if (args.n is None and schedule == d2.D2_SCHED_AUTO
+                                              and init == d2.D2_INIT_NWC) else None
+    cfg = w.config()
+    cfg.update({"init": args.init, "schedule": args.schedule})
     out = {
         "metric": "exact Mallows distances/sec at <=1e-10 rel err vs FP64 oracle",
-        "value": value,
+        "value": w.pairs * args.steps / wall,
         "unit": "distances/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -207,11 +370,7 @@ def main(argv=None) -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": spec["name"], "n": X.n, "k": Z.n, "d": X.points.shape[1],
-            "t_range": list(spec["t_range"]), "s": spec["s"], "inputs": "f32",
-            "pairs_per_step": npairs, "init": args.init, "kernel": "k_assign<16,float>",
-        },
+        "config": cfg,
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
@@ -220,13 +379,13 @@ def main(argv=None) -> int:
             "profile_kernel_ms": prof["profile_avg_ms"] if prof else None,
             "kernel_ms": float(np.mean(kern_ms)),
             "algorithmic_flops_per_launch": flops,
-            "algorithmic_bytes_per_launch": algorithmic_bytes(X, Z),
-            "hbm_gbs_algorithmic": algorithmic_bytes(X, Z) / kernel_s / 1e9,
+            "algorithmic_bytes_per_launch": w.bytes(),
+            "hbm_gbs_algorithmic": w.bytes() / kernel_s / 1e9,
         },
-        "failed_pairs_rows": failed,
+        "failed_pairs_or_rows": w.failed(),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(X, Z, g_labels, g_best, args.cpu_seconds, init - 1)
+        out["cpu_baseline"] = w.cpu_baseline(args.cpu_seconds, init - 1)
     print(json.dumps(out), flush=True)
     return 0
 

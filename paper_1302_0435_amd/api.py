@@ -155,6 +155,17 @@ def d2_assign(h: Handle, X: DeviceSet, Z: DeviceSet, opts: Optional[Opts] = None
     return labels, best, allv, status
 
 
+def d2_assign_into(h: Handle, X: DeviceSet, Z: DeviceSet, opts: Optional[Opts],
+                   labels: torch.Tensor, best: torch.Tensor, all_: Optional[torch.Tensor],
+                   status: Optional[torch.Tensor], ws: Optional[torch.Tensor], ws_bytes: int):
+    """d2_assign into caller-provided tensors, on the current torch stream."""
+    opts = opts or Opts()
+    x, z, o = X.c(), Z.c(), opts.c()
+    check(_ffi.lib().d2_assign(h.ptr, ctypes.byref(x), ctypes.byref(z), ctypes.byref(o),
+                               _ptr(labels), _ptr(best), _ptr(all_), _ptr(status), _ptr(ws),
+                               ws_bytes, _stream(_dev(h))), "d2_assign")
+
+
 def _pair_sizes(A: DeviceSet, B: DeviceSet, pairs: torch.Tensor):
     sa = (A.offsets[1:] - A.offsets[:-1])[pairs[:, 0]]
     sb = (B.offsets[1:] - B.offsets[:-1])[pairs[:, 1]]

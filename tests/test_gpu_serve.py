@@ -1,0 +1,51 @@
+"""Serving on the GPU: a request's result is the same alone and in the mix
+(bitwise), and matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.parity import assert_close, coupling_cost
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_serving_results_alone_equal_mix():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests selected but no GPU is visible")
+    import paper_1302_0435_amd as d2
+    from paper_1302_0435_amd import serve
+    Z = synth.make_centroids(5, k=48)
+    Zd = d2.DeviceSet.from_ragged(Z, "cuda:0")
+    q = synth.make_data(5, n=90)
+    pool = serve.QueryPool(q.offsets, q.points.astype(np.float64), q.weights.astype(np.float64))
+    n_req = 360
+    arrivals = np.sort(np.random.default_rng(3).uniform(0.0, 0.05, n_req))
+    req_idx = np.arange(n_req) % pool.n
+    ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, slots=3, max_batch=48, keep_results=True)
+    sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, 1 << 28, 48, 3)
+    st = sch.run(arrivals)
+    assert np.all(~np.isnan(st.done_s))
+    assert max(st.batch_sizes) > 1
+    assert all(ex.results[r][3] == 0 for r in range(n_req))
+    # the same pool entry served in different batches gives the same bits
+    for r in range(pool.n, n_req):
+        assert np.array_equal(ex.results[r][2], ex.results[r - pool.n][2])
+    # alone: each pool entry as a one-request call
+    h = d2.Handle(0)
+    P = synth.RaggedSet(pool.offsets, pool.points, pool.weights)
+    for q in range(0, pool.n, 7):
+        one = P.subset([q])
+        lab, best, allv, stt = d2.d2_assign(h, d2.DeviceSet.from_ragged(one, "cuda:0"), Zd,
+                                            want_all=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(allv.cpu().numpy()[0], ex.results[q][2])
+        assert int(lab.cpu().numpy()[0]) == ex.results[q][0]
+    # and the oracle agrees
+    sub = P.subset(list(range(0, pool.n, 9)))
+    o_lab, o_best, o_all, _, _ = oracle.assign(sub, Z)
+    g_all = np.stack([ex.results[q][2] for q in range(0, pool.n, 9)])
+    floor = np.array([[1e-14 * coupling_cost(*sub.bag(i), *Z.bag(j)) for j in range(Z.n)]
+                      for i in range(sub.n)])
+    assert_close(g_all, o_all, floor)

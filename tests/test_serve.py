@@ -1,0 +1,90 @@
+"""Serving scheduler on the CPU: admission by HBM budget, slots, continuous
+batching and latency accounting, driven by a scripted executor on a virtual
+clock (no GPU, deterministic)."""
+import numpy as np
+import pytest
+
+from paper_1302_0435_amd.serve import ScriptedExecutor, Scheduler, request_bytes
+
+
+class VClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+def run(arrivals, sizes, duration, budget, max_batch=64, slots=2, d=4, k=8):
+    clk = VClock()
+    ex = ScriptedExecutor(duration, clock=clk)
+    sch = Scheduler(ex, np.asarray(sizes), d, k, budget, max_batch, slots)
+    st = sch.run(np.asarray(arrivals, dtype=float), clock=clk, sleep=clk.sleep)
+    return st, ex
+
+
+def test_every_request_served_once_in_arrival_order():
+    arrivals = np.cumsum(np.full(200, 0.001))
+    st, ex = run(arrivals, [5] * 200, lambda c: 0.004, budget=1 << 30)
+    assert np.all(~np.isnan(st.done_s))
+    covered = []
+    for first, count, _ in ex.submitted:
+        covered.extend(range(first, first + count))
+    assert covered == list(range(200))
+
+
+def test_latency_is_measured_from_scheduled_arrival():
+    arrivals = np.array([0.0, 0.5, 1.0])
+    st, _ = run(arrivals, [3, 3, 3], lambda c: 0.010, budget=1 << 30)
+    lat = st.latencies_ms()
+    # alone in an idle system: latency = service time plus at most one poll step
+    assert np.all(lat >= 10.0 - 1e-9) and np.all(lat <= 10.2)
+
+
+def test_continuous_batching_packs_waiting_requests():
+    # 100 requests arrive in 1 ms while two slots are busy for 50 ms each
+    arrivals = np.linspace(0.0, 0.001, 100)
+    st, ex = run(arrivals, [4] * 100, lambda c: 0.050, budget=1 << 30, max_batch=64, slots=2)
+    sizes = [c for _, c, _ in ex.submitted]
+    assert sum(sizes) == 100
+    assert max(sizes) > 1            # later arrivals were batched together
+    assert len(sizes) < 100
+
+
+def test_budget_limits_bytes_in_flight():
+    d, k = 4, 8
+    one = request_bytes(10, d, k)
+    arrivals = np.zeros(12)
+    st, ex = run(arrivals, [10] * 12, lambda c: 0.01, budget=3 * one, max_batch=64, slots=4, d=d, k=k)
+    assert all(c <= 3 for _, c, _ in ex.submitted)
+    assert np.all(~np.isnan(st.done_s))
+
+
+def test_budget_below_one_request_queues_without_crashing():
+    d, k = 4, 8
+    arrivals = np.array([0.0, 0.001])
+    st, ex = run(arrivals, [10, 10], lambda c: 0.01, budget=request_bytes(10, d, k) - 1, d=d, k=k)
+    assert ex.submitted == []
+    assert np.all(np.isnan(st.done_s))
+    assert st.summary(k)["completed"] == 0
+
+
+def test_overload_grows_the_queue_but_serves_everyone():
+    # service 20 ms per batch of <= 8, arrivals every 1 ms: over capacity
+    arrivals = np.cumsum(np.full(400, 0.001))
+    st, _ = run(arrivals, [6] * 400, lambda c: 0.020, budget=1 << 30, max_batch=8, slots=1)
+    lat = st.latencies_ms()
+    assert lat.size == 400
+    assert st.max_queue > 100
+    assert lat[-10:].mean() > 10 * lat[:10].mean()
+
+
+@pytest.mark.parametrize("slots", [1, 3])
+def test_slots_bound_concurrency(slots):
+    arrivals = np.zeros(50)
+    st, ex = run(arrivals, [5] * 50, lambda c: 0.01, budget=1 << 30, max_batch=5, slots=slots)
+    assert sorted({s for _, _, s in ex.submitted}) == list(range(slots))
+    assert np.all(~np.isnan(st.done_s))
