@@ -66,7 +66,11 @@ enum {
     D2_COST_BF16_MFMA = 1   /* C_ab = max(0, |x|^2 + |y|^2 - 2 x.y): x.y by BF16   *
                              * MFMA with FP32 accumulation, norms in FP32 from the *
                              * same BF16-rounded values, result widened to FP64.  *
-                             * Approximate: not held to the FP64 tolerance.        */
+                             * Approximate: not held to the FP64 tolerance.  Each  *
+                             * coordinate is rounded FP64->FP32->BF16 (nearest,    *
+                             * ties to even).  Supports up to 32 only (else        *
+                             * D2_EUNSUPPORTED); accepted by d2_cost_tiles and     *
+                             * d2_assign (d2_emd_batch and d2_pairwise: EUNSUPP.). */
 };
 
 /* starting basis of the transportation simplex */
@@ -161,7 +165,8 @@ d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int
  * for every object i of X, D^2 to every centroid j of Z, then
  * labels[i] = argmin_j (ties: lowest j), best[i] = the minimum.  all[n][K]
  * (nullable) receives every D^2; row_status[n] (nullable) the worst pair
- * status of the row. */
+ * status of the row.  With D2_COST_BF16_MFMA the workspace also holds the
+ * cost tiles of a block of rows (4 KiB per pair, at most 1 GiB). */
 d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opts *opts,
                     int32_t *labels, double *best, double *all, int32_t *row_status, void *ws,
                     size_t ws_bytes, void *stream);

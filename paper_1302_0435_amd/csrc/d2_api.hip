@@ -242,7 +242,8 @@ size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set
     const int sched = sched_of(opts);
     if (which == 2 && B && set_ok(B)) {
         KSet X = kset(A), Z = kset(B);
-        return d2::plan_assign(X, Z, ms(A), ms(B), h->cu_count, sched).ws_bytes;
+        return d2::plan_assign(X, Z, ms(A), ms(B), h->cu_count, sched,
+                               opts ? opts->cost_mode : D2_COST_F64_DIRECT).ws_bytes;
     }
     if (which == 3) return d2::plan_pairwise(kset(A), ms(A), sched).ws_bytes;
     return 0;
@@ -258,7 +259,8 @@ d2_status d2_cost_tiles(d2_handle *h, const d2_set *A, const d2_set *B, const in
     if (st != D2_OK) return st;
     if (cost_mode != D2_COST_F64_DIRECT && cost_mode != D2_COST_BF16_MFMA) return D2_EINVAL;
     if (npairs > 0 && (!pairs || !tiles || !tile_offsets)) return D2_EINVAL;
-    if (cost_mode == D2_COST_BF16_MFMA) return D2_EUNSUPPORTED;
+    if (cost_mode == D2_COST_BF16_MFMA && (A->max_support > 32 || B->max_support > 32))
+        return D2_EUNSUPPORTED;
     if ((st = bind_device(h)) != D2_OK) return st;
     hipError_t e = d2::launch_cost_tiles(ctx(h, (hipStream_t)stream), kset(A), kset(B), pairs, npairs,
                                          cost_mode, tiles, tile_offsets);
@@ -297,12 +299,12 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
     if (st != D2_OK) return st;
     KOpts k;
     if ((st = opts_ok(opts, k)) != D2_OK) return st;
-    if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
+    if (k.cost_mode == D2_COST_BF16_MFMA && (ms(X) > 32 || ms(Z) > 32)) return D2_EUNSUPPORTED;
     if (X->n > 0 && (!labels || !best)) return D2_EINVAL;
     if (X->n > 0 && Z->n < 1) return D2_EINVAL;
     if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
     KSet kx = kset(X), kz = kset(Z);
-    d2::AssignPlan p = d2::plan_assign(kx, kz, ms(X), ms(Z), h->cu_count, sched_of(opts));
+    d2::AssignPlan p = d2::plan_assign(kx, kz, ms(X), ms(Z), h->cu_count, sched_of(opts), k.cost_mode);
     if (p.ws_bytes > 0 && (!ws || ws_bytes < p.ws_bytes)) return D2_EWORKSPACE;
     if ((st = bind_device(h)) != D2_OK) return st;
     if (X->n == 0) return D2_OK;

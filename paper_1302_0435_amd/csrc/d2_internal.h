@@ -46,13 +46,15 @@ int class_for(int maxsup_a, int maxsup_b);
 // (row, centroid chunk) item handled by one workgroup; partial minima go to
 // the workspace when the centroids are split into chunks.
 struct AssignPlan {
-    bool plain, binned;
+    bool plain, binned, bf16;
     int single_class;
     int zmax;
     int64_t chunks, per_chunk;
-    size_t part_bytes, sort_bytes, ws_bytes;
+    int64_t bf16_rows;   // rows per block of BF16 cost tiles
+    size_t part_bytes, sort_bytes, tile_bytes, ws_bytes;
 };
-AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_count, int schedule);
+AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_count, int schedule,
+                       int cost_mode);
 hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X, const KSet &Z,
                          const KOpts &o, int32_t *labels, double *best, double *all,
                          int32_t *row_status, void *ws);

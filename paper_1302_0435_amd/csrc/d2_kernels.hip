@@ -129,17 +129,18 @@ __global__ void k_sort_scatter(KSet X, void *ws) {
 template <int CLS, typename TIn, bool VOGEL>
 __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_assign(
     KSet X, KSet Z, KOpts o, const int64_t *perm, const int64_t *bounds, int cls_lo_idx,
-    int64_t chunks, int64_t per_chunk, int32_t *labels, double *best, double *all,
-    int32_t *row_status, double *ws_best, int32_t *ws_label, int32_t *ws_status) {
+    int64_t row_begin, int64_t row_end, int64_t chunks, int64_t per_chunk, int32_t *labels,
+    double *best, double *all, int32_t *row_status, double *ws_best, int32_t *ws_label,
+    int32_t *ws_status, const float *tiles) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
     __shared__ GroupMem<G, GS> mem[NG];
-    __shared__ TileOf<CLS, VOGEL> tiles[NG];
+    __shared__ TileOf<CLS, VOGEL> ltile[NG];
     __shared__ double red_v[NG];
     __shared__ int red_i[NG], red_s[NG];
     const int tid = threadIdx.x;
     const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
-    int64_t row_lo = 0, row_hi = X.n;
+    int64_t row_lo = row_begin, row_hi = row_end;
     if (bounds) {
         row_lo = cls_lo_idx > 0 ? bounds[cls_lo_idx - 1] : 0;
         row_hi = bounds[cls_lo_idx];
@@ -156,7 +157,8 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_assign(
         for (int64_t j = j0 + g; j < j1; j += NG) {
             NodeState<G, GS, LT> N;
             PairView pv = orient(X, i, Z, j, (int)sizeof(TIn));
-            SolveOut res = solve_pair<G, GS, LT, TIn, VOGEL>(mem[g], tiles[g], N, pv, X.d, o, l, gbase);
+            const float *ct = tiles ? tiles + ((r - row_begin) * K + j) * 1024 : nullptr;
+            SolveOut res = solve_pair<G, GS, LT, TIn, VOGEL>(mem[g], ltile[g], N, pv, X.d, o, l, gbase, ct);
             if (res.status != kOk) {
                 worst = res.status > worst ? res.status : worst;
                 res.d2 = __builtin_nan("");
@@ -386,6 +388,108 @@ __global__ void k_cost_tiles_f64(KSet A, KSet B, const int64_t *pairs, int64_t n
     }
 }
 
+// ------------------------------------------------------- BF16 cost tiles
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {  // round to nearest even
+    unsigned int u = __float_as_uint(f);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (unsigned short)((u >> 16) | 0x40u);  // NaN stays NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+    return __uint_as_float((unsigned int)h << 16);
+}
+
+// Cost tile of one oriented pair (both supports <= 32) by one wavefront:
+// C_ab = max(0, |x_a|^2 + |y_b|^2 - 2 x_a.y_b) with x, y rounded to BF16,
+// x.y by MFMA (32x32x8, FP32 accumulation), the squared norms summed in FP32
+// from the same rounded values.  Written row-major as 32 x 32 FP32 (rows
+// and columns beyond the supports hold the norms of zero vectors).
+// MFMA operand layout: lane l supplies row (l mod 32) of A and column
+// (l mod 32) of B for k = 4*(l div 32) .. +3; accumulator j of lane l is
+// D[8*(j div 4) + 4*(l div 32) + (j mod 4)][l mod 32].
+template <typename TIn>
+__device__ void bf16_tile(const PairView &pv, int d, float *out, float *nx_lds) {
+    const int l = threadIdx.x & 63, r = l & 31, h = l >> 5;
+    const bool rowok = r < pv.T, colok = r < pv.S;
+    const TIn *xr = (const TIn *)pv.xr + (int64_t)r * d;
+    const TIn *yc = (const TIn *)pv.xc + (int64_t)r * d;
+    f32x16 acc = {};
+    float nx = 0.f, ny = 0.f;
+    for (int k0 = 0; k0 < d; k0 += 8) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + 4 * h + q;
+            const float xv = (rowok && k < d) ? (float)xr[k] : 0.f;
+            const float yv = (colok && k < d) ? (float)yc[k] : 0.f;
+            const unsigned short xb = f32_to_bf16(xv), yb = f32_to_bf16(yv);
+            const float xq = bf16_to_f32(xb), yq = bf16_to_f32(yb);
+            nx = fmaf(xq, xq, nx);
+            ny = fmaf(yq, yq, ny);
+            a[q] = (short)xb;
+            b[q] = (short)yb;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    nx += __shfl_xor(nx, 32, 64);
+    ny += __shfl_xor(ny, 32, 64);
+    if (h == 0) nx_lds[r] = nx;
+    wsync();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = (j >> 2) * 8 + h * 4 + (j & 3);
+        const float c = (nx_lds[row] + ny) - 2.f * acc[j];
+        out[row * 32 + r] = c < 0.f ? 0.f : c;   // NaN passes through, to be flagged
+    }
+    wsync();
+}
+
+// Tiles for rows [r0, r1) against every centroid, one wavefront per pair:
+// tile of (row r, centroid j) at tiles + ((r - r0) * K + j) * 1024.
+template <typename TIn>
+__global__ __launch_bounds__(256) void k_cost_bf16_assign(KSet X, KSet Z, int64_t r0, int64_t r1,
+                                                          float *tiles) {
+    __shared__ float nx[4][32];
+    const int w = threadIdx.x >> 6;
+    const int64_t K = Z.n, total = (r1 - r0) * K;
+    for (int64_t p = (int64_t)blockIdx.x * 4 + w; p < total; p += (int64_t)gridDim.x * 4) {
+        const int64_t i = r0 + p / K, j = p % K;
+        PairView pv = orient(X, i, Z, j, (int)sizeof(TIn));
+        if (pv.T < 1 || pv.S < 1 || pv.T > 32 || pv.S > 32) continue;
+        bf16_tile<TIn>(pv, X.d, tiles + p * 1024, nx[w]);
+    }
+}
+
+// Explicit pairs into caller tiles (FP64, caller orientation t_i x s_j).
+template <typename TIn>
+__global__ __launch_bounds__(256) void k_cost_bf16_pairs(KSet A, KSet B, const int64_t *pairs,
+                                                         int64_t npairs, double *tiles,
+                                                         const int64_t *tile_off) {
+    __shared__ float nx[4][32];
+    __shared__ float tl[4][1024];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int64_t k = (int64_t)blockIdx.x * 4 + w; k < npairs; k += (int64_t)gridDim.x * 4) {
+        const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+        if (i < 0 || i >= A.n || j < 0 || j >= B.n) continue;
+        PairView pv = orient(A, i, B, j, (int)sizeof(TIn));
+        if (pv.T < 1 || pv.S < 1 || pv.T > 32 || pv.S > 32) continue;
+        bf16_tile<TIn>(pv, A.d, tl[w], nx[w]);
+        double *dst = tiles + tile_off[k];
+        for (int c = l; c < pv.T * pv.S; c += 64) {
+            const int a = c / pv.S, b = c % pv.S;     // oriented row a, column b
+            const double v = (double)tl[w][a * 32 + b];
+            if (!pv.swapped) dst[(int64_t)a * pv.S + b] = v;
+            else dst[(int64_t)b * pv.T + a] = v;
+        }
+        wsync();
+    }
+}
+
 // ------------------------------------------------------------ launchers
 
 template <typename F>
@@ -429,17 +533,33 @@ int class_threads(int cls) {
 
 // ---- labelling
 
-AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_count, int schedule) {
+AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_count, int schedule,
+                       int cost_mode) {
     AssignPlan p;
-    p.plain = schedule == D2_SCHED_PLAIN;
+    p.bf16 = cost_mode == D2_COST_BF16_MFMA;
+    p.plain = schedule == D2_SCHED_PLAIN && !p.bf16;
     // classes the rows can fall in: rows of support 1..xmax against zmax
     const int cmin = class_for(1, zmax), cmax = class_for(xmax, zmax);
-    p.binned = !p.plain && cmin != cmax;
+    p.binned = !p.plain && !p.bf16 && cmin != cmax;
     p.single_class = p.plain ? 3 : cmax;
     const int NG = class_groups(p.single_class);
     const int64_t K = Z.n > 0 ? Z.n : 1;
     const int64_t target = (int64_t)(cu_count > 0 ? cu_count : 256) * 8;
-    int64_t chunks = X.n > 0 ? (target + X.n - 1) / X.n : 1;
+    // BF16 mode: cost tiles (32 x 32 FP32 per pair) for a block of rows at
+    // a time, at most 1 GiB of them; the simplex launch runs per block.
+    p.bf16_rows = 0;
+    p.tile_bytes = 0;
+    if (p.bf16) {
+        const int64_t per_row = K * 1024 * (int64_t)sizeof(float);
+        int64_t rows = (1LL << 30) / per_row;
+        if (rows < 1) rows = 1;
+        if (rows > X.n) rows = X.n > 0 ? X.n : 1;
+        p.bf16_rows = rows;
+        p.tile_bytes = (size_t)rows * per_row;
+    }
+    const int64_t rows_per_launch = p.bf16 ? p.bf16_rows : X.n;
+    int64_t chunks = rows_per_launch > 0 ? (2 * target + rows_per_launch - 1) / rows_per_launch : 1;
+    if (!p.bf16) chunks = X.n > 0 ? (target + X.n - 1) / X.n : 1;
     const int64_t max_chunks = (K + NG - 1) / NG;
     if (chunks > max_chunks) chunks = max_chunks;
     if (chunks < 1) chunks = 1;
@@ -447,7 +567,7 @@ AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_
     p.per_chunk = (K + chunks - 1) / chunks;
     p.part_bytes = chunks > 1 ? (size_t)X.n * chunks * (sizeof(double) + 2 * sizeof(int32_t)) : 0;
     p.sort_bytes = p.binned ? sort_ws_bytes(X.n) : 0;
-    p.ws_bytes = p.part_bytes + p.sort_bytes;
+    p.ws_bytes = p.part_bytes + p.sort_bytes + p.tile_bytes;
     p.zmax = zmax;
     return p;
 }
@@ -462,11 +582,13 @@ struct AssignRun {
     const int64_t *perm, *bounds;
     int cls_idx;
     int64_t grid;
+    int64_t row_begin, row_end;
+    const float *tiles;
     template <int C, typename TIn, bool V>
     hipError_t run() {
         hipLaunchKernelGGL((k_assign<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
-                           c.stream, X, Z, o, perm, bounds, cls_idx, p.chunks, p.per_chunk, labels,
-                           best, all, row_status, wb, wl, wsn);
+                           c.stream, X, Z, o, perm, bounds, cls_idx, row_begin, row_end, p.chunks,
+                           p.per_chunk, labels, best, all, row_status, wb, wl, wsn, tiles);
         return hipGetLastError();
     }
 };
@@ -485,9 +607,30 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
     }
     hipError_t e = hipSuccess;
     const int64_t items = X.n * p.chunks;
-    if (!p.binned) {
+    if (p.bf16) {
+        // BF16 cost tiles for a block of rows, then the simplex on them
+        float *tiles = (float *)((char *)ws + p.part_bytes);
+        for (int64_t r0 = 0; r0 < X.n && e == hipSuccess; r0 += p.bf16_rows) {
+            const int64_t r1 = r0 + p.bf16_rows < X.n ? r0 + p.bf16_rows : X.n;
+            const int64_t pairs = (r1 - r0) * Z.n;
+            const int64_t cg = (pairs + 3) / 4 < 65536 ? (pairs + 3) / 4 : 65536;
+            if (f32)
+                hipLaunchKernelGGL(k_cost_bf16_assign<float>, dim3((unsigned)cg), dim3(256), 0, c.stream,
+                                   X, Z, r0, r1, tiles);
+            else
+                hipLaunchKernelGGL(k_cost_bf16_assign<double>, dim3((unsigned)cg), dim3(256), 0, c.stream,
+                                   X, Z, r0, r1, tiles);
+            if ((e = hipGetLastError()) != hipSuccess) break;
+            const int64_t it = (r1 - r0) * p.chunks;
+            const int64_t grid = it < (1LL << 30) ? it : (1LL << 30);
+            AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, nullptr, nullptr, 0,
+                        grid, r0, r1, tiles};
+            e = dispatch_class(p.single_class, f32, vogel, r);
+        }
+    } else if (!p.binned) {
         const int64_t grid = items < (1LL << 30) ? items : (1LL << 30);
-        AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, nullptr, nullptr, 0, grid};
+        AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, nullptr, nullptr, 0, grid,
+                    0, X.n, nullptr};
         e = dispatch_class(p.single_class, f32, vogel, r);
     } else {
         void *sws = (char *)ws + p.part_bytes;
@@ -508,7 +651,7 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
             const int64_t grid = (int64_t)(c.cu_count > 0 ? c.cu_count : 256) * 16;
             const int64_t g2 = items < grid ? (items > 0 ? items : 1) : grid;
             AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, hs.perm, hs.bounds,
-                        cls, g2};
+                        cls, g2, 0, X.n, nullptr};
             e = dispatch_class(cls, f32, vogel, r);
         }
     }
@@ -616,7 +759,16 @@ hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
                              const int64_t *pairs, int64_t npairs, int cost_mode, double *tiles,
                              const int64_t *tile_off) {
     if (npairs == 0) return hipSuccess;
-    (void)cost_mode;
+    if (cost_mode == D2_COST_BF16_MFMA) {
+        const int64_t g = (npairs + 3) / 4 < 65536 ? (npairs + 3) / 4 : 65536;
+        if (A.dtype == D2_F32)
+            hipLaunchKernelGGL(k_cost_bf16_pairs<float>, dim3((unsigned)g), dim3(256), 0, c.stream, A, B,
+                               pairs, npairs, tiles, tile_off);
+        else
+            hipLaunchKernelGGL(k_cost_bf16_pairs<double>, dim3((unsigned)g), dim3(256), 0, c.stream, A, B,
+                               pairs, npairs, tiles, tile_off);
+        return hipGetLastError();
+    }
     const int64_t grid = npairs < (1LL << 30) ? npairs : (1LL << 30);
     if (A.dtype == D2_F32)
         hipLaunchKernelGGL(k_cost_tiles_f64<float>, dim3((unsigned)grid), dim3(256), 0, c.stream, A, B,

@@ -391,9 +391,12 @@ struct SolveOut {
 // Solve the LP of one oriented pair with the G lanes of this group.  On
 // return every lane holds the same SolveOut; N holds the optimal basis tree
 // and potentials (valid when status == kOk).
+// `ctile`, when given, is this pair's cost tile already computed (row-major,
+// 32 columns, oriented like the pair); otherwise costs come from the points.
 template <int G, int GS, bool LT, typename TIn, bool VOGEL, typename TileT>
 __device__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS, LT> &N,
-                               const PairView &pv, int d, const KOpts &o, int l, int gbase) {
+                               const PairView &pv, int d, const KOpts &o, int l, int gbase,
+                               const float *ctile = nullptr) {
     SolveOut out{kOk, __builtin_nan("")};
     const int T = pv.T, S = pv.S;
     if (T < 1 || S < 1 || T > G || S > GS) { out.status = kTooLarge; return out; }
@@ -421,7 +424,16 @@ __device__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS,
     // every lane of the group by a register broadcast.  Columns go in blocks
     // of 16 to bound the registers in flight.
     const int Sw = wave_max<G>(S);
-    {
+    if (ctile) {
+        if constexpr (GS <= 32) {
+#pragma unroll
+            for (int j = 0; j < GS; ++j) {
+                const double c = (hasR && j < S) ? (double)ctile[l * 32 + j] : INFINITY;
+                if constexpr (LT) tile.C[j][l] = c;
+                else N.crow[j] = c;
+            }
+        }
+    } else {
         const TIn *xr = (const TIn *)pv.xr + (int64_t)l * d;
         const TIn *yc = (const TIn *)pv.xc + (int64_t)l * d;
         constexpr int KC = 4;

@@ -172,7 +172,7 @@ class GpuExecutor:
     resident centroids, copy out.  Completion times come from HIP events."""
 
     def __init__(self, pool: QueryPool, req_pool_index: np.ndarray, Zd, k: int, slots: int,
-                 max_batch: int, device: int = 0, keep_results: bool = False):
+                 max_batch: int, device: int = 0, keep_results: bool = False, init: int = 0):
         import torch
         from . import api
         self.torch = torch
@@ -184,7 +184,7 @@ class GpuExecutor:
         self.Zd = Zd
         self.k = k
         self.d = pool.d
-        self.opts = api.Opts(flags=1)          # eager: batch shapes vary
+        self.opts = api.Opts(init=init, flags=1)   # eager: batch shapes vary
         tmax = int(pool.sizes().max())
         self.max_batch = max_batch
         self.max_atoms = max_batch * tmax
