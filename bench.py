@@ -158,7 +158,8 @@ class AssignWorkload:
         base = {"value": len(rows) * Z.n / dt, "unit": "distances/s", "cores": threads,
                 "kind": "oracle",
                 "sample": f"{len(rows)} seeded rows x all {Z.n} centroids ({len(rows) * Z.n} LPs), "
-                          f"{dt:.1f} s, same start rule", "cpu_model": _cpu_model()}
+                          f"{dt:.1f} s, {'Vogel' if init_oracle else 'north-west-corner'} start",
+                "cpu_model": _cpu_model()}
         if self.cost_mode == 1:
             # BF16 ground cost: report its error against the FP64 oracle
             gb = g_best[rows]
@@ -242,7 +243,8 @@ class PairwiseWorkload:
         tol = np.maximum(1e-10 * np.abs(o), pair_tolerance(X, X, p))
         fails = int((~(np.abs(g[idx] - o) <= tol)).sum())
         return {"value": len(p) / dt, "unit": "distances/s", "cores": threads, "kind": "oracle",
-                "sample": f"{len(p)} seeded pairs i<j, {dt:.1f} s, same start rule",
+                "sample": f"{len(p)} seeded pairs i<j, {dt:.1f} s, "
+                          f"{'Vogel' if init_oracle else 'north-west-corner'} start",
                 "parity_checked": len(p), "parity_failures": fails, "cpu_model": _cpu_model()}
 
 
@@ -266,7 +268,7 @@ def run_serving(argv) -> int:
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=512)
     ap.add_argument("--budget-mib", type=float, default=256.0)
-    ap.add_argument("--init", choices=["auto", "nwc", "vogel"], default="auto")
+    ap.add_argument("--init", choices=["auto", "nwc", "vogel", "lcm"], default="auto")
     args = ap.parse_args(argv)
     import torch
     import synth
@@ -281,7 +283,8 @@ def run_serving(argv) -> int:
     for rate in [float(r) for r in args.rates.split(",")]:
         arrivals = synth.arrivals(5, rate, args.duration)
         req_idx = np.arange(arrivals.size) % pool.n
-        init = {"auto": d2.D2_INIT_AUTO, "nwc": d2.D2_INIT_NWC, "vogel": d2.D2_INIT_VOGEL}[args.init]
+        init = {"auto": d2.D2_INIT_AUTO, "nwc": d2.D2_INIT_NWC, "vogel": d2.D2_INIT_VOGEL,
+                "lcm": d2.D2_INIT_LCM}[args.init]
         ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, args.slots, args.max_batch, init=init)
         sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n,
                               int(args.budget_mib * 2**20), args.max_batch, args.slots)
@@ -316,7 +319,8 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
-    ap.add_argument("--init", choices=["nwc", "vogel"], default="nwc")
+    ap.add_argument("--init", choices=["auto", "nwc", "vogel", "lcm"], default="auto",
+                    help="starting basis (auto: the library default, least cost)")
     ap.add_argument("--schedule", choices=["auto", "plain"], default="auto")
     ap.add_argument("--cost", choices=["f64", "bf16"], default="f64",
                     help="ground-cost arithmetic (bf16: MFMA tiles, supports <= 32)")
@@ -335,13 +339,14 @@ def main(argv=None) -> int:
               "multi-GPU sharding is a design note, not a measured mode.", file=sys.stderr)
         return 2
     if args.config == 5:
-        return run_serving(rest + (["--init", args.init] if args.init != "nwc" else []))
+        return run_serving(rest + ["--init", args.init])
 
     import torch
     import paper_1302_0435_amd as d2
 
     dev = "cuda:0"
-    init = d2.D2_INIT_VOGEL if args.init == "vogel" else d2.D2_INIT_NWC
+    init = {"auto": d2.D2_INIT_AUTO, "nwc": d2.D2_INIT_NWC, "vogel": d2.D2_INIT_VOGEL,
+            "lcm": d2.D2_INIT_LCM}[args.init]
     schedule = d2.D2_SCHED_PLAIN if args.schedule == "plain" else d2.D2_SCHED_AUTO
     if args.config == 4:
         w = PairwiseWorkload(4, d2, dev, init, schedule, n=args.n, tune=args.tune)
@@ -369,7 +374,7 @@ def main(argv=None) -> int:
     flops = w.flops()
     achieved = flops / kernel_s / 1e12
     prof = profile_counters(args.config) if (args.n is None and schedule == d2.D2_SCHED_AUTO
-                                              and init == d2.D2_INIT_NWC
+                                              and init == d2.D2_INIT_AUTO
                                               and args.cost == "f64") else None
     cfg = w.config()
     cfg.update({"init": args.init, "schedule": args.schedule, "cost": args.cost})
@@ -403,7 +408,8 @@ def main(argv=None) -> int:
         "failed_pairs_or_rows": w.failed(),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = w.cpu_baseline(args.cpu_seconds, init - 1)
+        # the oracle has the north-west-corner and Vogel starts
+        out["cpu_baseline"] = w.cpu_baseline(args.cpu_seconds, 1 if init == d2.D2_INIT_VOGEL else 0)
     print(json.dumps(out), flush=True)
     return 0
 

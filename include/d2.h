@@ -73,8 +73,14 @@ enum {
                              * d2_assign (d2_emd_batch and d2_pairwise: EUNSUPP.). */
 };
 
-/* starting basis of the transportation simplex */
-enum { D2_INIT_AUTO = 0, D2_INIT_NWC = 1, D2_INIT_VOGEL = 2 };
+/* starting basis of the transportation simplex (every rule reaches the same
+ * optimum; they differ in how many pivots remain):
+ *   D2_INIT_NWC   north-west corner;
+ *   D2_INIT_VOGEL Vogel's approximation (largest gap between a line's two
+ *                 cheapest open cells first);
+ *   D2_INIT_LCM   least cost (cheapest open cell first);
+ *   D2_INIT_AUTO  the library's default (D2_INIT_LCM). */
+enum { D2_INIT_AUTO = 0, D2_INIT_NWC = 1, D2_INIT_VOGEL = 2, D2_INIT_LCM = 3 };
 
 /* per-pair status codes written by the device */
 enum {

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libd2.so")
 D2_OK, D2_EINVAL, D2_EWORKSPACE, D2_EUNSUPPORTED, D2_EHIP, D2_ENOMEM = range(6)
 D2_F64, D2_F32 = 0, 1
 D2_COST_F64_DIRECT, D2_COST_BF16_MFMA = 0, 1
-D2_INIT_AUTO, D2_INIT_NWC, D2_INIT_VOGEL = 0, 1, 2
+D2_INIT_AUTO, D2_INIT_NWC, D2_INIT_VOGEL, D2_INIT_LCM = 0, 1, 2, 3
 D2_SCHED_AUTO, D2_SCHED_PLAIN = 0, 1
 D2_FLAG_EAGER = 1
 D2_PAIR_OK, D2_PAIR_BAD_WEIGHTS, D2_PAIR_TOO_LARGE, D2_PAIR_PIVOT_CAP, D2_PAIR_BAD_POINTS = range(5)

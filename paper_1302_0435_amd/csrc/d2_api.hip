@@ -78,13 +78,13 @@ d2_status opts_ok(const d2_opts *o, KOpts &k) {
     static const d2_opts def = defaults();
     if (!o) o = &def;
     if (o->cost_mode != D2_COST_F64_DIRECT && o->cost_mode != D2_COST_BF16_MFMA) return D2_EINVAL;
-    if (o->init != D2_INIT_AUTO && o->init != D2_INIT_NWC && o->init != D2_INIT_VOGEL) return D2_EINVAL;
+    if (o->init < D2_INIT_AUTO || o->init > D2_INIT_LCM) return D2_EINVAL;
     if (o->max_pivots < 0) return D2_EINVAL;
     if (o->want_sqrt != 0 && o->want_sqrt != 1) return D2_EINVAL;
     if (!(o->opt_tol >= 0.0) || !isfinite(o->opt_tol) || o->opt_tol >= 1.0) return D2_EINVAL;
     if (o->schedule != D2_SCHED_AUTO && o->schedule != D2_SCHED_PLAIN) return D2_EINVAL;
     if (o->flags & ~D2_FLAG_EAGER) return D2_EINVAL;
-    k.init = o->init == D2_INIT_VOGEL ? D2_INIT_VOGEL : D2_INIT_NWC;
+    k.init = o->init == D2_INIT_NWC ? d2::kStartNWC : o->init == D2_INIT_VOGEL ? d2::kStartVogel : d2::kStartLCM;
     k.max_pivots = o->max_pivots;
     k.want_sqrt = o->want_sqrt;
     k.cost_mode = o->cost_mode;

@@ -9,9 +9,12 @@
 
 namespace d2 {
 
+// Starting-basis rules as compiled into the kernels.
+enum { kStartNWC = 0, kStartVogel = 1, kStartLCM = 2 };
+
 // Options as the kernels see them (validated and defaulted on the host).
 struct KOpts {
-    int init;        // D2_INIT_NWC or D2_INIT_VOGEL (AUTO resolved on the host)
+    int init;        // kStart* (D2_INIT_AUTO resolved on the host)
     int max_pivots;  // 0 = max(50 t s, 100)
     int want_sqrt;
     int cost_mode;

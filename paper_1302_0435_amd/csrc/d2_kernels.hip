@@ -37,8 +37,8 @@ struct ShapeCfg {
     static constexpr int groups = threads / G;
 };
 
-template <int CLS, bool VOGEL>
-using TileOf = typename std::conditional<(Shape<CLS>::LT || VOGEL), Tile<Shape<CLS>::G, Shape<CLS>::GS>,
+template <int CLS, int START>
+using TileOf = typename std::conditional<(Shape<CLS>::LT || START == kStartVogel), Tile<Shape<CLS>::G, Shape<CLS>::GS>,
                                          NoTile>::type;
 
 __host__ __device__ inline int class_of(int64_t T, int64_t S) {
@@ -126,7 +126,7 @@ __global__ void k_sort_scatter(KSet X, void *ws) {
 
 // Rows [row_lo, row_hi) of the (optionally permuted) row order, each against
 // centroid chunk c of `chunks`; one workgroup per (row, chunk) item.
-template <int CLS, typename TIn, bool VOGEL>
+template <int CLS, typename TIn, int START>
 __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_assign(
     KSet X, KSet Z, KOpts o, const int64_t *perm, const int64_t *bounds, int cls_lo_idx,
     int64_t row_begin, int64_t row_end, int64_t chunks, int64_t per_chunk, int32_t *labels,
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_assign(
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
     __shared__ GroupMem<G, GS> mem[NG];
-    __shared__ TileOf<CLS, VOGEL> ltile[NG];
+    __shared__ TileOf<CLS, START> ltile[NG];
     __shared__ double red_v[NG];
     __shared__ int red_i[NG], red_s[NG];
     const int tid = threadIdx.x;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_assign(
             NodeState<G, GS, LT> N;
             PairView pv = orient(X, i, Z, j, (int)sizeof(TIn));
             const float *ct = tiles ? tiles + ((r - row_begin) * K + j) * 1024 : nullptr;
-            SolveOut res = solve_pair<G, GS, LT, TIn, VOGEL>(mem[g], ltile[g], N, pv, X.d, o, l, gbase, ct);
+            SolveOut res = solve_pair<G, GS, LT, TIn, START>(mem[g], ltile[g], N, pv, X.d, o, l, gbase, ct);
             if (res.status != kOk) {
                 worst = res.status > worst ? res.status : worst;
                 res.d2 = __builtin_nan("");
@@ -212,14 +212,14 @@ __global__ void k_assign_reduce(int64_t n, int64_t chunks, const double *ws_best
 
 // ------------------------------------------------------- explicit pairs
 
-template <int CLS, typename TIn, bool VOGEL>
+template <int CLS, typename TIn, int START>
 __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_emd_pairs(
     KSet A, KSet B, const int64_t *pairs, int64_t npairs, KOpts o, double *dist,
     const int64_t *plan_off, double *plan, const int64_t *dual_off, double *duals, int32_t *status) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
     __shared__ GroupMem<G, GS> mem[NG];
-    __shared__ TileOf<CLS, VOGEL> tiles[NG];
+    __shared__ TileOf<CLS, START> tiles[NG];
     const int tid = threadIdx.x;
     const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
     const int64_t stride = (int64_t)gridDim.x * NG;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_emd_pairs(
         } else {
             NodeState<G, GS, LT> N;
             PairView pv = orient(A, i, B, j, (int)sizeof(TIn));
-            SolveOut r = solve_pair<G, GS, LT, TIn, VOGEL>(mem[g], tiles[g], N, pv, A.d, o, l, gbase);
+            SolveOut r = solve_pair<G, GS, LT, TIn, START>(mem[g], tiles[g], N, pv, A.d, o, l, gbase);
             st = r.status;
             if (st == kOk) {
                 val = r.d2;
@@ -286,13 +286,13 @@ __device__ __forceinline__ void class_item(int cls, int64_t k, int64_t n16, int6
     }
 }
 
-template <int CLS, typename TIn, bool VOGEL>
+template <int CLS, typename TIn, int START>
 __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_pairwise_q(
     KSet X, KOpts o, void *ws, int cls, int chunk, double *out, int32_t *status) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
     __shared__ GroupMem<G, GS> mem[NG];
-    __shared__ TileOf<CLS, VOGEL> tiles[NG];
+    __shared__ TileOf<CLS, START> tiles[NG];
     const int tid = threadIdx.x;
     const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
     SortWS s = sort_ws(ws);
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_pairwise_q(
             const int64_t lo = pi < pj ? pi : pj, hi = pi < pj ? pj : pi;
             NodeState<G, GS, LT> N;
             PairView pv = orient(X, lo, X, hi, (int)sizeof(TIn));
-            SolveOut r = solve_pair<G, GS, LT, TIn, VOGEL>(M, tiles[g], N, pv, X.d, o, l, gbase);
+            SolveOut r = solve_pair<G, GS, LT, TIn, START>(M, tiles[g], N, pv, X.d, o, l, gbase);
             if (l == 0) {
                 const int64_t idx = condensed_index(n, lo, hi);
                 out[idx] = r.status == kOk ? r.d2 : __builtin_nan("");
@@ -338,13 +338,13 @@ __device__ __forceinline__ void condensed_ij(int64_t n, int64_t k, int64_t &i, i
 }
 
 // Plain schedule: one shape for every pair, pairs in input order.
-template <int CLS, typename TIn, bool VOGEL>
+template <int CLS, typename TIn, int START>
 __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_pairwise_plain(KSet X, KOpts o, double *out,
                                                                            int32_t *status) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
     __shared__ GroupMem<G, GS> mem[NG];
-    __shared__ TileOf<CLS, VOGEL> tiles[NG];
+    __shared__ TileOf<CLS, START> tiles[NG];
     const int tid = threadIdx.x;
     const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
     const int64_t m = X.n * (X.n - 1) / 2;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_pairwise_plain(KSet 
         condensed_ij(X.n, k, i, j);
         NodeState<G, GS, LT> N;
         PairView pv = orient(X, i, X, j, (int)sizeof(TIn));
-        SolveOut r = solve_pair<G, GS, LT, TIn, VOGEL>(mem[g], tiles[g], N, pv, X.d, o, l, gbase);
+        SolveOut r = solve_pair<G, GS, LT, TIn, START>(mem[g], tiles[g], N, pv, X.d, o, l, gbase);
         if (l == 0) {
             out[k] = r.status == kOk ? r.d2 : __builtin_nan("");
             if (status) status[k] = r.status;
@@ -493,11 +493,15 @@ __global__ __launch_bounds__(256) void k_cost_bf16_pairs(KSet A, KSet B, const i
 // ------------------------------------------------------------ launchers
 
 template <typename F>
-static hipError_t dispatch_class(int cls, bool f32, bool vogel, F &&f) {
+static hipError_t dispatch_class(int cls, bool f32, int start, F &&f) {
 #define D2_CASE(C)                                                                      \
     case C:                                                                             \
-        if (f32) return vogel ? f.template run<C, float, true>() : f.template run<C, float, false>(); \
-        return vogel ? f.template run<C, double, true>() : f.template run<C, double, false>();
+        if (f32) return start == kStartVogel ? f.template run<C, float, kStartVogel>()             \
+                      : start == kStartLCM ? f.template run<C, float, kStartLCM>()                   \
+                                           : f.template run<C, float, kStartNWC>();                  \
+        return start == kStartVogel ? f.template run<C, double, kStartVogel>()                       \
+               : start == kStartLCM ? f.template run<C, double, kStartLCM>()                         \
+                                    : f.template run<C, double, kStartNWC>();
     switch (cls) {
         D2_CASE(0)
         D2_CASE(1)
@@ -584,7 +588,7 @@ struct AssignRun {
     int64_t grid;
     int64_t row_begin, row_end;
     const float *tiles;
-    template <int C, typename TIn, bool V>
+    template <int C, typename TIn, int V>
     hipError_t run() {
         hipLaunchKernelGGL((k_assign<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
                            c.stream, X, Z, o, perm, bounds, cls_idx, row_begin, row_end, p.chunks,
@@ -597,7 +601,8 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
                          const KOpts &o, int32_t *labels, double *best, double *all,
                          int32_t *row_status, void *ws) {
     if (X.n == 0) return hipSuccess;
-    const bool f32 = X.dtype == D2_F32, vogel = o.init == D2_INIT_VOGEL;
+    const bool f32 = X.dtype == D2_F32;
+    const int start = o.init;
     double *wb = nullptr;
     int32_t *wl = nullptr, *wsn = nullptr;
     if (p.chunks > 1) {
@@ -625,13 +630,13 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
             const int64_t grid = it < (1LL << 30) ? it : (1LL << 30);
             AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, nullptr, nullptr, 0,
                         grid, r0, r1, tiles};
-            e = dispatch_class(p.single_class, f32, vogel, r);
+            e = dispatch_class(p.single_class, f32, start, r);
         }
     } else if (!p.binned) {
         const int64_t grid = items < (1LL << 30) ? items : (1LL << 30);
         AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, nullptr, nullptr, 0, grid,
                     0, X.n, nullptr};
-        e = dispatch_class(p.single_class, f32, vogel, r);
+        e = dispatch_class(p.single_class, f32, start, r);
     } else {
         void *sws = (char *)ws + p.part_bytes;
         SortWS hs;  // host view of the device pointers
@@ -652,7 +657,7 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
             const int64_t g2 = items < grid ? (items > 0 ? items : 1) : grid;
             AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, hs.perm, hs.bounds,
                         cls, g2, 0, X.n, nullptr};
-            e = dispatch_class(cls, f32, vogel, r);
+            e = dispatch_class(cls, f32, start, r);
         }
     }
     if (e != hipSuccess || p.chunks == 1) return e;
@@ -671,7 +676,7 @@ struct EmdRun {
     const KOpts &o;
     double *dist; const int64_t *plan_off; double *plan; const int64_t *dual_off; double *duals;
     int32_t *status;
-    template <int C, typename TIn, bool V>
+    template <int C, typename TIn, int V>
     hipError_t run() {
         const int NG = ShapeCfg<C>::groups;
         int64_t grid = (npairs + NG - 1) / NG;
@@ -688,7 +693,7 @@ hipError_t launch_emd_pairs(const LaunchCtx &c, int cls, const KSet &A, const KS
                             double *duals, int32_t *status) {
     if (npairs == 0) return hipSuccess;
     EmdRun r{c, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status};
-    return dispatch_class(cls, A.dtype == D2_F32, o.init == D2_INIT_VOGEL, r);
+    return dispatch_class(cls, A.dtype == D2_F32, o.init, r);
 }
 
 // ---- pairwise
@@ -705,7 +710,7 @@ PairwisePlan plan_pairwise(const KSet &X, int xmax, int schedule) {
 struct PairwisePlainRun {
     const LaunchCtx &c;
     const KSet &X; const KOpts &o; double *out; int32_t *status;
-    template <int C, typename TIn, bool V>
+    template <int C, typename TIn, int V>
     hipError_t run() {
         const int NG = ShapeCfg<C>::groups;
         const int64_t m = X.n * (X.n - 1) / 2;
@@ -721,7 +726,7 @@ struct PairwiseQRun {
     const LaunchCtx &c;
     const KSet &X; const KOpts &o; void *ws; int cls; int chunk; int64_t grid;
     double *out; int32_t *status;
-    template <int C, typename TIn, bool V>
+    template <int C, typename TIn, int V>
     hipError_t run() {
         hipLaunchKernelGGL((k_pairwise_q<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
                            c.stream, X, o, ws, cls, chunk, out, status);
@@ -732,10 +737,11 @@ struct PairwiseQRun {
 hipError_t launch_pairwise(const LaunchCtx &c, const PairwisePlan &p, const KSet &X, const KOpts &o,
                            double *condensed, int32_t *status, void *ws, const Schedule &sch) {
     if (X.n < 2) return hipSuccess;
-    const bool f32 = X.dtype == D2_F32, vogel = o.init == D2_INIT_VOGEL;
+    const bool f32 = X.dtype == D2_F32;
+    const int start = o.init;
     if (p.plain) {
         PairwisePlainRun r{c, X, o, condensed, status};
-        return dispatch_class(p.plain_class, f32, vogel, r);
+        return dispatch_class(p.plain_class, f32, start, r);
     }
     const int sb = (int)((X.n + 255) / 256 < 1024 ? (X.n + 255) / 256 : 1024);
     hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(128), 0, c.stream, ws);
@@ -748,7 +754,7 @@ hipError_t launch_pairwise(const LaunchCtx &c, const PairwisePlan &p, const KSet
         const int per_cu = sch.blocks_per_cu[cls] > 0 ? sch.blocks_per_cu[cls] : 4;
         const int64_t grid = (int64_t)(c.cu_count > 0 ? c.cu_count : 256) * per_cu;
         PairwiseQRun r{c, X, o, ws, cls, sch.chunk[cls] > 0 ? sch.chunk[cls] : 4, grid, condensed, status};
-        e = dispatch_class(cls, f32, vogel, r);
+        e = dispatch_class(cls, f32, start, r);
     }
     return e;
 }

@@ -393,7 +393,7 @@ struct SolveOut {
 // and potentials (valid when status == kOk).
 // `ctile`, when given, is this pair's cost tile already computed (row-major,
 // 32 columns, oriented like the pair); otherwise costs come from the points.
-template <int G, int GS, bool LT, typename TIn, bool VOGEL, typename TileT>
+template <int G, int GS, bool LT, typename TIn, int START, typename TileT>
 __device__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS, LT> &N,
                                const PairView &pv, int d, const KOpts &o, int l, int gbase,
                                const float *ctile = nullptr) {
@@ -496,7 +496,87 @@ __device__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS,
     N.parR = -1; N.parC = -1;
     N.flowR = 0.0; N.flowC = 0.0; N.cparR = 0.0; N.cparC = 0.0;
     wsync();
-    if constexpr (VOGEL) {
+    if constexpr (START == kStartLCM) {
+        // Least-cost (matrix minimum) start: each round fills the cheapest
+        // open cell (ties: lowest row, then lowest column) with all that its
+        // row or column has left and closes that line (the row when both run
+        // out); the last open row (column) takes every open column's
+        // remaining demand (row's remaining supply) and becomes the root.
+        // Each open row keeps its cheapest open cell; only the rows whose
+        // cheapest column closes look again.
+        double remR = pr, remC = pc;
+        uint64_t rowon = (T == 64) ? ~0ull : ((1ull << T) - 1ull);
+        uint64_t colon = (S == 64) ? ~0ull : ((1ull << S) - 1ull);
+        double m1 = INFINITY;
+        int j1 = GS;
+#pragma unroll
+        for (int j = 0; j < GS; ++j) {   // +inf beyond the support
+            const double c = cost_at<G, GS, LT>(N, tile, l, j);
+            const bool lt = c < m1;
+            m1 = lt ? c : m1;
+            j1 = lt ? j : j1;
+        }
+#pragma unroll 1
+        for (;;) {
+            const int nr = __popcll(rowon), nc = __popcll(colon);
+            if (nr == 1) {
+                const int a = __ffsll((long long)rowon) - 1;
+                if (l == a) {
+#pragma unroll
+                    for (int j = 0; j < GS; ++j) M.u.init.colcpar[j] = cost_at<G, GS, LT>(N, tile, l, j);
+                }
+                wsync();
+                if (hasC && ((colon >> l) & 1ull)) {
+                    N.parC = a; N.flowC = remC; N.cparC = M.u.init.colcpar[l];
+                }
+                break;
+            }
+            if (nc == 1) {
+                const int b = __ffsll((long long)colon) - 1;
+                if (hasR && ((rowon >> l) & 1ull)) {
+                    N.parR = b; N.flowR = remR; N.cparR = cost_pick<G, GS, LT>(N, tile, l, b);
+                }
+                break;
+            }
+            const bool open = hasR && ((rowon >> l) & 1ull);
+            double key = open ? m1 : INFINITY;
+            int kidx = open ? l * 64 + j1 : kNoKey;
+            group_argmin<G>(key, kidx);
+            const int a = kidx >> 6, b = kidx & 63;
+            const double ra0 = __shfl(remR, gbase + a, 64);
+            const double rb0 = __shfl(remC, gbase + b, 64);
+            const double x = ra0 < rb0 ? ra0 : rb0;
+            if (l == a) remR = ra0 - x;
+            if (l == b) remC = rb0 - x;
+            if (ra0 <= rb0) {
+                if (l == a) { N.parR = b; N.flowR = x; N.cparR = key; }
+                rowon &= ~(1ull << a);
+            } else {
+                if (l == b) { N.parC = a; N.flowC = x; N.cparC = key; }
+                colon &= ~(1ull << b);
+                if (open && j1 == b) {
+                    m1 = INFINITY;
+                    j1 = GS;
+#pragma unroll
+                    for (int j = 0; j < GS; ++j) {
+                        const double c = ((colon >> j) & 1ull) ? cost_at<G, GS, LT>(N, tile, l, j) : INFINITY;
+                        const bool lt = c < m1;
+                        m1 = lt ? c : m1;
+                        j1 = lt ? j : j1;
+                    }
+                }
+            }
+        }
+        wsync();
+        if (l < GS) M.u.init.colpar[l] = hasC ? N.parC : -1;
+        wsync();
+        N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0u;
+#pragma unroll
+        for (int c = 0; c < GS; ++c)
+            if (hasR && c < S && M.u.init.colpar[c] == l) N.bas |= (decltype(N.bas))1 << c;
+        wsync();
+        anc_by_jumping<G, GS, LT>(M, N, l, T, S);
+    } else if constexpr (START == kStartVogel) {
         // Vogel: close, one per round, the line whose two cheapest open cells
         // differ most (ties: rows first, lower index), filling its cheapest
         // open cell; the last open row (column) takes every open column's

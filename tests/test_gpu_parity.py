@@ -61,7 +61,7 @@ def run_assign(d2, h, X, Z, init=0, max_support=None, want_all=True):
             allv.cpu().numpy() if allv is not None else None, st.cpu().numpy())
 
 
-@pytest.mark.parametrize("init", [1, 2])
+@pytest.mark.parametrize("init", [1, 2, 3])
 def test_config1_full_assign(d2, h, init):
     """All 2,000 pairs of the plain FP64 configuration, plus labels."""
     X = synth.make_data(1)
@@ -76,7 +76,7 @@ def test_config1_full_assign(d2, h, init):
 
 
 @pytest.mark.parametrize("cfg,n,k", [(2, 120, 64), (3, 24, 20), (5, 20, 40)])
-@pytest.mark.parametrize("init", [1, 2])
+@pytest.mark.parametrize("init", [1, 2, 3])
 def test_config_shapes_assign(d2, h, cfg, n, k, init):
     """Config-shaped subsets: FP32 inputs (2, 3), d=128 (3), supports to 64 (5)."""
     X = synth.make_data(cfg, n=n)
@@ -88,13 +88,14 @@ def test_config_shapes_assign(d2, h, cfg, n, k, init):
     assert_labels(lab, o_lab, o_all, row_floor(X, Z))
 
 
-def test_group_widths_are_bitwise_identical(d2, h):
+@pytest.mark.parametrize("init", [1, 2, 3])
+def test_group_widths_are_bitwise_identical(d2, h, init):
     """The same pair gives the same bits whichever group width runs it."""
     X = synth.make_data(2, n=60)
     Z = synth.make_centroids(2, k=24)
-    ref = run_assign(d2, h, X, Z)
+    ref = run_assign(d2, h, X, Z, init=init)
     for ms in (32, 64):
-        got = run_assign(d2, h, X, Z, max_support=ms)
+        got = run_assign(d2, h, X, Z, init=init, max_support=ms)
         for a, b in zip(ref, got):
             assert np.array_equal(a, b)
 
@@ -191,7 +192,7 @@ def test_pairwise_tiny_and_empty(d2, h):
 def test_identical_distributions_give_exact_zero(d2, h):
     X = synth.make_data(5, n=30)
     pairs = np.stack([np.arange(30), np.arange(30)], 1)
-    for init in (1, 2):
+    for init in (1, 2, 3):
         dist, st, _, _ = d2.d2_emd_batch(h, dev(d2, X), dev(d2, X), torch.as_tensor(pairs),
                                          d2.Opts(init=init))
         torch.cuda.synchronize()
