@@ -17,6 +17,9 @@ FLAGS = [
     # hipcc forms the packed FP32 ops by itself otherwise; they are kept off.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    # the Vogel-start kernels keep an LDS cost tile, which caps their occupancy
+    # below the register target; that is expected
+    "-Wno-pass-failed",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -24,16 +24,21 @@ namespace d2 {
 // ------------------------------------------------------------------ shapes
 
 template <int CLS> struct Shape;
-template <> struct Shape<0> { static constexpr int G = 16, GS = 16, waves = 4; static constexpr bool LT = false; };
-template <> struct Shape<1> { static constexpr int G = 32, GS = 32, waves = 4; static constexpr bool LT = false; };
-template <> struct Shape<2> { static constexpr int G = 64, GS = 32, waves = 2; static constexpr bool LT = false; };
-template <> struct Shape<3> { static constexpr int G = 64, GS = 64, waves = 1; static constexpr bool LT = true; };
+// G: lanes per pair; GS: column capacity; waves per workgroup; occ: waves per
+// SIMD the register allocation is held to (the pivot loop waits on LDS and
+// lane exchanges, so more resident waves beat a few spilled registers:
+// measured best at 4 / 3 / 2 / 1).
+template <> struct Shape<0> { static constexpr int G = 16, GS = 16, waves = 4, occ = 4; static constexpr bool LT = false; };
+template <> struct Shape<1> { static constexpr int G = 32, GS = 32, waves = 4, occ = 3; static constexpr bool LT = false; };
+template <> struct Shape<2> { static constexpr int G = 64, GS = 32, waves = 2, occ = 2; static constexpr bool LT = false; };
+template <> struct Shape<3> { static constexpr int G = 64, GS = 64, waves = 1, occ = 1; static constexpr bool LT = true; };
 
 template <int CLS>
 struct ShapeCfg {
     static constexpr int G = Shape<CLS>::G, GS = Shape<CLS>::GS;
     static constexpr bool LT = Shape<CLS>::LT;
     static constexpr int threads = Shape<CLS>::waves * 64;
+    static constexpr int occ = Shape<CLS>::occ;
     static constexpr int groups = threads / G;
 };
 
@@ -127,7 +132,7 @@ __global__ void k_sort_scatter(KSet X, void *ws) {
 // Rows [row_lo, row_hi) of the (optionally permuted) row order, each against
 // centroid chunk c of `chunks`; one workgroup per (row, chunk) item.
 template <int CLS, typename TIn, int START>
-__global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_assign(
+__global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_assign(
     KSet X, KSet Z, KOpts o, const int64_t *perm, const int64_t *bounds, int cls_lo_idx,
     int64_t row_begin, int64_t row_end, int64_t chunks, int64_t per_chunk, int32_t *labels,
     double *best, double *all, int32_t *row_status, double *ws_best, int32_t *ws_label,
@@ -213,7 +218,7 @@ __global__ void k_assign_reduce(int64_t n, int64_t chunks, const double *ws_best
 // ------------------------------------------------------- explicit pairs
 
 template <int CLS, typename TIn, int START>
-__global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_emd_pairs(
+__global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_emd_pairs(
     KSet A, KSet B, const int64_t *pairs, int64_t npairs, KOpts o, double *dist,
     const int64_t *plan_off, double *plan, const int64_t *dual_off, double *duals, int32_t *status) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
@@ -287,7 +292,7 @@ __device__ __forceinline__ void class_item(int cls, int64_t k, int64_t n16, int6
 }
 
 template <int CLS, typename TIn, int START>
-__global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_pairwise_q(
+__global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_pairwise_q(
     KSet X, KOpts o, void *ws, int cls, int chunk, double *out, int32_t *status) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
@@ -339,7 +344,7 @@ __device__ __forceinline__ void condensed_ij(int64_t n, int64_t k, int64_t &i, i
 
 // Plain schedule: one shape for every pair, pairs in input order.
 template <int CLS, typename TIn, int START>
-__global__ __launch_bounds__(ShapeCfg<CLS>::threads) void k_pairwise_plain(KSet X, KOpts o, double *out,
+__global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_pairwise_plain(KSet X, KOpts o, double *out,
                                                                            int32_t *status) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
