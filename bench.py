@@ -92,6 +92,30 @@ def copy_calibration(mib: int) -> int:
 
 # ------------------------------------------------------------- workloads
 
+
+def _timed(fn, reps=2):
+    """Mean seconds of fn() over reps calls after one warm call (device-synchronised)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def _pinned_set(S):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a)).pin_memory() for a in (S.offsets, S.points, S.weights)]
+
+
+def _h2d(d2, host, dev_bufs, max_support):
+    for h, d in zip(host, dev_bufs):
+        d.copy_(h, non_blocking=True)
+    return d2.DeviceSet(dev_bufs[0], dev_bufs[1], dev_bufs[2], max_support)
+
+
 class AssignWorkload:
     """d2_assign of a configuration's objects against its centroids."""
 
@@ -127,6 +151,36 @@ class AssignWorkload:
 
     def failed(self):
         return int((self.out[3].cpu().numpy() != 0).sum())
+
+    def plain_baseline(self, rows=2000):
+        """The plain per-pair solver (one wavefront per pair in input order,
+        north-west corner, FP64 cost, no binning, no graph) on the first rows."""
+        d2 = self.d2
+        sub = self.X.subset(np.arange(min(rows, self.X.n)))
+        Xs = d2.DeviceSet.from_ragged(sub, "cuda:0")
+        opts = d2.Opts(init=d2.D2_INIT_NWC, schedule=d2.D2_SCHED_PLAIN, flags=d2.D2_FLAG_EAGER)
+        dt = _timed(lambda: d2.d2_assign(self.h, Xs, self.Zd, opts))
+        return {"value": sub.n * self.Z.n / dt, "unit": "distances/s",
+                "sample": f"first {sub.n} objects x all {self.Z.n} centroids"}
+
+    def end_to_end(self):
+        """One step with the objects copied in from pinned host memory and
+        labels and minima copied back (the centroids stay resident)."""
+        import torch
+        d2 = self.d2
+        host = _pinned_set(self.X)
+        bufs = [torch.empty_like(hh, device="cuda:0") for hh in host]
+        lab_h = torch.empty(self.X.n, dtype=torch.int32).pin_memory()
+        best_h = torch.empty(self.X.n, dtype=torch.float64).pin_memory()
+
+        def run():
+            Xd = _h2d(d2, host, bufs, self.Xd.max_support)
+            lab, best, _, _ = d2.d2_assign(self.h, Xd, self.Zd, self.opts)
+            lab_h.copy_(lab, non_blocking=True)
+            best_h.copy_(best, non_blocking=True)
+        dt = _timed(run)
+        return {"ms_per_step": dt * 1e3, "value": self.pairs / dt,
+                "input_bytes": int(sum(hh.numel() * hh.element_size() for hh in host))}
 
     def config(self):
         s = self.spec
@@ -211,6 +265,31 @@ class PairwiseWorkload:
 
     def failed(self):
         return int((self.out[1].cpu().numpy() != 0).sum())
+
+    def plain_baseline(self, objects=1024):
+        d2 = self.d2
+        sub = self.X.subset(np.arange(min(objects, self.X.n)))
+        Xs = d2.DeviceSet.from_ragged(sub, "cuda:0")
+        opts = d2.Opts(init=d2.D2_INIT_NWC, schedule=d2.D2_SCHED_PLAIN, flags=d2.D2_FLAG_EAGER)
+        dt = _timed(lambda: d2.d2_pairwise(self.h, Xs, opts))
+        return {"value": sub.n * (sub.n - 1) / 2 / dt, "unit": "distances/s",
+                "sample": f"all pairs of the first {sub.n} objects"}
+
+    def end_to_end(self):
+        import torch
+        d2 = self.d2
+        host = _pinned_set(self.X)
+        bufs = [torch.empty_like(hh, device="cuda:0") for hh in host]
+        out_h = torch.empty(self.pairs, dtype=torch.float64).pin_memory()
+
+        def run():
+            Xd = _h2d(d2, host, bufs, self.Xd.max_support)
+            out, _ = d2.d2_pairwise(self.h, Xd, self.opts)
+            out_h.copy_(out, non_blocking=True)
+        dt = _timed(run)
+        return {"ms_per_step": dt * 1e3, "value": self.pairs / dt,
+                "input_bytes": int(sum(hh.numel() * hh.element_size() for hh in host)),
+                "output_bytes": self.pairs * 8}
 
     def config(self):
         s = self.spec
@@ -407,6 +486,11 @@ def main(argv=None) -> int:
         },
         "failed_pairs_or_rows": w.failed(),
     }
+    if args.n is None:
+        out["end_to_end_with_copies"] = w.end_to_end()
+        plain = w.plain_baseline()
+        plain["speedup_of_value"] = out["value"] / plain["value"]
+        out["plain_solver"] = plain
     if not args.no_cpu_baseline:
         # the oracle has the north-west-corner and Vogel starts
         out["cpu_baseline"] = w.cpu_baseline(args.cpu_seconds, 1 if init == d2.D2_INIT_VOGEL else 0)

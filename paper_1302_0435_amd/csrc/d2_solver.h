@@ -324,7 +324,7 @@ __device__ __forceinline__ double cost_pick(const NodeState<G, GS, LT> &N, const
 // node indices in order (rows, then columns).  Also refreshes the LDS
 // mirrors read when pricing and when broadcasting the entering cell.
 template <int G, int GS, bool LT>
-__device__ void set_potentials(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int l, int T, int S) {
+__device__ __forceinline__ void set_potentials(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int l, int T, int S) {
     const bool hasR = l < T, hasC = l < S;
     const double sR = ((N.ancR.popc() - 1) & 1) ? -1.0 : 1.0;
     const double sC = ((N.ancC.popc() - 1) & 1) ? -1.0 : 1.0;
@@ -350,7 +350,7 @@ __device__ void set_potentials(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int 
 
 // Ancestor masks from parent pointers by pointer jumping (Vogel's tree).
 template <int G, int GS, bool LT>
-__device__ void anc_by_jumping(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int l, int T, int S) {
+__device__ __forceinline__ void anc_by_jumping(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int l, int T, int S) {
     const bool hasR = l < T, hasC = l < S;
     const int idR = l, idC = G + l;
     int jR = (hasR && N.parR >= 0) ? G + N.parR : idR;
@@ -394,9 +394,9 @@ struct SolveOut {
 // `ctile`, when given, is this pair's cost tile already computed (row-major,
 // 32 columns, oriented like the pair); otherwise costs come from the points.
 template <int G, int GS, bool LT, typename TIn, int START, typename TileT>
-__device__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS, LT> &N,
-                               const PairView &pv, int d, const KOpts &o, int l, int gbase,
-                               const float *ctile = nullptr) {
+__device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS, LT> &N,
+                                               const PairView &pv, int d, const KOpts &o, int l, int gbase,
+                                               const float *ctile = nullptr) {
     SolveOut out{kOk, __builtin_nan("")};
     const int T = pv.T, S = pv.S;
     if (T < 1 || S < 1 || T > G || S > GS) { out.status = kTooLarge; return out; }
@@ -918,8 +918,8 @@ __device__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS,
 
 // Dense plan (caller's orientation) and duals of a solved pair.
 template <int G, int GS, bool LT>
-__device__ void write_certificate(GroupMem<G, GS> &M, const NodeState<G, GS, LT> &N,
-                                  const PairView &pv, int l, double *plan, double *duals) {
+__device__ __forceinline__ void write_certificate(GroupMem<G, GS> &M, const NodeState<G, GS, LT> &N,
+                                                  const PairView &pv, int l, double *plan, double *duals) {
     const int T = pv.T, S = pv.S;
     const bool hasR = l < T, hasC = l < S;
     if (l < GS) {
