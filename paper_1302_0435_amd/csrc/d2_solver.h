@@ -190,34 +190,6 @@ __device__ __forceinline__ uint64_t group_bits(bool p, int gbase) {
     return (b >> gbase) & gm;
 }
 
-// Value of lane J of the group, to every lane of the group (J fixed at
-// compile time): DPP row broadcast for 16 lanes, lane reads otherwise.
-template <int G, int J>
-__device__ __forceinline__ int gbcast(int v, int gbase) {
-    if constexpr (G == 16) {
-        return __builtin_amdgcn_update_dpp(0, v, 0x150 + J, 0xF, 0xF, false);
-    } else if constexpr (G == 32) {
-        const int a = __builtin_amdgcn_readlane(v, J);
-        const int b = __builtin_amdgcn_readlane(v, 32 + J);
-        return gbase ? b : a;
-    } else {
-        return __builtin_amdgcn_readlane(v, J);
-    }
-}
-
-template <int G, int J>
-__device__ __forceinline__ double gbcast_widen(float v, int gbase) {
-    return (double)__int_as_float(gbcast<G, J>(__float_as_int(v), gbase));
-}
-
-template <int G, int J>
-__device__ __forceinline__ double gbcast_widen(double v, int gbase) {
-    const long long b = __double_as_longlong(v);
-    const int lo = gbcast<G, J>((int)(b & 0xffffffffll), gbase);
-    const int hi = gbcast<G, J>((int)(b >> 32), gbase);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 template <int J, int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
     if constexpr (J < N) {
@@ -228,9 +200,11 @@ __device__ __forceinline__ void static_for(F &&f) {
 
 // ------------------------------------------------------------ group memory
 
+constexpr int kStageK = 8;   // coordinates per LDS staging round of the cost rows
+
 template <int G, int GS>
 struct GroupMem {
-    double vpot[GS];         // column potentials, read by every row lane when pricing
+    alignas(16) double vpot[GS];  // column potentials, read by every row lane when pricing
     Mask<G> ancRm[G];        // ancestor masks of row nodes (mirror for broadcast)
     Mask<G> ancCm[GS];       // ancestor masks of column nodes
     double bc_r, bc_c;       // entering cell: reduced cost and cost
@@ -243,6 +217,7 @@ struct GroupMem {
         struct { int newpar[2 * G]; int stemtab[2 * G]; double newflow[2 * G];
                  double newcpar[2 * G]; } piv;
         struct { double obj[2 * G]; double colflow[GS]; int colpar[GS]; } fin;
+        struct { alignas(16) double y[GS][kStageK]; } stage;   // column points, KC coordinates
     } u;
 };
 
@@ -420,9 +395,11 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     pc = pc / sumc;
 
     // Cost row l, direct form: C_lj = sum_k (x_lk - y_jk)^2, k ascending.
-    // Lane l holds row point l and column point l; column point j reaches
-    // every lane of the group by a register broadcast.  Columns go in blocks
-    // of 16 to bound the registers in flight.
+    // Lane l holds row point l; column points pass through LDS, KC
+    // coordinates at a time, widened to FP64 once by the lane that owns the
+    // column and read back by every row lane as a broadcast.  The narrow
+    // shapes accumulate straight into the register row; the LDS-tile shape
+    // goes in blocks of 16 columns.
     const int Sw = wave_max<G>(S);
     if (ctile) {
         if constexpr (GS <= 32) {
@@ -436,43 +413,57 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     } else {
         const TIn *xr = (const TIn *)pv.xr + (int64_t)l * d;
         const TIn *yc = (const TIn *)pv.xc + (int64_t)l * d;
-        constexpr int KC = 4;
-        static_for<0, (GS + 15) / 16>([&](auto bc) {
-            constexpr int jb = decltype(bc)::value * 16;
+        constexpr int KC = kStageK;
+        constexpr int JB = LT ? 16 : GS;
+        static_for<0, GS / JB>([&](auto bc) {
+            constexpr int jb = decltype(bc)::value * JB;
+            double accl[LT ? JB : 1];
+            auto acc = [&](auto jc) -> double & {
+                if constexpr (LT) return accl[decltype(jc)::value];
+                else return N.crow[jb + decltype(jc)::value];
+            };
             if (jb < Sw) {
-                double acc[16];
-#pragma unroll
-                for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+                static_for<0, JB>([&](auto jc) { acc(jc) = 0.0; });
                 for (int k0 = 0; k0 < d; k0 += KC) {
-                    TIn xv[KC], yv[KC];
+                    double xd[KC];
 #pragma unroll
-                    for (int kk = 0; kk < KC; ++kk) {
-                        const bool in = k0 + kk < d;
-                        xv[kk] = (hasR && in) ? xr[k0 + kk] : (TIn)0;
-                        yv[kk] = (hasC && in) ? yc[k0 + kk] : (TIn)0;
+                    for (int q = 0; q < KC; ++q) {
+                        const bool in = k0 + q < d;
+                        xd[q] = (hasR && in) ? (double)xr[k0 + q] : 0.0;
+                        const double yv = (hasC && in) ? (double)yc[k0 + q] : 0.0;
+                        if (hasC) M.u.stage.y[l][q] = yv;
                     }
-                    static_for<0, 16>([&](auto jc) {
+                    wsync();
+                    static_for<0, JB>([&](auto jc) {
                         constexpr int j = decltype(jc)::value;
                         if (jb + j < Sw) {
+                            double yv[KC];
 #pragma unroll
-                            for (int kk = 0; kk < KC; ++kk) {
-                                if (k0 + kk < d) {
-                                    const double diff = (double)xv[kk] - gbcast_widen<G, jb + j>(yv[kk], gbase);
-                                    acc[j] = fma(diff, diff, acc[j]);
+                            for (int q = 0; q < KC; q += 2) {
+                                const double2 t = *(const double2 *)&M.u.stage.y[jb + j][q];
+                                yv[q] = t.x;
+                                yv[q + 1] = t.y;
+                            }
+#pragma unroll
+                            for (int q = 0; q < KC; ++q) {
+                                if (k0 + q < d) {
+                                    const double diff = xd[q] - yv[q];
+                                    acc(jc) = fma(diff, diff, acc(jc));
                                 }
                             }
                         }
                     });
+                    wsync();
                 }
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const double c = (hasR && jb + j < S) ? acc[j] : INFINITY;
+                static_for<0, JB>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    const double c = (hasR && jb + j < S) ? acc(jc) : INFINITY;
                     if constexpr (LT) tile.C[jb + j][l] = c;
                     else N.crow[jb + j] = c;
-                }
+                });
             } else {
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
+                for (int j = 0; j < JB; ++j) {
                     if constexpr (LT) tile.C[jb + j][l] = INFINITY;
                     else N.crow[jb + j] = INFINITY;
                 }
@@ -769,28 +760,50 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         double best = -delta, bestC = 0.0;
         int bidx = kNoKey;
         const double u = N.potR;
+        // Columns go in chunks of PC so that their loads are in flight
+        // together: the 64-lane shapes run few waves per SIMD and cannot
+        // hide the LDS latency otherwise (the narrow shapes gain nothing).
+        constexpr int PC = LT ? 8 : (G == 64 ? 4 : 1);
         if (!bland) {
 #pragma unroll
-            for (int j = 0; j < GS; ++j) {
-                if (j < Sw) {
-                    const double c = cost_at<G, GS, LT>(N, tile, l, j);
-                    const double r = (c - u) - M.vpot[j];
-                    const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < best);
-                    best = cand ? r : best;
-                    bestC = cand ? c : bestC;
-                    bidx = cand ? l * 64 + j : bidx;
+            for (int j0 = 0; j0 < GS; j0 += PC) {
+                if (j0 < Sw) {
+                    double cc[PC], vv[PC];
+#pragma unroll
+                    for (int q = 0; q < PC; ++q) {
+                        cc[q] = cost_at<G, GS, LT>(N, tile, l, j0 + q);
+                        vv[q] = M.vpot[j0 + q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < PC; ++q) {
+                        const int j = j0 + q;
+                        const double r = (cc[q] - u) - vv[q];
+                        const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < best);
+                        best = cand ? r : best;
+                        bestC = cand ? cc[q] : bestC;
+                        bidx = cand ? l * 64 + j : bidx;
+                    }
                 }
             }
         } else {
 #pragma unroll
-            for (int j = GS - 1; j >= 0; --j) {
-                if (j < Sw) {
-                    const double c = cost_at<G, GS, LT>(N, tile, l, j);
-                    const double r = (c - u) - M.vpot[j];
-                    const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < -delta);
-                    best = cand ? r : best;
-                    bestC = cand ? c : bestC;
-                    bidx = cand ? l * 64 + j : bidx;
+            for (int j0 = GS - PC; j0 >= 0; j0 -= PC) {
+                if (j0 < Sw) {
+                    double cc[PC], vv[PC];
+#pragma unroll
+                    for (int q = 0; q < PC; ++q) {
+                        cc[q] = cost_at<G, GS, LT>(N, tile, l, j0 + q);
+                        vv[q] = M.vpot[j0 + q];
+                    }
+#pragma unroll
+                    for (int q = PC - 1; q >= 0; --q) {
+                        const int j = j0 + q;
+                        const double r = (cc[q] - u) - vv[q];
+                        const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < -delta);
+                        best = cand ? r : best;
+                        bestC = cand ? cc[q] : bestC;
+                        bidx = cand ? l * 64 + j : bidx;
+                    }
                 }
             }
         }
