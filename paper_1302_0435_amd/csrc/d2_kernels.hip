@@ -398,6 +398,9 @@ __global__ void k_cost_tiles_f64(KSet A, KSet B, const int64_t *pairs, int64_t n
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+constexpr int kBfSteps = 16;      // MFMA k-steps (8 coordinates each) held in registers
+constexpr int kBfCentroids = 8;   // centroids per wavefront item, sharing the row's operands
+
 __device__ __forceinline__ unsigned short f32_to_bf16(float f) {  // round to nearest even
     unsigned int u = __float_as_uint(f);
     if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (unsigned short)((u >> 16) | 0x40u);  // NaN stays NaN
@@ -409,64 +412,127 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
     return __uint_as_float((unsigned int)h << 16);
 }
 
-// Cost tile of one oriented pair (both supports <= 32) by one wavefront:
-// C_ab = max(0, |x_a|^2 + |y_b|^2 - 2 x_a.y_b) with x, y rounded to BF16,
-// x.y by MFMA (32x32x8, FP32 accumulation), the squared norms summed in FP32
-// from the same rounded values.  Written row-major as 32 x 32 FP32 (rows
-// and columns beyond the supports hold the norms of zero vectors).
-// MFMA operand layout: lane l supplies row (l mod 32) of A and column
-// (l mod 32) of B for k = 4*(l div 32) .. +3; accumulator j of lane l is
-// D[8*(j div 4) + 4*(l div 32) + (j mod 4)][l mod 32].
+// MFMA operand fragments (v_mfma_f32_32x32x8_bf16) of one object's atoms for
+// coordinates [kc, kc + 8 kBfSteps): lane l supplies atom (l mod 32) and, at
+// step m, coordinates kc + 8m + 4(l div 32) .. +3, rounded FP32 -> BF16;
+// `norm` accumulates the squares of the rounded values in FP32, in that
+// order.  The same fragment serves as the A operand (atoms as rows) or the B
+// operand (atoms as columns).  All loads are issued before any rounding.
 template <typename TIn>
-__device__ void bf16_tile(const PairView &pv, int d, float *out, float *nx_lds) {
+__device__ __forceinline__ void bf16_frags(const TIn *pts, int natoms, int d, int kc,
+                                           bf16x4 (&f)[kBfSteps], float &norm) {
     const int l = threadIdx.x & 63, r = l & 31, h = l >> 5;
-    const bool rowok = r < pv.T, colok = r < pv.S;
-    const TIn *xr = (const TIn *)pv.xr + (int64_t)r * d;
-    const TIn *yc = (const TIn *)pv.xc + (int64_t)r * d;
-    f32x16 acc = {};
-    float nx = 0.f, ny = 0.f;
-    for (int k0 = 0; k0 < d; k0 += 8) {
-        bf16x4 a, b;
+    const bool ok = r < natoms;
+    const TIn *p = pts + (int64_t)(ok ? r : 0) * d;
+    float v[kBfSteps][4];
+    const bool vec = ((d & 3) == 0) && ((((uintptr_t)pts) & 15) == 0);
+    if (vec) {
+#pragma unroll
+        for (int m = 0; m < kBfSteps; ++m) {
+            const int k = kc + 8 * m + 4 * h;
+            if constexpr (sizeof(TIn) == 4) {
+                const float4 t = (ok && k < d) ? *(const float4 *)(p + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+                v[m][0] = t.x; v[m][1] = t.y; v[m][2] = t.z; v[m][3] = t.w;
+            } else {
+                const double2 z2 = make_double2(0.0, 0.0);
+                const double2 t0 = (ok && k < d) ? *(const double2 *)(p + k) : z2;
+                const double2 t1 = (ok && k < d) ? *(const double2 *)(p + k + 2) : z2;
+                v[m][0] = (float)t0.x; v[m][1] = (float)t0.y; v[m][2] = (float)t1.x; v[m][3] = (float)t1.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < kBfSteps; ++m)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = kc + 8 * m + 4 * h + q;
+                v[m][q] = (ok && k < d) ? (float)p[k] : 0.f;
+            }
+    }
+#pragma unroll
+    for (int m = 0; m < kBfSteps; ++m)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int k = k0 + 4 * h + q;
-            const float xv = (rowok && k < d) ? (float)xr[k] : 0.f;
-            const float yv = (colok && k < d) ? (float)yc[k] : 0.f;
-            const unsigned short xb = f32_to_bf16(xv), yb = f32_to_bf16(yv);
-            const float xq = bf16_to_f32(xb), yq = bf16_to_f32(yb);
-            nx = fmaf(xq, xq, nx);
-            ny = fmaf(yq, yq, ny);
-            a[q] = (short)xb;
-            b[q] = (short)yb;
+            const unsigned short b = f32_to_bf16(v[m][q]);
+            const float fq = bf16_to_f32(b);
+            norm = fmaf(fq, fq, norm);
+            f[m][q] = (short)b;
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    nx += __shfl_xor(nx, 32, 64);
-    ny += __shfl_xor(ny, 32, 64);
-    if (h == 0) nx_lds[r] = nx;
+}
+
+// acc += rows . cols over the steps of one coordinate round.
+__device__ __forceinline__ void bf16_mma(const bf16x4 (&rows)[kBfSteps], const bf16x4 (&cols)[kBfSteps],
+                                         int steps, f32x16 &acc) {
+#pragma unroll
+    for (int m = 0; m < kBfSteps; ++m)
+        if (m < steps) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(rows[m], cols[m], acc, 0, 0, 0);
+}
+
+// C_ab = max(0, |row a|^2 + |col b|^2 - 2 acc_ab) into a row-major 32 x 32
+// tile.  Accumulator j of lane l is entry (8 (j div 4) + 4 (l div 32) +
+// (j mod 4), l mod 32); rowN / colN are the squared norms of atom (l mod 32)
+// on the row / column side.  NaN passes through the clamp, to be flagged.
+__device__ __forceinline__ void bf16_epilogue(const f32x16 &acc, float rowN, float colN, float *out,
+                                              float *lds32) {
+    const int l = threadIdx.x & 63, r = l & 31, h = l >> 5;
+    if (h == 0) lds32[r] = rowN;
     wsync();
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int row = (j >> 2) * 8 + h * 4 + (j & 3);
-        const float c = (nx_lds[row] + ny) - 2.f * acc[j];
-        out[row * 32 + r] = c < 0.f ? 0.f : c;   // NaN passes through, to be flagged
+        const float c = (lds32[row] + colN) - 2.f * acc[j];
+        out[row * 32 + r] = c < 0.f ? 0.f : c;
     }
     wsync();
 }
 
-// Tiles for rows [r0, r1) against every centroid, one wavefront per pair:
-// tile of (row r, centroid j) at tiles + ((r - r0) * K + j) * 1024.
+// Tiles of rows [r0, r1) against every centroid, oriented like the solver
+// (rows = the larger support, ties: the object), row-major 32 x 32 FP32 at
+// tiles + ((r - r0) K + j) 1024.  One wavefront per (row, block of
+// kBfCentroids centroids); with d <= 8 kBfSteps the row's fragments and
+// norms stay in registers across the block.
 template <typename TIn>
 __global__ __launch_bounds__(256) void k_cost_bf16_assign(KSet X, KSet Z, int64_t r0, int64_t r1,
                                                           float *tiles) {
-    __shared__ float nx[4][32];
+    __shared__ float lds[4][32];
     const int w = threadIdx.x >> 6;
-    const int64_t K = Z.n, total = (r1 - r0) * K;
-    for (int64_t p = (int64_t)blockIdx.x * 4 + w; p < total; p += (int64_t)gridDim.x * 4) {
-        const int64_t i = r0 + p / K, j = p % K;
-        PairView pv = orient(X, i, Z, j, (int)sizeof(TIn));
-        if (pv.T < 1 || pv.S < 1 || pv.T > 32 || pv.S > 32) continue;
-        bf16_tile<TIn>(pv, X.d, tiles + p * 1024, nx[w]);
+    const int d = X.d;
+    const int64_t K = Z.n, nblk = (K + kBfCentroids - 1) / kBfCentroids, items = (r1 - r0) * nblk;
+    const bool cache = d <= 8 * kBfSteps;
+    for (int64_t it = (int64_t)blockIdx.x * 4 + w; it < items; it += (int64_t)gridDim.x * 4) {
+        const int64_t i = r0 + it / nblk, j0 = (it % nblk) * kBfCentroids;
+        const int64_t j1 = j0 + kBfCentroids < K ? j0 + kBfCentroids : K;
+        const int64_t a0 = X.off[i];
+        const int t = (int)(X.off[i + 1] - a0);
+        if (t < 1 || t > 32) continue;
+        const TIn *px = (const TIn *)X.pts + a0 * d;
+        bf16x4 fx[kBfSteps];
+        float nx = 0.f;
+        if (cache) {
+            bf16_frags<TIn>(px, t, d, 0, fx, nx);
+            nx += __shfl_xor(nx, 32, 64);
+        }
+        for (int64_t j = j0; j < j1; ++j) {
+            const int64_t b0 = Z.off[j];
+            const int s = (int)(Z.off[j + 1] - b0);
+            if (s < 1 || s > 32) continue;
+            const TIn *pz = (const TIn *)Z.pts + b0 * d;
+            const bool sw = t < s;
+            f32x16 acc = {};
+            float ny = 0.f, nxj = 0.f;
+            for (int kc = 0; kc < d; kc += 8 * kBfSteps) {
+                if (!cache) bf16_frags<TIn>(px, t, d, kc, fx, nxj);
+                bf16x4 fz[kBfSteps];
+                bf16_frags<TIn>(pz, s, d, kc, fz, ny);
+                const int steps = (d - kc + 7) / 8;
+                if (sw) bf16_mma(fz, fx, steps, acc);
+                else bf16_mma(fx, fz, steps, acc);
+            }
+            ny += __shfl_xor(ny, 32, 64);
+            if (!cache) nxj += __shfl_xor(nxj, 32, 64);
+            const float nxv = cache ? nx : nxj;
+            bf16_epilogue(acc, sw ? ny : nxv, sw ? nxv : ny, tiles + ((i - r0) * K + j) * 1024, lds[w]);
+        }
     }
 }
 
@@ -475,21 +541,39 @@ template <typename TIn>
 __global__ __launch_bounds__(256) void k_cost_bf16_pairs(KSet A, KSet B, const int64_t *pairs,
                                                          int64_t npairs, double *tiles,
                                                          const int64_t *tile_off) {
-    __shared__ float nx[4][32];
+    __shared__ float lds[4][32];
     __shared__ float tl[4][1024];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int d = A.d;
     for (int64_t k = (int64_t)blockIdx.x * 4 + w; k < npairs; k += (int64_t)gridDim.x * 4) {
         const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
         if (i < 0 || i >= A.n || j < 0 || j >= B.n) continue;
-        PairView pv = orient(A, i, B, j, (int)sizeof(TIn));
-        if (pv.T < 1 || pv.S < 1 || pv.T > 32 || pv.S > 32) continue;
-        bf16_tile<TIn>(pv, A.d, tl[w], nx[w]);
+        const int64_t a0 = A.off[i], b0 = B.off[j];
+        const int t = (int)(A.off[i + 1] - a0), s = (int)(B.off[j + 1] - b0);
+        if (t < 1 || s < 1 || t > 32 || s > 32) continue;
+        const TIn *pa = (const TIn *)A.pts + a0 * d;
+        const TIn *pb = (const TIn *)B.pts + b0 * d;
+        const bool sw = t < s;
+        f32x16 acc = {};
+        float na = 0.f, nb = 0.f;
+        for (int kc = 0; kc < d; kc += 8 * kBfSteps) {
+            bf16x4 fa[kBfSteps], fb[kBfSteps];
+            bf16_frags<TIn>(pa, t, d, kc, fa, na);
+            bf16_frags<TIn>(pb, s, d, kc, fb, nb);
+            const int steps = (d - kc + 7) / 8;
+            if (sw) bf16_mma(fb, fa, steps, acc);
+            else bf16_mma(fa, fb, steps, acc);
+        }
+        na += __shfl_xor(na, 32, 64);
+        nb += __shfl_xor(nb, 32, 64);
+        bf16_epilogue(acc, sw ? nb : na, sw ? na : nb, tl[w], lds[w]);
         double *dst = tiles + tile_off[k];
-        for (int c = l; c < pv.T * pv.S; c += 64) {
-            const int a = c / pv.S, b = c % pv.S;     // oriented row a, column b
+        const int T = sw ? s : t, S = sw ? t : s;   // oriented sizes
+        for (int c = l; c < T * S; c += 64) {
+            const int a = c / S, b = c % S;      // oriented row a, column b
             const double v = (double)tl[w][a * 32 + b];
-            if (!pv.swapped) dst[(int64_t)a * pv.S + b] = v;
-            else dst[(int64_t)b * pv.T + a] = v;
+            if (!sw) dst[(int64_t)a * S + b] = v;
+            else dst[(int64_t)b * T + a] = v;
         }
         wsync();
     }
@@ -622,8 +706,8 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
         float *tiles = (float *)((char *)ws + p.part_bytes);
         for (int64_t r0 = 0; r0 < X.n && e == hipSuccess; r0 += p.bf16_rows) {
             const int64_t r1 = r0 + p.bf16_rows < X.n ? r0 + p.bf16_rows : X.n;
-            const int64_t pairs = (r1 - r0) * Z.n;
-            const int64_t cg = (pairs + 3) / 4 < 65536 ? (pairs + 3) / 4 : 65536;
+            const int64_t items = (r1 - r0) * ((Z.n + kBfCentroids - 1) / kBfCentroids);
+            const int64_t cg = (items + 3) / 4 < 65536 ? (items + 3) / 4 : 65536;
             if (f32)
                 hipLaunchKernelGGL(k_cost_bf16_assign<float>, dim3((unsigned)cg), dim3(256), 0, c.stream,
                                    X, Z, r0, r1, tiles);
