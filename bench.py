@@ -28,9 +28,16 @@ if ROOT not in sys.path:
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+# Committed rocprofv3 summaries of each workload's dominant kernel, keyed by
+# (configuration, cost mode); the MFMA cost kernel of the BF16 mode has one
+# of its own.
 PROFILES = {
-    2: os.path.join(ROOT, "profiles", "k_assign_16_f32_c2_100k_x512.txt"),
+    (2, "f64"): "k_assign_cls0_f32_c2_100k_x512.txt",
+    (3, "f64"): "k_assign_cls1_f32_c3_50k_x256_d128.txt",
+    (3, "bf16"): "k_assign_cls1_f32_c3_bf16_tiles.txt",
+    (4, "f64"): "k_pairwise_q_cls2_f64_c4_4096.txt",
 }
+MFMA_PROFILES = {(3, "bf16"): "k_cost_bf16_assign_f32_c3_50k_x256_d128.txt"}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
                for f in ("d2_solver.h", "d2_kernels.hip")]
 
@@ -43,26 +50,41 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def profile_counters(cfg: int):
-    """HBM bytes and VALU busy of the dominant kernel from the committed
-    rocprofv3 summary, valid only while the kernel sources are unchanged."""
-    if cfg not in PROFILES:
-        return None
+def _read_profile(name):
+    kv = {}
     try:
-        kv = {}
-        for line in open(PROFILES[cfg]):
-            line = line.split("#", 1)[0].strip()
-            if "=" in line:
-                k, v = line.split("=", 1)
-                kv[k.strip()] = v.strip()
-        sha = kernel_sha()
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            first = f.readline()
+            for line in [first] + f.readlines():
+                body = line.split("#", 1)[0].strip()
+                if "=" in body:
+                    for part in body.split():
+                        if "=" in part:
+                            k, v = part.split("=", 1)
+                            kv[k] = v
+        kv["_kernel"] = first.lstrip("# ").strip()
     except OSError:
         return None
-    if kv.get("kernel_source_sha256_16") != sha:
+    return kv
+
+
+def profile_counters(cfg: int, cost: str):
+    """Counter figures of the dominant kernel from the committed rocprofv3
+    summary, valid only while the kernel sources are unchanged."""
+    kv = _read_profile(PROFILES.get((cfg, cost), ""))
+    if not kv or kv.get("kernel_source_sha256_16") != kernel_sha():
         return None
-    return {"traffic": float(kv["hbm_bytes_per_dispatch"]),
-            "valu_issue_busy": float(kv["valu_issue_busy_fraction"]),
-            "profile_avg_ms": float(kv["avg_duration_ns"]) / 1e6}
+    out = {"kernel": kv["_kernel"],
+           "traffic": float(kv["hbm_bytes_per_dispatch"]),
+           "valu_issue_busy": float(kv["valu_issue_busy_fraction"]),
+           "lds_util_percent": float(kv["lds_util_percent"]),
+           "profile_avg_ms": float(kv["avg_duration_ns"]) / 1e6}
+    mk = _read_profile(MFMA_PROFILES.get((cfg, cost), ""))
+    if mk and mk.get("kernel_source_sha256_16") == kernel_sha():
+        out["mfma"] = {"kernel": mk["_kernel"], "bf16_tflops": float(mk["mfma_bf16_tflops"]),
+                       "peak_tflops": 2500.0, "mfma_util_percent": float(mk["mfma_util_percent"]),
+                       "avg_ms": float(mk["avg_duration_ns"]) / 1e6}
+    return out
 
 
 def _cpu_model() -> str:
@@ -452,9 +474,8 @@ def main(argv=None) -> int:
     kernel_s = float(np.mean(kern_ms)) / 1e3
     flops = w.flops()
     achieved = flops / kernel_s / 1e12
-    prof = profile_counters(args.config) if (args.n is None and schedule == d2.D2_SCHED_AUTO
-                                              and init == d2.D2_INIT_AUTO
-                                              and args.cost == "f64") else None
+    prof = profile_counters(args.config, args.cost) if (args.n is None and schedule == d2.D2_SCHED_AUTO
+                                                         and init == d2.D2_INIT_AUTO) else None
     cfg = w.config()
     cfg.update({"init": args.init, "schedule": args.schedule, "cost": args.cost})
     bf16 = args.cost == "bf16"
@@ -477,7 +498,9 @@ def main(argv=None) -> int:
             "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
             "traffic": prof["traffic"] if prof else None,
+            "traffic_kernel": prof["kernel"] if prof else None,
             "valu_issue_busy": prof["valu_issue_busy"] if prof else None,
+            "lds_util_percent": prof["lds_util_percent"] if prof else None,
             "profile_kernel_ms": prof["profile_avg_ms"] if prof else None,
             "kernel_ms": float(np.mean(kern_ms)),
             "algorithmic_flops_per_launch": flops,
@@ -486,6 +509,8 @@ def main(argv=None) -> int:
         },
         "failed_pairs_or_rows": w.failed(),
     }
+    if prof and "mfma" in prof:
+        out["roofline"]["mfma_cost_kernel"] = prof["mfma"]
     if args.n is None:
         out["end_to_end_with_copies"] = w.end_to_end()
         plain = w.plain_baseline()

@@ -626,6 +626,9 @@ int class_threads(int cls) {
 
 // ---- labelling
 
+constexpr int kXcds = 8;                        // XCDs of the MI355X, each with its own L2
+constexpr size_t kXcdSplitBytes = 1u << 20;     // a quarter of one XCD's 4 MiB L2
+
 AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_count, int schedule,
                        int cost_mode) {
     AssignPlan p;
@@ -653,6 +656,15 @@ AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_
     const int64_t rows_per_launch = p.bf16 ? p.bf16_rows : X.n;
     int64_t chunks = rows_per_launch > 0 ? (2 * target + rows_per_launch - 1) / rows_per_launch : 1;
     if (!p.bf16) chunks = X.n > 0 ? (target + X.n - 1) / X.n : 1;
+    // XCD-aware split.  Workgroups are dealt to the 8 XCDs round-robin by
+    // index, and item = row * chunks + chunk, so with a multiple of 8 chunks
+    // every workgroup of one XCD works on the same eighth of the centroids,
+    // which then stays in that XCD's L2 instead of streaming from HBM once
+    // per row.  Used when the centroid points (bounded by K x max support x
+    // d) are more than a quarter of one L2.
+    const size_t zbytes = (size_t)K * (size_t)(zmax > 0 ? zmax : 1) * (size_t)(Z.d > 0 ? Z.d : 1) *
+                          (Z.dtype == D2_F32 ? 4u : 8u);
+    if (!p.bf16 && zbytes > kXcdSplitBytes) chunks = ((chunks + kXcds - 1) / kXcds) * kXcds;
     const int64_t max_chunks = (K + NG - 1) / NG;
     if (chunks > max_chunks) chunks = max_chunks;
     if (chunks < 1) chunks = 1;
