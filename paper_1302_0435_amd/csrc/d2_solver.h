@@ -218,6 +218,8 @@ struct GroupMem {
                  double newcpar[2 * G]; } piv;
         struct { double obj[2 * G]; double colflow[GS]; int colpar[GS]; } fin;
         struct { alignas(16) double y[GS][kStageK]; } stage;   // column points, KC coordinates
+        struct { unsigned long long key[GS]; int row[GS]; int shut[GS]; double x[GS]; double cost[GS];
+                 double remR[G]; double remC[GS]; double lastrow[GS]; unsigned long long gkey; } lcm;
     } u;
 };
 
@@ -488,18 +490,22 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     N.flowR = 0.0; N.flowC = 0.0; N.cparR = 0.0; N.cparC = 0.0;
     wsync();
     if constexpr (START == kStartLCM) {
-        // Least-cost (matrix minimum) start: each round fills the cheapest
-        // open cell (ties: lowest row, then lowest column) with all that its
-        // row or column has left and closes that line (the row when both run
-        // out); the last open row (column) takes every open column's
-        // remaining demand (row's remaining supply) and becomes the root.
-        // Each open row keeps its cheapest open cell; only the rows whose
-        // cheapest column closes look again.
-        double remR = pr, remC = pc;
-        uint64_t rowon = (T == 64) ? ~0ull : ((1ull << T) - 1ull);
-        uint64_t colon = (S == 64) ? ~0ull : ((1ull << S) - 1ull);
+        // Least-cost start, many cells per round.  Every open row proposes
+        // its cheapest open cell; for each column the cheapest proposal wins
+        // (ties: lowest row).  The winners share no row and no column, so
+        // they are filled together, each with all that its row or column has
+        // left, closing that line (the row when both run out).  A round that
+        // would close every open row or every open column takes only the
+        // cheapest proposal.  When one row (column) is left open it takes the
+        // remaining columns (rows) and becomes the root.  Rows rescan only
+        // when their cheapest column closes.
+        using LMask = typename std::conditional<(G <= 32 && GS <= 32), uint32_t, uint64_t>::type;
+        M.u.lcm.remR[l] = pr;
+        if (l < GS) M.u.lcm.remC[l] = pc;
+        LMask rowon = (LMask)((T == 64) ? ~0ull : ((1ull << T) - 1ull));
+        LMask colon = (LMask)((S == 64) ? ~0ull : ((1ull << S) - 1ull));
         double m1 = INFINITY;
-        int j1 = GS;
+        int j1 = 0;
 #pragma unroll
         for (int j = 0; j < GS; ++j) {   // +inf beyond the support
             const double c = cost_at<G, GS, LT>(N, tile, l, j);
@@ -507,54 +513,84 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
             m1 = lt ? c : m1;
             j1 = lt ? j : j1;
         }
+        // Every round closes at least one line, so T + S - 2 rounds suffice;
+        // the bound makes termination unconditional.
+        int rounds = 0;
 #pragma unroll 1
         for (;;) {
-            const int nr = __popcll(rowon), nc = __popcll(colon);
+            if (++rounds > T + S) { out.status = kPivotCap; return out; }
+            const int nr = __popcll((uint64_t)rowon), nc = __popcll((uint64_t)colon);
             if (nr == 1) {
-                const int a = __ffsll((long long)rowon) - 1;
+                const int a = __ffsll((long long)(uint64_t)rowon) - 1;
                 if (l == a) {
 #pragma unroll
-                    for (int j = 0; j < GS; ++j) M.u.init.colcpar[j] = cost_at<G, GS, LT>(N, tile, l, j);
+                    for (int j = 0; j < GS; ++j) M.u.lcm.lastrow[j] = cost_at<G, GS, LT>(N, tile, l, j);
                 }
                 wsync();
-                if (hasC && ((colon >> l) & 1ull)) {
-                    N.parC = a; N.flowC = remC; N.cparC = M.u.init.colcpar[l];
+                if (hasC && ((colon >> l) & 1u)) {
+                    N.parC = a; N.flowC = M.u.lcm.remC[l]; N.cparC = M.u.lcm.lastrow[l];
                 }
                 break;
             }
             if (nc == 1) {
-                const int b = __ffsll((long long)colon) - 1;
-                if (hasR && ((rowon >> l) & 1ull)) {
-                    N.parR = b; N.flowR = remR; N.cparR = cost_pick<G, GS, LT>(N, tile, l, b);
+                const int b = __ffsll((long long)(uint64_t)colon) - 1;
+                if (hasR && ((rowon >> l) & 1u)) {
+                    N.parR = b; N.flowR = M.u.lcm.remR[l]; N.cparR = cost_pick<G, GS, LT>(N, tile, l, b);
                 }
                 break;
             }
-            const bool open = hasR && ((rowon >> l) & 1ull);
-            double key = open ? m1 : INFINITY;
-            int kidx = open ? l * 64 + j1 : kNoKey;
-            group_argmin<G>(key, kidx);
-            const int a = kidx >> 6, b = kidx & 63;
-            const double ra0 = __shfl(remR, gbase + a, 64);
-            const double rb0 = __shfl(remC, gbase + b, 64);
-            const double x = ra0 < rb0 ? ra0 : rb0;
-            if (l == a) remR = ra0 - x;
-            if (l == b) remC = rb0 - x;
-            if (ra0 <= rb0) {
-                if (l == a) { N.parR = b; N.flowR = x; N.cparR = key; }
-                rowon &= ~(1ull << a);
-            } else {
-                if (l == b) { N.parC = a; N.flowC = x; N.cparC = key; }
-                colon &= ~(1ull << b);
-                if (open && j1 == b) {
-                    m1 = INFINITY;
-                    j1 = GS;
+            const bool open = hasR && ((rowon >> l) & 1u);
+            // Proposal key: the cost's bits (non-negative doubles order as
+            // integers) with the row in the low 6 bits, so one 64-bit
+            // minimum per column picks the cheapest, then the lowest row.
+            const unsigned long long key =
+                (((unsigned long long)__double_as_longlong(m1)) & ~63ull) | (unsigned long long)l;
+            if (l < GS) { M.u.lcm.key[l] = ~0ull; M.u.lcm.row[l] = -1; }
+            if (l == 0) M.u.lcm.gkey = ~0ull;
+            wsync();
+            if (open) atomicMin(&M.u.lcm.key[j1], key);
+            wsync();
+            bool won = open && M.u.lcm.key[j1] == key;
+            const double ra = M.u.lcm.remR[l], rb = M.u.lcm.remC[j1];
+            const bool closeRow = ra <= rb;
+            const int rclose = __popcll(group_bits<G>(won && closeRow, gbase));
+            const int cclose = __popcll(group_bits<G>(won && !closeRow, gbase));
+            if (rclose >= nr || cclose >= nc) {
+                // only the cheapest proposal this round: an exact integer
+                // minimum over the keys, which are distinct (they hold the row)
+                if (open) atomicMin(&M.u.lcm.gkey, key);
+                wsync();
+                won = open && M.u.lcm.gkey == key;
+            }
+            const double x = ra < rb ? ra : rb;
+            wsync();
+            if (won) {
+                // the only winner of row l and of column j1 this round
+                M.u.lcm.remR[l] = ra - x;
+                M.u.lcm.remC[j1] = rb - x;
+                if (closeRow) { N.parR = j1; N.flowR = x; N.cparR = m1; }
+                M.u.lcm.row[j1] = l;
+                M.u.lcm.x[j1] = x;
+                M.u.lcm.cost[j1] = m1;
+                M.u.lcm.shut[j1] = closeRow ? 0 : 1;
+            }
+            const LMask rshut = (LMask)group_bits<G>(won && closeRow, gbase);
+            wsync();
+            const bool cdone = hasC && l < GS && M.u.lcm.row[l] >= 0 && M.u.lcm.shut[l];
+            if (cdone) { N.parC = M.u.lcm.row[l]; N.flowC = M.u.lcm.x[l]; N.cparC = M.u.lcm.cost[l]; }
+            const LMask cshut = (LMask)group_bits<G>(cdone, gbase);
+            rowon &= ~rshut;
+            colon &= ~cshut;
+            wsync();
+            if (hasR && ((rowon >> l) & 1u) && ((cshut >> j1) & 1u)) {
+                m1 = INFINITY;
+                j1 = 0;
 #pragma unroll
-                    for (int j = 0; j < GS; ++j) {
-                        const double c = ((colon >> j) & 1ull) ? cost_at<G, GS, LT>(N, tile, l, j) : INFINITY;
-                        const bool lt = c < m1;
-                        m1 = lt ? c : m1;
-                        j1 = lt ? j : j1;
-                    }
+                for (int j = 0; j < GS; ++j) {
+                    const double c = ((colon >> j) & 1u) ? cost_at<G, GS, LT>(N, tile, l, j) : INFINITY;
+                    const bool lt = c < m1;
+                    m1 = lt ? c : m1;
+                    j1 = lt ? j : j1;
                 }
             }
         }
@@ -758,7 +794,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         // Pricing: most negative reduced cost (Bland: first negative cell).
         // Padding cells hold +inf, so every lane runs the same loop.
         double best = -delta, bestC = 0.0;
-        int bidx = kNoKey;
+        int bj = -1;   // column of the lane's best cell (the key is formed after the loop)
         const double u = N.potR;
         // Columns go in chunks of PC so that their loads are in flight
         // together: the 64-lane shapes run few waves per SIMD and cannot
@@ -781,7 +817,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
                         const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < best);
                         best = cand ? r : best;
                         bestC = cand ? cc[q] : bestC;
-                        bidx = cand ? l * 64 + j : bidx;
+                        bj = cand ? j : bj;
                     }
                 }
             }
@@ -802,13 +838,13 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
                         const bool cand = (((N.bas >> j) & 1u) == 0u) & (r < -delta);
                         best = cand ? r : best;
                         bestC = cand ? cc[q] : bestC;
-                        bidx = cand ? l * 64 + j : bidx;
+                        bj = cand ? j : bj;
                     }
                 }
             }
         }
         double key = bland ? 0.0 : best;
-        int kidx = bidx;
+        int kidx = bj >= 0 ? l * 64 + bj : kNoKey;
         group_argmin<G>(key, kidx);
         if (kidx == kNoKey) {
             if (fresh) break;
