@@ -426,14 +426,29 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
             };
             if (jb < Sw) {
                 static_for<0, JB>([&](auto jc) { acc(jc) = 0.0; });
+                // The next round's coordinates are loaded while this round
+                // computes (kept in the input type until used).
+                TIn xn[KC], yn[KC];
+#pragma unroll
+                for (int q = 0; q < KC; ++q) {
+                    const bool in = q < d;
+                    xn[q] = (hasR && in) ? xr[q] : (TIn)0;
+                    yn[q] = (hasC && in) ? yc[q] : (TIn)0;
+                }
                 for (int k0 = 0; k0 < d; k0 += KC) {
                     double xd[KC];
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
-                        const bool in = k0 + q < d;
-                        xd[q] = (hasR && in) ? (double)xr[k0 + q] : 0.0;
-                        const double yv = (hasC && in) ? (double)yc[k0 + q] : 0.0;
-                        if (hasC) M.u.stage.y[l][q] = yv;
+                        xd[q] = (double)xn[q];
+                        if (hasC) M.u.stage.y[l][q] = (double)yn[q];
+                    }
+                    if (k0 + KC < d) {
+#pragma unroll
+                        for (int q = 0; q < KC; ++q) {
+                            const bool in = k0 + KC + q < d;
+                            xn[q] = (hasR && in) ? xr[k0 + KC + q] : (TIn)0;
+                            yn[q] = (hasC && in) ? yc[k0 + KC + q] : (TIn)0;
+                        }
                     }
                     wsync();
                     static_for<0, JB>([&](auto jc) {
