@@ -812,9 +812,9 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         int bj = -1;   // column of the lane's best cell (the key is formed after the loop)
         const double u = N.potR;
         // Columns go in chunks of PC so that their loads are in flight
-        // together: the 64-lane shapes run few waves per SIMD and cannot
-        // hide the LDS latency otherwise (the narrow shapes gain nothing).
-        constexpr int PC = LT ? 8 : (G == 64 ? 4 : 1);
+        // together; the 64-lane shapes run few waves per SIMD and need the
+        // widest chunks to hide the LDS latency (measured: 8 / 4 / 2).
+        constexpr int PC = LT ? 8 : (G == 64 ? 4 : 2);
         if (!bland) {
 #pragma unroll
             for (int j0 = 0; j0 < GS; j0 += PC) {
