@@ -43,10 +43,16 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
 
 
 def kernel_sha() -> str:
+    """Hash of the kernel sources with comments and blank space removed, so
+    that a profile stays valid across edits that change no code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SRCS:
-        h.update(open(f, "rb").read())
+        text = open(f, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

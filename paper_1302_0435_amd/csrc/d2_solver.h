@@ -3,10 +3,10 @@
 // One pair (P, Q) is the LP of Eq. (1) with the centroid fixed (paper,
 // Sec. 1.1): minimise sum_ab w_ab |x_a - y_b|^2 over w >= 0 with row sums p
 // and column sums q.  The paper leaves the LP solver open; this file solves
-// it with the transportation simplex (u-v method): a starting basis (north-
-// west corner or Vogel), dual potentials u, v with u_a + v_b = C_ab on the
-// basis, pricing r_ab = C_ab - u_a - v_b, and pivots around the cycle that
-// the entering cell closes in the basis spanning tree.
+// it with the transportation simplex (u-v method): a starting basis (least
+// cost, north-west corner or Vogel), dual potentials u, v with u_a + v_b =
+// C_ab on the basis, pricing r_ab = C_ab - u_a - v_b, and pivots around the
+// cycle that the entering cell closes in the basis spanning tree.
 //
 // GPU mapping.  A "group" of G lanes (G = 16, 32 or 64; 64/G pairs per
 // wavefront) owns one pair at a time.  The pair is oriented so that rows are
@@ -33,7 +33,9 @@
 //
 // Group communication: reductions are butterflies over DPP row permutations
 // (16 lanes), plus a swizzle (32) and a lane permute (64); broadcasts go
-// through a few LDS words.
+// through a few LDS words, and the column points of the cost rows through an
+// LDS staging area.  All loops are bounded: the start by the number of lines,
+// the pivots by a cap that reports failure.
 //
 // Every arithmetic step that decides the result runs in an order that does
 // not depend on the shape (index-order sums, exact min/max reductions), so
