@@ -494,6 +494,7 @@ def main(argv=None) -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step_median": float(np.median(kern_ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
