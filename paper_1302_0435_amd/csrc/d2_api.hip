@@ -181,6 +181,7 @@ d2::Schedule schedule_for(d2_handle *h, const d2_set *X, const KOpts &k) {
             return t.sch;
     d2::Schedule s;
     for (int c = 0; c < 4; ++c) { s.blocks_per_cu[c] = 4; s.chunk[c] = 4; }
+    s.blocks_per_cu[3] = 8;   // one-wave workgroups, two per SIMD
     return s;
 }
 

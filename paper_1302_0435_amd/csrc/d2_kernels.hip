@@ -31,7 +31,7 @@ template <int CLS> struct Shape;
 template <> struct Shape<0> { static constexpr int G = 16, GS = 16, waves = 4, occ = 4; static constexpr bool LT = false; };
 template <> struct Shape<1> { static constexpr int G = 32, GS = 32, waves = 4, occ = 3; static constexpr bool LT = false; };
 template <> struct Shape<2> { static constexpr int G = 64, GS = 32, waves = 2, occ = 2; static constexpr bool LT = false; };
-template <> struct Shape<3> { static constexpr int G = 64, GS = 64, waves = 1, occ = 1; static constexpr bool LT = true; };
+template <> struct Shape<3> { static constexpr int G = 64, GS = 64, waves = 1, occ = 2; static constexpr bool LT = true; };
 
 template <int CLS>
 struct ShapeCfg {
@@ -42,9 +42,12 @@ struct ShapeCfg {
     static constexpr int groups = threads / G;
 };
 
+// LDS tile of a shape and start rule: Vogel's start scans columns and keeps
+// the whole tile; otherwise only the widest shape keeps its upper columns.
 template <int CLS, int START>
-using TileOf = typename std::conditional<(Shape<CLS>::LT || START == kStartVogel), Tile<Shape<CLS>::G, Shape<CLS>::GS>,
-                                         NoTile>::type;
+using TileOf = typename std::conditional<
+    START == kStartVogel, Tile<Shape<CLS>::G, Shape<CLS>::GS>,
+    typename std::conditional<Shape<CLS>::LT, TileHalf<Shape<CLS>::G, Shape<CLS>::GS>, NoTile>::type>::type;
 
 __host__ __device__ inline int class_of(int64_t T, int64_t S) {
     if (T <= 16) return 0;

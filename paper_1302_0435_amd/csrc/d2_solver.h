@@ -225,11 +225,19 @@ struct GroupMem {
     } u;
 };
 
-// Cost tile, column-major C[b][a], for the widest shape and for Vogel's
-// start (which scans columns).
+// Cost tile, column-major C[b][a], for Vogel's start (which scans columns).
 template <int G, int GS>
 struct Tile { double C[GS][G + 1]; };
 struct NoTile { char pad; };
+
+// The widest shape keeps columns [0, kSplitCols) of its cost row in
+// registers and the rest in this LDS tile (column-major, C[b - kSplitCols][a]),
+// which halves the LDS a pair needs and lets two wavefronts share a SIMD.
+constexpr int kSplitCols = 32;
+template <int G, int GS>
+struct TileHalf { double C[GS - kSplitCols][G]; };
+template <typename T> struct IsTileHalf : std::false_type {};
+template <int G, int GS> struct IsTileHalf<TileHalf<G, GS>> : std::true_type {};
 
 // Per-lane state: row node l, column node l, and row l of the cost tile.
 template <int G, int GS, bool LT>
@@ -240,7 +248,8 @@ struct NodeState {
     double potR, potC;       // u_l, v_l
     Mask<G> ancR, ancC;      // ancestors including the node itself
     typename std::conditional<GS == 64, uint64_t, uint32_t>::type bas;  // basic cells of row l
-    double crow[LT ? 1 : GS];  // C[l][j]; +inf beyond the columns and on rows beyond the support
+    double crow[LT ? kSplitCols : GS];  // C[l][j] (LDS-tile shape: j < kSplitCols); +inf beyond
+                                        // the columns and on rows beyond the support
 };
 
 template <typename T>
@@ -275,22 +284,41 @@ __device__ __forceinline__ PairView orient(const KSet &A, int64_t i, const KSet 
     return v;
 }
 
-// Cost of cell (l, j) from the lane's registers or the LDS tile; in
-// register mode j must be a compile-time index.
+// Cost of cell (l, j) from the lane's registers or the LDS tile; j must be
+// a compile-time index wherever it can select a register.
 template <int G, int GS, bool LT, typename TileT>
 __device__ __forceinline__ double cost_at(const NodeState<G, GS, LT> &N, const TileT &tile, int l, int j) {
-    if constexpr (LT) return tile.C[j][l];
+    if constexpr (LT && IsTileHalf<TileT>::value)
+        return j < kSplitCols ? N.crow[j < kSplitCols ? j : 0] : tile.C[j - kSplitCols][l];
+    else if constexpr (LT) return tile.C[j][l];
     else return N.crow[j];
 }
 
 template <int G, int GS, bool LT, typename TileT>
+__device__ __forceinline__ void put_cost(NodeState<G, GS, LT> &N, TileT &tile, int l, int j, double c) {
+    if constexpr (LT && IsTileHalf<TileT>::value) {
+        if (j < kSplitCols) N.crow[j < kSplitCols ? j : 0] = c;
+        else tile.C[j - kSplitCols][l] = c;
+    } else if constexpr (LT) {
+        tile.C[j][l] = c;
+    } else {
+        N.crow[j] = c;
+    }
+}
+
+// Cost of cell (l, j) for a run-time j.
+template <int G, int GS, bool LT, typename TileT>
 __device__ __forceinline__ double cost_pick(const NodeState<G, GS, LT> &N, const TileT &tile, int l, int j) {
-    if constexpr (LT) {
+    if constexpr (LT && !IsTileHalf<TileT>::value) {
         return tile.C[j][l];
     } else {
+        constexpr int RC = LT ? kSplitCols : GS;
+        if constexpr (LT) {
+            if (j >= RC) return tile.C[j - RC][l];
+        }
         double r = 0.0;
 #pragma unroll
-        for (int k = 0; k < GS; ++k) r = (k == j) ? N.crow[k] : r;
+        for (int k = 0; k < RC; ++k) r = (k == j) ? N.crow[k] : r;
         return r;
     }
 }
@@ -410,8 +438,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
 #pragma unroll
             for (int j = 0; j < GS; ++j) {
                 const double c = (hasR && j < S) ? (double)ctile[l * 32 + j] : INFINITY;
-                if constexpr (LT) tile.C[j][l] = c;
-                else N.crow[j] = c;
+                put_cost<G, GS, LT>(N, tile, l, j, c);
             }
         }
     } else {
@@ -477,14 +504,12 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
                 static_for<0, JB>([&](auto jc) {
                     constexpr int j = decltype(jc)::value;
                     const double c = (hasR && jb + j < S) ? acc(jc) : INFINITY;
-                    if constexpr (LT) tile.C[jb + j][l] = c;
-                    else N.crow[jb + j] = c;
+                    put_cost<G, GS, LT>(N, tile, l, jb + j, c);
                 });
             } else {
 #pragma unroll
                 for (int j = 0; j < JB; ++j) {
-                    if constexpr (LT) tile.C[jb + j][l] = INFINITY;
-                    else N.crow[jb + j] = INFINITY;
+                    put_cost<G, GS, LT>(N, tile, l, jb + j, INFINITY);
                 }
             }
         });
