@@ -202,7 +202,10 @@ __device__ __forceinline__ void static_for(F &&f) {
 
 // ------------------------------------------------------------ group memory
 
-constexpr int kStageK = 8;   // coordinates per LDS staging round of the cost rows
+// Coordinates per LDS staging round of the cost rows: 8 for the 32-lane
+// shape, 4 for the others, whose register budgets are tighter (measured).
+template <int G>
+constexpr int stage_k() { return G == 32 ? 8 : 4; }
 
 template <int G, int GS>
 struct GroupMem {
@@ -219,7 +222,7 @@ struct GroupMem {
         struct { int newpar[2 * G]; int stemtab[2 * G]; double newflow[2 * G];
                  double newcpar[2 * G]; } piv;
         struct { double obj[2 * G]; double colflow[GS]; int colpar[GS]; } fin;
-        struct { alignas(16) double y[GS][kStageK]; } stage;   // column points, KC coordinates
+        struct { alignas(16) double y[GS][stage_k<G>()]; } stage;   // column points, KC coordinates
         struct { unsigned long long key[GS]; int row[GS]; int shut[GS]; double x[GS]; double cost[GS];
                  double remR[G]; double remC[GS]; double lastrow[GS]; unsigned long long gkey; } lcm;
     } u;
@@ -444,7 +447,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     } else {
         const TIn *xr = (const TIn *)pv.xr + (int64_t)l * d;
         const TIn *yc = (const TIn *)pv.xc + (int64_t)l * d;
-        constexpr int KC = kStageK;
+        constexpr int KC = stage_k<G>();
         constexpr int JB = LT ? 16 : GS;
         static_for<0, GS / JB>([&](auto bc) {
             constexpr int jb = decltype(bc)::value * JB;
