@@ -9,6 +9,8 @@ with ctypes, and widens every input to FP64 exactly before the call.
     emd_batch(A, B, pairs)            -> (D^2[npairs], status, pivots)
     assign(X, Z)                      -> (labels, best, all[n,K], status, pivots)
     pairwise(X)                       -> (condensed D^2, status, pivots)
+    centroid_update(X, Z, labels)     -> (z_new, eps_step1, eps_step3, status)
+                                         (``update.py``: Alg. 2 Step 3*)
 
 Sets are ``synth.RaggedSet``-like objects with ``offsets``, ``points``,
 ``weights``.  Labels follow Alg. 2 Step 2 (argmin over centroids, ties to the
@@ -104,7 +106,9 @@ def emd_pair(x, p, y, q, init: int = INIT_NWC):
     st = lib.oracle_emd_pair(t, s, d, _p(x), _p(p), _p(y), _p(q), init, _p(d2), _p(plan), _p(u),
                              _p(v), _p(piv))
     if st != 0:
-        raise ArithmeticError(f"oracle status {st}")
+        err = ArithmeticError(f"oracle status {st}")
+        err.status = st
+        raise err
     return float(d2[0]), plan, u, v, int(piv[0])
 
 
@@ -168,3 +172,6 @@ def independent_coupling_cost(x, p, y, q) -> float:
     diff = x[:, None, :] - y[None, :, :]
     C = np.einsum("abk,abk->ab", diff, diff)
     return float(p @ C @ q)
+
+
+from .update import centroid_update  # noqa: E402  (uses emd_pair above)
