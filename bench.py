@@ -38,17 +38,21 @@ PROFILES = {
     (4, "f64"): "k_pairwise_q_cls2_f64_c4_4096.txt",
 }
 MFMA_PROFILES = {(3, "bf16"): "k_cost_bf16_assign_f32_c3_50k_x256_d128.txt"}
+# the centroid update's dominant kernel (--op update), keyed by configuration
+UPDATE_PROFILES = {2: "k_upd_solve_cls0_f32_c2_100k_x512.txt"}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
-               for f in ("d2_solver.h", "d2_kernels.hip")]
+               for f in ("d2_solver.h", "d2_shapes.h", "d2_kernels.hip")]
+UPDATE_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
+               for f in ("d2_solver.h", "d2_shapes.h", "d2_update.hip")]
 
 
-def kernel_sha() -> str:
+def kernel_sha(srcs=None) -> str:
     """Hash of the kernel sources with comments and blank space removed, so
     that a profile stays valid across edits that change no code."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in KERNEL_SRCS:
+    for f in (srcs or KERNEL_SRCS):
         text = open(f, encoding="utf-8").read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
@@ -74,11 +78,16 @@ def _read_profile(name):
     return kv
 
 
-def profile_counters(cfg: int, cost: str):
+def profile_counters(cfg: int, cost: str, op: str = "assign"):
     """Counter figures of the dominant kernel from the committed rocprofv3
     summary, valid only while the kernel sources are unchanged."""
-    kv = _read_profile(PROFILES.get((cfg, cost), ""))
-    if not kv or kv.get("kernel_source_sha256_16") != kernel_sha():
+    if op == "update":
+        kv = _read_profile(UPDATE_PROFILES.get(cfg, ""))
+        sha = kernel_sha(UPDATE_SRCS)
+    else:
+        kv = _read_profile(PROFILES.get((cfg, cost), ""))
+        sha = kernel_sha()
+    if not kv or kv.get("kernel_source_sha256_16") != sha:
         return None
     out = {"kernel": kv["_kernel"],
            "traffic": float(kv["hbm_bytes_per_dispatch"]),
@@ -355,6 +364,96 @@ class PairwiseWorkload:
                 "parity_checked": len(p), "parity_failures": fails, "cpu_model": _cpu_model()}
 
 
+class UpdateWorkload:
+    """d2_centroid_update: one pass of the constrained D2 centroid update
+    (Alg. 2 Step 3*) over a configuration's objects, each against its own
+    centroid (centroid weights uniform, 1/s).  The labels are the nearest
+    centroids, from one d2_assign in the untimed set-up."""
+
+    metric = "constrained D2 centroid update: objects/sec (member LP + Eq. (2) mean + objective)"
+    unit = "objects/s"
+
+    def __init__(self, cfg, d2, dev, init, schedule, n=None):
+        import synth
+        import torch
+        self.cfg = cfg
+        self.spec = synth.CONFIGS[cfg]
+        self.X = synth.make_data(cfg, n=n)
+        Z = synth.make_centroids(cfg)
+        w = np.concatenate([np.full(int(t), 1.0 / int(t)) for t in np.diff(Z.offsets)])
+        self.Z = synth.RaggedSet(Z.offsets, Z.points, w.astype(Z.points.dtype))
+        self.d2 = d2
+        self.h = d2.Handle(0)
+        self.Xd = d2.DeviceSet.from_ragged(self.X, dev)
+        self.Zd = d2.DeviceSet.from_ragged(self.Z, dev)
+        self.opts = d2.Opts(init=init, schedule=schedule)
+        self.labels = d2.d2_assign(self.h, self.Xd, self.Zd, d2.Opts(init=init))[0]
+        torch.cuda.synchronize()
+        self.pairs = self.X.n
+        self.out = None
+
+    def step(self):
+        self.out = self.d2.d2_centroid_update(self.h, self.Xd, self.Zd, self.labels, self.opts)
+
+    def flops(self):
+        """Pivot-free work of the member problems: per member the ground-cost
+        tile (3 t s d) plus one certifying pricing pass (3 t s)."""
+        lab = self.labels.cpu().numpy()
+        ts = np.diff(self.X.offsets).astype(np.float64)
+        ss = np.diff(self.Z.offsets).astype(np.float64)[lab]
+        return float((ts * ss).sum() * (3 * self.X.points.shape[1] + 3))
+
+    def bytes(self):
+        X, Z = self.X, self.Z
+        return float(X.points.nbytes + X.weights.nbytes + X.offsets.nbytes + 2 * Z.points.nbytes +
+                     Z.weights.nbytes + Z.offsets.nbytes + X.n * (4 + 4) + Z.n * 20)
+
+    def failed(self):
+        return int((self.out[4].cpu().numpy() != 0).sum())
+
+    def config(self):
+        s = self.spec
+        return {"workload": s["name"] + " centroid update", "n": self.X.n, "k": self.Z.n,
+                "d": self.X.points.shape[1], "t_range": list(s["t_range"]), "s": s["s"],
+                "inputs": s["dtype"], "centroid_weights": "uniform", "objects_per_step": self.X.n}
+
+    def cpu_baseline(self, target_s, init_oracle):
+        """The oracle's centroid update on the members of a seeded sample of
+        clusters; also checks the device's moved atoms and objectives there."""
+        import oracle
+        import synth
+        X, Z = self.X, self.Z
+        lab = self.labels.cpu().numpy()
+        z, e1, e3 = (t.cpu().numpy() for t in self.out[:3])
+        order = synth.rng_for(self.cfg, synth.STREAM_SAMPLE, 300).permutation(Z.n)
+
+        def run(k):
+            pick = order[:k]
+            rows = np.flatnonzero(np.isin(lab, pick))
+            sub = X.subset(rows)
+            t0 = time.perf_counter()
+            res = oracle.centroid_update(sub, Z, lab[rows], init=init_oracle)
+            return pick, rows, res, time.perf_counter() - t0
+
+        _, rows, _, dt = run(2)
+        per_obj = dt / max(len(rows), 1)
+        k = int(min(Z.n, max(2, target_s / max(per_obj, 1e-9) / max(X.n / Z.n, 1))))
+        pick, rows, (oz, oe1, oe3, ost), dt = run(k)
+        fails = 0
+        M = float(np.abs(X.points).max())
+        for j in pick:
+            a0, a1 = int(Z.offsets[j]), int(Z.offsets[j + 1])
+            if np.abs(z[a0:a1] - oz[a0:a1]).max() > 1e-10 * M:
+                fails += 1
+            elif abs(e3[j] - oe3[j]) > 1e-10 * abs(oe3[j]) + 1e-14 * abs(oe1[j]):
+                fails += 1
+        return {"value": len(rows) / dt, "unit": "objects/s", "cores": 1, "kind": "oracle",
+                "sample": f"members of {len(pick)} seeded clusters ({len(rows)} objects), "
+                          f"{dt:.1f} s, {'Vogel' if init_oracle else 'north-west-corner'} start",
+                "cpu_model": _cpu_model(), "parity_checked_clusters": len(pick),
+                "parity_failures": fails}
+
+
 def make_pool(n_pool: int):
     """Query pool for the serving workload (configuration 5, stream 1)."""
     import synth
@@ -432,6 +531,8 @@ def main(argv=None) -> int:
     ap.add_argument("--cost", choices=["f64", "bf16"], default="f64",
                     help="ground-cost arithmetic (bf16: MFMA tiles, supports <= 32)")
     ap.add_argument("--tune", action="store_true", help="autotune the pairwise schedule first")
+    ap.add_argument("--op", choices=["assign", "update"], default="assign",
+                    help="update: the constrained D2 centroid update (configurations 1-3)")
     ap.add_argument("--n", type=int, default=None, help="override object count (testing)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -455,7 +556,12 @@ def main(argv=None) -> int:
     init = {"auto": d2.D2_INIT_AUTO, "nwc": d2.D2_INIT_NWC, "vogel": d2.D2_INIT_VOGEL,
             "lcm": d2.D2_INIT_LCM}[args.init]
     schedule = d2.D2_SCHED_PLAIN if args.schedule == "plain" else d2.D2_SCHED_AUTO
-    if args.config == 4:
+    if args.op == "update":
+        if args.config not in (1, 2, 3) or args.cost != "f64":
+            print("--op update runs configurations 1-3 with the FP64 cost", file=sys.stderr)
+            return 2
+        w = UpdateWorkload(args.config, d2, dev, init, schedule, n=args.n)
+    elif args.config == 4:
         w = PairwiseWorkload(4, d2, dev, init, schedule, n=args.n, tune=args.tune)
     else:
         w = AssignWorkload(args.config, d2, dev, init, schedule, n=args.n,
@@ -480,16 +586,17 @@ def main(argv=None) -> int:
     kernel_s = float(np.mean(kern_ms)) / 1e3
     flops = w.flops()
     achieved = flops / kernel_s / 1e12
-    prof = profile_counters(args.config, args.cost) if (args.n is None and schedule == d2.D2_SCHED_AUTO
-                                                         and init == d2.D2_INIT_AUTO) else None
+    prof = profile_counters(args.config, args.cost, args.op) if (
+        args.n is None and schedule == d2.D2_SCHED_AUTO and init == d2.D2_INIT_AUTO) else None
     cfg = w.config()
     cfg.update({"init": args.init, "schedule": args.schedule, "cost": args.cost})
     bf16 = args.cost == "bf16"
+    metric = ("Mallows distances/sec, BF16-MFMA ground cost + FP64 simplex (approximate)"
+              if bf16 else "exact Mallows distances/sec at <=1e-10 rel err vs FP64 oracle")
     out = {
-        "metric": ("Mallows distances/sec, BF16-MFMA ground cost + FP64 simplex (approximate)"
-                   if bf16 else "exact Mallows distances/sec at <=1e-10 rel err vs FP64 oracle"),
+        "metric": getattr(w, "metric", metric),
         "value": w.pairs * args.steps / wall,
-        "unit": "distances/s",
+        "unit": getattr(w, "unit", "distances/s"),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -518,7 +625,7 @@ def main(argv=None) -> int:
     }
     if prof and "mfma" in prof:
         out["roofline"]["mfma_cost_kernel"] = prof["mfma"]
-    if args.n is None:
+    if args.n is None and args.op == "assign":
         out["end_to_end_with_copies"] = w.end_to_end()
         plain = w.plain_baseline()
         plain["speedup_of_value"] = out["value"] / plain["value"]

@@ -88,7 +88,9 @@ enum {
     D2_PAIR_BAD_WEIGHTS = 1, /* a weight is NaN/inf/negative, or the sum is <= 0 */
     D2_PAIR_TOO_LARGE = 2,   /* empty support or more than D2_MAX_SUPPORT atoms   */
     D2_PAIR_PIVOT_CAP = 3,   /* pivot cap reached; the value is NaN               */
-    D2_PAIR_BAD_POINTS = 4   /* a ground cost is not finite (NaN/inf coordinates) */
+    D2_PAIR_BAD_POINTS = 4,  /* a ground cost is not finite (NaN/inf coordinates) */
+    D2_PAIR_UNLABELLED = 5   /* d2_centroid_update: label outside [0, K); the     *
+                              * object is left out                                 */
 };
 
 /* A ragged set of n discrete distributions in R^d (device memory). */
@@ -140,8 +142,8 @@ const char *d2_version(void);
 
 /* Bytes of device workspace the call with these arguments needs (may be 0).
  * `which` is 0 = d2_cost_tiles, 1 = d2_emd_batch, 2 = d2_assign,
- * 3 = d2_pairwise; `npairs` is the pair count for 0 and 1, ignored otherwise;
- * B may be NULL for d2_pairwise. */
+ * 3 = d2_pairwise, 4 = d2_centroid_update (A = X, B = Z); `npairs` is the
+ * pair count for 0 and 1, ignored otherwise; B may be NULL for d2_pairwise. */
 size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set *B,
                           int64_t npairs, const d2_opts *opts);
 
@@ -176,6 +178,41 @@ d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int
 d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opts *opts,
                     int32_t *labels, double *best, double *all, int32_t *row_status, void *ws,
                     size_t ws_bytes, void *stream);
+
+/* Centroid update of constrained D2-clustering (Alg. 2 Step 3*: the update
+ * of Alg. 1 with every centroid's weights held fixed), one pass over all
+ * clusters.  With the weights fixed, the LP of Alg. 1 Step 1 separates into
+ * one transport problem per member (Sec. 2.2), so the pass is:
+ *   Step 1  for each object i with 0 <= labels[i] < K: the optimal plan
+ *           w^(i) between X_i and Z_{labels[i]} (Eq. (1), centroid fixed);
+ *   Step 2  every atom r of centroid j moves to the mean of its members'
+ *           atoms weighted by their flows to r (Eq. (2));
+ *   Step 3  the objective of Eq. (1) with the moved atoms and the Step 1
+ *           plans.
+ * The centroid weights are not changed: uniform 1/s_j is the paper's case;
+ * any fixed non-negative weights are accepted (normalised by their sum).
+ *   labels[n]      device int32, e.g. from d2_assign.  Objects whose label is
+ *                  outside [0, K) are left out (status D2_PAIR_UNLABELLED).
+ *   z_new          device FP64 [Z.offsets[K]][d]: the moved atoms, in the
+ *                  layout of Z.points, which it must not overlap.  An atom
+ *                  that receives no flow (empty cluster, zero weight) keeps
+ *                  its coordinates.
+ *   eps_step1[K]   device FP64, nullable: sum of the members' D^2 to the old
+ *                  atoms (the Step 1 objective).
+ *   eps_step3[K]   device FP64, nullable: the Step 3 objective.
+ *   counts[K]      device int32, nullable: members that entered Step 2.
+ *   obj_status[n]  device int32, nullable: D2_PAIR_* of each object; an
+ *                  object whose transport problem fails is left out of
+ *                  Steps 2 and 3.  Supports above the declared max_support of
+ *                  X or Z give D2_PAIR_TOO_LARGE.
+ * Workspace: d2_workspace_bytes(h, 4, X, Z, 0, opts) bytes (required).
+ * Sums run in a fixed order, so repeated calls give identical bits.  FP64
+ * direct cost only (D2_COST_BF16_MFMA: D2_EUNSUPPORTED); opts->want_sqrt is
+ * ignored.  Always enqueued directly (no graph is recorded). */
+d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *labels,
+                             const d2_opts *opts, double *z_new, double *eps_step1, double *eps_step3,
+                             int32_t *counts, int32_t *obj_status, void *ws, size_t ws_bytes,
+                             void *stream);
 
 /* All unordered pairs i<j of one set (one segment's pairwise matrix):
  * condensed[k] for k = i*n - i*(i+1)/2 + (j-i-1), the order of

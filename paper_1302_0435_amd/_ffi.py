@@ -17,13 +17,14 @@ D2_COST_F64_DIRECT, D2_COST_BF16_MFMA = 0, 1
 D2_INIT_AUTO, D2_INIT_NWC, D2_INIT_VOGEL, D2_INIT_LCM = 0, 1, 2, 3
 D2_SCHED_AUTO, D2_SCHED_PLAIN = 0, 1
 D2_FLAG_EAGER = 1
-D2_PAIR_OK, D2_PAIR_BAD_WEIGHTS, D2_PAIR_TOO_LARGE, D2_PAIR_PIVOT_CAP, D2_PAIR_BAD_POINTS = range(5)
-WHICH_COST_TILES, WHICH_EMD_BATCH, WHICH_ASSIGN, WHICH_PAIRWISE = range(4)
+(D2_PAIR_OK, D2_PAIR_BAD_WEIGHTS, D2_PAIR_TOO_LARGE, D2_PAIR_PIVOT_CAP, D2_PAIR_BAD_POINTS,
+ D2_PAIR_UNLABELLED) = range(6)
+WHICH_COST_TILES, WHICH_EMD_BATCH, WHICH_ASSIGN, WHICH_PAIRWISE, WHICH_UPDATE = range(5)
 
 # Every function the header declares (checked against the header by the tests).
 EXPORTS = ["d2_create", "d2_destroy", "d2_status_string", "d2_max_support", "d2_version",
            "d2_workspace_bytes", "d2_cost_tiles", "d2_emd_batch", "d2_assign", "d2_pairwise",
-           "d2_tune_pairwise"]
+           "d2_tune_pairwise", "d2_centroid_update"]
 
 
 class d2_set(ctypes.Structure):
@@ -72,8 +73,9 @@ def lib():
     L.d2_assign.argtypes = [P, S, S, O, P, P, P, P, P, SZ, P]
     L.d2_pairwise.argtypes = [P, S, O, P, P, P, SZ, P]
     L.d2_tune_pairwise.argtypes = [P, S, O, P, P, P, SZ, P, ctypes.POINTER(ctypes.c_double)]
+    L.d2_centroid_update.argtypes = [P, S, S, P, O, P, P, P, P, P, P, SZ, P]
     for name in ("d2_create", "d2_destroy", "d2_cost_tiles", "d2_emd_batch", "d2_assign",
-                 "d2_pairwise", "d2_max_support", "d2_tune_pairwise"):
+                 "d2_pairwise", "d2_max_support", "d2_tune_pairwise", "d2_centroid_update"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -11,6 +11,8 @@ the stream.
     dist, status = d2_emd_batch(h, A, B, pairs)[:2]
     condensed, status = d2_pairwise(h, X)
     tiles, tile_offsets = d2_cost_tiles(h, A, B, pairs)
+    z_new, eps1, eps3, counts, status = d2_centroid_update(h, X, Z, labels)
+    Z, labels, history = constrained_d2(h, X, Z0)      # Alg. 2 with Step 3*
 """
 from __future__ import annotations
 
@@ -60,6 +62,12 @@ class DeviceSet:
         w = torch.as_tensor(s.weights).to(pts.dtype)
         return cls(off.to(device), pts.reshape(off[-1].item() if off.numel() else 0, -1)
                    .contiguous().to(device), w.contiguous().to(device), max(ms, 1))
+
+    def with_points(self, points: torch.Tensor) -> "DeviceSet":
+        """The same supports and weights at new atom coordinates (the weights
+        are converted to the points' dtype)."""
+        return DeviceSet(self.offsets, points.contiguous(),
+                         self.weights.to(points.dtype).contiguous(), self.max_support)
 
     def c(self) -> _ffi.d2_set:
         if self.points.dtype == torch.float64:
@@ -253,3 +261,68 @@ def d2_cost_tiles(h: Handle, A: DeviceSet, B: DeviceSet, pairs: torch.Tensor,
                                    cost_mode, _ptr(tiles), _ptr(off), _ptr(ws), nbytes,
                                    _stream(dev)), "d2_cost_tiles")
     return tiles, off
+
+
+def d2_centroid_update(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch.Tensor,
+                       opts: Optional[Opts] = None):
+    """One pass of the constrained D2 centroid update (Alg. 2 Step 3*).
+
+    Returns z_new [Z.offsets[K], d] f64, eps_step1 [K] f64, eps_step3 [K] f64,
+    counts [K] int32, status [n] int32 (see d2_centroid_update in d2.h)."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    labels = labels.to(device=dev, dtype=torch.int32).contiguous()
+    K = Z.n
+    z_new = torch.empty((int(Z.points.shape[0]), Z.d), dtype=torch.float64, device=dev)
+    eps1 = torch.empty(K, dtype=torch.float64, device=dev)
+    eps3 = torch.empty(K, dtype=torch.float64, device=dev)
+    counts = torch.empty(K, dtype=torch.int32, device=dev)
+    status = torch.empty(X.n, dtype=torch.int32, device=dev)
+    ws, nbytes = _workspace(h, _ffi.WHICH_UPDATE, X, Z, 0, opts)
+    x, z, o = X.c(), Z.c(), opts.c()
+    check(_ffi.lib().d2_centroid_update(h.ptr, ctypes.byref(x), ctypes.byref(z), _ptr(labels),
+                                        ctypes.byref(o), _ptr(z_new), _ptr(eps1), _ptr(eps3),
+                                        _ptr(counts), _ptr(status), _ptr(ws), nbytes,
+                                        _stream(dev)), "d2_centroid_update")
+    return z_new, eps1, eps3, counts, status
+
+
+def constrained_d2(h: Handle, X: DeviceSet, Z: DeviceSet, opts: Optional[Opts] = None,
+                   max_rounds: int = 20, max_passes: int = 10, rtol: float = 1e-9):
+    """Constrained D2-clustering (Alg. 2 with Step 3* in place of Step 3).
+
+    Each round labels every object by its nearest centroid (Step 2, d2_assign),
+    then repeats the fixed-weight centroid update (Step 3*, d2_centroid_update)
+    until its objective changes by at most rtol relative (Alg. 1 Step 3); the
+    rounds stop when the clustering objective eps(C) = sum_j eps_j does
+    (Step 4).  The centroid weights are kept as given (uniform in the paper).
+    Host control only: every step runs in the library.  FP32 inputs are
+    widened to FP64 once, since the moved atoms are FP64.
+
+    Returns (Z, labels, history) with history a list of (round, passes,
+    eps(C)) tuples.
+    """
+    if X.points.dtype != torch.float64:
+        X = X.with_points(X.points.double())
+    if Z.points.dtype != torch.float64:
+        Z = Z.with_points(Z.points.double())
+    history = []
+    labels = None
+    prev_round = None
+    for rnd in range(max_rounds):
+        labels, _, _, row_status = d2_assign(h, X, Z, opts)                 # Step 2
+        prev = None
+        passes = 0
+        eps = None
+        for passes in range(1, max_passes + 1):                              # Step 3*
+            z_new, _, eps3, _, _ = d2_centroid_update(h, X, Z, labels, opts)
+            Z = Z.with_points(z_new)
+            eps = float(eps3.sum().item())
+            if prev is not None and abs(prev - eps) <= rtol * max(abs(eps), 1e-300):
+                break
+            prev = eps
+        history.append((rnd, passes, eps))
+        if prev_round is not None and abs(prev_round - eps) <= rtol * max(abs(eps), 1e-300):
+            break                                                            # Step 4
+        prev_round = eps
+    return Z, labels, history

@@ -247,6 +247,7 @@ size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set
                                opts ? opts->cost_mode : D2_COST_F64_DIRECT).ws_bytes;
     }
     if (which == 3) return d2::plan_pairwise(kset(A), ms(A), sched).ws_bytes;
+    if (which == 4 && B && set_ok(B)) return d2::update_ws_bytes(A->n, B->n, ms(A), ms(B));
     return 0;
 }
 
@@ -324,6 +325,30 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
     return run_graph(h, 2, key, eager_of(opts), (hipStream_t)stream, [&](hipStream_t s) {
         return d2::launch_assign(ctx(h, s), p, kx, kz, k, labels, best, all, row_status, ws);
     });
+}
+
+d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *labels,
+                             const d2_opts *opts, double *z_new, double *eps_step1, double *eps_step3,
+                             int32_t *counts, int32_t *obj_status, void *ws, size_t ws_bytes,
+                             void *stream) {
+    if (!h) return D2_EINVAL;
+    d2_status st = pair_sets_ok(X, Z);
+    if (st != D2_OK) return st;
+    KOpts k;
+    if ((st = opts_ok(opts, k)) != D2_OK) return st;
+    if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
+    if (X->n > 0 && !labels) return D2_EINVAL;
+    if (Z->n > 0 && !z_new) return D2_EINVAL;
+    if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
+    if (Z->n > 0 && (const void *)z_new == Z->points) return D2_EINVAL;
+    const size_t need = d2::update_ws_bytes(X->n, Z->n, ms(X), ms(Z));
+    if (!ws || ws_bytes < need) return D2_EWORKSPACE;
+    if ((st = bind_device(h)) != D2_OK) return st;
+    if (X->n == 0 && Z->n == 0) return D2_OK;
+    const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(ms(X), ms(Z));
+    hipError_t e = d2::launch_update(ctx(h, (hipStream_t)stream), cls, kset(X), kset(Z), ms(X), ms(Z), k,
+                                     labels, z_new, eps_step1, eps_step3, counts, obj_status, ws);
+    return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 
 d2_status d2_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double *condensed,

@@ -17,43 +17,10 @@
 #include <stdint.h>
 
 #include "d2_internal.h"
+#include "d2_shapes.h"
 #include "d2_solver.h"
 
 namespace d2 {
-
-// ------------------------------------------------------------------ shapes
-
-template <int CLS> struct Shape;
-// G: lanes per pair; GS: column capacity; waves per workgroup; occ: waves per
-// SIMD the register allocation is held to (the pivot loop waits on LDS and
-// lane exchanges, so more resident waves beat a few spilled registers:
-// measured best at 4 / 3 / 2 / 1).
-template <> struct Shape<0> { static constexpr int G = 16, GS = 16, waves = 4, occ = 4; static constexpr bool LT = false; };
-template <> struct Shape<1> { static constexpr int G = 32, GS = 32, waves = 4, occ = 3; static constexpr bool LT = false; };
-template <> struct Shape<2> { static constexpr int G = 64, GS = 32, waves = 2, occ = 2; static constexpr bool LT = false; };
-template <> struct Shape<3> { static constexpr int G = 64, GS = 64, waves = 1, occ = 2; static constexpr bool LT = true; };
-
-template <int CLS>
-struct ShapeCfg {
-    static constexpr int G = Shape<CLS>::G, GS = Shape<CLS>::GS;
-    static constexpr bool LT = Shape<CLS>::LT;
-    static constexpr int threads = Shape<CLS>::waves * 64;
-    static constexpr int occ = Shape<CLS>::occ;
-    static constexpr int groups = threads / G;
-};
-
-// LDS tile of a shape and start rule: Vogel's start scans columns and keeps
-// the whole tile; otherwise only the widest shape keeps its upper columns.
-template <int CLS, int START>
-using TileOf = typename std::conditional<
-    START == kStartVogel, Tile<Shape<CLS>::G, Shape<CLS>::GS>,
-    typename std::conditional<Shape<CLS>::LT, TileHalf<Shape<CLS>::G, Shape<CLS>::GS>, NoTile>::type>::type;
-
-__host__ __device__ inline int class_of(int64_t T, int64_t S) {
-    if (T <= 16) return 0;
-    if (T <= 32) return 1;
-    return S <= 32 ? 2 : 3;
-}
 
 // Support-value bucket: 0..64, and 65 for anything larger (reported as too
 // large by the solver).
@@ -584,24 +551,6 @@ __global__ __launch_bounds__(256) void k_cost_bf16_pairs(KSet A, KSet B, const i
 
 // ------------------------------------------------------------ launchers
 
-template <typename F>
-static hipError_t dispatch_class(int cls, bool f32, int start, F &&f) {
-#define D2_CASE(C)                                                                      \
-    case C:                                                                             \
-        if (f32) return start == kStartVogel ? f.template run<C, float, kStartVogel>()             \
-                      : start == kStartLCM ? f.template run<C, float, kStartLCM>()                   \
-                                           : f.template run<C, float, kStartNWC>();                  \
-        return start == kStartVogel ? f.template run<C, double, kStartVogel>()                       \
-               : start == kStartLCM ? f.template run<C, double, kStartLCM>()                         \
-                                    : f.template run<C, double, kStartNWC>();
-    switch (cls) {
-        D2_CASE(0)
-        D2_CASE(1)
-        D2_CASE(2)
-        default: D2_CASE(3)
-    }
-#undef D2_CASE
-}
 
 int class_for(int maxsup_a, int maxsup_b) {
     const int T = maxsup_a > maxsup_b ? maxsup_a : maxsup_b;
