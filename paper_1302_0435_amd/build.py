@@ -24,20 +24,29 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source to an object file in parallel, then link."""
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source to an object file in parallel, then link.  With
+    ``incremental``, objects newer than their source and every header are
+    kept."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     compile_flags = [f for f in FLAGS if f != "-shared"]
     procs = []
     objs = []
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    headers.append(os.path.join(ROOT, "include", "d2.h"))
+    newest_header = max(os.path.getmtime(f) for f in headers)
     for s in SOURCES:
         obj = os.path.join(objdir, s.replace(".hip", ".o"))
+        objs.append(obj)
+        if incremental and os.path.exists(obj):
+            t = os.path.getmtime(obj)
+            if t > os.path.getmtime(os.path.join(CSRC, s)) and t > newest_header:
+                continue
         cmd = [HIPCC, *compile_flags, "-c", "-o", obj, os.path.join(CSRC, s)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, cwd=CSRC), cmd))
-        objs.append(obj)
     failed = [cmd for p, cmd in procs if p.wait() != 0]
     if failed:
         raise subprocess.CalledProcessError(1, failed[0])

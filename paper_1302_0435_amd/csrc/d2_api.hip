@@ -247,7 +247,7 @@ size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set
                                opts ? opts->cost_mode : D2_COST_F64_DIRECT).ws_bytes;
     }
     if (which == 3) return d2::plan_pairwise(kset(A), ms(A), sched).ws_bytes;
-    if (which == 4 && B && set_ok(B)) return d2::update_ws_bytes(A->n, B->n, ms(A), ms(B));
+    if (which == 4 && B && set_ok(B)) return d2::update_ws_bytes(A->n, B->n, A->d, ms(A), ms(B));
     return 0;
 }
 
@@ -341,7 +341,7 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
     if (Z->n > 0 && !z_new) return D2_EINVAL;
     if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
     if (Z->n > 0 && (const void *)z_new == Z->points) return D2_EINVAL;
-    const size_t need = d2::update_ws_bytes(X->n, Z->n, ms(X), ms(Z));
+    const size_t need = d2::update_ws_bytes(X->n, Z->n, X->d, ms(X), ms(Z));
     if (!ws || ws_bytes < need) return D2_EWORKSPACE;
     if ((st = bind_device(h)) != D2_OK) return st;
     if (X->n == 0 && Z->n == 0) return D2_OK;

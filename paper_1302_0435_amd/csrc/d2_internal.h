@@ -82,7 +82,7 @@ hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
 
 // Centroid update with fixed centroid weights (Alg. 2 Step 3*): workspace
 // size and the enqueue of the whole pass.
-size_t update_ws_bytes(int64_t n, int64_t K, int xmax, int zmax);
+size_t update_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax);
 void update_mean_shape(int d, int zmax, int *kb, int *P);
 hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet &Z, int xmax, int zmax,
                          const KOpts &o, const int32_t *labels, double *z_new, double *eps1, double *eps3,

@@ -10,14 +10,17 @@
 //            against the member's own centroid (the same solver as every
 //            other entry point) and stores the basis tree as a cell list:
 //            (member atom, centroid atom, flow) per tree edge.
-//   mean     Step 2, Eq. (2): one workgroup per cluster.  Member slices
-//            accumulate flow * coordinate into private LDS rows, which are
-//            then summed in slice order; each atom becomes numerator over
-//            its total flow.  No atomics, so the result does not depend on
-//            timing.
+//   mean     Step 2, Eq. (2): a cluster's members are cut into items of 64
+//            (so one large cluster spreads over many workgroups).  In an
+//            item's workgroup, member slices accumulate flow * coordinate
+//            into private LDS rows, summed in slice order into the item's
+//            partial numerators and flow totals; one workgroup per cluster
+//            then adds its items in order, and each atom becomes numerator
+//            over total flow.  No atomics anywhere, so repeated calls give
+//            the same bits.
 //   eps      Step 3: one wave per member evaluates its plan against the
-//            moved atoms; then one wave per cluster sums the members' Step 1
-//            and Step 3 values.
+//            moved atoms; the members' Step 1 and Step 3 values are summed
+//            per item, then per cluster.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -31,6 +34,7 @@ namespace d2 {
 namespace {
 
 constexpr int kTile = 64;          // objects per tile of the counting sort
+constexpr int kItem = 64;          // members per item of the mean and the sums
 constexpr int kScanPer = 4096;     // entries per workgroup of the scan
 constexpr int kUnlabelled = 5;     // D2_PAIR_UNLABELLED
 
@@ -46,21 +50,30 @@ struct UpdWS {
     int32_t *stm;     // [n]: status
     int32_t *code;    // [n * cs]: (member atom << 16) | centroid atom, -1 = none
     double *flow;     // [n * cs]
+    int64_t *itemoff; // [K+1]: first item of each cluster
+    double *part;     // [items][zmax][d+1]: partial numerators, flow total last
+    double *ie1, *ie3;   // [items]: partial objectives
+    int64_t *icnt;    // [items]: members that entered Step 2
 };
 
 struct UpdDims {
-    int64_t n, K, tiles, entries, sblocks;
-    int cs;
+    int64_t n, K, tiles, entries, sblocks, items;
+    int cs, zmax, d;
 };
 
-UpdDims upd_dims(int64_t n, int64_t K, int xmax, int zmax) {
+UpdDims upd_dims(int64_t n, int64_t K, int d, int xmax, int zmax) {
     UpdDims u;
     u.n = n;
     u.K = K;
     u.tiles = n > 0 ? (n + kTile - 1) / kTile : 1;
     u.entries = (K + 1) * u.tiles;
     u.sblocks = (u.entries + kScanPer - 1) / kScanPer;
+    // each cluster has ceil(n_j / kItem) <= n_j / kItem + 1 items
+    u.items = (n > 0 ? (n + kItem - 1) / kItem : 0) + K;
+    if (u.items < 1) u.items = 1;
     u.cs = xmax + zmax;
+    u.zmax = zmax;
+    u.d = d;
     return u;
 }
 
@@ -79,6 +92,11 @@ size_t upd_layout(const UpdDims &u, void *base, UpdWS *w) {
     s.stm = (int32_t *)take((size_t)n * 4);
     s.code = (int32_t *)take((size_t)n * u.cs * 4);
     s.flow = (double *)take((size_t)n * u.cs * 8);
+    s.itemoff = (int64_t *)take((size_t)(u.K + 1) * 8);
+    s.part = (double *)take((size_t)u.items * u.zmax * (u.d + 1) * 8);
+    s.ie1 = (double *)take((size_t)u.items * 8);
+    s.ie3 = (double *)take((size_t)u.items * 8);
+    s.icnt = (int64_t *)take((size_t)u.items * 8);
     if (w) *w = s;
     return off;
 }
@@ -138,14 +156,55 @@ __global__ void k_upd_scan_blocks(const int64_t *cnt, int64_t m, int64_t *bsum) 
     }
 }
 
-__global__ void k_upd_scan_top(int64_t *bsum, int64_t nb) {
-    if (threadIdx.x != 0) return;
-    int64_t acc = 0;
-    for (int64_t b = 0; b < nb; ++b) {
-        const int64_t v = bsum[b];
-        bsum[b] = acc;
-        acc += v;
+// Exclusive prefix of v[0, L) in place, by one workgroup of 1024 threads:
+// contiguous chunks per thread, then a scan of the chunk sums in LDS.
+__device__ void block_exclusive_scan(int64_t *v, int64_t L) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (L + 1023) / 1024;
+    const int64_t b = t * chunk, e = b + chunk < L ? b + chunk : L;
+    int64_t s = 0;
+    for (int64_t q = b; q < e; ++q) s += v[q];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
+        const int64_t add = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
     }
+    int64_t acc = t > 0 ? part[t - 1] : 0;
+    for (int64_t q = b; q < e; ++q) {
+        const int64_t x = v[q];
+        v[q] = acc;
+        acc += x;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_upd_scan_top(int64_t *bsum, int64_t nb) {
+    block_exclusive_scan(bsum, nb);
+}
+
+// Items per cluster (ceil of its members over kItem), then their prefix.
+__global__ __launch_bounds__(1024) void k_upd_items(const int64_t *pre, int64_t K, int64_t tiles,
+                                                    int64_t *itemoff) {
+    for (int64_t j = threadIdx.x; j <= K; j += blockDim.x) {
+        const int64_t cnt = j < K ? pre[(j + 1) * tiles] - pre[j * tiles] : 0;
+        itemoff[j] = (cnt + kItem - 1) / kItem;
+    }
+    __syncthreads();
+    block_exclusive_scan(itemoff, K + 1);
+}
+
+// Cluster of an item: the last j with itemoff[j] <= item (clusters without
+// members own no items).
+__device__ __forceinline__ int64_t item_cluster(const int64_t *itemoff, int64_t K, int64_t item) {
+    int64_t lo = 0, hi = K;   // itemoff[lo] <= item < itemoff[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (itemoff[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
 }
 
 __global__ void k_upd_scan_apply(int64_t *cnt, int64_t m, const int64_t *bsum) {
@@ -186,13 +245,13 @@ __global__ void k_upd_place(const int32_t *labels, int64_t n, int64_t K, int64_t
     const int64_t i = tile * kTile + (threadIdx.x & 63);
     const bool live = i < n;
     const int64_t key = live ? label_key(labels, i, K) : -1;
-    int64_t pos = -1;
+    int64_t pos = live ? pre[key * tiles + tile] : -1;   // all lanes' loads at once
     uint64_t todo = __ballot(live);
     while (todo) {
         const int first = __builtin_ctzll(todo);
         const int64_t k0 = __shfl(key, first, 64);
         const uint64_t same = __ballot(live && key == k0);
-        if (live && key == k0) pos = pre[k0 * tiles + tile] + __builtin_popcountll(same & lanes_below());
+        if (live && key == k0) pos += __builtin_popcountll(same & lanes_below());
         todo &= ~same;
     }
     if (live) {
@@ -252,63 +311,98 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_
 
 // ------------------------------------------------------------ Step 2
 
-// One workgroup of 256 per cluster.  Thread (p, c) with c < kb, p < P adds
-// flow * x[a][k0 + c] of the members m = m0 + p, m0 + p + P, ... into its
-// own LDS accumulators acc[p][r][c] (and the flows into acc[p][r][kb]).
+// One workgroup of 256 per item (up to kItem members of one cluster).
+// Thread (p, c), c < kb, p < P, adds flow * x[a][k0 + c] of the item's
+// members m = lo + p, lo + p + P, ... into its own LDS accumulators
+// acc[p][r][c], and the flows into acc[p][r][kb]; the slices are then summed
+// in order into the item's partial row.
 template <typename TIn>
-__global__ __launch_bounds__(256) void k_upd_mean(KSet X, KSet Z, UpdWS w, int64_t tiles, int cs, int kb,
-                                                   int P, int zmax, double *z_new) {
+__global__ __launch_bounds__(256) void k_upd_partial(KSet X, KSet Z, UpdWS w, int64_t tiles, int cs, int kb,
+                                                      int P, int zmax) {
     extern __shared__ double acc[];   // [P][zmax][kb + 1]
-    const int64_t j = blockIdx.x;
-    const int d = X.d;
+    const int64_t K = Z.n;
+    const int64_t item = blockIdx.x;
+    if (item >= w.itemoff[K]) return;   // uniform over the workgroup
+    const int64_t j = item_cluster(w.itemoff, K, item);
     const int64_t m0 = w.cnt[j * tiles], m1 = w.cnt[(j + 1) * tiles];
-    const int64_t z0 = Z.off[j];
-    const int64_t S = Z.off[j + 1] - z0;
-    const int Sl = (int)(S < zmax ? (S > 0 ? S : 0) : zmax);   // atoms with LDS rows
-    const int row = kb + 1;
+    const int64_t lo = m0 + (item - w.itemoff[j]) * kItem;
+    const int64_t hi = lo + kItem < m1 ? lo + kItem : m1;
+    const int64_t S = Z.off[j + 1] - Z.off[j];
+    const int Sl = (int)(S < zmax ? S : zmax);   // members exist only if S <= zmax
+    const int d = X.d, row = kb + 1;
     const int p = threadIdx.x / kb, c = threadIdx.x % kb;
-    const bool worker = p < P;
+    double *out = w.part + (size_t)item * zmax * (d + 1);
     for (int k0 = 0; k0 < d; k0 += kb) {
         for (int e = threadIdx.x; e < P * Sl * row; e += blockDim.x) acc[e] = 0.0;
         __syncthreads();
-        if (worker) {
+        if (p < P) {
             double *mine = acc + (size_t)p * Sl * row;
             const int k = k0 + c;
-            for (int64_t m = m0 + p; m < m1; m += P) {
+            for (int64_t m = lo + p; m < hi; m += P) {
                 if (w.stm[m] != kOk) continue;
                 const int64_t i = w.perm[m];
                 const int64_t x0 = X.off[i];
                 const int ncell = (int)(X.off[i + 1] - x0 + S);
                 const int32_t *code = w.code + m * cs;
                 const double *flow = w.flow + m * cs;
-                for (int q = 0; q < ncell; ++q) {
-                    const int cd = code[q];
-                    if (cd < 0) continue;
-                    const int a = cd >> 16, r = cd & 0xffff;
-                    const double f = flow[q];
-                    if (k < d) mine[r * row + c] += f * ldw<TIn>(X.pts, (x0 + a) * d + k);
-                    if (c == 0) mine[r * row + kb] += f;
+                for (int q = 0; q < ncell; q += 4) {   // four cells' loads in flight
+                    int cd[4];
+                    double f[4], xv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        cd[u] = q + u < ncell ? code[q + u] : -1;
+                        f[u] = q + u < ncell ? flow[q + u] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        xv[u] = (cd[u] >= 0 && k < d) ? ldw<TIn>(X.pts, (x0 + (cd[u] >> 16)) * d + k) : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (cd[u] < 0) continue;
+                        const int r = cd[u] & 0xffff;
+                        if (k < d) mine[r * row + c] += f[u] * xv[u];
+                        if (c == 0) mine[r * row + kb] += f[u];
+                    }
                 }
             }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < Sl * kb; e += blockDim.x) {
-            const int r = e / kb, cc = e % kb, k = k0 + cc;
-            if (k >= d) continue;
-            double num = 0.0, den = 0.0;
-            for (int q = 0; q < P; ++q) {
-                num += acc[((size_t)q * Sl + r) * row + cc];
-                den += acc[((size_t)q * Sl + r) * row + kb];
-            }
-            const int64_t at = (z0 + r) * d + k;
-            z_new[at] = den > 0.0 ? num / den : ldw<TIn>(Z.pts, at);
-        }
-        // atoms beyond the declared bound (no member was solved) keep their place
-        for (int64_t e = (int64_t)Sl * kb + threadIdx.x; e < S * kb; e += blockDim.x) {
-            const int64_t r = e / kb, k = k0 + e % kb;
-            if (k < d) z_new[(z0 + r) * d + k] = ldw<TIn>(Z.pts, (z0 + r) * d + k);
+        for (int e = threadIdx.x; e < Sl * row; e += blockDim.x) {
+            const int r = e / row, cc = e % row;
+            const int k = cc < kb ? k0 + cc : d;   // column kb holds the flow total
+            if (k > d || (cc < kb && k >= d)) continue;
+            if (cc == kb && k0 > 0) continue;      // flow total once
+            double v = 0.0;
+            for (int q = 0; q < P; ++q) v += acc[((size_t)q * Sl + r) * row + cc];
+            out[(size_t)r * (d + 1) + k] = v;
         }
         __syncthreads();
+    }
+}
+
+// One workgroup per cluster: its items' partial rows added in item order;
+// an atom with no flow keeps its coordinates.
+template <typename TIn>
+__global__ __launch_bounds__(256) void k_upd_finish(KSet Z, UpdWS w, int zmax, double *z_new) {
+    const int64_t j = blockIdx.x;
+    const int d = Z.d;
+    const int64_t z0 = Z.off[j];
+    const int64_t S = Z.off[j + 1] - z0;
+    const int64_t Sl = S < zmax ? S : zmax;
+    const int64_t it0 = w.itemoff[j], it1 = w.itemoff[j + 1];
+    const size_t stride = (size_t)zmax * (d + 1);
+    for (int64_t e = threadIdx.x; e < S * d; e += blockDim.x) {
+        const int64_t r = e / d, k = e % d;
+        const int64_t at = (z0 + r) * d + k;
+        double num = 0.0, den = 0.0;
+        if (r < Sl) {
+            const double *src = w.part + (size_t)r * (d + 1);
+            for (int64_t it = it0; it < it1; ++it) {
+                num += src[it * stride + k];
+                den += src[it * stride + d];
+            }
+        }
+        z_new[at] = den > 0.0 ? num / den : ldw<TIn>(Z.pts, at);
     }
 }
 
@@ -347,20 +441,48 @@ __global__ __launch_bounds__(256) void k_upd_eps(KSet X, KSet Z, UpdWS w, int64_
     }
 }
 
-// One wave per cluster: sums of the members' Step 1 and Step 3 values.
-__global__ __launch_bounds__(256) void k_upd_sums(UpdWS w, int64_t K, int64_t tiles, double *eps1,
-                                                   double *eps3, int32_t *counts) {
+// One wave per item: sums of its members' Step 1 and Step 3 values.
+__global__ __launch_bounds__(256) void k_upd_isums(UpdWS w, int64_t K, int64_t tiles) {
+    const int lane = threadIdx.x & 63;
+    const int64_t items = w.itemoff[K];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t item = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; item < items;
+         item += waves) {
+        const int64_t j = item_cluster(w.itemoff, K, item);
+        const int64_t m1 = w.cnt[(j + 1) * tiles];
+        const int64_t m = w.cnt[j * tiles] + (item - w.itemoff[j]) * kItem + lane;   // kItem == 64
+        double a1 = 0.0, a3 = 0.0;
+        int64_t cnt = 0;
+        if (m < m1 && w.stm[m] == kOk) {
+            a1 = w.d2m[m];
+            a3 = w.eps3m[m];
+            cnt = 1;
+        }
+        for (int sh = 32; sh >= 1; sh >>= 1) {
+            a1 += __shfl_xor(a1, sh, 64);
+            a3 += __shfl_xor(a3, sh, 64);
+            cnt += __shfl_xor(cnt, sh, 64);
+        }
+        if (lane == 0) {
+            w.ie1[item] = a1;
+            w.ie3[item] = a3;
+            w.icnt[item] = cnt;
+        }
+    }
+}
+
+// One wave per cluster: its items' sums.
+__global__ __launch_bounds__(256) void k_upd_csums(UpdWS w, int64_t K, double *eps1, double *eps3,
+                                                    int32_t *counts) {
     const int64_t j = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     if (j >= K) return;
     const int lane = threadIdx.x & 63;
-    const int64_t m0 = w.cnt[j * tiles], m1 = w.cnt[(j + 1) * tiles];
     double a1 = 0.0, a3 = 0.0;
     int64_t cnt = 0;
-    for (int64_t m = m0 + lane; m < m1; m += 64) {
-        if (w.stm[m] != kOk) continue;
-        a1 += w.d2m[m];
-        a3 += w.eps3m[m];
-        ++cnt;
+    for (int64_t it = w.itemoff[j] + lane; it < w.itemoff[j + 1]; it += 64) {
+        a1 += w.ie1[it];
+        a3 += w.ie3[it];
+        cnt += w.icnt[it];
     }
     for (int sh = 32; sh >= 1; sh >>= 1) {
         a1 += __shfl_xor(a1, sh, 64);
@@ -412,14 +534,14 @@ void update_mean_shape(int d, int zmax, int *kb, int *P) {
     *P = p;
 }
 
-size_t update_ws_bytes(int64_t n, int64_t K, int xmax, int zmax) {
-    return upd_layout(upd_dims(n, K, xmax, zmax), nullptr, nullptr);
+size_t update_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax) {
+    return upd_layout(upd_dims(n, K, d, xmax, zmax), nullptr, nullptr);
 }
 
 hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet &Z, int xmax, int zmax,
                          const KOpts &o, const int32_t *labels, double *z_new, double *eps1, double *eps3,
                          int32_t *counts, int32_t *obj_status, void *ws) {
-    const UpdDims u = upd_dims(X.n, Z.n, xmax, zmax);
+    const UpdDims u = upd_dims(X.n, Z.n, X.d, xmax, zmax);
     UpdWS w;
     upd_layout(u, ws, &w);
     const bool f32 = X.dtype == D2_F32;
@@ -432,7 +554,7 @@ hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet 
                            w.cnt, obj_status);
     hipLaunchKernelGGL(k_upd_scan_blocks, dim3((unsigned)u.sblocks), dim3(256), 0, c.stream, w.cnt, u.entries,
                        w.bsum);
-    hipLaunchKernelGGL(k_upd_scan_top, dim3(1), dim3(64), 0, c.stream, w.bsum, u.sblocks);
+    hipLaunchKernelGGL(k_upd_scan_top, dim3(1), dim3(1024), 0, c.stream, w.bsum, u.sblocks);
     hipLaunchKernelGGL(k_upd_scan_apply, dim3((unsigned)u.sblocks), dim3(256), 0, c.stream, w.cnt, u.entries,
                        w.bsum);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -443,15 +565,22 @@ hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet 
         if ((e = dispatch_class(cls, f32, o.init, r)) != hipSuccess) return e;
     }
     if (Z.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_upd_items, dim3(1), dim3(1024), 0, c.stream, w.cnt, Z.n, u.tiles, w.itemoff);
     int kb, P;
     update_mean_shape(X.d, zmax, &kb, &P);
     const size_t lds = (size_t)P * zmax * (kb + 1) * sizeof(double);
+    if (X.n > 0) {
+        if (f32)
+            hipLaunchKernelGGL(k_upd_partial<float>, dim3((unsigned)u.items), dim3(256), lds, c.stream, X, Z, w,
+                               u.tiles, u.cs, kb, P, zmax);
+        else
+            hipLaunchKernelGGL(k_upd_partial<double>, dim3((unsigned)u.items), dim3(256), lds, c.stream, X, Z, w,
+                               u.tiles, u.cs, kb, P, zmax);
+    }
     if (f32)
-        hipLaunchKernelGGL(k_upd_mean<float>, dim3((unsigned)Z.n), dim3(256), lds, c.stream, X, Z, w, u.tiles,
-                           u.cs, kb, P, zmax, z_new);
+        hipLaunchKernelGGL(k_upd_finish<float>, dim3((unsigned)Z.n), dim3(256), 0, c.stream, Z, w, zmax, z_new);
     else
-        hipLaunchKernelGGL(k_upd_mean<double>, dim3((unsigned)Z.n), dim3(256), lds, c.stream, X, Z, w, u.tiles,
-                           u.cs, kb, P, zmax, z_new);
+        hipLaunchKernelGGL(k_upd_finish<double>, dim3((unsigned)Z.n), dim3(256), 0, c.stream, Z, w, zmax, z_new);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (X.n > 0) {
         int kl = 1;
@@ -463,9 +592,11 @@ hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet 
         else
             hipLaunchKernelGGL(k_upd_eps<double>, dim3((unsigned)eg), dim3(256), 0, c.stream, X, Z, w, u.tiles,
                                u.cs, kl, z_new);
+        const int64_t ig = (u.items + 3) / 4 < 65536 ? (u.items + 3) / 4 : 65536;
+        hipLaunchKernelGGL(k_upd_isums, dim3((unsigned)ig), dim3(256), 0, c.stream, w, Z.n, u.tiles);
     }
-    hipLaunchKernelGGL(k_upd_sums, dim3((unsigned)((Z.n + 3) / 4)), dim3(256), 0, c.stream, w, Z.n, u.tiles,
-                       eps1, eps3, counts);
+    hipLaunchKernelGGL(k_upd_csums, dim3((unsigned)((Z.n + 3) / 4)), dim3(256), 0, c.stream, w, Z.n, eps1,
+                       eps3, counts);
     return hipGetLastError();
 }
 
