@@ -11,6 +11,8 @@ with ctypes, and widens every input to FP64 exactly before the call.
     pairwise(X)                       -> (condensed D^2, status, pivots)
     centroid_update(X, Z, labels)     -> (z_new, eps_step1, eps_step3, status)
                                          (``update.py``: Alg. 2 Step 3*)
+    emd_cost(C, p, q)                 -> (value, plan, u, v, pivots), given cost
+    mm_distance(Z1, p1, Z2, p2)       -> (MM^2, D^2 matrix, plan)  (``mm.py``: Eq. (10))
 
 Sets are ``synth.RaggedSet``-like objects with ``offsets``, ``points``,
 ``weights``.  Labels follow Alg. 2 Step 2 (argmin over centroids, ties to the
@@ -55,13 +57,15 @@ def _load():
     I64 = ctypes.c_int64
     lib.oracle_emd_pair.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P,
                                     ctypes.c_int, P, P, P, P, P]
+    lib.oracle_emd_cost.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P]
     lib.oracle_emd_batch.argtypes = [ctypes.c_int, P, P, P, I64, P, P, P, I64, P, I64,
                                      ctypes.c_int, ctypes.c_int, P, P, P]
     lib.oracle_assign.argtypes = [ctypes.c_int, P, P, P, I64, P, P, P, I64, ctypes.c_int,
                                   ctypes.c_int, P, P, P, P, P]
     lib.oracle_pairwise.argtypes = [ctypes.c_int, P, P, P, I64, ctypes.c_int, ctypes.c_int,
                                     P, P, P]
-    for f in (lib.oracle_emd_pair, lib.oracle_emd_batch, lib.oracle_assign, lib.oracle_pairwise):
+    for f in (lib.oracle_emd_pair, lib.oracle_emd_cost, lib.oracle_emd_batch, lib.oracle_assign,
+              lib.oracle_pairwise):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -110,6 +114,29 @@ def emd_pair(x, p, y, q, init: int = INIT_NWC):
         err.status = st
         raise err
     return float(d2[0]), plan, u, v, int(piv[0])
+
+
+def emd_cost(C, p, q, init: int = INIT_NWC):
+    """The transport LP with the given t x s cost matrix (any finite values):
+    (value, plan[t,s], u[t], v[s], pivots)."""
+    lib = _load()
+    C = _f64(C)
+    t, s = C.shape
+    p = _f64(p).reshape(-1); q = _f64(q).reshape(-1)
+    if p.size != t or q.size != s:
+        raise ValueError("shape mismatch")
+    val = np.zeros(1)
+    plan = np.zeros((t, s))
+    u = np.zeros(t)
+    v = np.zeros(s)
+    piv = np.zeros(1, dtype=np.int64)
+    st = lib.oracle_emd_cost(t, s, _p(C), _p(p), _p(q), init, _p(val), _p(plan), _p(u), _p(v),
+                             _p(piv))
+    if st != 0:
+        err = ArithmeticError(f"oracle status {st}")
+        err.status = st
+        raise err
+    return float(val[0]), plan, u, v, int(piv[0])
 
 
 def emd_batch(A, B, pairs, init: int = INIT_NWC, threads: int | None = None):
@@ -175,3 +202,4 @@ def independent_coupling_cost(x, p, y, q) -> float:
 
 
 from .update import centroid_update  # noqa: E402  (uses emd_pair above)
+from .mm import mm_distance  # noqa: E402  (uses assign and emd_cost above)

@@ -43,6 +43,10 @@
  *   8. a pivot count above max(50 t s, 100) is reported as failure;
  *   9. the objective is sum over basic cells of w_ab C_ab in row-major order.
  *
+ * oracle_emd_cost takes the ground cost as given instead of step 2 (any
+ * finite values; non-finite ones give status 4), which serves the MM
+ * distance of Eq. (10) and any other cost.
+ *
  * Batches run over host threads, each pair independent (the labelling step
  * parallelises per point, Sec. 1.2).
  */
@@ -58,6 +62,7 @@
 #define ORACLE_BAD_WEIGHTS 1
 #define ORACLE_TOO_LARGE 2
 #define ORACLE_PIVOT_CAP 3
+#define ORACLE_BAD_COST 4
 
 /* ---------------------------------------------------------------- scratch */
 
@@ -306,19 +311,31 @@ static int tree_path(scratch_t *sc, int t, int s, int nb, int ra, int cb) {
 
 /* ----------------------------------------------------------- one LP solve */
 
+/* `cost`, when given, is the t x s ground cost (row-major) to use instead of
+ * step 2; it may hold any finite values (the transport LP with a general
+ * cost, as in the MM distance of Eq. (10)).  The stopping tolerance is taken
+ * against max |C|, which for the squared distances of step 2 is max C. */
 static int solve_pair(scratch_t *sc, int t, int s, int d, const double *x, const double *pw,
-                      const double *y, const double *qw, int init_rule, double *d2_out,
-                      double *plan_out, double *u_out, double *v_out, long long *pivots_out) {
+                      const double *y, const double *qw, const double *cost, int init_rule,
+                      double *d2_out, double *plan_out, double *u_out, double *v_out,
+                      long long *pivots_out) {
     *d2_out = NAN;
     if (pivots_out) *pivots_out = 0;
     if (t < 1 || s < 1) return ORACLE_TOO_LARGE;
     if (normalise(t, pw, sc->p) != ORACLE_OK) return ORACLE_BAD_WEIGHTS;
     if (normalise(s, qw, sc->q) != ORACLE_OK) return ORACLE_BAD_WEIGHTS;
-    ground_cost(t, s, d, x, y, sc->C);
+    if (cost) {
+        for (size_t c = 0; c < (size_t)t * s; ++c) {
+            if (!isfinite(cost[c])) return ORACLE_BAD_COST;
+            sc->C[c] = cost[c];
+        }
+    } else {
+        ground_cost(t, s, d, x, y, sc->C);
+    }
 
     double cmax = 0.0;
     for (size_t c = 0; c < (size_t)t * s; ++c) {
-        if (sc->C[c] > cmax) cmax = sc->C[c];
+        if (fabs(sc->C[c]) > cmax) cmax = fabs(sc->C[c]);
         sc->basic_at[c] = -1;
     }
     const double delta = 1e-14 * cmax;
@@ -409,8 +426,20 @@ int oracle_emd_pair(int t, int s, int d, const double *x, const double *p, const
     scratch_t sc;
     if (t < 1 || s < 1 || d < 1) return ORACLE_TOO_LARGE;
     if (scratch_init(&sc, t, s) != 0) return -1;
-    int st = solve_pair(&sc, t, s, d, x, p, y, q, init_rule, d2_out, plan_out, u_out, v_out,
+    int st = solve_pair(&sc, t, s, d, x, p, y, q, NULL, init_rule, d2_out, plan_out, u_out, v_out,
                         pivots_out);
+    scratch_free(&sc);
+    return st;
+}
+
+int oracle_emd_cost(int t, int s, const double *cost, const double *p, const double *q,
+                    int init_rule, double *d2_out, double *plan_out, double *u_out, double *v_out,
+                    long long *pivots_out) {
+    scratch_t sc;
+    if (t < 1 || s < 1 || !cost) return ORACLE_TOO_LARGE;
+    if (scratch_init(&sc, t, s) != 0) return -1;
+    int st = solve_pair(&sc, t, s, 1, NULL, p, NULL, q, cost, init_rule, d2_out, plan_out, u_out,
+                        v_out, pivots_out);
     scratch_free(&sc);
     return st;
 }
@@ -441,7 +470,7 @@ static int solve_ij(scratch_t *sc, const job_t *J, int64_t i, int64_t j, double 
     int t = (int)(a1 - a0), s = (int)(b1 - b0);
     if (t < 1 || s < 1 || t > J->max_t || s > J->max_s) { *out = NAN; return ORACLE_TOO_LARGE; }
     return solve_pair(sc, t, s, J->d, J->xA + a0 * J->d, J->wA + a0, J->xB + b0 * J->d,
-                      J->wB + b0, J->init, out, NULL, NULL, NULL, piv);
+                      J->wB + b0, NULL, J->init, out, NULL, NULL, NULL, piv);
 }
 
 /* Pair k of the strict upper triangle, row-major: row i holds n-1-i pairs. */

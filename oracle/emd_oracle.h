@@ -7,7 +7,8 @@
  * Ragged sets: offsets[n+1] (int64), points[offsets[n]][d] row-major FP64,
  * weights[offsets[n]] FP64 (any non-negative finite vector with positive sum;
  * it is divided by its sum).  Status per pair: 0 optimal, 1 bad weights,
- * 2 empty or oversize support, 3 pivot cap reached (value NaN).
+ * 2 empty or oversize support, 3 pivot cap reached (value NaN), 4 a
+ * non-finite given cost.
  */
 #ifndef EMD_ORACLE_H
 #define EMD_ORACLE_H
@@ -19,6 +20,11 @@
 int oracle_emd_pair(int t, int s, int d, const double *x, const double *p, const double *y,
                     const double *q, int init_rule, double *d2_out, double *plan_out,
                     double *u_out, double *v_out, long long *pivots_out);
+
+/* The transport LP with a caller-given t x s cost (row-major, finite). */
+int oracle_emd_cost(int t, int s, const double *cost, const double *p, const double *q,
+                    int init_rule, double *d2_out, double *plan_out, double *u_out, double *v_out,
+                    long long *pivots_out);
 
 int oracle_emd_batch(int d, const int64_t *offA, const double *xA, const double *wA, int64_t nA,
                      const int64_t *offB, const double *xB, const double *wB, int64_t nB,
