@@ -40,10 +40,14 @@ PROFILES = {
 MFMA_PROFILES = {(3, "bf16"): "k_cost_bf16_assign_f32_c3_50k_x256_d128.txt"}
 # the centroid update's dominant kernel (--op update), keyed by configuration
 UPDATE_PROFILES = {2: "k_upd_solve_cls0_f32_c2_100k_x512.txt"}
+# the given-cost LP kernel (--op cost), configuration 2 shapes
+COST_PROFILES = {2: "k_emd_cost_cls0_c2_shapes_2m.txt"}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
                for f in ("d2_solver.h", "d2_shapes.h", "d2_kernels.hip")]
 UPDATE_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
                for f in ("d2_solver.h", "d2_shapes.h", "d2_update.hip")]
+COST_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
+             for f in ("d2_solver.h", "d2_shapes.h", "d2_cost.hip")]
 
 
 def kernel_sha(srcs=None) -> str:
@@ -84,6 +88,9 @@ def profile_counters(cfg: int, cost: str, op: str = "assign"):
     if op == "update":
         kv = _read_profile(UPDATE_PROFILES.get(cfg, ""))
         sha = kernel_sha(UPDATE_SRCS)
+    elif op == "cost":
+        kv = _read_profile(COST_PROFILES.get(cfg, ""))
+        sha = kernel_sha(COST_SRCS)
     else:
         kv = _read_profile(PROFILES.get((cfg, cost), ""))
         sha = kernel_sha()
@@ -454,6 +461,108 @@ class UpdateWorkload:
                 "parity_failures": fails}
 
 
+class CostWorkload:
+    """d2_emd_cost_batch: transport LPs over caller-given FP64 cost matrices,
+    at configuration 2's shapes: the first `rows` objects against all 512
+    centroids, their 16 x t cost matrices written by d2_cost_tiles in the
+    untimed set-up and resident in HBM."""
+
+    metric = "exact transport LPs/sec from given FP64 cost matrices"
+    unit = "LPs/s"
+
+    def __init__(self, cfg, d2, dev, init, schedule, rows=4000):
+        import synth
+        import torch
+        self.cfg = cfg
+        self.spec = synth.CONFIGS[cfg]
+        X = synth.make_data(cfg).subset(np.arange(rows))
+        Z = synth.make_centroids(cfg)
+        self.X, self.Z = X, Z
+        self.d2 = d2
+        self.h = d2.Handle(0)
+        Xd, Zd = d2.DeviceSet.from_ragged(X, dev), d2.DeviceSet.from_ragged(Z, dev)
+        ii, jj = np.meshgrid(np.arange(X.n), np.arange(Z.n), indexing="ij")
+        pairs = torch.as_tensor(np.stack([ii.ravel(), jj.ravel()], 1), device=dev)
+        self.tiles, self.toff = d2.d2_cost_tiles(self.h, Xd, Zd, pairs)
+        ts = torch.as_tensor(np.diff(X.offsets), device=dev)
+        ss = torch.as_tensor(np.diff(Z.offsets), device=dev)
+        pi, pj = pairs[:, 0], pairs[:, 1]
+        self.roff = torch.zeros(len(pairs) + 1, dtype=torch.int64, device=dev)
+        self.roff[1:] = torch.cumsum(ts[pi], 0)
+        self.coff = torch.zeros_like(self.roff)
+        self.coff[1:] = torch.cumsum(ss[pj], 0)
+        xw = torch.as_tensor(X.weights, dtype=torch.float64, device=dev)
+        zw = torch.as_tensor(Z.weights, dtype=torch.float64, device=dev)
+        xo = torch.as_tensor(X.offsets, device=dev)
+        zo = torch.as_tensor(Z.offsets, device=dev)
+        # each problem's weight vectors, laid out contiguously
+        ridx = torch.repeat_interleave(xo[pi], ts[pi]) + (torch.arange(int(self.roff[-1]), device=dev)
+                                                          - torch.repeat_interleave(self.roff[:-1], ts[pi]))
+        cidx = torch.repeat_interleave(zo[pj], ss[pj]) + (torch.arange(int(self.coff[-1]), device=dev)
+                                                          - torch.repeat_interleave(self.coff[:-1], ss[pj]))
+        self.rw, self.cw = xw[ridx].contiguous(), zw[cidx].contiguous()
+        self.moff = self.toff[:-1].contiguous()
+        self.max_rows, self.max_cols = X.max_support, Z.max_support
+        self.opts = d2.Opts(init=init, schedule=schedule)
+        self.pairs = len(pairs)
+        self.pair_list = pairs.cpu().numpy()
+        torch.cuda.synchronize()
+        self.out = None
+
+    def step(self):
+        self.out = self.d2.d2_emd_cost_batch(self.h, self.roff, self.rw, self.coff, self.cw, self.tiles,
+                                             self.moff, self.max_rows, self.max_cols, self.opts)
+
+    def flops(self):
+        """Pivot-free work: one certifying pricing pass (3 t s) per LP."""
+        ts = np.diff(self.X.offsets).astype(np.float64)
+        ss = np.diff(self.Z.offsets).astype(np.float64)
+        return float(ts.sum() * ss.sum() * 3)
+
+    def bytes(self):
+        cells = float(self.tiles.numel())
+        return cells * 8 + float(self.rw.numel() + self.cw.numel()) * 8 + self.pairs * (8 + 8 + 8 + 4)
+
+    def failed(self):
+        return int((self.out[1].cpu().numpy() != 0).sum())
+
+    def config(self):
+        return {"workload": f"given-cost LPs, {self.X.n} x {self.Z.n} pairs of configuration 2 shapes",
+                "problems": self.pairs, "t_range": list(self.spec["t_range"]), "s": self.spec["s"],
+                "cost_bytes": int(self.tiles.numel() * 8)}
+
+    def cpu_baseline(self, target_s, init_oracle):
+        """The oracle's given-cost LP on a seeded sample of the problems (one
+        core); also checks the device's values there."""
+        import oracle
+        import synth
+        dist = self.out[0].cpu().numpy()
+        tiles = self.tiles.cpu().numpy()
+        toff = self.toff.cpu().numpy()
+        order = synth.rng_for(self.cfg, synth.STREAM_SAMPLE, 400).permutation(self.pairs)
+
+        def one(k):
+            i, j = self.pair_list[k]
+            x, p = self.X.bag(int(i)); y, q = self.Z.bag(int(j))
+            C = tiles[toff[k]:toff[k + 1]].reshape(len(p), len(q))
+            return oracle.emd_cost(C, p, q, init_oracle)[0], C, p, q
+
+        t0 = time.perf_counter()
+        done, fails = 0, 0
+        while time.perf_counter() - t0 < target_s and done < len(order):
+            k = int(order[done])
+            o, C, p, q = one(k)
+            S = float((p / p.sum()) @ np.abs(C) @ (q / q.sum()))
+            if not abs(dist[k] - o) <= 1e-10 * max(abs(o), 1e-4 * S):
+                fails += 1
+            done += 1
+        dt = time.perf_counter() - t0
+        return {"value": done / dt, "unit": "LPs/s", "cores": 1, "kind": "oracle",
+                "sample": f"{done} seeded problems, {dt:.1f} s, "
+                          f"{'Vogel' if init_oracle else 'north-west-corner'} start",
+                "cpu_model": _cpu_model(), "parity_checked": done, "parity_failures": fails}
+
+
 def make_pool(n_pool: int):
     """Query pool for the serving workload (configuration 5, stream 1)."""
     import synth
@@ -531,8 +640,9 @@ def main(argv=None) -> int:
     ap.add_argument("--cost", choices=["f64", "bf16"], default="f64",
                     help="ground-cost arithmetic (bf16: MFMA tiles, supports <= 32)")
     ap.add_argument("--tune", action="store_true", help="autotune the pairwise schedule first")
-    ap.add_argument("--op", choices=["assign", "update"], default="assign",
-                    help="update: the constrained D2 centroid update (configurations 1-3)")
+    ap.add_argument("--op", choices=["assign", "update", "cost"], default="assign",
+                    help="update: the constrained D2 centroid update (configurations 1-3); "
+                         "cost: LPs over given cost matrices (configuration 2 shapes)")
     ap.add_argument("--n", type=int, default=None, help="override object count (testing)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -561,6 +671,8 @@ def main(argv=None) -> int:
             print("--op update runs configurations 1-3 with the FP64 cost", file=sys.stderr)
             return 2
         w = UpdateWorkload(args.config, d2, dev, init, schedule, n=args.n)
+    elif args.op == "cost":
+        w = CostWorkload(2, d2, dev, init, schedule, rows=args.n or 4000)
     elif args.config == 4:
         w = PairwiseWorkload(4, d2, dev, init, schedule, n=args.n, tune=args.tune)
     else:

@@ -169,6 +169,33 @@ d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int
                        double *duals, int32_t *pair_status, void *ws, size_t ws_bytes,
                        void *stream);
 
+/* The transport LP of Eq. (1) over caller-given ground costs, for the MM
+ * distance of Eq. (10) (whose ground cost is the matrix of squared Mallows
+ * distances between two centroid sets) or any other cost.  Problem k:
+ *   rows     t_k = row_offsets[k+1] - row_offsets[k] weights at
+ *            row_weights + row_offsets[k] (device FP64);
+ *   columns  s_k likewise from col_offsets / col_weights;
+ *   cost     t_k x s_k FP64, row-major, at costs + cost_offsets[k] (device;
+ *            problems may share a matrix); any finite values, including
+ *            negative ones.
+ * Weights are normalised by their sums as everywhere (status 1 when a
+ * vector is invalid); a non-finite cost gives D2_PAIR_BAD_POINTS.
+ * max_rows, max_cols: host-known bounds on t_k and s_k, at most
+ * D2_MAX_SUPPORT (else D2_EUNSUPPORTED); a problem beyond them gets
+ * D2_PAIR_TOO_LARGE.  dist[k] is the LP value (opts->want_sqrt and
+ * opts->cost_mode do not apply; D2_COST_BF16_MFMA gives D2_EUNSUPPORTED).
+ * The simplex stops when every reduced cost is >= -opt_tol * max |C|.
+ * plan_offsets, plan (nullable, both or neither): the optimal plan, dense
+ * row-major t_k x s_k in the caller's frame.  status[nprob] may be NULL.
+ * No workspace (ws may be NULL). */
+d2_status d2_emd_cost_batch(d2_handle *h, int64_t nprob, const int64_t *row_offsets,
+                            const double *row_weights, const int64_t *col_offsets,
+                            const double *col_weights, const double *costs,
+                            const int64_t *cost_offsets, int32_t max_rows, int32_t max_cols,
+                            const d2_opts *opts, double *dist, const int64_t *plan_offsets,
+                            double *plan, int32_t *status, void *ws, size_t ws_bytes,
+                            void *stream);
+
 /* Nearest-centroid labelling (Alg. 2, Step 2) over the full cross product:
  * for every object i of X, D^2 to every centroid j of Z, then
  * labels[i] = argmin_j (ties: lowest j), best[i] = the minimum.  all[n][K]

@@ -13,6 +13,9 @@ the stream.
     tiles, tile_offsets = d2_cost_tiles(h, A, B, pairs)
     z_new, eps1, eps3, counts, status = d2_centroid_update(h, X, Z, labels)
     Z, labels, history = constrained_d2(h, X, Z0)      # Alg. 2 with Step 3*
+    dist, status, (plan, plan_off) = d2_emd_cost_batch(h, row_off, row_w, col_off, col_w,
+                                                       costs, cost_off)
+    mm2, M, plan = d2_mm_distance(h, Z1, p1, Z2, p2)   # Eq. (10)
 """
 from __future__ import annotations
 
@@ -326,3 +329,58 @@ def constrained_d2(h: Handle, X: DeviceSet, Z: DeviceSet, opts: Optional[Opts] =
             break                                                            # Step 4
         prev_round = eps
     return Z, labels, history
+
+
+def d2_emd_cost_batch(h: Handle, row_offsets: torch.Tensor, row_weights: torch.Tensor,
+                      col_offsets: torch.Tensor, col_weights: torch.Tensor, costs: torch.Tensor,
+                      cost_offsets: torch.Tensor, max_rows: Optional[int] = None,
+                      max_cols: Optional[int] = None, opts: Optional[Opts] = None,
+                      want_plan: bool = False):
+    """Transport LPs over given FP64 cost matrices (see d2_emd_cost_batch in
+    d2.h).  Returns dist[m], status[m], (plan, plan_offsets)."""
+    opts = opts or Opts()
+    dev = _dev(h)
+
+    def prep(t, dt):
+        return t.to(device=dev, dtype=dt).contiguous()
+
+    roff, coff = prep(row_offsets, torch.int64), prep(col_offsets, torch.int64)
+    rw, cw = prep(row_weights, torch.float64), prep(col_weights, torch.float64)
+    C, moff = prep(costs, torch.float64).reshape(-1), prep(cost_offsets, torch.int64)
+    m = int(roff.numel()) - 1
+    rs = roff[1:] - roff[:-1]
+    cs = coff[1:] - coff[:-1]
+    if max_rows is None:
+        max_rows = int(rs.max().item()) if m > 0 else 1
+    if max_cols is None:
+        max_cols = int(cs.max().item()) if m > 0 else 1
+    dist = torch.empty(m, dtype=torch.float64, device=dev)
+    status = torch.empty(m, dtype=torch.int32, device=dev)
+    plan = plan_off = None
+    if want_plan:
+        plan_off = _offsets_of(rs * cs)
+        plan = torch.empty(int(plan_off[-1].item()) if m else 0, dtype=torch.float64, device=dev)
+    o = opts.c()
+    check(_ffi.lib().d2_emd_cost_batch(h.ptr, m, _ptr(roff), _ptr(rw), _ptr(coff), _ptr(cw), _ptr(C),
+                                       _ptr(moff), int(max_rows), int(max_cols), ctypes.byref(o),
+                                       _ptr(dist), _ptr(plan_off), _ptr(plan), _ptr(status), None, 0,
+                                       _stream(dev)), "d2_emd_cost_batch")
+    return dist, status, (plan, plan_off)
+
+
+def d2_mm_distance(h: Handle, Z1: DeviceSet, p1: torch.Tensor, Z2: DeviceSet, p2: torch.Tensor,
+                   opts: Optional[Opts] = None):
+    """Squared MM distance of Eq. (10) between two centroid sets with cluster
+    proportions p1, p2: every D^2(z_i, z'_j) by d2_assign, then the transport
+    LP over the clusters on that matrix by d2_emd_cost_batch (both set sizes
+    at most 64).  Returns (MM^2 as a 0-d tensor, M [k1, k2], plan [k1, k2])."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    k1, k2 = Z1.n, Z2.n
+    _, _, M, st = d2_assign(h, Z1, Z2, opts, want_all=True)
+    off1 = torch.tensor([0, k1], dtype=torch.int64, device=dev)
+    off2 = torch.tensor([0, k2], dtype=torch.int64, device=dev)
+    zero = torch.zeros(1, dtype=torch.int64, device=dev)
+    dist, status, (plan, _) = d2_emd_cost_batch(h, off1, p1, off2, p2, M, zero, k1, k2, opts,
+                                                want_plan=True)
+    return dist[0], M, plan.reshape(k1, k2)

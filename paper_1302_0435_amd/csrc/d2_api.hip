@@ -327,6 +327,34 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
     });
 }
 
+d2_status d2_emd_cost_batch(d2_handle *h, int64_t nprob, const int64_t *row_offsets,
+                            const double *row_weights, const int64_t *col_offsets,
+                            const double *col_weights, const double *costs,
+                            const int64_t *cost_offsets, int32_t max_rows, int32_t max_cols,
+                            const d2_opts *opts, double *dist, const int64_t *plan_offsets,
+                            double *plan, int32_t *status, void *ws, size_t ws_bytes,
+                            void *stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (!h || nprob < 0) return D2_EINVAL;
+    if (max_rows < 1 || max_cols < 1) return D2_EINVAL;
+    if (max_rows > D2_MAX_SUPPORT || max_cols > D2_MAX_SUPPORT) return D2_EUNSUPPORTED;
+    KOpts k;
+    d2_status st = opts_ok(opts, k);
+    if (st != D2_OK) return st;
+    if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
+    if (nprob > 0 && (!row_offsets || !row_weights || !col_offsets || !col_weights || !costs ||
+                      !cost_offsets || !dist))
+        return D2_EINVAL;
+    if ((plan == nullptr) != (plan_offsets == nullptr)) return D2_EINVAL;
+    if ((st = bind_device(h)) != D2_OK) return st;
+    const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(max_rows, max_cols);
+    hipError_t e = d2::launch_emd_cost(ctx(h, (hipStream_t)stream), cls, nprob, row_offsets, row_weights,
+                                       col_offsets, col_weights, costs, cost_offsets, max_rows, max_cols, k,
+                                       dist, plan_offsets, plan, status);
+    return e == hipSuccess ? D2_OK : D2_EHIP;
+}
+
 d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *labels,
                              const d2_opts *opts, double *z_new, double *eps_step1, double *eps_step3,
                              int32_t *counts, int32_t *obj_status, void *ws, size_t ws_bytes,

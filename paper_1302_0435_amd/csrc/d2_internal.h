@@ -80,6 +80,12 @@ hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
                              const int64_t *pairs, int64_t npairs, int cost_mode, double *tiles,
                              const int64_t *tile_off);
 
+// The transport LP over caller-given FP64 cost matrices.
+hipError_t launch_emd_cost(const LaunchCtx &c, int cls, int64_t nprob, const int64_t *roff, const double *rw,
+                           const int64_t *coff, const double *cw, const double *cost, const int64_t *moff,
+                           int max_rows, int max_cols, const KOpts &o, double *dist, const int64_t *plan_off,
+                           double *plan, int32_t *status);
+
 // Centroid update with fixed centroid weights (Alg. 2 Step 3*): workspace
 // size and the enqueue of the whole pass.
 size_t update_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax);

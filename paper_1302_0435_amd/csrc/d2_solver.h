@@ -393,6 +393,13 @@ __device__ __forceinline__ void anc_by_jumping(GroupMem<G, GS> &M, NodeState<G, 
 
 // ------------------------------------------------------------ one solve
 
+// Integer key with the order of the double: negative values have every bit
+// flipped, others only the sign bit.
+__device__ __forceinline__ unsigned long long ordered_bits(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
 struct SolveOut {
     int status;
     double d2;
@@ -403,10 +410,16 @@ struct SolveOut {
 // and potentials (valid when status == kOk).
 // `ctile`, when given, is this pair's cost tile already computed (row-major,
 // 32 columns, oriented like the pair); otherwise costs come from the points.
-template <int G, int GS, bool LT, typename TIn, int START, typename TileT>
+//
+// GIVEN: the costs are the caller's FP64 matrix `gcost` instead of points:
+// row l, column j of the oriented pair is gcost[l * grs + j * gcs].  Such
+// costs may be negative, so the tolerance scales with max |C| and the
+// least-cost start orders costs by an order-preserving integer key.
+template <int G, int GS, bool LT, typename TIn, int START, typename TileT, bool GIVEN = false>
 __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS, LT> &N,
                                                const PairView &pv, int d, const KOpts &o, int l, int gbase,
-                                               const float *ctile = nullptr) {
+                                               const float *ctile = nullptr, const double *gcost = nullptr,
+                                               int64_t grs = 0, int64_t gcs = 0) {
     SolveOut out{kOk, __builtin_nan("")};
     const int T = pv.T, S = pv.S;
     if (T < 1 || S < 1 || T > G || S > GS) { out.status = kTooLarge; return out; }
@@ -436,7 +449,13 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     // shapes accumulate straight into the register row; the LDS-tile shape
     // goes in blocks of 16 columns.
     const int Sw = wave_max<G>(S);
-    if (ctile) {
+    if constexpr (GIVEN) {
+#pragma unroll
+        for (int j = 0; j < GS; ++j) {
+            const double c = (hasR && j < S) ? gcost[(int64_t)l * grs + (int64_t)j * gcs] : INFINITY;
+            put_cost<G, GS, LT>(N, tile, l, j, c);
+        }
+    } else if (ctile) {
         if constexpr (GS <= 32) {
 #pragma unroll
             for (int j = 0; j < GS; ++j) {
@@ -524,7 +543,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         const bool live = hasR && j < S;
         const double c = cost_at<G, GS, LT>(N, tile, l, j);
         finite = finite & (!live | isfinite(c));
-        cmax = live ? fmax(cmax, c) : cmax;
+        cmax = live ? fmax(cmax, GIVEN ? fabs(c) : c) : cmax;
     }
     if (group_bits<G>(!finite, gbase) != 0ull) { out.status = kBadPoints; return out; }
     cmax = group_max<G>(cmax);
@@ -586,10 +605,13 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
             }
             const bool open = hasR && ((rowon >> l) & 1u);
             // Proposal key: the cost's bits (non-negative doubles order as
-            // integers) with the row in the low 6 bits, so one 64-bit
-            // minimum per column picks the cheapest, then the lowest row.
+            // integers; given costs of either sign through an
+            // order-preserving map) with the row in the low 6 bits, so one
+            // 64-bit minimum per column picks the cheapest, then the lowest
+            // row.
             const unsigned long long key =
-                (((unsigned long long)__double_as_longlong(m1)) & ~63ull) | (unsigned long long)l;
+                ((GIVEN ? ordered_bits(m1) : (unsigned long long)__double_as_longlong(m1)) & ~63ull) |
+                (unsigned long long)l;
             if (l < GS) { M.u.lcm.key[l] = ~0ull; M.u.lcm.row[l] = -1; }
             if (l == 0) M.u.lcm.gkey = ~0ull;
             wsync();
