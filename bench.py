@@ -91,6 +91,8 @@ def profile_counters(cfg: int, cost: str, op: str = "assign"):
     elif op == "cost":
         kv = _read_profile(COST_PROFILES.get(cfg, ""))
         sha = kernel_sha(COST_SRCS)
+    elif op != "assign":
+        return None   # no committed profile of this workload
     else:
         kv = _read_profile(PROFILES.get((cfg, cost), ""))
         sha = kernel_sha()
@@ -563,6 +565,90 @@ class CostWorkload:
                 "cpu_model": _cpu_model(), "parity_checked": done, "parity_failures": fails}
 
 
+class MultiWorkload:
+    """d2_assign_multi: labelling under the combined distance of Eq. (9) with
+    two feature types at configuration 2's scale: the configuration's objects
+    and an independent draw of the same law as the second type, against its
+    512 centroids and a rotation of them (points shifted by one centroid) as
+    the second type's."""
+
+    metric = "combined two-type Mallows distances/sec (Eq. (9)), exact FP64"
+    unit = "distances/s"
+
+    def __init__(self, cfg, d2, dev, init, schedule, n=None):
+        import synth
+        self.cfg = cfg
+        self.spec = synth.CONFIGS[cfg]
+        X1 = synth.make_data(cfg, n=n)
+        X2 = synth.make_data(cfg, n=X1.n, chunk=1)
+        Z1 = synth.make_centroids(cfg)
+        Z2 = synth.RaggedSet(Z1.offsets, np.roll(Z1.points, Z1.max_support, axis=0), Z1.weights)
+        self.Xs, self.Zs = [X1, X2], [Z1, Z2]
+        self.d2 = d2
+        self.h = d2.Handle(0)
+        self.Xd = [d2.DeviceSet.from_ragged(X, dev) for X in self.Xs]
+        self.Zd = [d2.DeviceSet.from_ragged(Z, dev) for Z in self.Zs]
+        self.opts = d2.Opts(init=init, schedule=schedule)
+        self.pairs = X1.n * Z1.n
+        self.out = None
+
+    def step(self):
+        self.out = self.d2.d2_assign_multi(self.h, self.Xd, self.Zd, self.opts)
+
+    def flops(self):
+        tot = 0.0
+        for X, Z in zip(self.Xs, self.Zs):
+            ts = np.diff(X.offsets).astype(np.float64)
+            ss = np.diff(Z.offsets).astype(np.float64)
+            tot += float(ts.sum() * ss.sum() * (3 * X.points.shape[1] + 3))
+        return tot
+
+    def bytes(self):
+        b = sum(float(X.points.nbytes + X.weights.nbytes + X.offsets.nbytes) for X in self.Xs)
+        b += sum(float(Z.points.nbytes + Z.weights.nbytes + Z.offsets.nbytes) for Z in self.Zs)
+        # per type: the n x K matrix written, read back once by the sum or argmin
+        return b + 2 * self.pairs * 8 * 2 + self.Xs[0].n * 12
+
+    def failed(self):
+        return int((self.out[3].cpu().numpy() != 0).sum())
+
+    def config(self):
+        s = self.spec
+        return {"workload": s["name"] + " x 2 feature types (Eq. (9))", "n": self.Xs[0].n,
+                "k": self.Zs[0].n, "d": self.Xs[0].points.shape[1], "t_range": list(s["t_range"]),
+                "s": s["s"], "inputs": s["dtype"], "types": 2, "lps_per_step": 2 * self.pairs}
+
+    def cpu_baseline(self, target_s, init_oracle):
+        """The oracle's combined labelling on a seeded row sample; also checks
+        the device's labels and minima there."""
+        import oracle
+        import synth
+        g_lab = self.out[0].cpu().numpy()
+        g_best = self.out[1].cpu().numpy()
+        rows = synth.sample_rows(self.cfg, self.Xs[0].n, 16, tag=5)
+        t0 = time.perf_counter()
+        oracle.assign_multi([X.subset(rows) for X in self.Xs], self.Zs, init=init_oracle)
+        per_row = (time.perf_counter() - t0) / len(rows)
+        k = int(min(self.Xs[0].n, max(16, target_s / max(per_row, 1e-9))))
+        rows = synth.sample_rows(self.cfg, self.Xs[0].n, k, tag=6)
+        t0 = time.perf_counter()
+        o_lab, o_best, o_all, o_st = oracle.assign_multi([X.subset(rows) for X in self.Xs], self.Zs,
+                                                         init=init_oracle)
+        dt = time.perf_counter() - t0
+        fails = 0
+        for q, i in enumerate(rows):
+            if g_lab[i] == o_lab[q] and abs(g_best[i] - o_best[q]) <= 1e-10 * abs(o_best[q]):
+                continue
+            gap = o_all[q, g_lab[i]] - o_best[q] if g_lab[i] >= 0 else np.inf
+            if not (gap <= 1e-10 * abs(o_best[q]) and abs(g_best[i] - o_best[q]) <= 1e-10 * abs(o_best[q])):
+                fails += 1
+        return {"value": len(rows) * self.Zs[0].n / dt, "unit": "distances/s",
+                "cores": oracle.default_threads(), "kind": "oracle",
+                "sample": f"{len(rows)} seeded rows x all {self.Zs[0].n} centroids x 2 types, {dt:.1f} s, "
+                          f"{'Vogel' if init_oracle else 'north-west-corner'} start",
+                "cpu_model": _cpu_model(), "parity_checked": len(rows), "parity_failures": fails}
+
+
 def make_pool(n_pool: int):
     """Query pool for the serving workload (configuration 5, stream 1)."""
     import synth
@@ -640,9 +726,10 @@ def main(argv=None) -> int:
     ap.add_argument("--cost", choices=["f64", "bf16"], default="f64",
                     help="ground-cost arithmetic (bf16: MFMA tiles, supports <= 32)")
     ap.add_argument("--tune", action="store_true", help="autotune the pairwise schedule first")
-    ap.add_argument("--op", choices=["assign", "update", "cost"], default="assign",
+    ap.add_argument("--op", choices=["assign", "update", "cost", "multi"], default="assign",
                     help="update: the constrained D2 centroid update (configurations 1-3); "
-                         "cost: LPs over given cost matrices (configuration 2 shapes)")
+                         "cost: LPs over given cost matrices (configuration 2 shapes); "
+                         "multi: two-type labelling of Eq. (9) (configuration 2 scale)")
     ap.add_argument("--n", type=int, default=None, help="override object count (testing)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -673,6 +760,8 @@ def main(argv=None) -> int:
         w = UpdateWorkload(args.config, d2, dev, init, schedule, n=args.n)
     elif args.op == "cost":
         w = CostWorkload(2, d2, dev, init, schedule, rows=args.n or 4000)
+    elif args.op == "multi":
+        w = MultiWorkload(2, d2, dev, init, schedule, n=args.n)
     elif args.config == 4:
         w = PairwiseWorkload(4, d2, dev, init, schedule, n=args.n, tune=args.tune)
     else:

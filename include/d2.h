@@ -142,8 +142,10 @@ const char *d2_version(void);
 
 /* Bytes of device workspace the call with these arguments needs (may be 0).
  * `which` is 0 = d2_cost_tiles, 1 = d2_emd_batch, 2 = d2_assign,
- * 3 = d2_pairwise, 4 = d2_centroid_update (A = X, B = Z); `npairs` is the
- * pair count for 0 and 1, ignored otherwise; B may be NULL for d2_pairwise. */
+ * 3 = d2_pairwise, 4 = d2_centroid_update (A = X, B = Z), 5 =
+ * d2_assign_multi (A, B = the arrays of per-type sets, npairs = the number of
+ * types); `npairs` is the pair count for 0 and 1, ignored for 2-4; B may be
+ * NULL for d2_pairwise. */
 size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set *B,
                           int64_t npairs, const d2_opts *opts);
 
@@ -240,6 +242,21 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
                              const d2_opts *opts, double *z_new, double *eps_step1, double *eps_step3,
                              int32_t *counts, int32_t *obj_status, void *ws, size_t ws_bytes,
                              void *stream);
+
+/* Nearest-centroid labelling under the combined distance of Eq. (9), for
+ * objects described by several distributions (one per feature type, such as
+ * an image's colour bag and texture bag):
+ *     D^2(I_i, C_j) = sum over types m of D^2(X[m]_i, Z[m]_j).
+ * X[0..ntypes), Z[0..ntypes): host arrays of sets, type m of every object and
+ * of every centroid; all X[m] share n and all Z[m] share K (dimensions and
+ * supports may differ between types).  1 <= ntypes <= 16.  labels, best,
+ * all (the summed matrix, nullable), row_status (the worst status over the
+ * types, nullable) as for d2_assign; a row with any failed pair gets
+ * label -1.  Workspace: d2_workspace_bytes(h, 5, X, Z, ntypes, opts)
+ * (required; it holds two n x K matrices). */
+d2_status d2_assign_multi(d2_handle *h, int32_t ntypes, const d2_set *X, const d2_set *Z,
+                          const d2_opts *opts, int32_t *labels, double *best, double *all,
+                          int32_t *row_status, void *ws, size_t ws_bytes, void *stream);
 
 /* All unordered pairs i<j of one set (one segment's pairwise matrix):
  * condensed[k] for k = i*n - i*(i+1)/2 + (j-i-1), the order of

@@ -13,6 +13,7 @@ with ctypes, and widens every input to FP64 exactly before the call.
                                          (``update.py``: Alg. 2 Step 3*)
     emd_cost(C, p, q)                 -> (value, plan, u, v, pivots), given cost
     mm_distance(Z1, p1, Z2, p2)       -> (MM^2, D^2 matrix, plan)  (``mm.py``: Eq. (10))
+    assign_multi(Xs, Zs)              -> (labels, best, summed all, status)  (``multi.py``: Eq. (9))
 
 Sets are ``synth.RaggedSet``-like objects with ``offsets``, ``points``,
 ``weights``.  Labels follow Alg. 2 Step 2 (argmin over centroids, ties to the
@@ -203,3 +204,4 @@ def independent_coupling_cost(x, p, y, q) -> float:
 
 from .update import centroid_update  # noqa: E402  (uses emd_pair above)
 from .mm import mm_distance  # noqa: E402  (uses assign and emd_cost above)
+from .multi import assign_multi  # noqa: E402  (uses assign above)

@@ -16,6 +16,7 @@ the stream.
     dist, status, (plan, plan_off) = d2_emd_cost_batch(h, row_off, row_w, col_off, col_w,
                                                        costs, cost_off)
     mm2, M, plan = d2_mm_distance(h, Z1, p1, Z2, p2)   # Eq. (10)
+    labels, best, all_, status = d2_assign_multi(h, [X_colour, X_texture], [Z_colour, Z_texture])
 """
 from __future__ import annotations
 
@@ -384,3 +385,28 @@ def d2_mm_distance(h: Handle, Z1: DeviceSet, p1: torch.Tensor, Z2: DeviceSet, p2
     dist, status, (plan, _) = d2_emd_cost_batch(h, off1, p1, off2, p2, M, zero, k1, k2, opts,
                                                 want_plan=True)
     return dist[0], M, plan.reshape(k1, k2)
+
+
+def d2_assign_multi(h: Handle, Xs, Zs, opts: Optional[Opts] = None, want_all: bool = False):
+    """Nearest-centroid labels under the combined distance of Eq. (9): the sum
+    over feature types of the per-type D^2.  Xs, Zs: lists of DeviceSet, one
+    per type.  Returns labels[n], best[n], all[n, K] or None, row_status[n]."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    m = len(Xs)
+    if m != len(Zs) or m < 1:
+        raise ValueError("one centroid set per object set")
+    xs = (_ffi.d2_set * m)(*[X.c() for X in Xs])
+    zs = (_ffi.d2_set * m)(*[Z.c() for Z in Zs])
+    n, K = Xs[0].n, Zs[0].n
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    best = torch.empty(n, dtype=torch.float64, device=dev)
+    allv = torch.empty((n, K), dtype=torch.float64, device=dev) if want_all else None
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    o = opts.c()
+    nbytes = int(_ffi.lib().d2_workspace_bytes(h.ptr, _ffi.WHICH_MULTI, xs, zs, m, ctypes.byref(o)))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    check(_ffi.lib().d2_assign_multi(h.ptr, m, xs, zs, ctypes.byref(o), _ptr(labels), _ptr(best),
+                                     _ptr(allv), _ptr(status), _ptr(ws), nbytes, _stream(dev)),
+          "d2_assign_multi")
+    return labels, best, allv, status

@@ -174,6 +174,26 @@ d2_status run_graph(d2_handle *h, int which, const uint64_t *key, bool eager, hi
     return hipGraphLaunch(exec, stream) == hipSuccess ? D2_OK : D2_EHIP;
 }
 
+constexpr int kMaxTypes = 16;
+
+// Checks the sets of a multi-type call and plans each type's labelling;
+// returns the largest per-type workspace through *assign_bytes.
+d2_status multi_plans(d2_handle *h, int ntypes, const d2_set *X, const d2_set *Z, int sched, int cost_mode,
+                      d2::AssignPlan *plans, size_t *assign_bytes) {
+    if (ntypes < 1 || ntypes > kMaxTypes || !X || !Z) return D2_EINVAL;
+    size_t mx = 0;
+    for (int m = 0; m < ntypes; ++m) {
+        d2_status st = pair_sets_ok(&X[m], &Z[m]);
+        if (st != D2_OK) return st;
+        if (X[m].n != X[0].n || Z[m].n != Z[0].n) return D2_EINVAL;
+        if (cost_mode == D2_COST_BF16_MFMA && (ms(&X[m]) > 32 || ms(&Z[m]) > 32)) return D2_EUNSUPPORTED;
+        plans[m] = d2::plan_assign(kset(&X[m]), kset(&Z[m]), ms(&X[m]), ms(&Z[m]), h->cu_count, sched, cost_mode);
+        if (plans[m].ws_bytes > mx) mx = plans[m].ws_bytes;
+    }
+    *assign_bytes = mx;
+    return D2_OK;
+}
+
 d2::Schedule schedule_for(d2_handle *h, const d2_set *X, const KOpts &k) {
     for (auto &t : h->tuned)
         if (t.n == X->n && t.d == X->d && t.dtype == X->dtype && t.max_support == X->max_support &&
@@ -248,6 +268,14 @@ size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set
     }
     if (which == 3) return d2::plan_pairwise(kset(A), ms(A), sched).ws_bytes;
     if (which == 4 && B && set_ok(B)) return d2::update_ws_bytes(A->n, B->n, A->d, ms(A), ms(B));
+    if (which == 5 && B) {
+        d2::AssignPlan plans[kMaxTypes];
+        size_t ab = 0;
+        if (multi_plans(h, (int)npairs, A, B, sched, opts ? opts->cost_mode : D2_COST_F64_DIRECT, plans, &ab) !=
+            D2_OK)
+            return 0;
+        return d2::multi_ws_bytes(A->n, B->n, ab);
+    }
     return 0;
 }
 
@@ -376,6 +404,30 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
     const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(ms(X), ms(Z));
     hipError_t e = d2::launch_update(ctx(h, (hipStream_t)stream), cls, kset(X), kset(Z), ms(X), ms(Z), k,
                                      labels, z_new, eps_step1, eps_step3, counts, obj_status, ws);
+    return e == hipSuccess ? D2_OK : D2_EHIP;
+}
+
+d2_status d2_assign_multi(d2_handle *h, int32_t ntypes, const d2_set *X, const d2_set *Z,
+                          const d2_opts *opts, int32_t *labels, double *best, double *all,
+                          int32_t *row_status, void *ws, size_t ws_bytes, void *stream) {
+    if (!h) return D2_EINVAL;
+    KOpts k;
+    d2_status st = opts_ok(opts, k);
+    if (st != D2_OK) return st;
+    d2::AssignPlan plans[kMaxTypes];
+    size_t ab = 0;
+    if ((st = multi_plans(h, ntypes, X, Z, sched_of(opts), k.cost_mode, plans, &ab)) != D2_OK) return st;
+    const int64_t n = X[0].n, K = Z[0].n;
+    if (n > 0 && (!labels || !best)) return D2_EINVAL;
+    if (n > 0 && K < 1) return D2_EINVAL;
+    if (K > INT32_MAX) return D2_EUNSUPPORTED;
+    const size_t need = d2::multi_ws_bytes(n, K, ab);
+    if (!ws || ws_bytes < need) return D2_EWORKSPACE;
+    if ((st = bind_device(h)) != D2_OK) return st;
+    KSet kx[kMaxTypes], kz[kMaxTypes];
+    for (int m = 0; m < ntypes; ++m) { kx[m] = kset(&X[m]); kz[m] = kset(&Z[m]); }
+    hipError_t e = d2::launch_assign_multi(ctx(h, (hipStream_t)stream), ntypes, plans, kx, kz, k, labels, best,
+                                           all, row_status, ws, ab);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 

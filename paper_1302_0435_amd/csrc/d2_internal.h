@@ -80,6 +80,12 @@ hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
                              const int64_t *pairs, int64_t npairs, int cost_mode, double *tiles,
                              const int64_t *tile_off);
 
+// Labelling under the multi-type distance of Eq. (9).
+size_t multi_ws_bytes(int64_t n, int64_t K, size_t assign_bytes);
+hipError_t launch_assign_multi(const LaunchCtx &c, int ntypes, const AssignPlan *plans, const KSet *X,
+                               const KSet *Z, const KOpts &o, int32_t *labels, double *best, double *all,
+                               int32_t *row_status, void *ws, size_t assign_bytes);
+
 // The transport LP over caller-given FP64 cost matrices.
 hipError_t launch_emd_cost(const LaunchCtx &c, int cls, int64_t nprob, const int64_t *roff, const double *rw,
                            const int64_t *coff, const double *cw, const double *cost, const int64_t *moff,
