@@ -222,12 +222,17 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
  * any fixed non-negative weights are accepted (normalised by their sum).
  *   labels[n]      device int32, e.g. from d2_assign.  Objects whose label is
  *                  outside [0, K) are left out (status D2_PAIR_UNLABELLED).
+ *   obj_weights[n] device FP64, nullable (all 1): the object weights of
+ *                  weighted D2-clustering (Eq. (3)); each member's flows
+ *                  count with its weight in both sums of Eq. (4), and its
+ *                  D^2 terms in both objectives.  A negative or non-finite
+ *                  weight gives status D2_PAIR_BAD_WEIGHTS (left out).
  *   z_new          device FP64 [Z.offsets[K]][d]: the moved atoms, in the
  *                  layout of Z.points, which it must not overlap.  An atom
  *                  that receives no flow (empty cluster, zero weight) keeps
  *                  its coordinates.
  *   eps_step1[K]   device FP64, nullable: sum of the members' D^2 to the old
- *                  atoms (the Step 1 objective).
+ *                  atoms, each times its weight (the Step 1 objective).
  *   eps_step3[K]   device FP64, nullable: the Step 3 objective.
  *   counts[K]      device int32, nullable: members that entered Step 2.
  *   obj_status[n]  device int32, nullable: D2_PAIR_* of each object; an
@@ -239,9 +244,23 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
  * direct cost only (D2_COST_BF16_MFMA: D2_EUNSUPPORTED); opts->want_sqrt is
  * ignored.  Always enqueued directly (no graph is recorded). */
 d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *labels,
-                             const d2_opts *opts, double *z_new, double *eps_step1, double *eps_step3,
-                             int32_t *counts, int32_t *obj_status, void *ws, size_t ws_bytes,
-                             void *stream);
+                             const double *obj_weights, const d2_opts *opts, double *z_new,
+                             double *eps_step1, double *eps_step3, int32_t *counts,
+                             int32_t *obj_status, void *ws, size_t ws_bytes, void *stream);
+
+/* Nearest-centroid labelling within segments (Alg. 3 Step 2, where each
+ * segment of the data is clustered on its own): object i is compared only
+ * with the centroids zseg_offsets[seg[i]] .. zseg_offsets[seg[i]+1] of Z.
+ *   seg[n]             device int32, the segment of each object;
+ *   zseg_offsets[nseg+1]  device int64, each segment's centroid range.
+ * labels[i] is the global index in Z of the nearest of them (ties: lowest),
+ * best[i] its D^2; an object whose segment is outside [0, nseg) or has no
+ * centroids gets label -1 and status D2_PAIR_UNLABELLED; any failed pair
+ * gives label -1 and the worst status.  row_status[n] may be NULL.  No
+ * workspace.  FP64 direct cost only. */
+d2_status d2_assign_segmented(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *seg,
+                              int64_t nseg, const int64_t *zseg_offsets, const d2_opts *opts,
+                              int32_t *labels, double *best, int32_t *row_status, void *stream);
 
 /* Nearest-centroid labelling under the combined distance of Eq. (9), for
  * objects described by several distributions (one per feature type, such as

@@ -25,7 +25,7 @@ WHICH_COST_TILES, WHICH_EMD_BATCH, WHICH_ASSIGN, WHICH_PAIRWISE, WHICH_UPDATE, W
 EXPORTS = ["d2_create", "d2_destroy", "d2_status_string", "d2_max_support", "d2_version",
            "d2_workspace_bytes", "d2_cost_tiles", "d2_emd_batch", "d2_assign", "d2_pairwise",
            "d2_tune_pairwise", "d2_centroid_update", "d2_emd_cost_batch",
-           "d2_assign_multi"]
+           "d2_assign_multi", "d2_assign_segmented"]
 
 
 class d2_set(ctypes.Structure):
@@ -74,12 +74,13 @@ def lib():
     L.d2_assign.argtypes = [P, S, S, O, P, P, P, P, P, SZ, P]
     L.d2_pairwise.argtypes = [P, S, O, P, P, P, SZ, P]
     L.d2_tune_pairwise.argtypes = [P, S, O, P, P, P, SZ, P, ctypes.POINTER(ctypes.c_double)]
-    L.d2_centroid_update.argtypes = [P, S, S, P, O, P, P, P, P, P, P, SZ, P]
+    L.d2_centroid_update.argtypes = [P, S, S, P, P, O, P, P, P, P, P, P, SZ, P]
+    L.d2_assign_segmented.argtypes = [P, S, S, P, I64, P, O, P, P, P, P]
     L.d2_assign_multi.argtypes = [P, I32, S, S, O, P, P, P, P, P, SZ, P]
     L.d2_emd_cost_batch.argtypes = [P, I64, P, P, P, P, P, P, I32, I32, O, P, P, P, P, P, SZ, P]
     for name in ("d2_create", "d2_destroy", "d2_cost_tiles", "d2_emd_batch", "d2_assign",
                  "d2_pairwise", "d2_max_support", "d2_tune_pairwise", "d2_centroid_update",
-                 "d2_emd_cost_batch", "d2_assign_multi"):
+                 "d2_emd_cost_batch", "d2_assign_multi", "d2_assign_segmented"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

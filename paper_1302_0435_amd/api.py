@@ -268,14 +268,17 @@ def d2_cost_tiles(h: Handle, A: DeviceSet, B: DeviceSet, pairs: torch.Tensor,
 
 
 def d2_centroid_update(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch.Tensor,
-                       opts: Optional[Opts] = None):
-    """One pass of the constrained D2 centroid update (Alg. 2 Step 3*).
+                       opts: Optional[Opts] = None, weights: Optional[torch.Tensor] = None):
+    """One pass of the constrained D2 centroid update (Alg. 2 Step 3*), with
+    optional object weights (weighted D2-clustering, Eq. (3)-(4)).
 
     Returns z_new [Z.offsets[K], d] f64, eps_step1 [K] f64, eps_step3 [K] f64,
     counts [K] int32, status [n] int32 (see d2_centroid_update in d2.h)."""
     opts = opts or Opts()
     dev = _dev(h)
     labels = labels.to(device=dev, dtype=torch.int32).contiguous()
+    if weights is not None:
+        weights = weights.to(device=dev, dtype=torch.float64).contiguous()
     K = Z.n
     z_new = torch.empty((int(Z.points.shape[0]), Z.d), dtype=torch.float64, device=dev)
     eps1 = torch.empty(K, dtype=torch.float64, device=dev)
@@ -285,7 +288,8 @@ def d2_centroid_update(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch.Tens
     ws, nbytes = _workspace(h, _ffi.WHICH_UPDATE, X, Z, 0, opts)
     x, z, o = X.c(), Z.c(), opts.c()
     check(_ffi.lib().d2_centroid_update(h.ptr, ctypes.byref(x), ctypes.byref(z), _ptr(labels),
-                                        ctypes.byref(o), _ptr(z_new), _ptr(eps1), _ptr(eps3),
+                                        _ptr(weights), ctypes.byref(o), _ptr(z_new), _ptr(eps1),
+                                        _ptr(eps3),
                                         _ptr(counts), _ptr(status), _ptr(ws), nbytes,
                                         _stream(dev)), "d2_centroid_update")
     return z_new, eps1, eps3, counts, status
@@ -410,3 +414,25 @@ def d2_assign_multi(h: Handle, Xs, Zs, opts: Optional[Opts] = None, want_all: bo
                                      _ptr(allv), _ptr(status), _ptr(ws), nbytes, _stream(dev)),
           "d2_assign_multi")
     return labels, best, allv, status
+
+
+def d2_assign_segmented(h: Handle, X: DeviceSet, Z: DeviceSet, seg: torch.Tensor,
+                        zseg_offsets: torch.Tensor, opts: Optional[Opts] = None):
+    """Nearest centroid of each object among its own segment's centroids
+    (Alg. 3 Step 2).  seg[n]: segment of each object; zseg_offsets[nseg+1]:
+    each segment's range of Z.  Returns labels[n] (global centroid index),
+    best[n], row_status[n]."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    seg = seg.to(device=dev, dtype=torch.int32).contiguous()
+    zoff = zseg_offsets.to(device=dev, dtype=torch.int64).contiguous()
+    n = X.n
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    best = torch.empty(n, dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    x, z, o = X.c(), Z.c(), opts.c()
+    check(_ffi.lib().d2_assign_segmented(h.ptr, ctypes.byref(x), ctypes.byref(z), _ptr(seg),
+                                         int(zoff.numel()) - 1, _ptr(zoff), ctypes.byref(o),
+                                         _ptr(labels), _ptr(best), _ptr(status), _stream(dev)),
+          "d2_assign_segmented")
+    return labels, best, status

@@ -384,9 +384,9 @@ d2_status d2_emd_cost_batch(d2_handle *h, int64_t nprob, const int64_t *row_offs
 }
 
 d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *labels,
-                             const d2_opts *opts, double *z_new, double *eps_step1, double *eps_step3,
-                             int32_t *counts, int32_t *obj_status, void *ws, size_t ws_bytes,
-                             void *stream) {
+                             const double *obj_weights, const d2_opts *opts, double *z_new,
+                             double *eps_step1, double *eps_step3, int32_t *counts,
+                             int32_t *obj_status, void *ws, size_t ws_bytes, void *stream) {
     if (!h) return D2_EINVAL;
     d2_status st = pair_sets_ok(X, Z);
     if (st != D2_OK) return st;
@@ -403,7 +403,7 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
     if (X->n == 0 && Z->n == 0) return D2_OK;
     const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(ms(X), ms(Z));
     hipError_t e = d2::launch_update(ctx(h, (hipStream_t)stream), cls, kset(X), kset(Z), ms(X), ms(Z), k,
-                                     labels, z_new, eps_step1, eps_step3, counts, obj_status, ws);
+                                     labels, obj_weights, z_new, eps_step1, eps_step3, counts, obj_status, ws);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 
@@ -428,6 +428,24 @@ d2_status d2_assign_multi(d2_handle *h, int32_t ntypes, const d2_set *X, const d
     for (int m = 0; m < ntypes; ++m) { kx[m] = kset(&X[m]); kz[m] = kset(&Z[m]); }
     hipError_t e = d2::launch_assign_multi(ctx(h, (hipStream_t)stream), ntypes, plans, kx, kz, k, labels, best,
                                            all, row_status, ws, ab);
+    return e == hipSuccess ? D2_OK : D2_EHIP;
+}
+
+d2_status d2_assign_segmented(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *seg,
+                              int64_t nseg, const int64_t *zseg_offsets, const d2_opts *opts,
+                              int32_t *labels, double *best, int32_t *row_status, void *stream) {
+    if (!h || nseg < 0) return D2_EINVAL;
+    d2_status st = pair_sets_ok(X, Z);
+    if (st != D2_OK) return st;
+    KOpts k;
+    if ((st = opts_ok(opts, k)) != D2_OK) return st;
+    if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
+    if (X->n > 0 && (!seg || !labels || !best || (nseg > 0 && !zseg_offsets))) return D2_EINVAL;
+    if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
+    if ((st = bind_device(h)) != D2_OK) return st;
+    const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(ms(X), ms(Z));
+    hipError_t e = d2::launch_assign_seg(ctx(h, (hipStream_t)stream), cls, kset(X), kset(Z), k, seg, nseg,
+                                         zseg_offsets, labels, best, row_status);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 

@@ -97,7 +97,13 @@ hipError_t launch_emd_cost(const LaunchCtx &c, int cls, int64_t nprob, const int
 size_t update_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax);
 void update_mean_shape(int d, int zmax, int *kb, int *P);
 hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet &Z, int xmax, int zmax,
-                         const KOpts &o, const int32_t *labels, double *z_new, double *eps1, double *eps3,
-                         int32_t *counts, int32_t *obj_status, void *ws);
+                         const KOpts &o, const int32_t *labels, const double *obj_weights, double *z_new,
+                         double *eps1, double *eps3, int32_t *counts, int32_t *obj_status, void *ws);
+
+// Labelling within segments: object i against the centroids
+// zoff[seg[i]] .. zoff[seg[i]+1] of Z only.
+hipError_t launch_assign_seg(const LaunchCtx &c, int cls, const KSet &X, const KSet &Z, const KOpts &o,
+                             const int32_t *seg, int64_t nseg, const int64_t *zoff, int32_t *labels,
+                             double *best, int32_t *row_status);
 
 }  // namespace d2

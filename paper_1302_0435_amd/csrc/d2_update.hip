@@ -21,6 +21,8 @@
 //   eps      Step 3: one wave per member evaluates its plan against the
 //            moved atoms; the members' Step 1 and Step 3 values are summed
 //            per item, then per cluster.
+// Optional object weights (weighted D2-clustering, Eq. (3)-(4)) scale each
+// member's flows in both sums of Eq. (4) and its terms of the objectives.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -54,6 +56,7 @@ struct UpdWS {
     double *part;     // [items][zmax][d+1]: partial numerators, flow total last
     double *ie1, *ie3;   // [items]: partial objectives
     int64_t *icnt;    // [items]: members that entered Step 2
+    const double *objw;  // caller's object weights (Eq. (3)), or null for 1
 };
 
 struct UpdDims {
@@ -97,6 +100,7 @@ size_t upd_layout(const UpdDims &u, void *base, UpdWS *w) {
     s.ie1 = (double *)take((size_t)u.items * 8);
     s.ie3 = (double *)take((size_t)u.items * 8);
     s.icnt = (int64_t *)take((size_t)u.items * 8);
+    s.objw = nullptr;
     if (w) *w = s;
     return off;
 }
@@ -282,7 +286,10 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_
         NodeState<G, GS, LT> N;
         PairView pv = orient(X, i, Z, j, (int)sizeof(TIn));
         // the cell list and the mean's LDS rows are sized by the declared bounds
-        if (t >= 1 && s >= 1 && t <= xmax && s <= zmax)
+        const double om = w.objw ? w.objw[i] : 1.0;
+        if (!(om >= 0.0 && isfinite(om)))
+            r.status = kBadWeights;
+        else if (t >= 1 && s >= 1 && t <= xmax && s <= zmax)
             r = solve_pair<G, GS, LT, TIn, START>(mem[g], tiles_lds[g], N, pv, X.d, o, l, gbase);
         if (r.status == kOk) {
             const int T = pv.T, S = pv.S;
@@ -341,6 +348,7 @@ __global__ __launch_bounds__(256) void k_upd_partial(KSet X, KSet Z, UpdWS w, in
             for (int64_t m = lo + p; m < hi; m += P) {
                 if (w.stm[m] != kOk) continue;
                 const int64_t i = w.perm[m];
+                const double om = w.objw ? w.objw[i] : 1.0;   // Eq. (4): flows weighted by the object
                 const int64_t x0 = X.off[i];
                 const int ncell = (int)(X.off[i + 1] - x0 + S);
                 const int32_t *code = w.code + m * cs;
@@ -351,7 +359,7 @@ __global__ __launch_bounds__(256) void k_upd_partial(KSet X, KSet Z, UpdWS w, in
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         cd[u] = q + u < ncell ? code[q + u] : -1;
-                        f[u] = q + u < ncell ? flow[q + u] : 0.0;
+                        f[u] = q + u < ncell ? flow[q + u] * om : 0.0;
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
@@ -454,8 +462,9 @@ __global__ __launch_bounds__(256) void k_upd_isums(UpdWS w, int64_t K, int64_t t
         double a1 = 0.0, a3 = 0.0;
         int64_t cnt = 0;
         if (m < m1 && w.stm[m] == kOk) {
-            a1 = w.d2m[m];
-            a3 = w.eps3m[m];
+            const double om = w.objw ? w.objw[w.perm[m]] : 1.0;
+            a1 = w.d2m[m] * om;
+            a3 = w.eps3m[m] * om;
             cnt = 1;
         }
         for (int sh = 32; sh >= 1; sh >>= 1) {
@@ -539,11 +548,12 @@ size_t update_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax) {
 }
 
 hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet &Z, int xmax, int zmax,
-                         const KOpts &o, const int32_t *labels, double *z_new, double *eps1, double *eps3,
-                         int32_t *counts, int32_t *obj_status, void *ws) {
+                         const KOpts &o, const int32_t *labels, const double *obj_weights, double *z_new,
+                         double *eps1, double *eps3, int32_t *counts, int32_t *obj_status, void *ws) {
     const UpdDims u = upd_dims(X.n, Z.n, X.d, xmax, zmax);
     UpdWS w;
     upd_layout(u, ws, &w);
+    w.objw = obj_weights;
     const bool f32 = X.dtype == D2_F32;
     hipError_t e;
     const unsigned wave_blocks = (unsigned)((u.tiles + 3) / 4);   // 4 waves per block

@@ -1,0 +1,168 @@
+"""Hierarchical D2-clustering of Alg. 3 on one GPU.
+
+The paper runs each level as three synchronised steps between a master and
+slave processors.  Here the master's work (segment bookkeeping, the merge
+of Eq. (5) and the inheritance of Eq. (6)) is host control over small
+integer arrays.  All distance and update work of the slaves, and of the
+segmentation, runs in the library on the GPU, every segment of a level at
+once:
+
+* ``d2_assign_segmented`` labels each object among its own segment's
+  centroids;
+* ``d2_centroid_update`` with object weights moves every centroid by
+  Eq. (4).
+
+Per level:
+
+1. **Segmentation (Sec. 2.3).**  Segments larger than tau are split in two
+   by constrained D2-clustering with two centroids, repeated until none is
+   larger.  All oversize segments split in the same round: a split depends
+   only on its own segment, so the result is the one the largest-first
+   order gives.
+2. **Clustering.**  Every segment is clustered into ceil(n_mu / e) groups
+   (tau = c e, Sec. 2.6) by weighted constrained D2-clustering (Eq. (3),
+   (4) with the centroid weights held uniform).
+3. **Merge.**  The segments' centroids are concatenated in segment order,
+   labels are offset (Eq. (5)) and inherited (Eq. (6)), and a centroid's
+   weight is the sum of its members' weights.  The hierarchy stops at the
+   first level with at most k centroids.
+
+The random choices (initial centroids) consume a caller-given stream of
+uniforms in a fixed order:
+
+* a split takes positions floor(u |S|) and then floor(u' (|S| - 1)) among
+  the rest;
+* a segment's picks are a partial Fisher-Yates shuffle.
+
+Each clustering runs ``rounds`` rounds of (labelling, ``passes`` weighted
+update passes) and then labels once more.  A split that leaves a side empty
+halves the segment instead.  A cluster left without members is dropped at
+the merge.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from .api import DeviceSet, Handle, Opts, d2_assign_segmented, d2_centroid_update
+
+
+class _Stream:
+    """Caller-given uniforms, consumed in order."""
+
+    def __init__(self, u):
+        self._u = np.asarray(u, dtype=np.float64).ravel()
+        self._k = 0
+
+    def take(self) -> float:
+        if self._k == self._u.size:
+            raise RuntimeError("the stream of uniforms ran out")
+        self._k += 1
+        return float(self._u[self._k - 1])
+
+
+def _gather(G: DeviceSet, g_off: np.ndarray, objs) -> tuple:
+    """A centroid set made of the atoms of objects `objs` of G (in that
+    order) with uniform weights; returns (DeviceSet, host offsets)."""
+    sizes = g_off[1:][objs] - g_off[:-1][objs]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    rows = np.concatenate([np.arange(g_off[o], g_off[o + 1]) for o in objs]) if len(objs) else \
+        np.zeros(0, dtype=np.int64)
+    w = np.concatenate([np.full(int(t), 1.0 / int(t)) for t in sizes]) if len(objs) else np.zeros(0)
+    dev = G.points.device
+    pts = G.points.index_select(0, torch.as_tensor(rows, device=dev))
+    Z = DeviceSet(torch.as_tensor(off, device=dev), pts.contiguous(),
+                  torch.as_tensor(w, device=dev), int(sizes.max()) if len(objs) else 1)
+    return Z, off
+
+
+def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts):
+    """Weighted constrained D2-clustering of every segment at once; segment
+    mu starts from its objects starts[mu].  Returns (centroids, their host
+    offsets, the centroid range of each segment, labels over G)."""
+    order = [o for s in starts for o in s]
+    Z, z_off = _gather(G, g_off, order)
+    zseg = np.concatenate([[0], np.cumsum([len(s) for s in starts])]).astype(np.int64)
+    seg = np.full(G.n, -1, dtype=np.int32)
+    for mu, S in enumerate(segments):
+        seg[S] = mu
+    dev = G.points.device
+    seg_d = torch.as_tensor(seg, device=dev)
+    zseg_d = torch.as_tensor(zseg, device=dev)
+    for _ in range(rounds):
+        labels, _, _ = d2_assign_segmented(h, G, Z, seg_d, zseg_d, opts)
+        for _ in range(passes):
+            z_new = d2_centroid_update(h, G, Z, labels, opts, weights=omega)[0]
+            Z = Z.with_points(z_new)
+    labels, _, _ = d2_assign_segmented(h, G, Z, seg_d, zseg_d, opts)
+    return Z, z_off, zseg, labels.cpu().numpy()
+
+
+def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
+                    rounds: int = 3, passes: int = 2, opts: Optional[Opts] = None,
+                    max_levels: int = 16):
+    """Alg. 3 on one GPU.  Returns (centroids as a DeviceSet, labels of X as
+    a host int32 array, their weights, per-level statistics)."""
+    opts = opts or Opts()
+    U = _Stream(uniforms)
+    G = X if X.points.dtype == torch.float64 else X.with_points(X.points.double())
+    g_off = G.offsets.cpu().numpy()
+    omega = torch.ones(G.n, dtype=torch.float64, device=G.points.device)
+    C = np.arange(G.n)
+    levels = []
+    for _ in range(max_levels):
+        # Step 1: segmentation by binary splits
+        segments = [np.arange(G.n)]
+        while max(len(S) for S in segments) > tau:
+            split = [q for q, S in enumerate(segments) if len(S) > tau]
+            starts = []
+            for q in split:
+                S = segments[q]
+                a = math.floor(U.take() * len(S))
+                b = math.floor(U.take() * (len(S) - 1))
+                b += b >= a                       # the b-th position other than a
+                starts.append([int(S[a]), int(S[b])])
+            _, _, zseg, labels = _cluster_segments(h, G, g_off, omega, [segments[q] for q in split],
+                                                   starts, rounds, passes, opts)
+            out = []
+            for q, S in enumerate(segments):
+                if q not in split:
+                    out.append(S)
+                    continue
+                on_first = labels[S] == zseg[split.index(q)]
+                A, B = S[on_first], S[~on_first]
+                if A.size == 0 or B.size == 0:
+                    A, B = S[:S.size // 2], S[S.size // 2:]
+                out += [A, B]
+            segments = out
+        # Step 2: every segment into ceil(n_mu / e) clusters
+        starts = []
+        for S in segments:
+            pos = np.arange(S.size)
+            for q in range(math.ceil(S.size / e)):
+                r = q + math.floor(U.take() * (S.size - q))
+                pos[q], pos[r] = pos[r], pos[q]
+            starts.append([int(S[p]) for p in pos[:math.ceil(S.size / e)]])
+        Z, z_off, zseg, labels = _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes,
+                                                   opts)
+        if labels.min() < 0:
+            raise RuntimeError("an object's transport problem failed; check its weights and points")
+        # Step 3: merge (Eq. (5)), weights, inheritance (Eq. (6))
+        kept = [j for mu, S in enumerate(segments) for j in range(zseg[mu], zseg[mu + 1])
+                if np.any(labels[S] == j)]
+        new_index = np.full(int(zseg[-1]), -1, dtype=np.int64)
+        new_index[kept] = np.arange(len(kept))
+        level_label = new_index[labels]
+        w_host = omega.cpu().numpy()
+        new_w = np.bincount(level_label, weights=w_host, minlength=len(kept))
+        C = level_label[C]
+        levels.append({"objects": G.n, "segments": len(segments), "centroids": len(kept),
+                       "max_segment": int(max(S.size for S in segments))})
+        G, g_off = _gather(Z, z_off, kept)   # the same uniform weights the centroids carry
+        omega = torch.as_tensor(new_w, device=G.points.device)
+        if len(kept) <= k or len(kept) == levels[-1]["objects"]:
+            break
+    return G, C.astype(np.int32), omega.cpu().numpy(), levels

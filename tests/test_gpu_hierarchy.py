@@ -1,0 +1,125 @@
+"""GPU parity of the pieces of Alg. 3 through the C ABI, against the FP64
+oracle on the same seeded inputs:
+
+* labelling within segments (d2_assign_segmented): labels equal, values at
+  the pair rule, statuses equal;
+* the weighted centroid update (Eq. (4)): moved atoms within 1e-10 of the
+  coordinate scale, objectives at the summed pair rule;
+* the hierarchical driver (hierarchical_d2) against the oracle's: the same
+  segments and centroid counts per level, the same final labels and
+  weights, centroids within 1e-10 of the coordinate scale.  Both consume
+  the same seeded stream of uniforms.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.hierarchy import assign_segmented as o_assign_segmented
+from oracle.hierarchy import hierarchy as o_hierarchy
+from tests.parity import REL, coupling_cost
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def d2():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests selected but no GPU is visible")
+    import paper_1302_0435_amd as m
+    m._ffi.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def h(d2):
+    return d2.Handle(0)
+
+
+def random_sets(rng, n, K, tmax, smax, d):
+    X = synth.from_bags([(rng.normal(size=(t, d)) * 2, rng.dirichlet(np.ones(t)))
+                         for t in rng.integers(1, tmax + 1, size=n)])
+    Z = synth.from_bags([(rng.normal(size=(s, d)) * 2, np.full(s, 1.0 / s))
+                         for s in rng.integers(1, smax + 1, size=K)])
+    return X, Z
+
+
+@pytest.mark.parametrize("tmax,smax,init", [(8, 8, 0), (30, 16, 1), (64, 30, 2), (64, 64, 3)])
+def test_segmented_labelling(d2, h, tmax, smax, init):
+    rng = np.random.default_rng(61 + tmax + smax)
+    X, Z = random_sets(rng, 150, 14, tmax, smax, 3)
+    zoff = np.array([0, 2, 2, 7, 9, 14], dtype=np.int64)      # segment 1 is empty
+    seg = rng.integers(-1, 6, size=X.n).astype(np.int32)      # -1 and 5: no segment
+    lab, best, st = d2.d2_assign_segmented(h, d2.DeviceSet.from_ragged(X, DEV),
+                                           d2.DeviceSet.from_ragged(Z, DEV), torch.as_tensor(seg),
+                                           torch.as_tensor(zoff), d2.Opts(init=init))
+    torch.cuda.synchronize()
+    lab, best, st = lab.cpu().numpy(), best.cpu().numpy(), st.cpu().numpy()
+    o_lab, o_best, o_st = o_assign_segmented(X, Z, seg, zoff)
+    np.testing.assert_array_equal(st, o_st)
+    np.testing.assert_array_equal(lab, o_lab)
+    ok = o_st == 0
+    for i in np.flatnonzero(ok):
+        floor = 1e-14 * coupling_cost(*X.bag(i), *Z.bag(int(o_lab[i])))
+        assert abs(best[i] - o_best[i]) <= max(REL * abs(o_best[i]), floor)
+
+
+def test_weighted_update(d2, h):
+    rng = np.random.default_rng(62)
+    X, Z = random_sets(rng, 120, 6, 12, 10, 4)
+    labels = rng.integers(0, 6, size=X.n)
+    w = rng.integers(0, 5, size=X.n).astype(float)
+    w[7] = np.nan
+    z, e1, e3, cnt, st = d2.d2_centroid_update(h, d2.DeviceSet.from_ragged(X, DEV),
+                                               d2.DeviceSet.from_ragged(Z, DEV), torch.as_tensor(labels),
+                                               weights=torch.as_tensor(w))
+    torch.cuda.synchronize()
+    z, e1, e3, st = z.cpu().numpy(), e1.cpu().numpy(), e3.cpu().numpy(), st.cpu().numpy()
+    oz, oe1, oe3, ost = oracle.centroid_update(X, Z, labels, weights=w)
+    np.testing.assert_array_equal(st, ost)
+    assert st[7] == 1
+    M = max(np.abs(X.points).max(), np.abs(Z.points).max())
+    assert np.abs(z - oz).max() <= REL * M
+    S = np.zeros(Z.n)
+    for i in range(X.n):
+        if ost[i] == 0:
+            S[labels[i]] += w[i] * coupling_cost(*X.bag(i), *Z.bag(int(labels[i])))
+    assert np.all(np.abs(e1 - oe1) <= np.maximum(REL * np.abs(oe1), 1e-14 * S))
+    assert np.all(np.abs(e3 - oe3) <= np.maximum(REL * np.abs(oe3), 1e-14 * S))
+
+
+def blobs(rng, n_per, centres, spread=0.05):
+    bags = []
+    for c in centres:
+        for _ in range(n_per):
+            t = int(rng.integers(1, 5))
+            bags.append((c + spread * rng.normal(size=(t, len(c))), rng.dirichlet(np.ones(t))))
+    return synth.from_bags(bags)
+
+
+@pytest.mark.parametrize("case", ["blobs", "config1_mixture"])
+def test_hierarchy_matches_oracle(d2, h, case):
+    rng = np.random.default_rng(63)
+    if case == "blobs":
+        centres = [np.array([0.0, 0.0]), np.array([50.0, 0.0]), np.array([0.0, 50.0]),
+                   np.array([50.0, 50.0])]
+        X = blobs(rng, 60, centres)
+        X = X.subset(rng.permutation(X.n))
+        tau, e, k = 50, 5, 12
+    else:
+        X = synth.make_data(1, n=300)
+        tau, e, k = 40, 4, 6
+    U = synth.rng_for(1, synth.STREAM_SAMPLE, 64).random(20000)
+    Zg, lab_g, w_g, lv_g = d2.hierarchical_d2(h, d2.DeviceSet.from_ragged(X, DEV), tau, e, k, U)
+    torch.cuda.synchronize()
+    (off, pts, wts), lab_o, lv_o, w_o = o_hierarchy(X, tau, e, k, U)
+    assert lv_g == lv_o
+    np.testing.assert_array_equal(lab_g, lab_o)
+    np.testing.assert_array_equal(w_g, w_o)
+    np.testing.assert_array_equal(Zg.offsets.cpu().numpy(), off)
+    scale = float(np.abs(X.points).max())
+    assert np.abs(Zg.points.cpu().numpy() - pts).max() <= REL * scale
+    assert lv_g[-1]["centroids"] <= k
+    assert all(lv["max_segment"] <= tau for lv in lv_g)

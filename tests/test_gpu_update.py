@@ -184,12 +184,12 @@ def test_rejects_aliasing_and_bad_modes(d2, h):
     nb = d2.d2_workspace_bytes(h, 4, Xd, Zd)
     ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
     rc = d2._ffi.lib().d2_centroid_update(h.ptr, ctypes.byref(x), ctypes.byref(z),
-                                          ctypes.c_void_p(lab.data_ptr()), ctypes.byref(o),
+                                          ctypes.c_void_p(lab.data_ptr()), None, ctypes.byref(o),
                                           ctypes.c_void_p(Zd.points.data_ptr()), None, None, None,
                                           None, ctypes.c_void_p(ws.data_ptr()), nb, None)
     assert rc == 1
     rc = d2._ffi.lib().d2_centroid_update(h.ptr, ctypes.byref(x), ctypes.byref(z),
-                                          ctypes.c_void_p(lab.data_ptr()), ctypes.byref(o),
+                                          ctypes.c_void_p(lab.data_ptr()), None, ctypes.byref(o),
                                           ctypes.c_void_p(ws.data_ptr()), None, None, None,
                                           None, ctypes.c_void_p(ws.data_ptr()), nb - 1, None)
     assert rc == 2
