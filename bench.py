@@ -649,6 +649,84 @@ class MultiWorkload:
                 "cpu_model": _cpu_model(), "parity_checked": len(rows), "parity_failures": fails}
 
 
+class HierarchyWorkload:
+    """hierarchical_d2: Alg. 3 on one GPU over a configuration's objects
+    (tau = 50, e = 5 as in the paper's runs, stopping at the configuration's
+    K centroids), the random choices from a seeded stream of uniforms."""
+
+    metric = "hierarchical D2-clustering (Alg. 3): objects clustered/sec"
+    unit = "objects/s"
+
+    def __init__(self, cfg, d2, dev, init, schedule, n=None, tau=50, e=5):
+        import synth
+        self.cfg = cfg
+        self.spec = synth.CONFIGS[cfg]
+        self.X = synth.make_data(cfg, n=n)
+        self.k = synth.CONFIGS[cfg]["k"]
+        self.tau, self.e = tau, e
+        self.U = synth.rng_for(cfg, synth.STREAM_SAMPLE, 500).random(4 * self.X.n + 1000)
+        self.d2 = d2
+        self.h = d2.Handle(0)
+        self.Xd = d2.DeviceSet.from_ragged(self.X, dev).with_points(
+            d2.DeviceSet.from_ragged(self.X, dev).points.double())
+        self.opts = d2.Opts(init=init, schedule=schedule)
+        self.pairs = self.X.n
+        self.stats = {}
+        self.out = None
+
+    def step(self):
+        self.stats = {}
+        self.out = self.d2.hierarchical_d2(self.h, self.Xd, self.tau, self.e, self.k, self.U,
+                                           opts=self.opts, stats=self.stats)
+
+    def flops(self):
+        return float(self.stats.get("flops", 0.0))
+
+    def bytes(self):
+        return float(self.X.points.nbytes * 2 + self.X.weights.nbytes + self.X.offsets.nbytes)
+
+    def failed(self):
+        return 0
+
+    def config(self):
+        s = self.spec
+        lv = self.out[3] if self.out else []
+        return {"workload": s["name"] + " hierarchy", "n": self.X.n, "d": self.X.points.shape[1],
+                "t_range": list(s["t_range"]), "tau": self.tau, "e": self.e, "k": self.k,
+                "levels": lv, "lps_per_step": self.stats.get("lps"),
+                "labelling_lps_per_step": self.stats.get("lps_label"),
+                "update_lps_per_step": self.stats.get("lps_update"), "inputs": s["dtype"]}
+
+    def cpu_baseline(self, target_s, init_oracle):
+        """The oracle's hierarchy on the first 1,600 objects of the workload;
+        the device driver runs on the same objects and its labels are
+        compared.  The sample is fixed rather than sized by time: beyond a
+        few thousand objects a one-ulp change in a moved atom can flip a
+        near-tie and the whole later trajectory with it (the oracle against
+        itself, perturbed by one ulp, disagrees on 3,049 of 3,200 labels)."""
+        from oracle.hierarchy import hierarchy
+        import torch
+        sub = self.X.subset(np.arange(min(1600, self.X.n)))
+        t0 = time.perf_counter()
+        (off, pts, wts), lab_o, lv_o, w_o = hierarchy(sub, self.tau, self.e, self.k, self.U,
+                                                     init=init_oracle)
+        dt = time.perf_counter() - t0
+        Xs = self.d2.DeviceSet.from_ragged(sub, "cuda:0")
+        _, lab_g, _, lv_g = self.d2.hierarchical_d2(self.h, Xs, self.tau, self.e, self.k, self.U,
+                                                    opts=self.d2.Opts(init=init_oracle + 1))
+        torch.cuda.synchronize()
+        return {"value": sub.n / dt, "unit": "objects/s", "cores": oracle_threads(), "kind": "oracle",
+                "sample": f"the first {sub.n} objects, {dt:.1f} s, "
+                          f"{'Vogel' if init_oracle else 'north-west-corner'} start",
+                "cpu_model": _cpu_model(), "parity_checked": sub.n,
+                "parity_failures": int((lab_g != lab_o).sum()) + (0 if lv_g == lv_o else 1)}
+
+
+def oracle_threads():
+    import oracle
+    return oracle.default_threads()
+
+
 def make_pool(n_pool: int):
     """Query pool for the serving workload (configuration 5, stream 1)."""
     import synth
@@ -726,10 +804,11 @@ def main(argv=None) -> int:
     ap.add_argument("--cost", choices=["f64", "bf16"], default="f64",
                     help="ground-cost arithmetic (bf16: MFMA tiles, supports <= 32)")
     ap.add_argument("--tune", action="store_true", help="autotune the pairwise schedule first")
-    ap.add_argument("--op", choices=["assign", "update", "cost", "multi"], default="assign",
+    ap.add_argument("--op", choices=["assign", "update", "cost", "multi", "hierarchy"], default="assign",
                     help="update: the constrained D2 centroid update (configurations 1-3); "
                          "cost: LPs over given cost matrices (configuration 2 shapes); "
-                         "multi: two-type labelling of Eq. (9) (configuration 2 scale)")
+                         "multi: two-type labelling of Eq. (9) (configuration 2 scale); "
+                         "hierarchy: Alg. 3 over a configuration's objects")
     ap.add_argument("--n", type=int, default=None, help="override object count (testing)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -762,6 +841,9 @@ def main(argv=None) -> int:
         w = CostWorkload(2, d2, dev, init, schedule, rows=args.n or 4000)
     elif args.op == "multi":
         w = MultiWorkload(2, d2, dev, init, schedule, n=args.n)
+    elif args.op == "hierarchy":
+        w = HierarchyWorkload(args.config if args.config in (1, 2, 3) else 2, d2, dev, init, schedule,
+                              n=args.n)
     elif args.config == 4:
         w = PairwiseWorkload(4, d2, dev, init, schedule, n=args.n, tune=args.tune)
     else:

@@ -79,12 +79,38 @@ def _gather(G: DeviceSet, g_off: np.ndarray, objs) -> tuple:
     return Z, off
 
 
-def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts):
+def _count(stats, G, g_off, z_off, segments, starts, rounds, passes):
+    """Adds the LPs this clustering solves, and their pivot-free FP64 work
+    (3 t s d + 3 t s each), to `stats`."""
+    t = (g_off[1:] - g_off[:-1]).astype(np.float64)
+    s = (z_off[1:] - z_off[:-1]).astype(np.float64)
+    d = G.d
+    add = {"lps_label": 0.0, "flops_label": 0.0, "lps_update": 0.0, "flops_update": 0.0}
+    z0 = 0
+    for S, st in zip(segments, starts):
+        ss = s[z0:z0 + len(st)]
+        z0 += len(st)
+        tsum = t[S].sum()
+        # labelling: every member against every centroid of the segment
+        add["lps_label"] += (rounds + 1) * len(S) * len(st)
+        add["flops_label"] += (rounds + 1) * tsum * ss.sum() * (3 * d + 3)
+        # update: every member against one centroid (bounded by the largest)
+        add["lps_update"] += rounds * passes * len(S)
+        add["flops_update"] += rounds * passes * tsum * ss.max() * (3 * d + 3)
+    add["lps"] = add["lps_label"] + add["lps_update"]
+    add["flops"] = add["flops_label"] + add["flops_update"]
+    for key, v in add.items():
+        stats[key] = stats.get(key, 0.0) + v
+
+
+def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts, stats=None):
     """Weighted constrained D2-clustering of every segment at once; segment
     mu starts from its objects starts[mu].  Returns (centroids, their host
     offsets, the centroid range of each segment, labels over G)."""
     order = [o for s in starts for o in s]
     Z, z_off = _gather(G, g_off, order)
+    if stats is not None:
+        _count(stats, G, g_off, z_off, segments, starts, rounds, passes)
     zseg = np.concatenate([[0], np.cumsum([len(s) for s in starts])]).astype(np.int64)
     seg = np.full(G.n, -1, dtype=np.int32)
     for mu, S in enumerate(segments):
@@ -103,9 +129,11 @@ def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts
 
 def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
                     rounds: int = 3, passes: int = 2, opts: Optional[Opts] = None,
-                    max_levels: int = 16):
+                    max_levels: int = 16, stats: Optional[dict] = None):
     """Alg. 3 on one GPU.  Returns (centroids as a DeviceSet, labels of X as
-    a host int32 array, their weights, per-level statistics)."""
+    a host int32 array, their weights, per-level statistics).  `stats`, when
+    given, receives the count of LPs solved ("lps") and their pivot-free
+    FP64 work ("flops"; the update's is bounded by the largest centroid)."""
     opts = opts or Opts()
     U = _Stream(uniforms)
     G = X if X.points.dtype == torch.float64 else X.with_points(X.points.double())
@@ -126,7 +154,7 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
                 b += b >= a                       # the b-th position other than a
                 starts.append([int(S[a]), int(S[b])])
             _, _, zseg, labels = _cluster_segments(h, G, g_off, omega, [segments[q] for q in split],
-                                                   starts, rounds, passes, opts)
+                                                   starts, rounds, passes, opts, stats)
             out = []
             for q, S in enumerate(segments):
                 if q not in split:
@@ -147,7 +175,7 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
                 pos[q], pos[r] = pos[r], pos[q]
             starts.append([int(S[p]) for p in pos[:math.ceil(S.size / e)]])
         Z, z_off, zseg, labels = _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes,
-                                                   opts)
+                                                   opts, stats)
         if labels.min() < 0:
             raise RuntimeError("an object's transport problem failed; check its weights and points")
         # Step 3: merge (Eq. (5)), weights, inheritance (Eq. (6))
