@@ -42,12 +42,16 @@ MFMA_PROFILES = {(3, "bf16"): "k_cost_bf16_assign_f32_c3_50k_x256_d128.txt"}
 UPDATE_PROFILES = {2: "k_upd_solve_cls0_f32_c2_100k_x512.txt"}
 # the given-cost LP kernel (--op cost), configuration 2 shapes
 COST_PROFILES = {2: "k_emd_cost_cls0_c2_shapes_2m.txt"}
+# the hierarchy's labelling-within-segments kernel (--op hierarchy)
+HIER_PROFILES = {2: "k_assign_seg_cls0_f64_c2_hierarchy_100k.txt"}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
                for f in ("d2_solver.h", "d2_shapes.h", "d2_kernels.hip")]
 UPDATE_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
                for f in ("d2_solver.h", "d2_shapes.h", "d2_update.hip")]
 COST_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
              for f in ("d2_solver.h", "d2_shapes.h", "d2_cost.hip")]
+SEG_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
+            for f in ("d2_solver.h", "d2_shapes.h", "d2_seg.hip")]
 
 
 def kernel_sha(srcs=None) -> str:
@@ -91,6 +95,9 @@ def profile_counters(cfg: int, cost: str, op: str = "assign"):
     elif op == "cost":
         kv = _read_profile(COST_PROFILES.get(cfg, ""))
         sha = kernel_sha(COST_SRCS)
+    elif op == "hierarchy":
+        kv = _read_profile(HIER_PROFILES.get(cfg, ""))
+        sha = kernel_sha(SEG_SRCS)
     elif op != "assign":
         return None   # no committed profile of this workload
     else:
