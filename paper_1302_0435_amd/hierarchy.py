@@ -67,11 +67,12 @@ class _Stream:
 def _gather(G: DeviceSet, g_off: np.ndarray, objs) -> tuple:
     """A centroid set made of the atoms of objects `objs` of G (in that
     order) with uniform weights; returns (DeviceSet, host offsets)."""
+    objs = np.asarray(objs, dtype=np.int64)
     sizes = g_off[1:][objs] - g_off[:-1][objs]
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    rows = np.concatenate([np.arange(g_off[o], g_off[o + 1]) for o in objs]) if len(objs) else \
-        np.zeros(0, dtype=np.int64)
-    w = np.concatenate([np.full(int(t), 1.0 / int(t)) for t in sizes]) if len(objs) else np.zeros(0)
+    # atom rows of the picked objects, object after object
+    rows = np.repeat(g_off[:-1][objs] - off[:-1], sizes) + np.arange(int(off[-1]), dtype=np.int64)
+    w = np.repeat(1.0 / np.maximum(sizes, 1), sizes)
     dev = G.points.device
     pts = G.points.index_select(0, torch.as_tensor(rows, device=dev))
     Z = DeviceSet(torch.as_tensor(off, device=dev), pts.contiguous(),
@@ -85,18 +86,20 @@ def _count(stats, G, g_off, z_off, segments, starts, rounds, passes):
     t = (g_off[1:] - g_off[:-1]).astype(np.float64)
     s = (z_off[1:] - z_off[:-1]).astype(np.float64)
     d = G.d
-    add = {"lps_label": 0.0, "flops_label": 0.0, "lps_update": 0.0, "flops_update": 0.0}
-    z0 = 0
-    for S, st in zip(segments, starts):
-        ss = s[z0:z0 + len(st)]
-        z0 += len(st)
-        tsum = t[S].sum()
-        # labelling: every member against every centroid of the segment
-        add["lps_label"] += (rounds + 1) * len(S) * len(st)
-        add["flops_label"] += (rounds + 1) * tsum * ss.sum() * (3 * d + 3)
+    n_seg = np.array([len(S) for S in segments], dtype=np.float64)
+    k_seg = np.array([len(st) for st in starts], dtype=np.int64)
+    t_seg = np.add.reduceat(t[np.concatenate(segments)], np.concatenate([[0], np.cumsum(n_seg)[:-1]]).astype(np.int64))
+    z_first = np.concatenate([[0], np.cumsum(k_seg)[:-1]]).astype(np.int64)
+    s_sum = np.add.reduceat(s, z_first)
+    s_max = np.maximum.reduceat(s, z_first)
+    add = {
+        # labelling: every member against every centroid of its segment
+        "lps_label": float(((rounds + 1) * n_seg * k_seg).sum()),
+        "flops_label": float(((rounds + 1) * t_seg * s_sum * (3 * d + 3)).sum()),
         # update: every member against one centroid (bounded by the largest)
-        add["lps_update"] += rounds * passes * len(S)
-        add["flops_update"] += rounds * passes * tsum * ss.max() * (3 * d + 3)
+        "lps_update": float((rounds * passes * n_seg).sum()),
+        "flops_update": float((rounds * passes * t_seg * s_max * (3 * d + 3)).sum()),
+    }
     add["lps"] = add["lps_label"] + add["lps_update"]
     add["flops"] = add["flops_label"] + add["flops_update"]
     for key, v in add.items():
@@ -113,8 +116,9 @@ def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts
         _count(stats, G, g_off, z_off, segments, starts, rounds, passes)
     zseg = np.concatenate([[0], np.cumsum([len(s) for s in starts])]).astype(np.int64)
     seg = np.full(G.n, -1, dtype=np.int32)
-    for mu, S in enumerate(segments):
-        seg[S] = mu
+    if segments:
+        seg[np.concatenate(segments)] = np.repeat(np.arange(len(segments), dtype=np.int32),
+                                                  [len(S) for S in segments])
     dev = G.points.device
     seg_d = torch.as_tensor(seg, device=dev)
     zseg_d = torch.as_tensor(zseg, device=dev)
@@ -156,11 +160,12 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
             _, _, zseg, labels = _cluster_segments(h, G, g_off, omega, [segments[q] for q in split],
                                                    starts, rounds, passes, opts, stats)
             out = []
+            where = {q: mu for mu, q in enumerate(split)}
             for q, S in enumerate(segments):
-                if q not in split:
+                if q not in where:
                     out.append(S)
                     continue
-                on_first = labels[S] == zseg[split.index(q)]
+                on_first = labels[S] == zseg[where[q]]
                 A, B = S[on_first], S[~on_first]
                 if A.size == 0 or B.size == 0:
                     A, B = S[:S.size // 2], S[S.size // 2:]
@@ -179,8 +184,9 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
         if labels.min() < 0:
             raise RuntimeError("an object's transport problem failed; check its weights and points")
         # Step 3: merge (Eq. (5)), weights, inheritance (Eq. (6))
-        kept = [j for mu, S in enumerate(segments) for j in range(zseg[mu], zseg[mu + 1])
-                if np.any(labels[S] == j)]
+        # centroids with members, in segment order (a segment's centroids
+        # are a contiguous range, so index order is segment order)
+        kept = np.flatnonzero(np.bincount(labels, minlength=int(zseg[-1])) > 0)
         new_index = np.full(int(zseg[-1]), -1, dtype=np.int64)
         new_index[kept] = np.arange(len(kept))
         level_label = new_index[labels]
