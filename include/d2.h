@@ -34,7 +34,8 @@
  *    returns D = sqrt(D^2) instead.  Labels are 0-based; ties go to the lowest
  *    centroid index; a row with any failed pair gets label -1.
  *  - Supports of more than D2_MAX_SUPPORT atoms are not handled
- *    (D2_EUNSUPPORTED when declared, D2_PAIR_TOO_LARGE when found on device).
+ *    (D2_EUNSUPPORTED when declared, D2_PAIR_TOO_LARGE when found on device),
+ *    except by d2_emd_batch, which takes up to D2_MAX_SUPPORT_LARGE.
  */
 #ifndef D2_H
 #define D2_H
@@ -47,6 +48,9 @@ extern "C" {
 #endif
 
 #define D2_MAX_SUPPORT 64
+/* d2_emd_batch alone also takes supports up to this, through a workgroup
+ * simplex (slower per pair; see d2_emd_batch). */
+#define D2_MAX_SUPPORT_LARGE 1024
 
 typedef enum {
     D2_OK = 0,
@@ -86,7 +90,7 @@ enum { D2_INIT_AUTO = 0, D2_INIT_NWC = 1, D2_INIT_VOGEL = 2, D2_INIT_LCM = 3 };
 enum {
     D2_PAIR_OK = 0,
     D2_PAIR_BAD_WEIGHTS = 1, /* a weight is NaN/inf/negative, or the sum is <= 0 */
-    D2_PAIR_TOO_LARGE = 2,   /* empty support or more than D2_MAX_SUPPORT atoms   */
+    D2_PAIR_TOO_LARGE = 2,   /* empty support, or more atoms than the call takes  */
     D2_PAIR_PIVOT_CAP = 3,   /* pivot cap reached; the value is NaN               */
     D2_PAIR_BAD_POINTS = 4,  /* a ground cost is not finite (NaN/inf coordinates) */
     D2_PAIR_UNLABELLED = 5   /* d2_centroid_update: label outside [0, K); the     *
@@ -159,6 +163,13 @@ d2_status d2_cost_tiles(d2_handle *h, const d2_set *A, const d2_set *B, const in
                         const int64_t *tile_offsets, void *ws, size_t ws_bytes, void *stream);
 
 /* D^2 for an explicit pair list: dist[k] = D^2(A_i, B_j) for pairs[k] = (i,j).
+ * When the declared max_support of A or B exceeds D2_MAX_SUPPORT (up to
+ * D2_MAX_SUPPORT_LARGE, else D2_EUNSUPPORTED), every pair runs on a
+ * workgroup simplex instead of a lane group; it then needs a workspace of
+ * d2_workspace_bytes(h, 1, A, B, npairs, opts) bytes (cost matrices of
+ * max_support(A) x max_support(B) doubles per workgroup, at most 1 GiB in
+ * all).  The workgroup path starts from the north-west corner whatever
+ * opts->init says; results satisfy the same tolerance.
  * plan_offsets, plan (nullable, both or neither): the optimal transport plan
  * of pair k is written densely row-major (t_i x s_j doubles) at
  * plan + plan_offsets[k].  duals (nullable): u[t_i] then v[s_j] at

@@ -104,6 +104,11 @@ d2_status pair_sets_ok(const d2_set *A, const d2_set *B) {
 
 int ms(const d2_set *s) { return s && s->max_support > 0 ? s->max_support : 1; }
 
+// Pairs beyond the lane-group shapes go to the workgroup simplex.
+bool large_pairs(const d2_set *A, const d2_set *B) {
+    return A->max_support > D2_MAX_SUPPORT || B->max_support > D2_MAX_SUPPORT;
+}
+
 d2_status bind_device(d2_handle *h) {
     return hipSetDevice(h->device) == hipSuccess ? D2_OK : D2_EHIP;
 }
@@ -258,9 +263,13 @@ d2_status d2_destroy(d2_handle *h) {
 
 size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set *B,
                           int64_t npairs, const d2_opts *opts) {
-    (void)npairs;
     if (!h || !A || !set_ok(A)) return 0;
     const int sched = sched_of(opts);
+    if (which == 1 && B && set_ok(B) && large_pairs(A, B)) {
+        int64_t grid, elems;
+        d2::wg_plan(npairs, ms(A), ms(B), h->cu_count, &grid, &elems);
+        return (size_t)(grid * elems) * sizeof(double);
+    }
     if (which == 2 && B && set_ok(B)) {
         KSet X = kset(A), Z = kset(B);
         return d2::plan_assign(X, Z, ms(A), ms(B), h->cu_count, sched,
@@ -302,17 +311,26 @@ d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int
                        const int64_t *plan_offsets, double *plan, const int64_t *dual_offsets,
                        double *duals, int32_t *pair_status, void *ws, size_t ws_bytes,
                        void *stream) {
-    (void)ws;
-    (void)ws_bytes;
     if (!h || npairs < 0) return D2_EINVAL;
-    d2_status st = pair_sets_ok(A, B);
-    if (st != D2_OK) return st;
+    if (!set_ok(A) || !set_ok(B)) return D2_EINVAL;
+    if (A->d != B->d || A->dtype != B->dtype) return D2_EINVAL;
+    if (A->max_support > D2_MAX_SUPPORT_LARGE || B->max_support > D2_MAX_SUPPORT_LARGE) return D2_EUNSUPPORTED;
     KOpts k;
-    if ((st = opts_ok(opts, k)) != D2_OK) return st;
+    d2_status st = opts_ok(opts, k);
+    if (st != D2_OK) return st;
     if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
     if (npairs > 0 && (!pairs || !dist)) return D2_EINVAL;
     if ((plan == nullptr) != (plan_offsets == nullptr)) return D2_EINVAL;
     if ((duals == nullptr) != (dual_offsets == nullptr)) return D2_EINVAL;
+    if (large_pairs(A, B)) {
+        int64_t grid, elems;
+        d2::wg_plan(npairs, ms(A), ms(B), h->cu_count, &grid, &elems);
+        if (npairs > 0 && (!ws || ws_bytes < (size_t)(grid * elems) * sizeof(double))) return D2_EWORKSPACE;
+        if ((st = bind_device(h)) != D2_OK) return st;
+        hipError_t e = d2::launch_emd_wg(ctx(h, (hipStream_t)stream), kset(A), kset(B), pairs, npairs, k, ms(A),
+                                         ms(B), dist, plan_offsets, plan, dual_offsets, duals, pair_status, ws);
+        return e == hipSuccess ? D2_OK : D2_EHIP;
+    }
     if ((st = bind_device(h)) != D2_OK) return st;
     const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(ms(A), ms(B));
     hipError_t e = d2::launch_emd_pairs(ctx(h, (hipStream_t)stream), cls, kset(A), kset(B), pairs,

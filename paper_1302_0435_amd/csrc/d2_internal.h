@@ -80,6 +80,13 @@ hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
                              const int64_t *pairs, int64_t npairs, int cost_mode, double *tiles,
                              const int64_t *tile_off);
 
+// Workgroup simplex for pairs with more than 64 atoms on a side.
+int wg_max_support();
+void wg_plan(int64_t npairs, int tmax, int smax, int cu_count, int64_t *grid, int64_t *slab_elems);
+hipError_t launch_emd_wg(const LaunchCtx &c, const KSet &A, const KSet &B, const int64_t *pairs, int64_t npairs,
+                         const KOpts &o, int tmax, int smax, double *dist, const int64_t *plan_off, double *plan,
+                         const int64_t *dual_off, double *duals, int32_t *status, void *ws);
+
 // Labelling under the multi-type distance of Eq. (9).
 size_t multi_ws_bytes(int64_t n, int64_t K, size_t assign_bytes);
 hipError_t launch_assign_multi(const LaunchCtx &c, int ntypes, const AssignPlan *plans, const KSet *X,

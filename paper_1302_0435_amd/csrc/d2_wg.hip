@@ -1,0 +1,356 @@
+// Workgroup transportation simplex for supports beyond the lane-group
+// shapes (65 .. 1024 atoms per side), used by d2_emd_batch when a set's
+// declared max_support exceeds 64.  Same LP (Eq. (1), centroid fixed), same
+// rules: weights divided by their index-order sums, direct-form FP64 costs,
+// Dantzig pricing with Bland's rule after 2(t+s) degenerate pivots in a row,
+// a cap of max(50 t s, 100) pivots, stop when every reduced cost is
+// >= -opt_tol * max C.
+//
+// One workgroup of 256 threads owns a pair at a time (persistent over the
+// pair list).  The t x s cost matrix lives in the workgroup's slab of the
+// caller's workspace; the basis tree lives in LDS as parent pointers over
+// the t + s nodes (rows 0..t-1, columns t..t+s-1, root row 0), each node
+// holding the flow of the edge to its parent.  Per pivot:
+//   * potentials and depths by pointer jumping over the parent pointers
+//     (log2(t+s) rounds, every node in parallel): a node's potential is an
+//     alternating sum of the costs on its root path;
+//   * pricing over every cell by all threads, then a workgroup reduction;
+//   * one thread walks the tree path between the entering row and column
+//     (by depth), takes the ratio test on the edges at odd distance from
+//     either end, moves the flow, and re-hangs the cut-off part by reversing
+//     the parent pointers between the entering cell and the leaving edge.
+// The start is the north-west corner, built directly as a tree.  Every loop
+// has a bound: pivots by the cap, tree walks by t + s steps, jumping by a
+// fixed round count (a tree that does not resolve ends the pair with the
+// pivot-cap status).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "d2_internal.h"
+
+namespace d2 {
+
+namespace {
+
+constexpr int kWgMax = 1024;          // atoms per side
+constexpr int kNodes = 2 * kWgMax;
+constexpr int kJumpRounds = 12;       // ceil(log2(2048)) + 1
+constexpr int kThreads = 256;
+enum { kWOk = 0, kWBadWeights = 1, kWTooLarge = 2, kWPivotCap = 3, kWBadPoints = 4 };
+
+struct WgMem {
+    int16_t par[kNodes];
+    int16_t anc[2][kNodes];
+    int16_t dep[2][kNodes];
+    int8_t sg[2][kNodes];
+    double off[2][kNodes];
+    double pflow[kNodes];
+    double pw[kWgMax], qw[kWgMax];
+    int16_t pa[kNodes], pb[kNodes];
+    double rv[kThreads];
+    int32_t ri[kThreads];
+    double cmax;
+    int32_t bad, enter, stop, bland, status;
+};
+
+template <typename T>
+__device__ __forceinline__ double ldv(const void *p, int64_t i) {
+    return (double)((const T *)p)[i];
+}
+
+// cost of the edge from node x to its parent
+__device__ __forceinline__ double edge_cost(const WgMem &M, const double *C, int x, int T, int S) {
+    const int y = M.par[x];
+    return x < T ? C[(int64_t)x * S + (y - T)] : C[(int64_t)y * S + (x - T)];
+}
+
+__device__ __forceinline__ int edge_cell(const WgMem &M, int x, int T, int S) {
+    const int y = M.par[x];
+    return x < T ? x * S + (y - T) : y * S + (x - T);
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, const int64_t *pairs, int64_t npairs,
+                                                      KOpts o, double *slabs, int64_t slab_elems, double *dist,
+                                                      const int64_t *plan_off, double *plan,
+                                                      const int64_t *dual_off, double *duals,
+                                                      int32_t *status) {
+    __shared__ WgMem M;
+    const int tid = threadIdx.x;
+    double *C = slabs + (int64_t)blockIdx.x * slab_elems;
+    for (int64_t k = blockIdx.x; k < npairs; k += gridDim.x) {
+        const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+        int64_t t = -1, s = -1, a0 = 0, b0 = 0;
+        if (i >= 0 && i < A.n && j >= 0 && j < B.n) {
+            a0 = A.off[i]; b0 = B.off[j];
+            t = A.off[i + 1] - a0; s = B.off[j + 1] - b0;
+        }
+        if (t < 1 || s < 1 || t > kWgMax || s > kWgMax || t * s > slab_elems) {   // uniform
+            if (tid == 0) { dist[k] = __builtin_nan(""); if (status) status[k] = kWTooLarge; }
+            continue;
+        }
+        const int T = (int)t, S = (int)s, V = T + S;
+        // weights: validated, divided by their index-order sums
+        for (int a = tid; a < T; a += kThreads) M.pw[a] = ldv<TIn>(A.w, a0 + a);
+        for (int b = tid; b < S; b += kThreads) M.qw[b] = ldv<TIn>(B.w, b0 + b);
+        if (tid == 0) { M.bad = 0; M.cmax = 0.0; M.status = kWOk; M.bland = 0; }
+        __syncthreads();
+        if (tid == 0) {
+            double sp = 0.0, sq = 0.0;
+            int bad = 0;
+            for (int a = 0; a < T; ++a) { const double w = M.pw[a]; bad |= !(isfinite(w) && w >= 0.0); sp += w; }
+            for (int b = 0; b < S; ++b) { const double w = M.qw[b]; bad |= !(isfinite(w) && w >= 0.0); sq += w; }
+            bad |= !(sp > 0.0 && isfinite(sp) && sq > 0.0 && isfinite(sq));
+            M.bad = bad;
+            M.rv[0] = sp; M.rv[1] = sq;
+        }
+        __syncthreads();
+        if (M.bad) {
+            if (tid == 0) { dist[k] = __builtin_nan(""); if (status) status[k] = kWBadWeights; }
+            __syncthreads();
+            continue;
+        }
+        const double sp = M.rv[0], sq = M.rv[1];
+        __syncthreads();
+        for (int a = tid; a < T; a += kThreads) M.pw[a] = M.pw[a] / sp;
+        for (int b = tid; b < S; b += kThreads) M.qw[b] = M.qw[b] / sq;
+        // costs C_ab = sum_k (x_ak - y_bk)^2, k ascending
+        const int d = A.d;
+        double cm = 0.0;
+        int nonfinite = 0;
+        for (int c = tid; c < T * S; c += kThreads) {
+            const int a = c / S, b = c % S;
+            double acc = 0.0;
+            for (int q = 0; q < d; ++q) {
+                const double diff = ldv<TIn>(A.pts, (a0 + a) * d + q) - ldv<TIn>(B.pts, (b0 + b) * d + q);
+                acc = fma(diff, diff, acc);
+            }
+            C[c] = acc;
+            nonfinite |= !isfinite(acc);
+            cm = fmax(cm, acc);
+        }
+        M.rv[tid] = cm;
+        M.ri[tid] = nonfinite;
+        __syncthreads();
+        if (tid == 0) {
+            double mx = 0.0;
+            int nf = 0;
+            for (int q = 0; q < kThreads; ++q) { mx = fmax(mx, M.rv[q]); nf |= M.ri[q]; }
+            M.cmax = mx;
+            M.bad = nf;
+            // north-west corner, built as a tree rooted at row 0
+            for (int x = 0; x < V; ++x) { M.par[x] = -1; M.pflow[x] = 0.0; }
+            int a = 0, b = 0, child = T;
+            double rr = M.pw[0], rc = M.qw[0];
+            M.par[T] = 0;
+            for (int step = 0; step < V; ++step) {
+                const double f = fmin(rr, rc);
+                M.pflow[child] = f;
+                rr -= f;
+                rc -= f;
+                if (a == T - 1 && b == S - 1) break;
+                if ((rr <= rc && a < T - 1) || b == S - 1) {
+                    ++a; rr = M.pw[a]; M.par[a] = (int16_t)(T + b); child = a;
+                } else {
+                    ++b; rc = M.qw[b]; M.par[T + b] = (int16_t)a; child = T + b;
+                }
+            }
+        }
+        __syncthreads();
+        if (M.bad) {
+            if (tid == 0) { dist[k] = __builtin_nan(""); if (status) status[k] = kWBadPoints; }
+            __syncthreads();
+            continue;
+        }
+        const double delta = o.tol * M.cmax;
+        int64_t cap = o.max_pivots > 0 ? o.max_pivots : 50LL * T * S;
+        if (cap < 100) cap = 100;
+        int64_t pivots = 0;
+        int streak = 0;   // thread 0 only
+        int buf = 0;
+        for (;;) {
+            // potentials and depths by pointer jumping
+            for (int x = tid; x < V; x += kThreads) {
+                const int y = M.par[x];
+                M.anc[0][x] = (int16_t)y;
+                M.sg[0][x] = y >= 0 ? -1 : 0;
+                M.off[0][x] = y >= 0 ? edge_cost(M, C, x, T, S) : 0.0;
+                M.dep[0][x] = y >= 0 ? 1 : 0;
+            }
+            buf = 0;
+            __syncthreads();
+            for (int rnd = 0; rnd < kJumpRounds; ++rnd) {
+                for (int x = tid; x < V; x += kThreads) {
+                    const int an = M.anc[buf][x];
+                    if (an >= 0) {
+                        M.off[1 - buf][x] = (double)M.sg[buf][x] * M.off[buf][an] + M.off[buf][x];
+                        M.sg[1 - buf][x] = (int8_t)(M.sg[buf][x] * M.sg[buf][an]);
+                        M.anc[1 - buf][x] = M.anc[buf][an];
+                        M.dep[1 - buf][x] = (int16_t)(M.dep[buf][x] + M.dep[buf][an]);
+                    } else {
+                        M.off[1 - buf][x] = M.off[buf][x];
+                        M.sg[1 - buf][x] = M.sg[buf][x];
+                        M.anc[1 - buf][x] = -1;
+                        M.dep[1 - buf][x] = M.dep[buf][x];
+                    }
+                }
+                buf = 1 - buf;
+                __syncthreads();
+            }
+            // pricing: most negative reduced cost (lowest cell on ties), or
+            // under Bland's rule the lowest cell below -delta
+            const bool bland = M.bland != 0;
+            double best = -delta;
+            int bc = INT32_MAX;
+            int unresolved = 0;
+            for (int x = tid; x < V; x += kThreads) unresolved |= M.anc[buf][x] >= 0;
+            for (int c = tid; c < T * S; c += kThreads) {
+                const int a = c / S, b = c % S;
+                const double r = C[c] - M.off[buf][a] - M.off[buf][T + b];
+                if (bland) {
+                    if (r < -delta && c < bc) { best = r; bc = c; }
+                } else if (r < best || (r == best && c < bc && r < -delta)) {
+                    best = r; bc = c;
+                }
+            }
+            M.rv[tid] = best;
+            M.ri[tid] = bc;
+            if (unresolved) M.bad = 1;   // benign race: every writer stores 1
+            __syncthreads();
+            if (tid == 0) {
+                double bv = -delta;
+                int bi = INT32_MAX;
+                for (int q = 0; q < kThreads; ++q) {
+                    const double v = M.rv[q];
+                    const int ci = M.ri[q];
+                    if (ci == INT32_MAX) continue;
+                    if (bland ? ci < bi : (v < bv || (v == bv && ci < bi))) { bv = v; bi = ci; }
+                }
+                M.stop = 0;
+                if (M.bad) { M.status = kWPivotCap; M.stop = 1; }
+                else if (bi == INT32_MAX) M.stop = 1;
+                else if (pivots >= cap) { M.status = kWPivotCap; M.stop = 1; }
+                else {
+                    // tree path between row ei and column ej, by depth
+                    const int ei = bi / S, ej = bi % S;
+                    int x = ei, y = T + ej, na = 0, nb = 0;
+                    const int16_t *dp = M.dep[buf];
+                    bool ok = true;
+                    // every step checks its node, so a damaged tree ends the
+                    // pair instead of reading outside the arrays
+                    for (int st = 0; st < V && ok && dp[x] > dp[y]; ++st) {
+                        M.pa[na++] = (int16_t)x; x = M.par[x];
+                        ok = x >= 0 && na < kNodes;
+                    }
+                    for (int st = 0; st < V && ok && dp[y] > dp[x]; ++st) {
+                        M.pb[nb++] = (int16_t)y; y = M.par[y];
+                        ok = y >= 0 && nb < kNodes;
+                    }
+                    for (int st = 0; st < V && ok && x != y; ++st) {
+                        M.pa[na++] = (int16_t)x; x = M.par[x];
+                        M.pb[nb++] = (int16_t)y; y = M.par[y];
+                        ok = x >= 0 && y >= 0 && na < kNodes && nb < kNodes;
+                    }
+                    if (!ok || x != y || na + nb < 3) { M.status = kWPivotCap; M.stop = 1; }
+                    else {
+                        // ratio test over the edges at odd distance from either end
+                        double theta = INFINITY;
+                        int lside = -1, lpos = -1, lcell = INT32_MAX;
+                        for (int m = 0; m < na; m += 2) {
+                            const int e = M.pa[m], ce = edge_cell(M, e, T, S);
+                            if (M.pflow[e] < theta || (M.pflow[e] == theta && ce < lcell)) {
+                                theta = M.pflow[e]; lside = 0; lpos = m; lcell = ce;
+                            }
+                        }
+                        for (int m = 0; m < nb; m += 2) {
+                            const int e = M.pb[m], ce = edge_cell(M, e, T, S);
+                            if (M.pflow[e] < theta || (M.pflow[e] == theta && ce < lcell)) {
+                                theta = M.pflow[e]; lside = 1; lpos = m; lcell = ce;
+                            }
+                        }
+                        for (int m = 0; m < na; ++m) M.pflow[M.pa[m]] += (m & 1) ? theta : -theta;
+                        for (int m = 0; m < nb; ++m) M.pflow[M.pb[m]] += (m & 1) ? theta : -theta;
+                        // re-hang: reverse the parents from the entering end
+                        // down to the leaving edge's child
+                        const int16_t *path = lside == 0 ? M.pa : M.pb;
+                        const int top = lside == 0 ? ei : T + ej;
+                        const int other = lside == 0 ? T + ej : ei;
+                        for (int m = lpos; m >= 1; --m) {
+                            M.pflow[path[m]] = M.pflow[path[m - 1]];
+                            M.par[path[m]] = path[m - 1];
+                        }
+                        M.pflow[top] = theta;
+                        M.par[top] = (int16_t)other;
+                        ++pivots;
+                        if (theta == 0.0) {
+                            if (++streak >= 2 * V) M.bland = 1;
+                        } else {
+                            streak = 0;
+                            M.bland = 0;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (M.stop) break;
+        }
+        // objective over the basic cells, plan and duals
+        if (tid == 0) {
+            double obj = 0.0;
+            if (M.status == kWOk)
+                for (int x = 0; x < V; ++x)
+                    if (M.par[x] >= 0) obj += M.pflow[x] * edge_cost(M, C, x, T, S);
+            dist[k] = M.status == kWOk ? (o.want_sqrt ? sqrt(fmax(obj, 0.0)) : obj) : __builtin_nan("");
+            if (status) status[k] = M.status;
+        }
+        if (M.status == kWOk) {
+            if (plan) {
+                double *P = plan + plan_off[k];
+                for (int c = tid; c < T * S; c += kThreads) P[c] = 0.0;
+                __syncthreads();
+                for (int x = tid; x < V; x += kThreads)
+                    if (M.par[x] >= 0) P[edge_cell(M, x, T, S)] = M.pflow[x];
+            }
+            if (duals) {
+                double *D = duals + dual_off[k];
+                for (int x = tid; x < V; x += kThreads) D[x] = M.off[buf][x];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int wg_max_support() { return kWgMax; }
+
+// Workgroups for a batch and the slab of each (t_max x s_max doubles),
+// keeping the whole workspace within 1 GiB.
+void wg_plan(int64_t npairs, int tmax, int smax, int cu_count, int64_t *grid, int64_t *slab_elems) {
+    const int64_t elems = (int64_t)(tmax > 0 ? tmax : 1) * (smax > 0 ? smax : 1);
+    int64_t g = cu_count > 0 ? cu_count : 256;
+    const int64_t fit = (1LL << 30) / (elems * 8);
+    if (g > fit) g = fit;
+    if (g > npairs) g = npairs;
+    if (g < 1) g = 1;
+    *grid = g;
+    *slab_elems = elems;
+}
+
+hipError_t launch_emd_wg(const LaunchCtx &c, const KSet &A, const KSet &B, const int64_t *pairs, int64_t npairs,
+                         const KOpts &o, int tmax, int smax, double *dist, const int64_t *plan_off, double *plan,
+                         const int64_t *dual_off, double *duals, int32_t *status, void *ws) {
+    if (npairs == 0) return hipSuccess;
+    int64_t grid, elems;
+    wg_plan(npairs, tmax, smax, c.cu_count, &grid, &elems);
+    if (A.dtype == D2_F32)
+        hipLaunchKernelGGL(k_emd_wg<float>, dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, pairs, npairs,
+                           o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status);
+    else
+        hipLaunchKernelGGL(k_emd_wg<double>, dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, pairs,
+                           npairs, o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status);
+    return hipGetLastError();
+}
+
+}  // namespace d2

@@ -1,0 +1,159 @@
+"""GPU parity of d2_emd_batch on supports beyond 64 atoms (the workgroup
+simplex), through the C ABI, against the FP64 oracle on the same seeded
+inputs: values at the pair rule, statuses equal, plans by their marginals
+and value, duals by the LP certificate.  A 1,024 x 1,024 pair in one
+dimension is checked against the quantile closed form of W2^2 (the
+oracle would take minutes there).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.parity import REL, coupling_cost
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def d2():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests selected but no GPU is visible")
+    import paper_1302_0435_amd as m
+    m._ffi.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def h(d2):
+    return d2.Handle(0)
+
+
+def bags(rng, sizes, d, alpha=1.0):
+    return synth.from_bags([(rng.normal(size=(t, d)) * 2, rng.dirichlet(np.full(t, alpha))) for t in sizes])
+
+
+def run(d2, h, A, B, pairs, opts=None):
+    dist, st, (plan, poff), (duals, doff) = d2.d2_emd_batch(
+        h, d2.DeviceSet.from_ragged(A, DEV), d2.DeviceSet.from_ragged(B, DEV), torch.as_tensor(pairs),
+        opts or d2.Opts(), want_plan=True, want_duals=True)
+    torch.cuda.synchronize()
+    return (dist.cpu().numpy(), st.cpu().numpy(), plan.cpu().numpy(), poff.cpu().numpy(),
+            duals.cpu().numpy(), doff.cpu().numpy())
+
+
+def check(A, B, pairs, got):
+    dist, st, plan, poff, duals, doff = got
+    o, o_st, _ = oracle.emd_batch(A, B, pairs)
+    np.testing.assert_array_equal(st, o_st)
+    for k, (i, j) in enumerate(pairs):
+        if o_st[k] != 0:
+            assert np.isnan(dist[k])
+            continue
+        x, p = A.bag(int(i)); y, q = B.bag(int(j))
+        x = np.asarray(x, np.float64); y = np.asarray(y, np.float64)
+        pn = np.asarray(p, np.float64); pn = pn / pn.sum()
+        qn = np.asarray(q, np.float64); qn = qn / qn.sum()
+        S = coupling_cost(x, p, y, q)
+        assert abs(dist[k] - o[k]) <= max(REL * abs(o[k]), 1e-14 * S), (k, dist[k], o[k])
+        P = plan[poff[k]:poff[k + 1]].reshape(len(pn), len(qn))
+        C = ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+        assert P.min() >= 0.0
+        np.testing.assert_allclose(P.sum(1), pn, atol=1e-12)
+        np.testing.assert_allclose(P.sum(0), qn, atol=1e-12)
+        assert abs(float((P * C).sum()) - o[k]) <= max(REL * abs(o[k]), 1e-14 * S) + 1e-13 * C.max()
+        u = duals[doff[k]:doff[k] + len(pn)]
+        v = duals[doff[k] + len(pn):doff[k + 1]]
+        R = C - u[:, None] - v[None, :]
+        tol = 1e-12 * max(C.max(), 1e-300)
+        assert R.min() >= -tol
+        assert np.abs(R[P > 0]).max(initial=0.0) <= tol
+
+
+@pytest.mark.parametrize("dtype,d,alpha", [(np.float64, 2, 1.0), (np.float32, 5, 0.3)])
+def test_random_large_pairs(d2, h, dtype, d, alpha):
+    rng = np.random.default_rng(71 + d)
+    A = bags(rng, rng.integers(40, 161, size=24), d, alpha).astype(dtype)
+    B = bags(rng, rng.integers(1, 131, size=20), d, alpha).astype(dtype)
+    pairs = np.stack([rng.integers(0, A.n, 60), rng.integers(0, B.n, 60)], 1).astype(np.int64)
+    check(A, B, pairs, run(d2, h, A, B, pairs))
+
+
+def test_edge_cases_large(d2, h):
+    rng = np.random.default_rng(72)
+    sizes = [100, 80, 120, 70, 90]
+    A = bags(rng, sizes, 3)
+    w = A.weights.copy()
+    w[int(A.offsets[1]) + 3] = np.nan                        # object 1: bad weight
+    w[int(A.offsets[2]):int(A.offsets[2]) + 60] = 0.0        # object 2: 60 zero-mass atoms
+    A = synth.RaggedSet(A.offsets, A.points, w)
+    B = synth.from_bags([A.bag(0), A.bag(4)] + [(rng.normal(size=(75, 3)), rng.dirichlet(np.ones(75)))])
+    pairs = np.array([[0, 0], [1, 2], [2, 2], [3, 1], [4, 1], [0, 2]], dtype=np.int64)
+    got = run(d2, h, A, B, pairs)
+    assert got[1][1] == 1
+    check(A, B, pairs, got)
+    S0 = coupling_cost(*A.bag(0), *B.bag(0))
+    assert abs(got[0][0]) <= 1e-14 * S0                      # identical distributions
+    assert abs(got[0][4]) <= 1e-14 * coupling_cost(*A.bag(4), *B.bag(1))
+
+
+def w2sq_1d(x, p, y, q):
+    """Quantile coupling of two one-dimensional distributions."""
+    ix, iy = np.argsort(x), np.argsort(y)
+    x, p = x[ix], p[ix] / p.sum()
+    y, q = y[iy], q[iy] / q.sum()
+    a = b = 0
+    ra, rb = p[0], q[0]
+    tot = 0.0
+    while True:
+        m = min(ra, rb)
+        tot += m * (x[a] - y[b]) ** 2
+        ra -= m
+        rb -= m
+        if a == len(x) - 1 and b == len(y) - 1:
+            return tot
+        if (ra <= rb and a < len(x) - 1) or b == len(y) - 1:
+            a += 1
+            ra = p[a]
+        else:
+            b += 1
+            rb = q[b]
+
+
+def test_1024_atoms_per_side_closed_form(d2, h):
+    rng = np.random.default_rng(73)
+    x = rng.normal(size=1024); y = rng.normal(size=1024) * 1.5 + 0.3
+    p = rng.dirichlet(np.ones(1024)); q = rng.dirichlet(np.ones(1024))
+    A = synth.from_bags([(x[:, None], p)])
+    B = synth.from_bags([(y[:, None], q)])
+    pairs = np.array([[0, 0]], dtype=np.int64)
+    dist, st, *_ = run(d2, h, A, B, pairs, d2.Opts(max_pivots=200000))
+    assert st[0] == 0
+    want = w2sq_1d(x, p, y, q)
+    assert abs(dist[0] - want) <= 1e-10 * want
+
+
+def test_declared_bounds(d2, h):
+    import ctypes
+    rng = np.random.default_rng(74)
+    A = bags(rng, [1100], 2)
+    Ad = d2.DeviceSet.from_ragged(A, DEV)
+    a = Ad.c()
+    o = d2.Opts().c()
+    pairs = torch.zeros((1, 2), dtype=torch.int64, device=DEV)
+    dist = torch.empty(1, dtype=torch.float64, device=DEV)
+    rc = d2._ffi.lib().d2_emd_batch(h.ptr, ctypes.byref(a), ctypes.byref(a),
+                                    ctypes.c_void_p(pairs.data_ptr()), 1, ctypes.byref(o),
+                                    ctypes.c_void_p(dist.data_ptr()), None, None, None, None, None,
+                                    None, 0, None)
+    assert rc == 3                                           # above D2_MAX_SUPPORT_LARGE
+    B = bags(rng, [100], 2)
+    Bd = d2.DeviceSet.from_ragged(B, DEV)
+    b = Bd.c()
+    rc = d2._ffi.lib().d2_emd_batch(h.ptr, ctypes.byref(b), ctypes.byref(b),
+                                    ctypes.c_void_p(pairs.data_ptr()), 1, ctypes.byref(o),
+                                    ctypes.c_void_p(dist.data_ptr()), None, None, None, None, None,
+                                    None, 0, None)
+    assert rc == 2                                           # the workgroup path needs its workspace
