@@ -138,6 +138,10 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
     a host int32 array, their weights, per-level statistics).  `stats`, when
     given, receives the count of LPs solved ("lps") and their pivot-free
     FP64 work ("flops"; the update's is bounded by the largest centroid)."""
+    if tau < 2 or e < 1 or k < 1:
+        raise ValueError("need tau >= 2, e >= 1 and k >= 1")
+    if X.n < 1:
+        raise ValueError("no objects to cluster")
     opts = opts or Opts()
     U = _Stream(uniforms)
     G = X if X.points.dtype == torch.float64 else X.with_points(X.points.double())
