@@ -42,6 +42,9 @@ MFMA_PROFILES = {(3, "bf16"): "k_cost_bf16_assign_f32_c3_50k_x256_d128.txt"}
 UPDATE_PROFILES = {2: "k_upd_solve_cls0_f32_c2_100k_x512.txt"}
 # the given-cost LP kernel (--op cost), configuration 2 shapes
 COST_PROFILES = {2: "k_emd_cost_cls0_c2_shapes_2m.txt"}
+# the labelling kernel of the two-type distance of Eq. (9) (--op multi),
+# which also writes each type's D^2 matrix
+MULTI_PROFILES = {2: "k_assign_cls0_f32_c2_multi_type_all.txt"}
 # the hierarchy's labelling-within-segments kernel (--op hierarchy)
 HIER_PROFILES = {2: "k_assign_seg_cls0_f64_c2_hierarchy_100k.txt"}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
@@ -98,6 +101,9 @@ def profile_counters(cfg: int, cost: str, op: str = "assign"):
     elif op == "hierarchy":
         kv = _read_profile(HIER_PROFILES.get(cfg, ""))
         sha = kernel_sha(SEG_SRCS)
+    elif op == "multi":
+        kv = _read_profile(MULTI_PROFILES.get(cfg, ""))
+        sha = kernel_sha()
     elif op != "assign":
         return None   # no committed profile of this workload
     else:
@@ -848,6 +854,7 @@ def main(argv=None) -> int:
         w = CostWorkload(2, d2, dev, init, schedule, rows=args.n or 4000)
     elif args.op == "multi":
         w = MultiWorkload(2, d2, dev, init, schedule, n=args.n)
+        args.config = 2
     elif args.op == "hierarchy":
         w = HierarchyWorkload(args.config if args.config in (1, 2, 3) else 2, d2, dev, init, schedule,
                               n=args.n)
