@@ -167,3 +167,23 @@ def test_mm_distance_of_a_set_to_itself_is_zero(d2, h):
     torch.cuda.synchronize()
     assert float(mm2) == 0.0
     assert np.all(np.diag(M.cpu().numpy()) == 0.0)
+
+
+def test_plain_schedule_within_tolerance(d2, h):
+    rng = np.random.default_rng(9)
+    problems = []
+    for _ in range(50):
+        t, s = int(rng.integers(1, 20)), int(rng.integers(1, 20))
+        problems.append((rng.normal(size=(t, s)), rng.dirichlet(np.ones(t)), rng.dirichlet(np.ones(s))))
+    a = run(d2, h, problems, max_rows=20, max_cols=20)
+    roff, rw, coff, cw, cs, moff = batch(problems)
+    T = lambda x: torch.as_tensor(x, device=DEV)   # noqa: E731
+    dist, st, _ = d2.d2_emd_cost_batch(h, T(roff), T(rw), T(coff), T(cw), T(cs), T(moff), 20, 20,
+                                       d2.Opts(schedule=d2.D2_SCHED_PLAIN))
+    torch.cuda.synchronize()
+    # the plain schedule runs the widest shape; values agree to the tolerance
+    o = np.array([oracle.emd_cost(C, p, q)[0] for C, p, q in problems])
+    g = dist.cpu().numpy()
+    S = np.array([float((p / p.sum()) @ np.abs(C) @ (q / q.sum())) for C, p, q in problems])
+    assert np.all(np.abs(g - o) <= np.maximum(REL * np.abs(o), 1e-14 * S))
+    assert np.all(np.abs(a[0] - o) <= np.maximum(REL * np.abs(o), 1e-14 * S))

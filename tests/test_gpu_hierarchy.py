@@ -141,3 +141,22 @@ def test_hierarchy_invariants_at_config2_scale(d2, h):
     assert lab.min() >= 0 and lab.max() == Zg.n - 1
     assert np.array_equal(np.bincount(lab, minlength=Zg.n), w.astype(np.int64))
     assert np.isfinite(Zg.points.cpu().numpy()).all()
+
+
+def test_segmented_labelling_f32_and_plain_schedule(d2, h):
+    rng = np.random.default_rng(66)
+    X, Z = random_sets(rng, 120, 10, 20, 12, 4)
+    X, Z = X.astype(np.float32), Z.astype(np.float32)
+    zoff = np.array([0, 4, 10], dtype=np.int64)
+    seg = rng.integers(0, 2, size=X.n).astype(np.int32)
+    Xd, Zd = d2.DeviceSet.from_ragged(X, DEV), d2.DeviceSet.from_ragged(Z, DEV)
+    out = [d2.d2_assign_segmented(h, Xd, Zd, torch.as_tensor(seg), torch.as_tensor(zoff), o)
+           for o in (d2.Opts(), d2.Opts(schedule=d2.D2_SCHED_PLAIN))]
+    torch.cuda.synchronize()
+    o_lab, o_best, o_st = o_assign_segmented(X, Z, seg, zoff)
+    for lab, best, st in out:
+        np.testing.assert_array_equal(lab.cpu().numpy(), o_lab)
+        np.testing.assert_array_equal(st.cpu().numpy(), o_st)
+        b = best.cpu().numpy()
+        floors = np.array([1e-14 * coupling_cost(*X.bag(i), *Z.bag(int(o_lab[i]))) for i in range(X.n)])
+        assert np.all(np.abs(b - o_best) <= np.maximum(REL * np.abs(o_best), floors))

@@ -157,3 +157,17 @@ def test_declared_bounds(d2, h):
                                     ctypes.c_void_p(dist.data_ptr()), None, None, None, None, None,
                                     None, 0, None)
     assert rc == 2                                           # the workgroup path needs its workspace
+
+
+def test_large_pairs_root_and_plain_schedule(d2, h):
+    """want_sqrt returns D = sqrt(D^2) on the workgroup path, and the
+    schedule option does not change its results."""
+    rng = np.random.default_rng(75)
+    A = bags(rng, [90, 70], 3)
+    B = bags(rng, [80, 100], 3)
+    pairs = np.array([[0, 0], [1, 1], [0, 1]], dtype=np.int64)
+    d2sq = run(d2, h, A, B, pairs)[0]
+    root = run(d2, h, A, B, pairs, d2.Opts(want_sqrt=1))[0]
+    np.testing.assert_array_equal(root, np.sqrt(d2sq))
+    plain = run(d2, h, A, B, pairs, d2.Opts(schedule=d2.D2_SCHED_PLAIN))[0]
+    np.testing.assert_array_equal(plain, d2sq)

@@ -111,3 +111,22 @@ def test_single_type_equals_assign(d2, h):
     l2, b2, _, _ = d2.d2_assign_multi(h, [Xd], [Zd])
     torch.cuda.synchronize()
     assert torch.equal(l1, l2) and torch.equal(b1, b2)
+
+
+def test_bf16_mode_is_the_sum_of_the_types(d2, h):
+    """The BF16-MFMA cost mode through the multi-type path equals the sum of
+    the per-type BF16 matrices, bit for bit (each type runs the same launch;
+    one FP64 addition per cell)."""
+    rng = np.random.default_rng(36)
+    Xs, Zs = random_types(rng, 50, 7, [(16, 16, 40), (24, 20, 33)])
+    Xs = [X.astype(np.float32) for X in Xs]
+    Zs = [Z.astype(np.float32) for Z in Zs]
+    Xd = [d2.DeviceSet.from_ragged(X, DEV) for X in Xs]
+    Zd = [d2.DeviceSet.from_ragged(Z, DEV) for Z in Zs]
+    opts = d2.Opts(cost_mode=d2.D2_COST_BF16_MFMA)
+    singles = [d2.d2_assign(h, x, z, opts, want_all=True)[2] for x, z in zip(Xd, Zd)]
+    lab, best, allv, st = d2.d2_assign_multi(h, Xd, Zd, opts, want_all=True)
+    torch.cuda.synchronize()
+    assert int(st.max()) == 0
+    assert torch.equal(allv, singles[0] + singles[1])
+    assert torch.equal(best, allv.min(dim=1).values)
