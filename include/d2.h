@@ -35,7 +35,8 @@
  *    centroid index; a row with any failed pair gets label -1.
  *  - Supports of more than D2_MAX_SUPPORT atoms are not handled
  *    (D2_EUNSUPPORTED when declared, D2_PAIR_TOO_LARGE when found on device),
- *    except by d2_emd_batch, which takes up to D2_MAX_SUPPORT_LARGE.
+ *    except by d2_emd_batch, d2_assign and d2_pairwise, which take up to
+ *    D2_MAX_SUPPORT_LARGE on a workgroup simplex (FP64 cost only).
  */
 #ifndef D2_H
 #define D2_H
@@ -48,8 +49,8 @@ extern "C" {
 #endif
 
 #define D2_MAX_SUPPORT 64
-/* d2_emd_batch alone also takes supports up to this, through a workgroup
- * simplex (slower per pair; see d2_emd_batch). */
+/* d2_emd_batch, d2_assign and d2_pairwise also take supports up to this,
+ * through a workgroup simplex (slower per pair; see d2_emd_batch). */
 #define D2_MAX_SUPPORT_LARGE 1024
 
 typedef enum {
@@ -214,7 +215,11 @@ d2_status d2_emd_cost_batch(d2_handle *h, int64_t nprob, const int64_t *row_offs
  * labels[i] = argmin_j (ties: lowest j), best[i] = the minimum.  all[n][K]
  * (nullable) receives every D^2; row_status[n] (nullable) the worst pair
  * status of the row.  With D2_COST_BF16_MFMA the workspace also holds the
- * cost tiles of a block of rows (4 KiB per pair, at most 1 GiB). */
+ * cost tiles of a block of rows (4 KiB per pair, at most 1 GiB).  When a
+ * declared max_support exceeds D2_MAX_SUPPORT (up to D2_MAX_SUPPORT_LARGE),
+ * every pair runs on the workgroup simplex of d2_emd_batch and the
+ * workspace also holds the n x K distance matrix and its statuses; such a
+ * call is enqueued directly (no graph).  FP64 cost only. */
 d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opts *opts,
                     int32_t *labels, double *best, double *all, int32_t *row_status, void *ws,
                     size_t ws_bytes, void *stream);
@@ -291,7 +296,9 @@ d2_status d2_assign_multi(d2_handle *h, int32_t ntypes, const d2_set *X, const d
 /* All unordered pairs i<j of one set (one segment's pairwise matrix):
  * condensed[k] for k = i*n - i*(i+1)/2 + (j-i-1), the order of
  * scipy.spatial.distance.squareform.  pair_status (nullable) has the same
- * shape. */
+ * shape.  Supports beyond D2_MAX_SUPPORT (up to D2_MAX_SUPPORT_LARGE) run
+ * every pair on the workgroup simplex of d2_emd_batch, with its workspace
+ * of cost slabs, enqueued directly (no graph).  FP64 cost only. */
 d2_status d2_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double *condensed,
                       int32_t *pair_status, void *ws, size_t ws_bytes, void *stream);
 

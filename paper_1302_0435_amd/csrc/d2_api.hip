@@ -109,6 +109,14 @@ bool large_pairs(const d2_set *A, const d2_set *B) {
     return A->max_support > D2_MAX_SUPPORT || B->max_support > D2_MAX_SUPPORT;
 }
 
+// Sets a workgroup-simplex call accepts (supports up to D2_MAX_SUPPORT_LARGE).
+d2_status large_sets_ok(const d2_set *A, const d2_set *B) {
+    if (!set_ok(A) || !set_ok(B)) return D2_EINVAL;
+    if (A->d != B->d || A->dtype != B->dtype) return D2_EINVAL;
+    if (A->max_support > D2_MAX_SUPPORT_LARGE || B->max_support > D2_MAX_SUPPORT_LARGE) return D2_EUNSUPPORTED;
+    return D2_OK;
+}
+
 d2_status bind_device(d2_handle *h) {
     return hipSetDevice(h->device) == hipSuccess ? D2_OK : D2_EHIP;
 }
@@ -270,6 +278,9 @@ size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set
         d2::wg_plan(npairs, ms(A), ms(B), h->cu_count, &grid, &elems);
         return (size_t)(grid * elems) * sizeof(double);
     }
+    if (which == 2 && B && set_ok(B) && large_pairs(A, B))
+        return d2::wg_assign_bytes(A->n, B->n, ms(A), ms(B), h->cu_count);
+    if (which == 3 && large_pairs(A, A)) return d2::wg_pairwise_bytes(A->n, ms(A), h->cu_count);
     if (which == 2 && B && set_ok(B)) {
         KSet X = kset(A), Z = kset(B);
         return d2::plan_assign(X, Z, ms(A), ms(B), h->cu_count, sched,
@@ -343,6 +354,23 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
                     int32_t *labels, double *best, double *all, int32_t *row_status, void *ws,
                     size_t ws_bytes, void *stream) {
     if (!h) return D2_EINVAL;
+    if (X && Z && set_ok(X) && set_ok(Z) && large_pairs(X, Z)) {
+        // supports beyond the lane-group shapes: the workgroup simplex
+        d2_status st = large_sets_ok(X, Z);
+        if (st != D2_OK) return st;
+        KOpts k;
+        if ((st = opts_ok(opts, k)) != D2_OK) return st;
+        if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
+        if (X->n > 0 && (!labels || !best)) return D2_EINVAL;
+        if (X->n > 0 && Z->n < 1) return D2_EINVAL;
+        if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
+        const size_t need = d2::wg_assign_bytes(X->n, Z->n, ms(X), ms(Z), h->cu_count);
+        if (X->n > 0 && (!ws || ws_bytes < need)) return D2_EWORKSPACE;
+        if ((st = bind_device(h)) != D2_OK) return st;
+        hipError_t e = d2::launch_assign_wg(ctx(h, (hipStream_t)stream), kset(X), kset(Z), k, ms(X), ms(Z), labels,
+                                            best, all, row_status, ws);
+        return e == hipSuccess ? D2_OK : D2_EHIP;
+    }
     d2_status st = pair_sets_ok(X, Z);
     if (st != D2_OK) return st;
     KOpts k;
@@ -470,6 +498,21 @@ d2_status d2_assign_segmented(d2_handle *h, const d2_set *X, const d2_set *Z, co
 d2_status d2_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double *condensed,
                       int32_t *pair_status, void *ws, size_t ws_bytes, void *stream) {
     if (!h) return D2_EINVAL;
+    if (X && set_ok(X) && large_pairs(X, X)) {
+        // supports beyond the lane-group shapes: the workgroup simplex
+        d2_status st = large_sets_ok(X, X);
+        if (st != D2_OK) return st;
+        KOpts k;
+        if ((st = opts_ok(opts, k)) != D2_OK) return st;
+        if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
+        if (X->n > 1 && !condensed) return D2_EINVAL;
+        if (X->n > 1 && (!ws || ws_bytes < d2::wg_pairwise_bytes(X->n, ms(X), h->cu_count))) return D2_EWORKSPACE;
+        if ((st = bind_device(h)) != D2_OK) return st;
+        if (X->n < 2) return D2_OK;
+        hipError_t e = d2::launch_pairwise_wg(ctx(h, (hipStream_t)stream), kset(X), k, ms(X), condensed,
+                                              pair_status, ws);
+        return e == hipSuccess ? D2_OK : D2_EHIP;
+    }
     d2_status st = pair_sets_ok(X, X);
     if (st != D2_OK) return st;
     KOpts k;

@@ -86,6 +86,12 @@ void wg_plan(int64_t npairs, int tmax, int smax, int cu_count, int64_t *grid, in
 hipError_t launch_emd_wg(const LaunchCtx &c, const KSet &A, const KSet &B, const int64_t *pairs, int64_t npairs,
                          const KOpts &o, int tmax, int smax, double *dist, const int64_t *plan_off, double *plan,
                          const int64_t *dual_off, double *duals, int32_t *status, void *ws);
+size_t wg_assign_bytes(int64_t n, int64_t K, int tmax, int smax, int cu_count);
+hipError_t launch_assign_wg(const LaunchCtx &c, const KSet &X, const KSet &Z, const KOpts &o, int tmax, int smax,
+                            int32_t *labels, double *best, double *all, int32_t *row_status, void *ws);
+size_t wg_pairwise_bytes(int64_t n, int tmax, int cu_count);
+hipError_t launch_pairwise_wg(const LaunchCtx &c, const KSet &X, const KOpts &o, int tmax, double *condensed,
+                              int32_t *status, void *ws);
 
 // Labelling under the multi-type distance of Eq. (9).
 size_t multi_ws_bytes(int64_t n, int64_t K, size_t assign_bytes);

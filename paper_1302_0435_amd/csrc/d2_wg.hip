@@ -1,6 +1,6 @@
 // Workgroup transportation simplex for supports beyond the lane-group
-// shapes (65 .. 1024 atoms per side), used by d2_emd_batch when a set's
-// declared max_support exceeds 64.  Same LP (Eq. (1), centroid fixed), same
+// shapes (65 .. 1024 atoms per side), used by d2_emd_batch, d2_assign and
+// d2_pairwise when a set's declared max_support exceeds 64.  Same LP (Eq. (1), centroid fixed), same
 // rules: weights divided by their index-order sums, direct-form FP64 costs,
 // Dantzig pricing with Bland's rule after 2(t+s) degenerate pivots in a row,
 // a cap of max(50 t s, 100) pivots, stop when every reduced cost is
@@ -70,17 +70,40 @@ __device__ __forceinline__ int edge_cell(const WgMem &M, int x, int T, int S) {
     return x < T ? x * S + (y - T) : y * S + (x - T);
 }
 
+// Pair k of the work: an explicit list, the cross product A x B (row-major,
+// `ncols` = B.n), or the triangle i < j of one set (condensed row-major,
+// `ncols` = n).
+enum { kWgPairs = 0, kWgCross = 1, kWgTriangle = 2 };
+
+__device__ __forceinline__ void wg_pair(int mode, const int64_t *pairs, int64_t ncols, int64_t k, int64_t &i,
+                                        int64_t &j) {
+    if (mode == kWgPairs) { i = pairs[2 * k]; j = pairs[2 * k + 1]; return; }
+    if (mode == kWgCross) { i = k / ncols; j = k % ncols; return; }
+    // row i holds n-1-i pairs; first guess from the closed form, then exact
+    // integer steps (a handful at most)
+    const int64_t n = ncols;
+    double r = floor((2.0 * n - 1.0 - sqrt((2.0 * n - 1.0) * (2.0 * n - 1.0) - 8.0 * (double)k)) * 0.5);
+    int64_t ii = (int64_t)r;
+    if (ii < 0) ii = 0;
+    if (ii > n - 2) ii = n - 2;
+    for (int step = 0; step < 64 && ii > 0 && ii * n - ii * (ii + 1) / 2 > k; ++step) --ii;
+    for (int step = 0; step < 64 && ii < n - 2 && (ii + 1) * n - (ii + 1) * (ii + 2) / 2 <= k; ++step) ++ii;
+    i = ii;
+    j = k - (ii * n - ii * (ii + 1) / 2) + ii + 1;
+}
+
 template <typename TIn>
-__global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, const int64_t *pairs, int64_t npairs,
-                                                      KOpts o, double *slabs, int64_t slab_elems, double *dist,
-                                                      const int64_t *plan_off, double *plan,
-                                                      const int64_t *dual_off, double *duals,
+__global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, const int64_t *pairs,
+                                                      int64_t ncols, int64_t npairs, KOpts o, double *slabs,
+                                                      int64_t slab_elems, double *dist, const int64_t *plan_off,
+                                                      double *plan, const int64_t *dual_off, double *duals,
                                                       int32_t *status) {
     __shared__ WgMem M;
     const int tid = threadIdx.x;
     double *C = slabs + (int64_t)blockIdx.x * slab_elems;
     for (int64_t k = blockIdx.x; k < npairs; k += gridDim.x) {
-        const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+        int64_t i, j;
+        wg_pair(mode, pairs, ncols, k, i, j);
         int64_t t = -1, s = -1, a0 = 0, b0 = 0;
         if (i >= 0 && i < A.n && j >= 0 && j < B.n) {
             a0 = A.off[i]; b0 = B.off[j];
@@ -338,19 +361,106 @@ void wg_plan(int64_t npairs, int tmax, int smax, int cu_count, int64_t *grid, in
     *slab_elems = elems;
 }
 
-hipError_t launch_emd_wg(const LaunchCtx &c, const KSet &A, const KSet &B, const int64_t *pairs, int64_t npairs,
-                         const KOpts &o, int tmax, int smax, double *dist, const int64_t *plan_off, double *plan,
-                         const int64_t *dual_off, double *duals, int32_t *status, void *ws) {
+static hipError_t launch_wg(const LaunchCtx &c, const KSet &A, const KSet &B, int mode, const int64_t *pairs,
+                            int64_t ncols, int64_t npairs, const KOpts &o, int tmax, int smax, double *dist,
+                            const int64_t *plan_off, double *plan, const int64_t *dual_off, double *duals,
+                            int32_t *status, void *ws) {
     if (npairs == 0) return hipSuccess;
     int64_t grid, elems;
     wg_plan(npairs, tmax, smax, c.cu_count, &grid, &elems);
     if (A.dtype == D2_F32)
-        hipLaunchKernelGGL(k_emd_wg<float>, dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, pairs, npairs,
-                           o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status);
+        hipLaunchKernelGGL(k_emd_wg<float>, dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, mode, pairs,
+                           ncols, npairs, o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status);
     else
-        hipLaunchKernelGGL(k_emd_wg<double>, dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, pairs,
-                           npairs, o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status);
+        hipLaunchKernelGGL(k_emd_wg<double>, dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, mode, pairs,
+                           ncols, npairs, o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status);
     return hipGetLastError();
+}
+
+hipError_t launch_emd_wg(const LaunchCtx &c, const KSet &A, const KSet &B, const int64_t *pairs, int64_t npairs,
+                         const KOpts &o, int tmax, int smax, double *dist, const int64_t *plan_off, double *plan,
+                         const int64_t *dual_off, double *duals, int32_t *status, void *ws) {
+    return launch_wg(c, A, B, kWgPairs, pairs, 0, npairs, o, tmax, smax, dist, plan_off, plan, dual_off, duals,
+                     status, ws);
+}
+
+namespace {
+
+// One wave per row of the n x K matrix: the minimum (lowest index on ties)
+// and the worst status; label -1 when any pair of the row failed.
+__global__ __launch_bounds__(256) void k_wg_argmin(const double *all, const int32_t *st, int64_t n, int64_t K,
+                                                    int32_t *labels, double *best, int32_t *row_status) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < n; i += waves) {
+        double v = INFINITY;
+        int64_t jj = INT64_MAX;
+        int worst = 0;
+        for (int64_t j = lane; j < K; j += 64) {
+            const double x = all[i * K + j];
+            const int s = st[i * K + j];
+            worst = s > worst ? s : worst;
+            if (s == 0 && x < v) { v = x; jj = j; }
+        }
+        for (int sh = 32; sh >= 1; sh >>= 1) {
+            const double ov = __shfl_xor(v, sh, 64);
+            const int64_t oj = __shfl_xor(jj, sh, 64);
+            const int ow = __shfl_xor(worst, sh, 64);
+            if (ov < v || (ov == v && oj < jj)) { v = ov; jj = oj; }
+            worst = ow > worst ? ow : worst;
+        }
+        if (lane == 0) {
+            labels[i] = worst == 0 ? (int32_t)jj : -1;
+            best[i] = worst == 0 ? v : __builtin_nan("");
+            if (row_status) row_status[i] = worst;
+        }
+    }
+}
+
+}  // namespace
+
+// Labelling with supports beyond the lane-group shapes: the cross product on
+// the workgroup simplex into an n x K matrix, then the argmin per row.
+// Workspace: slabs, then (unless `all` is given) the matrix, then statuses.
+size_t wg_assign_bytes(int64_t n, int64_t K, int tmax, int smax, int cu_count) {
+    int64_t grid, elems;
+    wg_plan(n * K, tmax, smax, cu_count, &grid, &elems);
+    const size_t slab = ((size_t)(grid * elems) * sizeof(double) + 255) & ~(size_t)255;
+    const size_t mat = ((size_t)(n * K) * sizeof(double) + 255) & ~(size_t)255;
+    return slab + mat + (size_t)(n * K) * sizeof(int32_t);
+}
+
+hipError_t launch_assign_wg(const LaunchCtx &c, const KSet &X, const KSet &Z, const KOpts &o, int tmax, int smax,
+                            int32_t *labels, double *best, double *all, int32_t *row_status, void *ws) {
+    const int64_t n = X.n, K = Z.n;
+    if (n == 0) return hipSuccess;
+    int64_t grid, elems;
+    wg_plan(n * K, tmax, smax, c.cu_count, &grid, &elems);
+    const size_t slab = ((size_t)(grid * elems) * sizeof(double) + 255) & ~(size_t)255;
+    const size_t mat = ((size_t)(n * K) * sizeof(double) + 255) & ~(size_t)255;
+    double *m = all ? all : (double *)((char *)ws + slab);
+    int32_t *st = (int32_t *)((char *)ws + slab + mat);
+    hipError_t e = launch_wg(c, X, Z, kWgCross, nullptr, K, n * K, o, tmax, smax, m, nullptr, nullptr, nullptr,
+                             nullptr, st, ws);
+    if (e != hipSuccess) return e;
+    const int64_t g = (n + 3) / 4 < 65536 ? (n + 3) / 4 : 65536;
+    hipLaunchKernelGGL(k_wg_argmin, dim3((unsigned)g), dim3(256), 0, c.stream, m, st, n, K, labels, best,
+                       row_status);
+    return hipGetLastError();
+}
+
+// All pairs i < j of one set with supports beyond the lane-group shapes.
+size_t wg_pairwise_bytes(int64_t n, int tmax, int cu_count) {
+    int64_t grid, elems;
+    wg_plan(n * (n - 1) / 2, tmax, tmax, cu_count, &grid, &elems);
+    return (size_t)(grid * elems) * sizeof(double);
+}
+
+hipError_t launch_pairwise_wg(const LaunchCtx &c, const KSet &X, const KOpts &o, int tmax, double *condensed,
+                              int32_t *status, void *ws) {
+    const int64_t m = X.n * (X.n - 1) / 2;
+    return launch_wg(c, X, X, kWgTriangle, nullptr, X.n, m, o, tmax, tmax, condensed, nullptr, nullptr, nullptr,
+                     nullptr, status, ws);
 }
 
 }  // namespace d2

@@ -171,3 +171,43 @@ def test_large_pairs_root_and_plain_schedule(d2, h):
     np.testing.assert_array_equal(root, np.sqrt(d2sq))
     plain = run(d2, h, A, B, pairs, d2.Opts(schedule=d2.D2_SCHED_PLAIN))[0]
     np.testing.assert_array_equal(plain, d2sq)
+
+
+@pytest.mark.parametrize("want_all", [True, False])
+def test_assign_large_supports(d2, h, want_all):
+    rng = np.random.default_rng(76)
+    X = bags(rng, rng.integers(20, 101, size=30), 3)
+    Z = bags(rng, rng.integers(50, 91, size=6), 3)
+    lab, best, allv, st = d2.d2_assign(h, d2.DeviceSet.from_ragged(X, DEV), d2.DeviceSet.from_ragged(Z, DEV),
+                                       want_all=want_all)
+    torch.cuda.synchronize()
+    o_lab, o_best, o_all, o_st, _ = oracle.assign(X, Z)
+    np.testing.assert_array_equal(st.cpu().numpy(), o_st)
+    floor = np.array([[1e-14 * coupling_cost(*X.bag(i), *Z.bag(j)) for j in range(Z.n)] for i in range(X.n)])
+    if want_all:
+        g = allv.cpu().numpy()
+        assert np.all(np.abs(g - o_all) <= np.maximum(REL * np.abs(o_all), floor))
+    g_lab, g_best = lab.cpu().numpy(), best.cpu().numpy()
+    for i in range(X.n):
+        if g_lab[i] != o_lab[i]:
+            assert o_all[i, g_lab[i]] - o_all[i, o_lab[i]] <= max(REL * o_best[i], floor[i].max())
+        assert abs(g_best[i] - o_best[i]) <= max(REL * abs(o_best[i]), floor[i].max())
+
+
+def test_pairwise_large_supports(d2, h):
+    rng = np.random.default_rng(77)
+    X = bags(rng, rng.integers(10, 91, size=14), 2)
+    X = synth.from_bags([X.bag(i) for i in range(X.n)] + [X.bag(3)])   # one duplicate: D^2 = 0
+    out, st = d2.d2_pairwise(h, d2.DeviceSet.from_ragged(X, DEV))
+    torch.cuda.synchronize()
+    o, o_st, _ = oracle.pairwise(X)
+    np.testing.assert_array_equal(st.cpu().numpy(), o_st)
+    g = out.cpu().numpy()
+    n = X.n
+    k = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            S = coupling_cost(*X.bag(i), *X.bag(j))
+            assert abs(g[k] - o[k]) <= max(REL * abs(o[k]), 1e-14 * S), (i, j, g[k], o[k])
+            k += 1
+    assert g[3 * n - 3 * 4 // 2 + (n - 1 - 3 - 1)] <= 1e-14 * coupling_cost(*X.bag(3), *X.bag(3))

@@ -287,10 +287,18 @@ def test_host_validation_codes(d2, h):
     with pytest.raises(d2.D2Error) as e:
         d2.d2_assign(h, X, Z, d2.Opts(init=7))
     assert e.value.code == 1
-    big = dev(d2, synth.make_data(1, n=4), max_support=65)
+    big = dev(d2, synth.make_data(1, n=4), max_support=1025)
     with pytest.raises(d2.D2Error) as e:
         d2.d2_assign(h, big, Z)
     assert e.value.code == 3
+    # a declared bound above 64 takes the workgroup simplex: same labels
+    wide = dev(d2, synth.make_data(1, n=4), max_support=65)
+    l1, b1, _, _ = d2.d2_assign(h, X, Z)
+    l2, b2, _, s2 = d2.d2_assign(h, wide, Z)
+    torch.cuda.synchronize()
+    assert int(s2.max()) == 0
+    assert torch.equal(l1, l2)
+    assert torch.allclose(b1, b2, rtol=1e-12, atol=0)
 
 
 def test_cost_tiles_match_direct_form(d2, h):
