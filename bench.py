@@ -45,6 +45,8 @@ COST_PROFILES = {2: "k_emd_cost_cls0_c2_shapes_2m.txt"}
 # the labelling kernel of the two-type distance of Eq. (9) (--op multi),
 # which also writes each type's D^2 matrix
 MULTI_PROFILES = {2: "k_assign_cls0_f32_c2_multi_type_all.txt"}
+# the workgroup simplex on supports beyond 64 (--op large)
+LARGE_PROFILES = {2: "k_emd_wg_f64_large_96_192.txt"}
 # the hierarchy's labelling-within-segments kernel (--op hierarchy)
 HIER_PROFILES = {2: "k_assign_seg_cls0_f64_c2_hierarchy_100k.txt"}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
@@ -55,6 +57,7 @@ COST_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
              for f in ("d2_solver.h", "d2_shapes.h", "d2_cost.hip")]
 SEG_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
             for f in ("d2_solver.h", "d2_shapes.h", "d2_seg.hip")]
+WG_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", "d2_wg.hip")]
 
 
 def kernel_sha(srcs=None) -> str:
@@ -104,6 +107,9 @@ def profile_counters(cfg: int, cost: str, op: str = "assign"):
     elif op == "multi":
         kv = _read_profile(MULTI_PROFILES.get(cfg, ""))
         sha = kernel_sha()
+    elif op == "large":
+        kv = _read_profile(LARGE_PROFILES.get(cfg, ""))
+        sha = kernel_sha(WG_SRCS)
     elif op != "assign":
         return None   # no committed profile of this workload
     else:
@@ -735,6 +741,86 @@ class HierarchyWorkload:
                 "parity_failures": int((lab_g != lab_o).sum()) + (0 if lv_g == lv_o else 1)}
 
 
+class LargeWorkload:
+    """d2_emd_batch on supports beyond the lane-group shapes: pairs of 96 to
+    192 atoms per side (d=8, configuration 2's mixture law and weights),
+    which run on the workgroup simplex."""
+
+    metric = "exact Mallows distances/sec, supports 96..192 (workgroup simplex)"
+    unit = "distances/s"
+
+    def __init__(self, d2, dev, init, schedule, n=None):
+        import synth
+        import torch
+        m = n or 4096
+        rng = synth.rng_for(2, synth.STREAM_SAMPLE, 600)
+        spec = synth.CONFIGS[2]
+
+        def make(count, stream):
+            r = synth.rng_for(2, synth.STREAM_DATA, stream)
+            sizes = r.integers(96, 193, size=count)
+            off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+            means = synth._means(2, spec)
+            pts = synth.gmm_points(r, means, spec["sigma"], int(off[-1]))
+            w = synth.dirichlet_ragged(r, spec["alpha"], sizes)
+            return synth.RaggedSet(off, pts, w)
+
+        self.A, self.B = make(256, 901), make(64, 902)
+        self.pairs_np = np.stack([rng.integers(0, self.A.n, m), rng.integers(0, self.B.n, m)], 1).astype(np.int64)
+        self.d2 = d2
+        self.h = d2.Handle(0)
+        self.Ad = d2.DeviceSet.from_ragged(self.A, dev)
+        self.Bd = d2.DeviceSet.from_ragged(self.B, dev)
+        self.pairs_d = torch.as_tensor(self.pairs_np, device=dev)
+        self.opts = d2.Opts(init=init, schedule=schedule)
+        self.pairs = m
+        self.out = None
+
+    def step(self):
+        self.out = self.d2.d2_emd_batch(self.h, self.Ad, self.Bd, self.pairs_d, self.opts)
+
+    def flops(self):
+        ts = np.diff(self.A.offsets)[self.pairs_np[:, 0]].astype(np.float64)
+        ss = np.diff(self.B.offsets)[self.pairs_np[:, 1]].astype(np.float64)
+        return float((ts * ss).sum() * (3 * self.A.points.shape[1] + 3))
+
+    def bytes(self):
+        return float(self.A.points.nbytes + self.B.points.nbytes + self.pairs * 24)
+
+    def failed(self):
+        return int((self.out[1].cpu().numpy() != 0).sum())
+
+    def config(self):
+        return {"workload": "large supports 96..192 x 96..192, d=8", "pairs": self.pairs,
+                "objects": [self.A.n, self.B.n]}
+
+    def cpu_baseline(self, target_s, init_oracle):
+        """The oracle on a seeded sample of the pairs; checks the device's
+        values there."""
+        import oracle
+        from tests.parity import coupling_cost
+        dist = self.out[0].cpu().numpy()
+        t0 = time.perf_counter()
+        k = 16
+        while True:
+            sample = self.pairs_np[:k]
+            t1 = time.perf_counter()
+            o, st, _ = oracle.emd_batch(self.A, self.B, sample, init=init_oracle)
+            dt = time.perf_counter() - t1
+            if dt > target_s / 3 or k >= self.pairs or time.perf_counter() - t0 > target_s:
+                break
+            k *= 2
+        fails = 0
+        for q, (i, j) in enumerate(sample):
+            S = coupling_cost(*self.A.bag(int(i)), *self.B.bag(int(j)))
+            if not abs(dist[q] - o[q]) <= max(1e-10 * abs(o[q]), 1e-14 * S):
+                fails += 1
+        return {"value": len(sample) / dt, "unit": "distances/s", "cores": oracle_threads(), "kind": "oracle",
+                "sample": f"the first {len(sample)} pairs, {dt:.1f} s, "
+                          f"{'Vogel' if init_oracle else 'north-west-corner'} start",
+                "cpu_model": _cpu_model(), "parity_checked": len(sample), "parity_failures": fails}
+
+
 def oracle_threads():
     import oracle
     return oracle.default_threads()
@@ -817,11 +903,13 @@ def main(argv=None) -> int:
     ap.add_argument("--cost", choices=["f64", "bf16"], default="f64",
                     help="ground-cost arithmetic (bf16: MFMA tiles, supports <= 32)")
     ap.add_argument("--tune", action="store_true", help="autotune the pairwise schedule first")
-    ap.add_argument("--op", choices=["assign", "update", "cost", "multi", "hierarchy"], default="assign",
+    ap.add_argument("--op", choices=["assign", "update", "cost", "multi", "hierarchy", "large"],
+                    default="assign",
                     help="update: the constrained D2 centroid update (configurations 1-3); "
                          "cost: LPs over given cost matrices (configuration 2 shapes); "
                          "multi: two-type labelling of Eq. (9) (configuration 2 scale); "
-                         "hierarchy: Alg. 3 over a configuration's objects")
+                         "hierarchy: Alg. 3 over a configuration's objects; "
+                         "large: pairs of 96..192 atoms on the workgroup simplex")
     ap.add_argument("--n", type=int, default=None, help="override object count (testing)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -855,6 +943,8 @@ def main(argv=None) -> int:
     elif args.op == "multi":
         w = MultiWorkload(2, d2, dev, init, schedule, n=args.n)
         args.config = 2
+    elif args.op == "large":
+        w = LargeWorkload(d2, dev, init, schedule, n=args.n)
     elif args.op == "hierarchy":
         w = HierarchyWorkload(args.config if args.config in (1, 2, 3) else 2, d2, dev, init, schedule,
                               n=args.n)

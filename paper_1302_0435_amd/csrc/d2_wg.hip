@@ -33,20 +33,22 @@ namespace d2 {
 
 namespace {
 
-constexpr int kWgMax = 1024;          // atoms per side
-constexpr int kNodes = 2 * kWgMax;
-constexpr int kJumpRounds = 12;       // ceil(log2(2048)) + 1
+constexpr int kWgMax = 1024;          // atoms per side, largest instance
+constexpr int kWgSmall = 256;         // a smaller instance: 27 KB of LDS, four per CU
 constexpr int kThreads = 256;
 enum { kWOk = 0, kWBadWeights = 1, kWTooLarge = 2, kWPivotCap = 3, kWBadPoints = 4 };
 
+// LDS of one workgroup for supports up to CAP atoms per side.
+template <int CAP>
 struct WgMem {
+    static constexpr int kNodes = 2 * CAP;
     int16_t par[kNodes];
     int16_t anc[2][kNodes];
     int16_t dep[2][kNodes];
     int8_t sg[2][kNodes];
     double off[2][kNodes];
     double pflow[kNodes];
-    double pw[kWgMax], qw[kWgMax];
+    double pw[CAP], qw[CAP];
     int16_t pa[kNodes], pb[kNodes];
     double rv[kThreads];
     int32_t ri[kThreads];
@@ -60,12 +62,14 @@ __device__ __forceinline__ double ldv(const void *p, int64_t i) {
 }
 
 // cost of the edge from node x to its parent
-__device__ __forceinline__ double edge_cost(const WgMem &M, const double *C, int x, int T, int S) {
+template <typename Mem>
+__device__ __forceinline__ double edge_cost(const Mem &M, const double *C, int x, int T, int S) {
     const int y = M.par[x];
     return x < T ? C[(int64_t)x * S + (y - T)] : C[(int64_t)y * S + (x - T)];
 }
 
-__device__ __forceinline__ int edge_cell(const WgMem &M, int x, int T, int S) {
+template <typename Mem>
+__device__ __forceinline__ int edge_cell(const Mem &M, int x, int T, int S) {
     const int y = M.par[x];
     return x < T ? x * S + (y - T) : y * S + (x - T);
 }
@@ -92,13 +96,15 @@ __device__ __forceinline__ void wg_pair(int mode, const int64_t *pairs, int64_t 
     j = k - (ii * n - ii * (ii + 1) / 2) + ii + 1;
 }
 
-template <typename TIn>
+template <typename TIn, int CAP>
 __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, const int64_t *pairs,
                                                       int64_t ncols, int64_t npairs, KOpts o, double *slabs,
                                                       int64_t slab_elems, double *dist, const int64_t *plan_off,
                                                       double *plan, const int64_t *dual_off, double *duals,
                                                       int32_t *status) {
-    __shared__ WgMem M;
+    constexpr int kNodes = 2 * CAP;
+    constexpr int kJumpRounds = CAP <= 256 ? 10 : 12;   // ceil(log2(2 CAP)) + 1
+    __shared__ WgMem<CAP> M;
     const int tid = threadIdx.x;
     double *C = slabs + (int64_t)blockIdx.x * slab_elems;
     for (int64_t k = blockIdx.x; k < npairs; k += gridDim.x) {
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
             a0 = A.off[i]; b0 = B.off[j];
             t = A.off[i + 1] - a0; s = B.off[j + 1] - b0;
         }
-        if (t < 1 || s < 1 || t > kWgMax || s > kWgMax || t * s > slab_elems) {   // uniform
+        if (t < 1 || s < 1 || t > CAP || s > CAP || t * s > slab_elems) {   // uniform
             if (tid == 0) { dist[k] = __builtin_nan(""); if (status) status[k] = kWTooLarge; }
             continue;
         }
@@ -349,10 +355,12 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
 int wg_max_support() { return kWgMax; }
 
 // Workgroups for a batch and the slab of each (t_max x s_max doubles),
-// keeping the whole workspace within 1 GiB.
+// keeping the whole workspace within 1 GiB.  Supports up to kWgSmall run
+// the small instance, four workgroups per CU; larger ones one per CU.
 void wg_plan(int64_t npairs, int tmax, int smax, int cu_count, int64_t *grid, int64_t *slab_elems) {
     const int64_t elems = (int64_t)(tmax > 0 ? tmax : 1) * (smax > 0 ? smax : 1);
-    int64_t g = cu_count > 0 ? cu_count : 256;
+    const int per_cu = (tmax <= kWgSmall && smax <= kWgSmall) ? 4 : 1;
+    int64_t g = (int64_t)(cu_count > 0 ? cu_count : 256) * per_cu;
     const int64_t fit = (1LL << 30) / (elems * 8);
     if (g > fit) g = fit;
     if (g > npairs) g = npairs;
@@ -368,12 +376,16 @@ static hipError_t launch_wg(const LaunchCtx &c, const KSet &A, const KSet &B, in
     if (npairs == 0) return hipSuccess;
     int64_t grid, elems;
     wg_plan(npairs, tmax, smax, c.cu_count, &grid, &elems);
-    if (A.dtype == D2_F32)
-        hipLaunchKernelGGL(k_emd_wg<float>, dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, mode, pairs,
-                           ncols, npairs, o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status);
-    else
-        hipLaunchKernelGGL(k_emd_wg<double>, dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, mode, pairs,
-                           ncols, npairs, o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status);
+    const bool small = tmax <= kWgSmall && smax <= kWgSmall;
+#define D2_WG_LAUNCH(TIN, CAPV)                                                                                  \
+    hipLaunchKernelGGL((k_emd_wg<TIN, CAPV>), dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, mode,    \
+                       pairs, ncols, npairs, o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status)
+    if (A.dtype == D2_F32) {
+        if (small) D2_WG_LAUNCH(float, kWgSmall); else D2_WG_LAUNCH(float, kWgMax);
+    } else {
+        if (small) D2_WG_LAUNCH(double, kWgSmall); else D2_WG_LAUNCH(double, kWgMax);
+    }
+#undef D2_WG_LAUNCH
     return hipGetLastError();
 }
 
