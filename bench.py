@@ -920,7 +920,7 @@ def main(argv=None) -> int:
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the path on a single MI355X; "
+        print("bench.py measures one GPU only: the library runs the path on a single MI355X; "
               "multi-GPU sharding is a design note, not a measured mode.", file=sys.stderr)
         return 2
     if args.config == 5:
