@@ -169,8 +169,10 @@ d2_status d2_cost_tiles(d2_handle *h, const d2_set *A, const d2_set *B, const in
  * workgroup simplex instead of a lane group; it then needs a workspace of
  * d2_workspace_bytes(h, 1, A, B, npairs, opts) bytes (cost matrices of
  * max_support(A) x max_support(B) doubles per workgroup, at most 1 GiB in
- * all).  The workgroup path starts from the north-west corner whatever
- * opts->init says; results satisfy the same tolerance.
+ * all).  The workgroup path starts from the north-west corner under
+ * D2_INIT_NWC and from the least-cost start under every other choice
+ * (D2_INIT_VOGEL included), and prices in blocks of cells; results satisfy
+ * the same tolerance.
  * plan_offsets, plan (nullable, both or neither): the optimal transport plan
  * of pair k is written densely row-major (t_i x s_j doubles) at
  * plan + plan_offsets[k].  duals (nullable): u[t_i] then v[s_j] at

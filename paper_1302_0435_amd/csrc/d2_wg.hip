@@ -1,28 +1,32 @@
 // Workgroup transportation simplex for supports beyond the lane-group
 // shapes (65 .. 1024 atoms per side), used by d2_emd_batch, d2_assign and
 // d2_pairwise when a set's declared max_support exceeds 64.  Same LP (Eq. (1), centroid fixed), same
-// rules: weights divided by their index-order sums, direct-form FP64 costs,
-// Dantzig pricing with Bland's rule after 2(t+s) degenerate pivots in a row,
-// a cap of max(50 t s, 100) pivots, stop when every reduced cost is
-// >= -opt_tol * max C.
+// rules where they fix the result: weights divided by their index-order
+// sums, direct-form FP64 costs, Bland's rule after 2(t+s) degenerate pivots
+// in a row, a cap of max(50 t s, 100) pivots, stop when every reduced cost
+// is >= -opt_tol * max C.  The entering cell is chosen by block pricing
+// rather than over every cell (see below).
 //
 // One workgroup of 256 threads owns a pair at a time (persistent over the
 // pair list).  The t x s cost matrix lives in the workgroup's slab of the
 // caller's workspace; the basis tree lives in LDS as parent pointers over
-// the t + s nodes (rows 0..t-1, columns t..t+s-1, root row 0), each node
-// holding the flow of the edge to its parent.  Per pivot:
+// the t + s nodes (rows 0..t-1, columns t..t+s-1), each node holding the
+// flow and the cost of the cell that joins it to its parent.  Per pivot:
 //   * potentials and depths by pointer jumping over the parent pointers
 //     (log2(t+s) rounds, every node in parallel): a node's potential is an
 //     alternating sum of the costs on its root path;
-//   * pricing over every cell by all threads, then a workgroup reduction;
+//   * block pricing: cells in chunks of 2,048 from where the last search
+//     stopped, the most negative reduced cost of the first chunk holding one
+//     entering, so a pivot reads a chunk of the cost slab, not all of it;
+//     optimality is a full cycle of chunks with none;
 //   * one thread walks the tree path between the entering row and column
 //     (by depth), takes the ratio test on the edges at odd distance from
 //     either end, moves the flow, and re-hangs the cut-off part by reversing
 //     the parent pointers between the entering cell and the leaving edge.
-// The start is the north-west corner, built directly as a tree.  Every loop
-// has a bound: pivots by the cap, tree walks by t + s steps, jumping by a
-// fixed round count (a tree that does not resolve ends the pair with the
-// pivot-cap status).
+// The start is the least-cost one (north-west corner under D2_INIT_NWC),
+// built directly as a tree.  Every loop has a bound: pivots by the cap,
+// tree walks by t + s steps, jumping by a fixed round count (a tree that
+// does not resolve ends the pair with the pivot-cap status).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -36,6 +40,8 @@ namespace {
 constexpr int kWgMax = 1024;          // atoms per side, largest instance
 constexpr int kWgSmall = 256;         // a smaller instance: 27 KB of LDS, four per CU
 constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kChunk = 2048;          // cells per pricing block (eight a thread)
 enum { kWOk = 0, kWBadWeights = 1, kWTooLarge = 2, kWPivotCap = 3, kWBadPoints = 4 };
 
 // LDS of one workgroup for supports up to CAP atoms per side.
@@ -48,12 +54,13 @@ struct WgMem {
     int8_t sg[2][kNodes];
     double off[2][kNodes];
     double pflow[kNodes];
+    double ecost[kNodes];   // cost of the cell joining a node to its parent
     double pw[CAP], qw[CAP];
     int16_t pa[kNodes], pb[kNodes];
     double rv[kThreads];
     int32_t ri[kThreads];
     double cmax;
-    int32_t bad, enter, stop, bland, status;
+    int32_t bad, enter, stop, bland, status, scan;
 };
 
 template <typename T>
@@ -68,10 +75,122 @@ __device__ __forceinline__ double edge_cost(const Mem &M, const double *C, int x
     return x < T ? C[(int64_t)x * S + (y - T)] : C[(int64_t)y * S + (x - T)];
 }
 
+// (v, c) beats the best so far (bv, bi): under Bland's rule the lower cell,
+// else the lower reduced cost, then the lower cell; c = INT32_MAX is no
+// candidate.
+__device__ __forceinline__ bool better(double v, int c, double bv, int bi, bool bland) {
+    if (c == INT32_MAX) return false;
+    return bland ? c < bi : (v < bv || (v == bv && c < bi));
+}
+
 template <typename Mem>
 __device__ __forceinline__ int edge_cell(const Mem &M, int x, int T, int S) {
     const int y = M.par[x];
     return x < T ? x * S + (y - T) : y * S + (x - T);
+}
+
+// Cheapest cell of row a over the open columns (lowest column on ties),
+// by the 64 lanes of one wave; every lane returns the result.  `skip` is a
+// column to leave out beyond the closed ones (-1 for none).
+template <typename Mem>
+__device__ __forceinline__ void row_min(const Mem &M, const double *C, int a, int T, int S, int skip, int lane,
+                                        double &v, int &b) {
+    v = INFINITY;
+    b = INT32_MAX;
+    for (int c = lane; c < S; c += 64)
+        if (M.sg[0][T + c] && c != skip && better(C[(int64_t)a * S + c], c, v, b, false)) {
+            v = C[(int64_t)a * S + c];
+            b = c;
+        }
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        const double ov = __shfl_xor(v, sh);
+        const int oc = __shfl_xor(b, sh);
+        if (better(ov, oc, v, b, false)) { v = ov; b = oc; }
+    }
+}
+
+// Least-cost start (the cheapest cell over open rows and columns takes as
+// much flow as its row and column have left; the line that runs out closes,
+// the row on a tie unless it is the last open row or the last open column
+// remains), built directly as a tree: each closed line hangs from the line
+// its cell met, which closes later, so the t + s - 1 cells form a spanning
+// tree rooted at the line that stays open.  Every row keeps its cheapest
+// open cell; when a column closes, the rows whose cheapest cell was in it
+// look again.  Scratch: off[0] the lines' remaining mass, off[1] and anc[1]
+// the rows' cheapest cost and column, sg[0] the open flags.
+template <typename Mem>
+__device__ void lcm_start(Mem &M, const double *C, int T, int S, int tid) {
+    const int V = T + S, lane = tid & 63, wave = tid >> 6;
+    double *rest = M.off[0], *rmin = M.off[1];
+    int16_t *rarg = M.anc[1];
+    int8_t *open = M.sg[0];
+    for (int x = tid; x < V; x += kThreads) {
+        M.par[x] = -1;
+        M.pflow[x] = 0.0;
+        rest[x] = x < T ? M.pw[x] : M.qw[x - T];
+        open[x] = 1;
+    }
+    __syncthreads();
+    for (int a = wave; a < T; a += kWaves) {
+        double v;
+        int b;
+        row_min(M, C, a, T, S, -1, lane, v, b);
+        if (lane == 0) { rmin[a] = v; rarg[a] = (int16_t)b; }
+    }
+    __syncthreads();
+    int nr = T, nc = S;
+    int hold_i = -1, hold_j = 0;      // thread 0: the last step's remaining mass,
+    double hold_ri = 0.0, hold_cj = 0.0;   // stored once every thread has read it
+    for (int step = 0; step < V - 1; ++step) {
+        if (tid == 0 && hold_i >= 0) { rest[hold_i] = hold_ri; rest[hold_j] = hold_cj; }
+        // the cheapest open cell: lowest cost, then lowest cell index
+        double best = INFINITY;
+        int bc = INT32_MAX;
+        for (int a = tid; a < T; a += kThreads)
+            if (open[a] && better(rmin[a], a * S + rarg[a], best, bc, false)) { best = rmin[a]; bc = a * S + rarg[a]; }
+        for (int sh = 32; sh >= 1; sh >>= 1) {
+            const double ov = __shfl_xor(best, sh);
+            const int oc = __shfl_xor(bc, sh);
+            if (better(ov, oc, best, bc, false)) { best = ov; bc = oc; }
+        }
+        if (lane == 0) { M.rv[wave] = best; M.ri[wave] = bc; }
+        __syncthreads();
+        best = INFINITY;
+        bc = INT32_MAX;
+        for (int w = 0; w < kWaves; ++w)
+            if (better(M.rv[w], M.ri[w], best, bc, false)) { best = M.rv[w]; bc = M.ri[w]; }
+        if (bc == INT32_MAX) bc = 0;   // unreachable: an open row always has an open column
+        const int i = bc / S, j = bc - (bc / S) * S;
+        const double ri = rest[i], cj = rest[T + j], f = fmin(ri, cj);
+        const bool close_row = (ri - f <= cj - f && nr > 1) || nc == 1;
+        if (tid == 0) {
+            hold_i = i; hold_ri = ri - f;
+            hold_j = T + j; hold_cj = cj - f;
+            const int closed = close_row ? i : T + j, other = close_row ? T + j : i;
+            open[closed] = 0;
+            M.par[closed] = (int16_t)other;
+            M.pflow[closed] = f;
+        }
+        if (close_row) {
+            --nr;
+        } else {
+            --nc;
+            // rows whose cheapest cell was in column j look again
+            for (int a0 = wave * 64; a0 < T; a0 += kThreads) {
+                const int a = a0 + lane;
+                uint64_t mask = __ballot(a < T && open[a] && rarg[a] == j);
+                while (mask) {
+                    const int r = a0 + __ffsll((unsigned long long)mask) - 1;
+                    mask &= mask - 1;
+                    double v;
+                    int b;
+                    row_min(M, C, r, T, S, j, lane, v, b);
+                    if (lane == 0) { rmin[r] = v; rarg[r] = (int16_t)b; }
+                }
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // Pair k of the work: an explicit list, the cross product A x B (row-major,
@@ -99,9 +218,9 @@ __device__ __forceinline__ void wg_pair(int mode, const int64_t *pairs, int64_t 
 template <typename TIn, int CAP>
 __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, const int64_t *pairs,
                                                       int64_t ncols, int64_t npairs, KOpts o, double *slabs,
-                                                      int64_t slab_elems, double *dist, const int64_t *plan_off,
-                                                      double *plan, const int64_t *dual_off, double *duals,
-                                                      int32_t *status) {
+                                                      int64_t slab_elems, int chunk, double *dist,
+                                                      const int64_t *plan_off, double *plan,
+                                                      const int64_t *dual_off, double *duals, int32_t *status) {
     constexpr int kNodes = 2 * CAP;
     constexpr int kJumpRounds = CAP <= 256 ? 10 : 12;   // ceil(log2(2 CAP)) + 1
     __shared__ WgMem<CAP> M;
@@ -123,7 +242,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
         // weights: validated, divided by their index-order sums
         for (int a = tid; a < T; a += kThreads) M.pw[a] = ldv<TIn>(A.w, a0 + a);
         for (int b = tid; b < S; b += kThreads) M.qw[b] = ldv<TIn>(B.w, b0 + b);
-        if (tid == 0) { M.bad = 0; M.cmax = 0.0; M.status = kWOk; M.bland = 0; }
+        if (tid == 0) { M.bad = 0; M.cmax = 0.0; M.status = kWOk; M.bland = 0; M.scan = 0; }
         __syncthreads();
         if (tid == 0) {
             double sp = 0.0, sq = 0.0;
@@ -168,6 +287,9 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
             for (int q = 0; q < kThreads; ++q) { mx = fmax(mx, M.rv[q]); nf |= M.ri[q]; }
             M.cmax = mx;
             M.bad = nf;
+        }
+        __syncthreads();
+        if (tid == 0 && !M.bad && o.init == kStartNWC) {
             // north-west corner, built as a tree rooted at row 0
             for (int x = 0; x < V; ++x) { M.par[x] = -1; M.pflow[x] = 0.0; }
             int a = 0, b = 0, child = T;
@@ -192,6 +314,8 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
             __syncthreads();
             continue;
         }
+        if (o.init != kStartNWC) lcm_start(M, C, T, S, tid);
+        for (int x = tid; x < V; x += kThreads) M.ecost[x] = M.par[x] >= 0 ? edge_cost(M, C, x, T, S) : 0.0;
         const double delta = o.tol * M.cmax;
         int64_t cap = o.max_pivots > 0 ? o.max_pivots : 50LL * T * S;
         if (cap < 100) cap = 100;
@@ -204,7 +328,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                 const int y = M.par[x];
                 M.anc[0][x] = (int16_t)y;
                 M.sg[0][x] = y >= 0 ? -1 : 0;
-                M.off[0][x] = y >= 0 ? edge_cost(M, C, x, T, S) : 0.0;
+                M.off[0][x] = y >= 0 ? M.ecost[x] : 0.0;
                 M.dep[0][x] = y >= 0 ? 1 : 0;
             }
             buf = 0;
@@ -227,36 +351,52 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                 buf = 1 - buf;
                 __syncthreads();
             }
-            // pricing: most negative reduced cost (lowest cell on ties), or
-            // under Bland's rule the lowest cell below -delta
+            // pricing by blocks: cells in chunks of `chunk`, from where the
+            // last search stopped and wrapping; the most negative reduced cost
+            // of the first chunk holding one below -delta enters (lowest cell
+            // on ties), and the pair is optimal once a full cycle of chunks
+            // holds none.  Under Bland's rule one chunk covers every cell from
+            // cell 0 and the lowest cell below -delta enters.
             const bool bland = M.bland != 0;
-            double best = -delta;
-            int bc = INT32_MAX;
+            const int TS = T * S;
             int unresolved = 0;
             for (int x = tid; x < V; x += kThreads) unresolved |= M.anc[buf][x] >= 0;
-            for (int c = tid; c < T * S; c += kThreads) {
-                const int a = c / S, b = c % S;
-                const double r = C[c] - M.off[buf][a] - M.off[buf][T + b];
-                if (bland) {
-                    if (r < -delta && c < bc) { best = r; bc = c; }
-                } else if (r < best || (r == best && c < bc && r < -delta)) {
-                    best = r; bc = c;
-                }
-            }
-            M.rv[tid] = best;
-            M.ri[tid] = bc;
             if (unresolved) M.bad = 1;   // benign race: every writer stores 1
-            __syncthreads();
-            if (tid == 0) {
-                double bv = -delta;
-                int bi = INT32_MAX;
-                for (int q = 0; q < kThreads; ++q) {
-                    const double v = M.rv[q];
-                    const int ci = M.ri[q];
-                    if (ci == INT32_MAX) continue;
-                    if (bland ? ci < bi : (v < bv || (v == bv && ci < bi))) { bv = v; bi = ci; }
+            int pos = bland ? 0 : M.scan;
+            const int width = bland ? TS : chunk;
+            double bv = -delta;
+            int bi = INT32_MAX;
+            for (int scanned = 0, rb = 0; scanned < TS; rb ^= 1) {   // >= 1 cell a pass
+                const int n = min(width, TS - scanned);
+                double best = -delta;
+                int bc = INT32_MAX;
+                for (int q = tid; q < n; q += kThreads) {
+                    int c = pos + q;
+                    if (c >= TS) c -= TS;
+                    const int a = c / S, b = c - a * S;
+                    const double r = C[c] - M.off[buf][a] - M.off[buf][T + b];
+                    if (r < -delta && better(r, c, best, bc, bland)) { best = r; bc = c; }
                 }
+                for (int sh = 32; sh >= 1; sh >>= 1) {
+                    const double ov = __shfl_xor(best, sh);
+                    const int oc = __shfl_xor(bc, sh);
+                    if (better(ov, oc, best, bc, bland)) { best = ov; bc = oc; }
+                }
+                if ((tid & 63) == 0) { M.rv[rb * kWaves + (tid >> 6)] = best; M.ri[rb * kWaves + (tid >> 6)] = bc; }
+                __syncthreads();   // two result banks: the next pass writes the other
+                for (int w = 0; w < kWaves; ++w)
+                    if (better(M.rv[rb * kWaves + w], M.ri[rb * kWaves + w], bv, bi, bland)) {
+                        bv = M.rv[rb * kWaves + w];
+                        bi = M.ri[rb * kWaves + w];
+                    }
+                scanned += n;
+                pos += n;
+                if (pos >= TS) pos -= TS;
+                if (bi != INT32_MAX) break;
+            }
+            if (tid == 0) {
                 M.stop = 0;
+                M.scan = pos;
                 if (M.bad) { M.status = kWPivotCap; M.stop = 1; }
                 else if (bi == INT32_MAX) M.stop = 1;
                 else if (pivots >= cap) { M.status = kWPivotCap; M.stop = 1; }
@@ -307,9 +447,11 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                         const int other = lside == 0 ? T + ej : ei;
                         for (int m = lpos; m >= 1; --m) {
                             M.pflow[path[m]] = M.pflow[path[m - 1]];
+                            M.ecost[path[m]] = M.ecost[path[m - 1]];
                             M.par[path[m]] = path[m - 1];
                         }
                         M.pflow[top] = theta;
+                        M.ecost[top] = C[(int64_t)ei * S + ej];
                         M.par[top] = (int16_t)other;
                         ++pivots;
                         if (theta == 0.0) {
@@ -329,7 +471,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
             double obj = 0.0;
             if (M.status == kWOk)
                 for (int x = 0; x < V; ++x)
-                    if (M.par[x] >= 0) obj += M.pflow[x] * edge_cost(M, C, x, T, S);
+                    if (M.par[x] >= 0) obj += M.pflow[x] * M.ecost[x];
             dist[k] = M.status == kWOk ? (o.want_sqrt ? sqrt(fmax(obj, 0.0)) : obj) : __builtin_nan("");
             if (status) status[k] = M.status;
         }
@@ -377,9 +519,11 @@ static hipError_t launch_wg(const LaunchCtx &c, const KSet &A, const KSet &B, in
     int64_t grid, elems;
     wg_plan(npairs, tmax, smax, c.cu_count, &grid, &elems);
     const bool small = tmax <= kWgSmall && smax <= kWgSmall;
+    const int chunk = kChunk;
 #define D2_WG_LAUNCH(TIN, CAPV)                                                                                  \
     hipLaunchKernelGGL((k_emd_wg<TIN, CAPV>), dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, mode,    \
-                       pairs, ncols, npairs, o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals, status)
+                       pairs, ncols, npairs, o, (double *)ws, elems, chunk, dist, plan_off, plan, dual_off, duals, \
+                       status)
     if (A.dtype == D2_F32) {
         if (small) D2_WG_LAUNCH(float, kWgSmall); else D2_WG_LAUNCH(float, kWgMax);
     } else {

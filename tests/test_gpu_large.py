@@ -72,13 +72,26 @@ def check(A, B, pairs, got):
         assert np.abs(R[P > 0]).max(initial=0.0) <= tol
 
 
-@pytest.mark.parametrize("dtype,d,alpha", [(np.float64, 2, 1.0), (np.float32, 5, 0.3)])
+@pytest.mark.parametrize("dtype,d,alpha", [(np.float64, 2, 1.0), (np.float32, 5, 0.3), (np.float64, 8, 1.0),
+                                           (np.float64, 12, 0.5)])
 def test_random_large_pairs(d2, h, dtype, d, alpha):
     rng = np.random.default_rng(71 + d)
     A = bags(rng, rng.integers(40, 161, size=24), d, alpha).astype(dtype)
     B = bags(rng, rng.integers(1, 131, size=20), d, alpha).astype(dtype)
     pairs = np.stack([rng.integers(0, A.n, 60), rng.integers(0, B.n, 60)], 1).astype(np.int64)
     check(A, B, pairs, run(d2, h, A, B, pairs))
+
+
+@pytest.mark.parametrize("init", ["nwc", "vogel"])
+def test_large_pairs_other_starts(d2, h, init):
+    """The workgroup path starts from the north-west corner under
+    D2_INIT_NWC and from the least-cost start under every other choice."""
+    rng = np.random.default_rng(78)
+    A = bags(rng, rng.integers(65, 121, size=10), 4)
+    B = bags(rng, rng.integers(1, 101, size=8), 4)
+    pairs = np.stack([rng.integers(0, A.n, 30), rng.integers(0, B.n, 30)], 1).astype(np.int64)
+    code = d2.D2_INIT_NWC if init == "nwc" else d2.D2_INIT_VOGEL
+    check(A, B, pairs, run(d2, h, A, B, pairs, d2.Opts(init=code)))
 
 
 def test_edge_cases_large(d2, h):
