@@ -19,10 +19,11 @@
 //     stopped, the most negative reduced cost of the first chunk holding one
 //     entering, so a pivot reads a chunk of the cost slab, not all of it;
 //     optimality is a full cycle of chunks with none;
-//   * one thread walks the tree path between the entering row and column
-//     (by depth), takes the ratio test on the edges at odd distance from
-//     either end, moves the flow, and re-hangs the cut-off part by reversing
-//     the parent pointers between the entering cell and the leaving edge.
+//   * wave 0 walks the tree path between the entering row and column (by
+//     depth, all lanes in step), takes the ratio test on the edges at odd
+//     distance from either end, moves the flow, and re-hangs the cut-off
+//     part by reversing the parent pointers between the entering cell and
+//     the leaving edge; the last three spread over its lanes.
 // The start is the least-cost one (north-west corner under D2_INIT_NWC),
 // built directly as a tree.  Every loop has a bound: pivots by the cap,
 // tree walks by t + s steps, jumping by a fixed round count (a tree that
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
         int64_t cap = o.max_pivots > 0 ? o.max_pivots : 50LL * T * S;
         if (cap < 100) cap = 100;
         int64_t pivots = 0;
-        int streak = 0;   // thread 0 only
+        int streak = 0;   // wave 0 only
         int buf = 0;
         for (;;) {
             // potentials and depths by pointer jumping
@@ -394,12 +395,15 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                 if (pos >= TS) pos -= TS;
                 if (bi != INT32_MAX) break;
             }
-            if (tid == 0) {
-                M.stop = 0;
-                M.scan = pos;
-                if (M.bad) { M.status = kWPivotCap; M.stop = 1; }
-                else if (bi == INT32_MAX) M.stop = 1;
-                else if (pivots >= cap) { M.status = kWPivotCap; M.stop = 1; }
+            if (tid < 64) {
+                // wave 0 pivots: every lane takes the tree walk in step (one
+                // lane stores the path); the ratio test, the flow update and
+                // the re-hang spread over the lanes
+                const int lane = tid;
+                int stop = 0, stat = -1;
+                if (M.bad) { stat = kWPivotCap; stop = 1; }
+                else if (bi == INT32_MAX) stop = 1;
+                else if (pivots >= cap) { stat = kWPivotCap; stop = 1; }
                 else {
                     // tree path between row ei and column ej, by depth
                     const int ei = bi / S, ej = bi % S;
@@ -409,58 +413,85 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                     // every step checks its node, so a damaged tree ends the
                     // pair instead of reading outside the arrays
                     for (int st = 0; st < V && ok && dp[x] > dp[y]; ++st) {
-                        M.pa[na++] = (int16_t)x; x = M.par[x];
+                        if (lane == 0) M.pa[na] = (int16_t)x;
+                        ++na; x = M.par[x];
                         ok = x >= 0 && na < kNodes;
                     }
                     for (int st = 0; st < V && ok && dp[y] > dp[x]; ++st) {
-                        M.pb[nb++] = (int16_t)y; y = M.par[y];
+                        if (lane == 0) M.pb[nb] = (int16_t)y;
+                        ++nb; y = M.par[y];
                         ok = y >= 0 && nb < kNodes;
                     }
                     for (int st = 0; st < V && ok && x != y; ++st) {
-                        M.pa[na++] = (int16_t)x; x = M.par[x];
-                        M.pb[nb++] = (int16_t)y; y = M.par[y];
+                        if (lane == 0) { M.pa[na] = (int16_t)x; M.pb[nb] = (int16_t)y; }
+                        ++na; x = M.par[x];
+                        ++nb; y = M.par[y];
                         ok = x >= 0 && y >= 0 && na < kNodes && nb < kNodes;
                     }
-                    if (!ok || x != y || na + nb < 3) { M.status = kWPivotCap; M.stop = 1; }
+                    if (!ok || x != y || na + nb < 3) { stat = kWPivotCap; stop = 1; }
                     else {
-                        // ratio test over the edges at odd distance from either end
+                        // ratio test over the edges at odd distance from either
+                        // end: least flow, then lowest cell (unique)
                         double theta = INFINITY;
-                        int lside = -1, lpos = -1, lcell = INT32_MAX;
-                        for (int m = 0; m < na; m += 2) {
+                        int lcell = INT32_MAX, lcode = 0;
+                        for (int m = 2 * lane; m < na; m += 128) {
                             const int e = M.pa[m], ce = edge_cell(M, e, T, S);
-                            if (M.pflow[e] < theta || (M.pflow[e] == theta && ce < lcell)) {
-                                theta = M.pflow[e]; lside = 0; lpos = m; lcell = ce;
-                            }
+                            if (better(M.pflow[e], ce, theta, lcell, false)) { theta = M.pflow[e]; lcell = ce; lcode = m; }
                         }
-                        for (int m = 0; m < nb; m += 2) {
+                        for (int m = 2 * lane; m < nb; m += 128) {
                             const int e = M.pb[m], ce = edge_cell(M, e, T, S);
-                            if (M.pflow[e] < theta || (M.pflow[e] == theta && ce < lcell)) {
-                                theta = M.pflow[e]; lside = 1; lpos = m; lcell = ce;
-                            }
+                            if (better(M.pflow[e], ce, theta, lcell, false)) { theta = M.pflow[e]; lcell = ce; lcode = kNodes + m; }
                         }
-                        for (int m = 0; m < na; ++m) M.pflow[M.pa[m]] += (m & 1) ? theta : -theta;
-                        for (int m = 0; m < nb; ++m) M.pflow[M.pb[m]] += (m & 1) ? theta : -theta;
+                        for (int sh = 32; sh >= 1; sh >>= 1) {
+                            const double ov = __shfl_xor(theta, sh);
+                            const int oc = __shfl_xor(lcell, sh), ol = __shfl_xor(lcode, sh);
+                            if (better(ov, oc, theta, lcell, false)) { theta = ov; lcell = oc; lcode = ol; }
+                        }
+                        const int lside = lcode >= kNodes, lpos = lcode - lside * kNodes;
+                        for (int m = lane; m < na; m += 64) M.pflow[M.pa[m]] += (m & 1) ? theta : -theta;
+                        for (int m = lane; m < nb; m += 64) M.pflow[M.pb[m]] += (m & 1) ? theta : -theta;
                         // re-hang: reverse the parents from the entering end
                         // down to the leaving edge's child
                         const int16_t *path = lside == 0 ? M.pa : M.pb;
                         const int top = lside == 0 ? ei : T + ej;
                         const int other = lside == 0 ? T + ej : ei;
-                        for (int m = lpos; m >= 1; --m) {
-                            M.pflow[path[m]] = M.pflow[path[m - 1]];
-                            M.ecost[path[m]] = M.ecost[path[m - 1]];
-                            M.par[path[m]] = path[m - 1];
+                        if (lpos < 64) {
+                            // one step: the wave reads every old value before
+                            // any lane writes
+                            int xm = -1, xp = 0;
+                            double fm = 0.0, em = 0.0;
+                            if (lane >= 1 && lane <= lpos) {
+                                xm = path[lane];
+                                xp = path[lane - 1];
+                                fm = M.pflow[xp];
+                                em = M.ecost[xp];
+                            }
+                            if (xm >= 0) { M.pflow[xm] = fm; M.ecost[xm] = em; M.par[xm] = (int16_t)xp; }
+                        } else if (lane == 0) {
+                            for (int m = lpos; m >= 1; --m) {
+                                M.pflow[path[m]] = M.pflow[path[m - 1]];
+                                M.ecost[path[m]] = M.ecost[path[m - 1]];
+                                M.par[path[m]] = path[m - 1];
+                            }
                         }
-                        M.pflow[top] = theta;
-                        M.ecost[top] = C[(int64_t)ei * S + ej];
-                        M.par[top] = (int16_t)other;
+                        if (lane == 0) {
+                            M.pflow[top] = theta;
+                            M.ecost[top] = C[(int64_t)ei * S + ej];
+                            M.par[top] = (int16_t)other;
+                        }
                         ++pivots;
                         if (theta == 0.0) {
-                            if (++streak >= 2 * V) M.bland = 1;
+                            if (++streak >= 2 * V && lane == 0) M.bland = 1;
                         } else {
                             streak = 0;
-                            M.bland = 0;
+                            if (lane == 0) M.bland = 0;
                         }
                     }
+                }
+                if (lane == 0) {
+                    M.stop = stop;
+                    M.scan = pos;
+                    if (stat >= 0) M.status = stat;
                 }
             }
             __syncthreads();
