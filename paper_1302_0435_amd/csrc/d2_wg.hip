@@ -84,6 +84,52 @@ __device__ __forceinline__ bool better(double v, int c, double bv, int bi, bool 
     return bland ? c < bi : (v < bv || (v == bv && c < bi));
 }
 
+// Lane exchange within rows of 16 lanes (DPP): CTRL 0xB1 swaps neighbours,
+// 0x4E swaps pairs, 0x141 mirrors each half row, 0x140 each row.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)dpp_i32<CTRL>((int)(unsigned)u);
+    const unsigned hi = (unsigned)dpp_i32<CTRL>((int)(unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ void best_step(double &v, int &c, int &pay, bool bland) {
+    const double ov = dpp_f64<CTRL>(v);
+    const int oc = dpp_i32<CTRL>(c), op = dpp_i32<CTRL>(pay);
+    if (better(ov, oc, v, c, bland)) { v = ov; c = oc; pay = op; }
+}
+
+// The best (v, c) of the 64 lanes of a wave under `better`, with a payload
+// carried along, returned to every lane: four exchange steps leave each
+// row of 16 with its best, then the four rows are compared.  Every lane of
+// the wave must be active.
+__device__ __forceinline__ void wave_best(double &v, int &c, int &pay, bool bland) {
+    best_step<0xB1>(v, c, pay, bland);
+    best_step<0x4E>(v, c, pay, bland);
+    best_step<0x141>(v, c, pay, bland);
+    best_step<0x140>(v, c, pay, bland);
+    double bv = readlane_f64(v, 0);
+    int bc = __builtin_amdgcn_readlane(c, 0), bp = __builtin_amdgcn_readlane(pay, 0);
+    for (int r = 16; r < 64; r += 16) {
+        const double ov = readlane_f64(v, r);
+        const int oc = __builtin_amdgcn_readlane(c, r), op = __builtin_amdgcn_readlane(pay, r);
+        if (better(ov, oc, bv, bc, bland)) { bv = ov; bc = oc; bp = op; }
+    }
+    v = bv; c = bc; pay = bp;
+}
+
 template <typename Mem>
 __device__ __forceinline__ int edge_cell(const Mem &M, int x, int T, int S) {
     const int y = M.par[x];
@@ -103,11 +149,8 @@ __device__ __forceinline__ void row_min(const Mem &M, const double *C, int a, in
             v = C[(int64_t)a * S + c];
             b = c;
         }
-    for (int sh = 32; sh >= 1; sh >>= 1) {
-        const double ov = __shfl_xor(v, sh);
-        const int oc = __shfl_xor(b, sh);
-        if (better(ov, oc, v, b, false)) { v = ov; b = oc; }
-    }
+    int unused = 0;
+    wave_best(v, b, unused, false);
 }
 
 // Least-cost start (the cheapest cell over open rows and columns takes as
@@ -149,11 +192,8 @@ __device__ void lcm_start(Mem &M, const double *C, int T, int S, int tid) {
         int bc = INT32_MAX;
         for (int a = tid; a < T; a += kThreads)
             if (open[a] && better(rmin[a], a * S + rarg[a], best, bc, false)) { best = rmin[a]; bc = a * S + rarg[a]; }
-        for (int sh = 32; sh >= 1; sh >>= 1) {
-            const double ov = __shfl_xor(best, sh);
-            const int oc = __shfl_xor(bc, sh);
-            if (better(ov, oc, best, bc, false)) { best = ov; bc = oc; }
-        }
+        int unused = 0;
+        wave_best(best, bc, unused, false);
         if (lane == 0) { M.rv[wave] = best; M.ri[wave] = bc; }
         __syncthreads();
         best = INFINITY;
@@ -378,11 +418,8 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                     const double r = C[c] - M.off[buf][a] - M.off[buf][T + b];
                     if (r < -delta && better(r, c, best, bc, bland)) { best = r; bc = c; }
                 }
-                for (int sh = 32; sh >= 1; sh >>= 1) {
-                    const double ov = __shfl_xor(best, sh);
-                    const int oc = __shfl_xor(bc, sh);
-                    if (better(ov, oc, best, bc, bland)) { best = ov; bc = oc; }
-                }
+                int unused = 0;
+                wave_best(best, bc, unused, bland);
                 if ((tid & 63) == 0) { M.rv[rb * kWaves + (tid >> 6)] = best; M.ri[rb * kWaves + (tid >> 6)] = bc; }
                 __syncthreads();   // two result banks: the next pass writes the other
                 for (int w = 0; w < kWaves; ++w)
@@ -442,11 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                             const int e = M.pb[m], ce = edge_cell(M, e, T, S);
                             if (better(M.pflow[e], ce, theta, lcell, false)) { theta = M.pflow[e]; lcell = ce; lcode = kNodes + m; }
                         }
-                        for (int sh = 32; sh >= 1; sh >>= 1) {
-                            const double ov = __shfl_xor(theta, sh);
-                            const int oc = __shfl_xor(lcell, sh), ol = __shfl_xor(lcode, sh);
-                            if (better(ov, oc, theta, lcell, false)) { theta = ov; lcell = oc; lcode = ol; }
-                        }
+                        wave_best(theta, lcell, lcode, false);
                         const int lside = lcode >= kNodes, lpos = lcode - lside * kNodes;
                         for (int m = lane; m < na; m += 64) M.pflow[M.pa[m]] += (m & 1) ? theta : -theta;
                         for (int m = lane; m < nb; m += 64) M.pflow[M.pb[m]] += (m & 1) ? theta : -theta;
