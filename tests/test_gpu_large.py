@@ -94,6 +94,26 @@ def test_large_pairs_other_starts(d2, h, init):
     check(A, B, pairs, run(d2, h, A, B, pairs, d2.Opts(init=code)))
 
 
+def test_more_pairs_than_workgroups(d2, h):
+    """A batch of 2,600 pairs: the persistent workgroups take several pairs
+    each, so later pairs start from a workgroup's leftover LDS state.
+    Sampled pairs from every stretch of the list, including the last,
+    against the oracle."""
+    rng = np.random.default_rng(79)
+    A = bags(rng, rng.integers(65, 91, size=40), 3, 0.5)
+    B = bags(rng, rng.integers(1, 91, size=30), 3, 0.5)
+    pairs = np.stack([rng.integers(0, A.n, 2600), rng.integers(0, B.n, 2600)], 1).astype(np.int64)
+    dist, st, *_ = run(d2, h, A, B, pairs)
+    sample = np.unique(np.concatenate([np.arange(0, 2600, 37), [1023, 1024, 2047, 2048, 2599]]))
+    sub = pairs[sample]
+    o, o_st, _ = oracle.emd_batch(A, B, sub)
+    np.testing.assert_array_equal(st[sample], o_st)
+    for k, (i, j) in zip(sample, sub):
+        S = coupling_cost(*A.bag(int(i)), *B.bag(int(j)))
+        ok = o[list(sample).index(k)]
+        assert abs(dist[k] - ok) <= max(REL * abs(ok), 1e-14 * S), (k, dist[k], ok)
+
+
 def test_edge_cases_large(d2, h):
     rng = np.random.default_rng(72)
     sizes = [100, 80, 120, 70, 90]
