@@ -39,7 +39,8 @@ namespace d2 {
 namespace {
 
 constexpr int kWgMax = 1024;          // atoms per side, largest instance
-constexpr int kWgSmall = 256;         // a smaller instance: 27 KB of LDS, four per CU
+constexpr int kWgSmall = 256;         // a smaller instance: 32 KB of LDS, four per CU
+constexpr int kWgMid = 512;           // a middle one: 60 KB, two per CU
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kChunk = 2048;          // cells per pricing block (eight a thread)
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                                                       const int64_t *plan_off, double *plan,
                                                       const int64_t *dual_off, double *duals, int32_t *status) {
     constexpr int kNodes = 2 * CAP;
-    constexpr int kJumpRounds = CAP <= 256 ? 10 : 12;   // ceil(log2(2 CAP)) + 1
+    constexpr int kJumpRounds = CAP <= 256 ? 10 : CAP <= 512 ? 11 : 12;   // ceil(log2(2 CAP)) + 1
     __shared__ WgMem<CAP> M;
     const int tid = threadIdx.x;
     double *C = slabs + (int64_t)blockIdx.x * slab_elems;
@@ -562,10 +563,11 @@ int wg_max_support() { return kWgMax; }
 
 // Workgroups for a batch and the slab of each (t_max x s_max doubles),
 // keeping the whole workspace within 1 GiB.  Supports up to kWgSmall run
-// the small instance, four workgroups per CU; larger ones one per CU.
+// four workgroups per CU, up to kWgMid two, larger ones one.
 void wg_plan(int64_t npairs, int tmax, int smax, int cu_count, int64_t *grid, int64_t *slab_elems) {
     const int64_t elems = (int64_t)(tmax > 0 ? tmax : 1) * (smax > 0 ? smax : 1);
-    const int per_cu = (tmax <= kWgSmall && smax <= kWgSmall) ? 4 : 1;
+    const int top = tmax > smax ? tmax : smax;
+    const int per_cu = top <= kWgSmall ? 4 : top <= kWgMid ? 2 : 1;
     int64_t g = (int64_t)(cu_count > 0 ? cu_count : 256) * per_cu;
     const int64_t fit = (1LL << 30) / (elems * 8);
     if (g > fit) g = fit;
@@ -582,16 +584,20 @@ static hipError_t launch_wg(const LaunchCtx &c, const KSet &A, const KSet &B, in
     if (npairs == 0) return hipSuccess;
     int64_t grid, elems;
     wg_plan(npairs, tmax, smax, c.cu_count, &grid, &elems);
-    const bool small = tmax <= kWgSmall && smax <= kWgSmall;
+    const int top = tmax > smax ? tmax : smax;
     const int chunk = kChunk;
 #define D2_WG_LAUNCH(TIN, CAPV)                                                                                  \
     hipLaunchKernelGGL((k_emd_wg<TIN, CAPV>), dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, mode,    \
                        pairs, ncols, npairs, o, (double *)ws, elems, chunk, dist, plan_off, plan, dual_off, duals, \
                        status)
     if (A.dtype == D2_F32) {
-        if (small) D2_WG_LAUNCH(float, kWgSmall); else D2_WG_LAUNCH(float, kWgMax);
+        if (top <= kWgSmall) D2_WG_LAUNCH(float, kWgSmall);
+        else if (top <= kWgMid) D2_WG_LAUNCH(float, kWgMid);
+        else D2_WG_LAUNCH(float, kWgMax);
     } else {
-        if (small) D2_WG_LAUNCH(double, kWgSmall); else D2_WG_LAUNCH(double, kWgMax);
+        if (top <= kWgSmall) D2_WG_LAUNCH(double, kWgSmall);
+        else if (top <= kWgMid) D2_WG_LAUNCH(double, kWgMid);
+        else D2_WG_LAUNCH(double, kWgMax);
     }
 #undef D2_WG_LAUNCH
     return hipGetLastError();

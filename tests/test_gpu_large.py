@@ -168,6 +168,28 @@ def test_1024_atoms_per_side_closed_form(d2, h):
     assert abs(dist[0] - want) <= 1e-10 * want
 
 
+def test_middle_instance(d2, h):
+    """Supports of 257..512 run the middle instance (two workgroups per CU):
+    one-dimensional pairs against the quantile closed form, and 3-D pairs
+    against the oracle."""
+    rng = np.random.default_rng(80)
+    sizes_a, sizes_b = rng.integers(257, 513, size=6), rng.integers(200, 513, size=6)
+    one = [(rng.normal(size=(t, 1)), rng.dirichlet(np.ones(t))) for t in sizes_a]
+    two = [(rng.normal(size=(s, 1)) * 1.3 + 0.2, rng.dirichlet(np.ones(s))) for s in sizes_b]
+    A, B = synth.from_bags(one), synth.from_bags(two)
+    pairs = np.array([[k, k] for k in range(6)] + [[0, 5], [5, 0]], dtype=np.int64)
+    dist, st, *_ = run(d2, h, A, B, pairs)
+    assert (st == 0).all()
+    for k, (i, j) in enumerate(pairs):
+        (x, p), (y, q) = one[i], two[j]
+        want = w2sq_1d(x[:, 0], p, y[:, 0], q)
+        assert abs(dist[k] - want) <= 1e-10 * want, (k, dist[k], want)
+    A3 = bags(rng, [300, 270], 3)
+    B3 = bags(rng, [260, 280], 3)
+    check(A3, B3, np.array([[0, 0], [1, 1], [0, 1]], dtype=np.int64),
+          run(d2, h, A3, B3, np.array([[0, 0], [1, 1], [0, 1]], dtype=np.int64)))
+
+
 def test_declared_bounds(d2, h):
     import ctypes
     rng = np.random.default_rng(74)
