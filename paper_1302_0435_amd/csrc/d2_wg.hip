@@ -63,7 +63,32 @@ struct WgMem {
     int32_t ri[kThreads];
     double cmax;
     int32_t bad, enter, stop, bland, status, scan;
+    int32_t pend;   // a node still short of the root after the first jumping rounds
 };
+
+// One pointer-jumping round from bank `from` into the other bank: a node
+// whose target is not the root adds its target's sum (with its own sign)
+// and takes the target's target.  With `flag`, a node still short of the
+// root after this round sets M.pend.
+template <int CAP>
+__device__ __forceinline__ void jump_round(WgMem<CAP> &M, int V, int tid, int from, bool flag) {
+    const int to = 1 - from;
+    for (int x = tid; x < V; x += kThreads) {
+        const int an = M.anc[from][x];
+        if (an >= 0) {
+            M.off[to][x] = (double)M.sg[from][x] * M.off[from][an] + M.off[from][x];
+            M.sg[to][x] = (int8_t)(M.sg[from][x] * M.sg[from][an]);
+            M.anc[to][x] = M.anc[from][an];
+            M.dep[to][x] = (int16_t)(M.dep[from][x] + M.dep[from][an]);
+            if (flag && M.anc[from][an] >= 0) M.pend = 1;   // benign race: every writer stores 1
+        } else {
+            M.off[to][x] = M.off[from][x];
+            M.sg[to][x] = M.sg[from][x];
+            M.anc[to][x] = -1;
+            M.dep[to][x] = M.dep[from][x];
+        }
+    }
+}
 
 template <typename T>
 __device__ __forceinline__ double ldv(const void *p, int64_t i) {
@@ -265,6 +290,9 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                                                       const int64_t *dual_off, double *duals, int32_t *status) {
     constexpr int kNodes = 2 * CAP;
     constexpr int kJumpRounds = CAP <= 256 ? 10 : CAP <= 512 ? 11 : 12;   // ceil(log2(2 CAP)) + 1
+    // the first rounds resolve every node of depth < 2^kFirstRounds; the rest
+    // run only when a node is still short of the root (same bank parity)
+    constexpr int kFirstRounds = kJumpRounds - 4;
     __shared__ WgMem<CAP> M;
     const int tid = threadIdx.x;
     double *C = slabs + (int64_t)blockIdx.x * slab_elems;
@@ -373,26 +401,21 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                 M.off[0][x] = y >= 0 ? M.ecost[x] : 0.0;
                 M.dep[0][x] = y >= 0 ? 1 : 0;
             }
-            buf = 0;
+            if (tid == 0) M.pend = 0;
             __syncthreads();
-            for (int rnd = 0; rnd < kJumpRounds; ++rnd) {
-                for (int x = tid; x < V; x += kThreads) {
-                    const int an = M.anc[buf][x];
-                    if (an >= 0) {
-                        M.off[1 - buf][x] = (double)M.sg[buf][x] * M.off[buf][an] + M.off[buf][x];
-                        M.sg[1 - buf][x] = (int8_t)(M.sg[buf][x] * M.sg[buf][an]);
-                        M.anc[1 - buf][x] = M.anc[buf][an];
-                        M.dep[1 - buf][x] = (int16_t)(M.dep[buf][x] + M.dep[buf][an]);
-                    } else {
-                        M.off[1 - buf][x] = M.off[buf][x];
-                        M.sg[1 - buf][x] = M.sg[buf][x];
-                        M.anc[1 - buf][x] = -1;
-                        M.dep[1 - buf][x] = M.dep[buf][x];
-                    }
-                }
-                buf = 1 - buf;
+#pragma unroll
+            for (int rnd = 0; rnd < kFirstRounds; ++rnd) {
+                jump_round(M, V, tid, rnd & 1, rnd == kFirstRounds - 1);
                 __syncthreads();
             }
+            if (M.pend) {
+#pragma unroll
+                for (int rnd = kFirstRounds; rnd < kJumpRounds; ++rnd) {
+                    jump_round(M, V, tid, rnd & 1, false);
+                    __syncthreads();
+                }
+            }
+            buf = kJumpRounds & 1;   // extra rounds only copy resolved nodes
             // pricing by blocks: cells in chunks of `chunk`, from where the
             // last search stopped and wrapping; the most negative reduced cost
             // of the first chunk holding one below -delta enters (lowest cell
