@@ -43,7 +43,9 @@ constexpr int kWgSmall = 256;         // a smaller instance: 32 KB of LDS, four 
 constexpr int kWgMid = 512;           // a middle one: 60 KB, two per CU
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kChunk = 2048;          // cells per pricing block (eight a thread)
+constexpr int kChunk = 2048;          // cells per pricing block
+constexpr int kPer = kChunk / kThreads;   // cells of a block per thread
+constexpr int kBatch = 8;             // of which loaded together
 enum { kWOk = 0, kWBadWeights = 1, kWTooLarge = 2, kWPivotCap = 3, kWBadPoints = 4 };
 
 // LDS of one workgroup for supports up to CAP atoms per side.
@@ -435,12 +437,36 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                 const int n = min(width, TS - scanned);
                 double best = -delta;
                 int bc = INT32_MAX;
-                for (int q = tid; q < n; q += kThreads) {
-                    int c = pos + q;
-                    if (c >= TS) c -= TS;
-                    const int a = c / S, b = c - a * S;
-                    const double r = C[c] - M.off[buf][a] - M.off[buf][T + b];
-                    if (r < -delta && better(r, c, best, bc, bland)) { best = r; bc = c; }
+                if (!bland) {
+                    // a chunk: at most kPer cells a thread, their loads issued
+                    // together (a cell past the chunk reads cell 0, unused)
+#pragma unroll
+                    for (int e0 = 0; e0 < kPer; e0 += kBatch) {
+                        double cv[kBatch];
+                        int cc[kBatch];
+#pragma unroll
+                        for (int e = 0; e < kBatch; ++e) {
+                            const int q = tid + (e0 + e) * kThreads;
+                            int c = pos + q;
+                            if (c >= TS) c -= TS;
+                            cc[e] = q < n ? c : -1;
+                            cv[e] = C[q < n ? c : 0];
+                        }
+#pragma unroll
+                        for (int e = 0; e < kBatch; ++e) {
+                            if (cc[e] >= 0) {
+                                const int c = cc[e], a = c / S, b = c - a * S;
+                                const double r = cv[e] - M.off[buf][a] - M.off[buf][T + b];
+                                if (r < -delta && better(r, c, best, bc, false)) { best = r; bc = c; }
+                            }
+                        }
+                    }
+                } else {
+                    for (int q = tid; q < n; q += kThreads) {
+                        const int a = q / S, b = q - a * S;   // one pass from cell 0
+                        const double r = C[q] - M.off[buf][a] - M.off[buf][T + b];
+                        if (r < -delta && better(r, q, best, bc, true)) { best = r; bc = q; }
+                    }
                 }
                 int unused = 0;
                 wave_best(best, bc, unused, bland);
@@ -608,7 +634,7 @@ static hipError_t launch_wg(const LaunchCtx &c, const KSet &A, const KSet &B, in
     int64_t grid, elems;
     wg_plan(npairs, tmax, smax, c.cu_count, &grid, &elems);
     const int top = tmax > smax ? tmax : smax;
-    const int chunk = kChunk;
+    const int chunk = kChunk;   // the chunk passes take at most kPer cells a thread
 #define D2_WG_LAUNCH(TIN, CAPV)                                                                                  \
     hipLaunchKernelGGL((k_emd_wg<TIN, CAPV>), dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, mode,    \
                        pairs, ncols, npairs, o, (double *)ws, elems, chunk, dist, plan_off, plan, dual_off, duals, \
