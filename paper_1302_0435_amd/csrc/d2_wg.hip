@@ -498,13 +498,16 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                     const int16_t *dp = M.dep[buf];
                     bool ok = true;
                     // every step checks its node, so a damaged tree ends the
-                    // pair instead of reading outside the arrays
-                    for (int st = 0; st < V && ok && dp[x] > dp[y]; ++st) {
+                    // pair instead of reading outside the arrays; the deeper
+                    // end first climbs the depth difference (a parent is one
+                    // shallower), then both climb until they meet
+                    const int dx = dp[x], dy = dp[y];
+                    for (int st = 0; st < V && ok && st < dx - dy; ++st) {
                         if (lane == 0) M.pa[na] = (int16_t)x;
                         ++na; x = M.par[x];
                         ok = x >= 0 && na < kNodes;
                     }
-                    for (int st = 0; st < V && ok && dp[y] > dp[x]; ++st) {
+                    for (int st = 0; st < V && ok && st < dy - dx; ++st) {
                         if (lane == 0) M.pb[nb] = (int16_t)y;
                         ++nb; y = M.par[y];
                         ok = y >= 0 && nb < kNodes;
