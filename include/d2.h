@@ -94,8 +94,13 @@ enum {
     D2_PAIR_TOO_LARGE = 2,   /* empty support, or more atoms than the call takes  */
     D2_PAIR_PIVOT_CAP = 3,   /* pivot cap reached; the value is NaN               */
     D2_PAIR_BAD_POINTS = 4,  /* a ground cost is not finite (NaN/inf coordinates) */
-    D2_PAIR_UNLABELLED = 5   /* d2_centroid_update: label outside [0, K); the     *
+    D2_PAIR_UNLABELLED = 5,  /* d2_centroid_update: label outside [0, K); the     *
                               * object is left out                                 */
+    D2_PAIR_INTERNAL = 6     /* a solver invariant failed (a starting basis that   *
+                              * did not close within its round bound, a basis tree *
+                              * that did not resolve); the value is NaN.  Never    *
+                              * expected; reported apart from the pivot cap so a   *
+                              * defect cannot pass for an ordinary cap.            */
 };
 
 /* A ragged set of n discrete distributions in R^d (device memory). */
@@ -126,6 +131,12 @@ typedef struct {
                          * cost is >= -opt_tol * max_ab C_ab                       */
     int32_t schedule;   /* D2_SCHED_*                                              */
     int32_t flags;      /* D2_FLAG_* bits, 0 by default                            */
+    int32_t bland_after; /* run of consecutive degenerate pivots after which the   *
+                          * entering cell follows Bland's rule (lowest cell with a *
+                          * negative reduced cost) until a pivot moves flow again; *
+                          * 0 = the default 2 (t + s).  The paper leaves cycling   *
+                          * open (its LP solver is unnamed); every value reaches   *
+                          * the same optimum value.                                */
 } d2_opts;
 
 /* D2_FLAG_EAGER: enqueue the kernels directly instead of recording the call
@@ -163,7 +174,10 @@ d2_status d2_cost_tiles(d2_handle *h, const d2_set *A, const d2_set *B, const in
                         int64_t npairs, int32_t cost_mode, double *tiles,
                         const int64_t *tile_offsets, void *ws, size_t ws_bytes, void *stream);
 
-/* D^2 for an explicit pair list: dist[k] = D^2(A_i, B_j) for pairs[k] = (i,j).
+/* D^2 for an explicit pair list: the value of the transport LP of Eq. (1)
+ * with the centroid fixed (Sec. 1.1: for a fixed z the LP is the squared
+ * Mallows distance), dist[k] = D^2(A_i, B_j) for pairs[k] = (i,j) (device
+ * int64 [npairs][2]; an index outside its set gives D2_PAIR_TOO_LARGE).
  * When the declared max_support of A or B exceeds D2_MAX_SUPPORT (up to
  * D2_MAX_SUPPORT_LARGE, else D2_EUNSUPPORTED), every pair runs on a
  * workgroup simplex instead of a lane group; it then needs a workspace of
@@ -178,12 +192,15 @@ d2_status d2_cost_tiles(d2_handle *h, const d2_set *A, const d2_set *B, const in
  * plan + plan_offsets[k].  duals (nullable): u[t_i] then v[s_j] at
  * duals + dual_offsets[k] (dual_offsets[npairs+1], nullable with duals),
  * satisfying u_a + v_b = C_ab on the plan's support and u_a + v_b <= C_ab +
- * tol elsewhere.  pair_status[npairs] may be NULL. */
+ * tol elsewhere.  pair_status[npairs] may be NULL.
+ * pivots (nullable, device int32 [npairs][2]): the number of simplex pivots
+ * of pair k, then how many of them were taken under Bland's rule (see
+ * d2_opts.bland_after); 0, 0 for a pair that failed before its first pivot. */
 d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int64_t *pairs,
                        int64_t npairs, const d2_opts *opts, double *dist,
                        const int64_t *plan_offsets, double *plan, const int64_t *dual_offsets,
-                       double *duals, int32_t *pair_status, void *ws, size_t ws_bytes,
-                       void *stream);
+                       double *duals, int32_t *pair_status, int32_t *pivots, void *ws,
+                       size_t ws_bytes, void *stream);
 
 /* The transport LP of Eq. (1) over caller-given ground costs, for the MM
  * distance of Eq. (10) (whose ground cost is the matrix of squared Mallows
@@ -295,7 +312,11 @@ d2_status d2_assign_multi(d2_handle *h, int32_t ntypes, const d2_set *X, const d
                           const d2_opts *opts, int32_t *labels, double *best, double *all,
                           int32_t *row_status, void *ws, size_t ws_bytes, void *stream);
 
-/* All unordered pairs i<j of one set (one segment's pairwise matrix):
+/* All unordered pairs i<j of one set: the pairwise D^2 matrix of one data
+ * segment, the distances the segment-local clustering of Alg. 3 Step 2 works
+ * on (each segment holds at most tau objects and is clustered on its own,
+ * Sec. 2.1 and Sec. 2.4); D^2 is the LP value of Eq. (1) with one object
+ * as the fixed side (Sec. 1.1).
  * condensed[k] for k = i*n - i*(i+1)/2 + (j-i-1), the order of
  * scipy.spatial.distance.squareform.  pair_status (nullable) has the same
  * shape.  Supports beyond D2_MAX_SUPPORT (up to D2_MAX_SUPPORT_LARGE) run

@@ -7,6 +7,7 @@ with ctypes, and widens every input to FP64 exactly before the call.
 
     emd_pair(x, p, y, q)              -> (D^2, plan[t,s], u[t], v[s], pivots)
     emd_batch(A, B, pairs)            -> (D^2[npairs], status, pivots)
+    emd_batch_stats(A, B, pairs)      -> (D^2[npairs], status, pivots, Bland pivots)
     assign(X, Z)                      -> (labels, best, all[n,K], status, pivots)
     pairwise(X)                       -> (condensed D^2, status, pivots)
     centroid_update(X, Z, labels)     -> (z_new, eps_step1, eps_step3, status)
@@ -57,14 +58,15 @@ def _load():
     P = ctypes.c_void_p
     I64 = ctypes.c_int64
     lib.oracle_emd_pair.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P,
-                                    ctypes.c_int, P, P, P, P, P]
-    lib.oracle_emd_cost.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P]
+                                    ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+    lib.oracle_emd_cost.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int,
+                                    ctypes.c_int, P, P, P, P, P, P]
     lib.oracle_emd_batch.argtypes = [ctypes.c_int, P, P, P, I64, P, P, P, I64, P, I64,
-                                     ctypes.c_int, ctypes.c_int, P, P, P]
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P]
     lib.oracle_assign.argtypes = [ctypes.c_int, P, P, P, I64, P, P, P, I64, ctypes.c_int,
-                                  ctypes.c_int, P, P, P, P, P]
+                                  ctypes.c_int, P, P, P, P, P, P]
     lib.oracle_pairwise.argtypes = [ctypes.c_int, P, P, P, I64, ctypes.c_int, ctypes.c_int,
-                                    P, P, P]
+                                    P, P, P, P]
     for f in (lib.oracle_emd_pair, lib.oracle_emd_cost, lib.oracle_emd_batch, lib.oracle_assign,
               lib.oracle_pairwise):
         f.restype = ctypes.c_int
@@ -94,7 +96,10 @@ def _set(S):
     return off, pts.reshape(-1, d), _f64(S.weights).reshape(-1), off.shape[0] - 1, d
 
 
-def emd_pair(x, p, y, q, init: int = INIT_NWC):
+def emd_pair(x, p, y, q, init: int = INIT_NWC, stats: bool = False, bland_after: int = 0):
+    """(D^2, plan[t,s], u[t], v[s], pivots); with ``stats`` also the number of
+    pivots taken under Bland's rule.  ``bland_after``: the run of degenerate
+    pivots that switches to Bland's rule (0 = the default 2(t+s))."""
     lib = _load()
     x = _f64(x); y = _f64(y)
     x = x.reshape(x.shape[0], -1); y = y.reshape(y.shape[0], -1)
@@ -108,18 +113,22 @@ def emd_pair(x, p, y, q, init: int = INIT_NWC):
     u = np.zeros(t)
     v = np.zeros(s)
     piv = np.zeros(1, dtype=np.int64)
-    st = lib.oracle_emd_pair(t, s, d, _p(x), _p(p), _p(y), _p(q), init, _p(d2), _p(plan), _p(u),
-                             _p(v), _p(piv))
+    bl = np.zeros(1, dtype=np.int64)
+    st = lib.oracle_emd_pair(t, s, d, _p(x), _p(p), _p(y), _p(q), init, bland_after, _p(d2),
+                             _p(plan), _p(u), _p(v), _p(piv), _p(bl))
     if st != 0:
         err = ArithmeticError(f"oracle status {st}")
         err.status = st
         raise err
+    if stats:
+        return float(d2[0]), plan, u, v, int(piv[0]), int(bl[0])
     return float(d2[0]), plan, u, v, int(piv[0])
 
 
-def emd_cost(C, p, q, init: int = INIT_NWC):
+def emd_cost(C, p, q, init: int = INIT_NWC, stats: bool = False, bland_after: int = 0):
     """The transport LP with the given t x s cost matrix (any finite values):
-    (value, plan[t,s], u[t], v[s], pivots)."""
+    (value, plan[t,s], u[t], v[s], pivots); with ``stats`` also the number of
+    pivots taken under Bland's rule."""
     lib = _load()
     C = _f64(C)
     t, s = C.shape
@@ -131,16 +140,26 @@ def emd_cost(C, p, q, init: int = INIT_NWC):
     u = np.zeros(t)
     v = np.zeros(s)
     piv = np.zeros(1, dtype=np.int64)
-    st = lib.oracle_emd_cost(t, s, _p(C), _p(p), _p(q), init, _p(val), _p(plan), _p(u), _p(v),
-                             _p(piv))
+    bl = np.zeros(1, dtype=np.int64)
+    st = lib.oracle_emd_cost(t, s, _p(C), _p(p), _p(q), init, bland_after, _p(val), _p(plan),
+                             _p(u), _p(v), _p(piv), _p(bl))
     if st != 0:
         err = ArithmeticError(f"oracle status {st}")
         err.status = st
         raise err
+    if stats:
+        return float(val[0]), plan, u, v, int(piv[0]), int(bl[0])
     return float(val[0]), plan, u, v, int(piv[0])
 
 
 def emd_batch(A, B, pairs, init: int = INIT_NWC, threads: int | None = None):
+    dist, status, piv, _ = emd_batch_stats(A, B, pairs, init, threads)
+    return dist, status, piv
+
+
+def emd_batch_stats(A, B, pairs, init: int = INIT_NWC, threads: int | None = None,
+                    bland_after: int = 0):
+    """(D^2[npairs], status, pivots, pivots taken under Bland's rule)."""
     lib = _load()
     oa, xa, wa, na, d = _set(A)
     ob, xb, wb, nb, db = _set(B)
@@ -151,12 +170,13 @@ def emd_batch(A, B, pairs, init: int = INIT_NWC, threads: int | None = None):
     dist = np.full(m, np.nan)
     status = np.zeros(m, dtype=np.int32)
     piv = np.zeros(m, dtype=np.int64)
+    bl = np.zeros(m, dtype=np.int64)
     rc = lib.oracle_emd_batch(d, _p(oa), _p(xa), _p(wa), na, _p(ob), _p(xb), _p(wb), nb,
-                              _p(pairs), m, init, threads or default_threads(), _p(dist),
-                              _p(status), _p(piv))
+                              _p(pairs), m, init, bland_after, threads or default_threads(),
+                              _p(dist), _p(status), _p(piv), _p(bl))
     if rc != 0:
         raise RuntimeError(f"oracle_emd_batch failed ({rc})")
-    return dist, status, piv
+    return dist, status, piv, bl
 
 
 def assign(X, Z, init: int = INIT_NWC, threads: int | None = None, want_all: bool = True):
@@ -172,7 +192,7 @@ def assign(X, Z, init: int = INIT_NWC, threads: int | None = None, want_all: boo
     piv = np.zeros((nx, nz), dtype=np.int64) if want_all else None
     rc = lib.oracle_assign(d, _p(ox), _p(xx), _p(wx), nx, _p(oz), _p(xz), _p(wz), nz, init,
                            threads or default_threads(), _p(labels), _p(best), _p(allv),
-                           _p(status), _p(piv))
+                           _p(status), _p(piv), None)
     if rc != 0:
         raise RuntimeError(f"oracle_assign failed ({rc})")
     return labels, best, allv, status, piv
@@ -186,7 +206,7 @@ def pairwise(X, init: int = INIT_NWC, threads: int | None = None):
     status = np.zeros(m, dtype=np.int32)
     piv = np.zeros(m, dtype=np.int64)
     rc = lib.oracle_pairwise(d, _p(ox), _p(xx), _p(wx), nx, init, threads or default_threads(),
-                             _p(out), _p(status), _p(piv))
+                             _p(out), _p(status), _p(piv), None)
     if rc != 0:
         raise RuntimeError(f"oracle_pairwise failed ({rc})")
     return out, status, piv

@@ -33,15 +33,20 @@
  *      delta = 1e-14 * max C (the basis is then optimal for costs perturbed
  *      by at most delta, so the objective is within delta of the optimum);
  *   6. the entering cell is the most negative r (Dantzig), ties to the lowest
- *      row-major index; after 2(t+s) degenerate pivots in a row the rule
- *      switches to Bland's (first negative cell in row-major order) until a
- *      pivot moves flow again;
+ *      row-major index; after 2(t+s) degenerate pivots in a row (or a
+ *      caller-given streak length, `bland_after` > 0) the rule switches to
+ *      Bland's (first negative cell in row-major order) until a pivot moves
+ *      flow again;
  *   7. the cycle is the entering cell plus the tree path from its row to its
  *      column; signs alternate starting with + on the entering cell; theta
  *      is the least flow on a - cell and the leaving cell is the lowest
  *      row-major index among the - cells that reach theta;
  *   8. a pivot count above max(50 t s, 100) is reported as failure;
  *   9. the objective is sum over basic cells of w_ab C_ab in row-major order.
+ *
+ * Each solve also reports its pivot count and how many of those pivots were
+ * taken under Bland's rule (step 6), so tests can show that a family of
+ * inputs does reach the anti-cycling branch.
  *
  * oracle_emd_cost takes the ground cost as given instead of step 2 (any
  * finite values; non-finite ones give status 4), which serves the MM
@@ -317,10 +322,11 @@ static int tree_path(scratch_t *sc, int t, int s, int nb, int ra, int cb) {
  * against max |C|, which for the squared distances of step 2 is max C. */
 static int solve_pair(scratch_t *sc, int t, int s, int d, const double *x, const double *pw,
                       const double *y, const double *qw, const double *cost, int init_rule,
-                      double *d2_out, double *plan_out, double *u_out, double *v_out,
-                      long long *pivots_out) {
+                      int bland_after, double *d2_out, double *plan_out, double *u_out, double *v_out,
+                      long long *pivots_out, long long *bland_out) {
     *d2_out = NAN;
     if (pivots_out) *pivots_out = 0;
+    if (bland_out) *bland_out = 0;
     if (t < 1 || s < 1) return ORACLE_TOO_LARGE;
     if (normalise(t, pw, sc->p) != ORACLE_OK) return ORACLE_BAD_WEIGHTS;
     if (normalise(s, qw, sc->q) != ORACLE_OK) return ORACLE_BAD_WEIGHTS;
@@ -344,7 +350,7 @@ static int solve_pair(scratch_t *sc, int t, int s, int d, const double *x, const
 
     long long cap = 50LL * t * s;
     if (cap < 100) cap = 100;
-    long long pivots = 0;
+    long long pivots = 0, bland_pivots = 0;
     int degenerate_run = 0, bland = 0;
     for (;;) {
         potentials(sc, t, s, nb);
@@ -365,6 +371,7 @@ static int solve_pair(scratch_t *sc, int t, int s, int d, const double *x, const
         if (enter < 0) break;
         if (pivots >= cap) {
             if (pivots_out) *pivots_out = pivots;
+            if (bland_out) *bland_out = bland_pivots;
             return ORACLE_PIVOT_CAP;
         }
         int ea = enter / s, eb = enter % s;
@@ -392,9 +399,10 @@ static int solve_pair(scratch_t *sc, int t, int s, int d, const double *x, const
         sc->bw[leave] = theta;
         sc->basic_at[enter] = leave;
         pivots++;
+        if (bland) bland_pivots++;
         if (theta == 0.0) {
             degenerate_run++;
-            if (degenerate_run >= 2 * (t + s)) bland = 1;
+            if (degenerate_run >= (bland_after > 0 ? bland_after : 2 * (t + s))) bland = 1;
         } else {
             degenerate_run = 0;
             bland = 0;
@@ -417,29 +425,30 @@ static int solve_pair(scratch_t *sc, int t, int s, int d, const double *x, const
     if (u_out) memcpy(u_out, sc->u, sizeof(double) * t);
     if (v_out) memcpy(v_out, sc->v, sizeof(double) * s);
     if (pivots_out) *pivots_out = pivots;
+    if (bland_out) *bland_out = bland_pivots;
     return ORACLE_OK;
 }
 
 int oracle_emd_pair(int t, int s, int d, const double *x, const double *p, const double *y,
-                    const double *q, int init_rule, double *d2_out, double *plan_out,
-                    double *u_out, double *v_out, long long *pivots_out) {
+                    const double *q, int init_rule, int bland_after, double *d2_out, double *plan_out,
+                    double *u_out, double *v_out, long long *pivots_out, long long *bland_out) {
     scratch_t sc;
     if (t < 1 || s < 1 || d < 1) return ORACLE_TOO_LARGE;
     if (scratch_init(&sc, t, s) != 0) return -1;
-    int st = solve_pair(&sc, t, s, d, x, p, y, q, NULL, init_rule, d2_out, plan_out, u_out, v_out,
-                        pivots_out);
+    int st = solve_pair(&sc, t, s, d, x, p, y, q, NULL, init_rule, bland_after, d2_out, plan_out,
+                        u_out, v_out, pivots_out, bland_out);
     scratch_free(&sc);
     return st;
 }
 
 int oracle_emd_cost(int t, int s, const double *cost, const double *p, const double *q,
-                    int init_rule, double *d2_out, double *plan_out, double *u_out, double *v_out,
-                    long long *pivots_out) {
+                    int init_rule, int bland_after, double *d2_out, double *plan_out, double *u_out, double *v_out,
+                    long long *pivots_out, long long *bland_out) {
     scratch_t sc;
     if (t < 1 || s < 1 || !cost) return ORACLE_TOO_LARGE;
     if (scratch_init(&sc, t, s) != 0) return -1;
-    int st = solve_pair(&sc, t, s, 1, NULL, p, NULL, q, cost, init_rule, d2_out, plan_out, u_out,
-                        v_out, pivots_out);
+    int st = solve_pair(&sc, t, s, 1, NULL, p, NULL, q, cost, init_rule, bland_after, d2_out,
+                        plan_out, u_out, v_out, pivots_out, bland_out);
     scratch_free(&sc);
     return st;
 }
@@ -451,12 +460,12 @@ typedef struct {
     const int64_t *offA; const double *xA; const double *wA;
     const int64_t *offB; const double *xB; const double *wB;
     int64_t nA, nB;
-    int init;
+    int init, bland_after;
     /* mode 0: explicit pairs; 1: all (i,j) of A x B with argmin; 2: i<j of A */
     int mode;
     const int64_t *pairs;
     int64_t npairs;
-    double *dist; int32_t *status; long long *pivots;
+    double *dist; int32_t *status; long long *pivots, *bland;
     int32_t *labels; double *best;
     int max_t, max_s;
     int64_t begin, end;   /* chunk: pairs (modes 0, 2) or rows (mode 1) */
@@ -464,13 +473,13 @@ typedef struct {
 } job_t;
 
 static int solve_ij(scratch_t *sc, const job_t *J, int64_t i, int64_t j, double *out,
-                    long long *piv) {
+                    long long *piv, long long *bl) {
     int64_t a0 = J->offA[i], a1 = J->offA[i + 1];
     int64_t b0 = J->offB[j], b1 = J->offB[j + 1];
     int t = (int)(a1 - a0), s = (int)(b1 - b0);
     if (t < 1 || s < 1 || t > J->max_t || s > J->max_s) { *out = NAN; return ORACLE_TOO_LARGE; }
     return solve_pair(sc, t, s, J->d, J->xA + a0 * J->d, J->wA + a0, J->xB + b0 * J->d,
-                      J->wB + b0, NULL, J->init, out, NULL, NULL, NULL, piv);
+                      J->wB + b0, NULL, J->init, J->bland_after, out, NULL, NULL, NULL, piv, bl);
 }
 
 /* Pair k of the strict upper triangle, row-major: row i holds n-1-i pairs. */
@@ -487,10 +496,11 @@ static void *worker(void *arg) {
     if (scratch_init(&sc, J->max_t, J->max_s) != 0) { J->failed_alloc = 1; return NULL; }
     if (J->mode == 0) {
         for (int64_t k = J->begin; k < J->end; ++k) {
-            long long piv = 0;
-            int st = solve_ij(&sc, J, J->pairs[2 * k], J->pairs[2 * k + 1], &J->dist[k], &piv);
+            long long piv = 0, bl = 0;
+            int st = solve_ij(&sc, J, J->pairs[2 * k], J->pairs[2 * k + 1], &J->dist[k], &piv, &bl);
             if (J->status) J->status[k] = st;
             if (J->pivots) J->pivots[k] = piv;
+            if (J->bland) J->bland[k] = bl;
         }
     } else if (J->mode == 1) {
         for (int64_t i = J->begin; i < J->end; ++i) {
@@ -498,10 +508,11 @@ static void *worker(void *arg) {
             double bestv = INFINITY;
             for (int64_t j = 0; j < J->nB; ++j) {
                 double dv;
-                long long piv = 0;
-                int st = solve_ij(&sc, J, i, j, &dv, &piv);
+                long long piv = 0, bl = 0;
+                int st = solve_ij(&sc, J, i, j, &dv, &piv, &bl);
                 if (J->dist) J->dist[i * J->nB + j] = dv;
                 if (J->pivots) J->pivots[i * J->nB + j] = piv;
+                if (J->bland) J->bland[i * J->nB + j] = bl;
                 if (st != ORACLE_OK) { if (st > worst) worst = st; continue; }
                 if (dv < bestv) { bestv = dv; label = (int)j; }   /* ties: lowest j */
             }
@@ -514,10 +525,11 @@ static void *worker(void *arg) {
         int64_t i, j;
         if (J->begin < J->end) condensed_to_ij(J->nA, J->begin, &i, &j);
         for (int64_t k = J->begin; k < J->end; ++k) {
-            long long piv = 0;
-            int st = solve_ij(&sc, J, i, j, &J->dist[k], &piv);
+            long long piv = 0, bl = 0;
+            int st = solve_ij(&sc, J, i, j, &J->dist[k], &piv, &bl);
             if (J->status) J->status[k] = st;
             if (J->pivots) J->pivots[k] = piv;
+            if (J->bland) J->bland[k] = bl;
             if (++j == J->nA) { i++; j = i + 1; }
         }
     }
@@ -557,14 +569,16 @@ static int run_jobs(job_t *proto, int64_t total, int nthreads) {
 
 int oracle_emd_batch(int d, const int64_t *offA, const double *xA, const double *wA, int64_t nA,
                      const int64_t *offB, const double *xB, const double *wB, int64_t nB,
-                     const int64_t *pairs, int64_t npairs, int init_rule, int nthreads,
-                     double *dist, int32_t *status, long long *pivots) {
+                     const int64_t *pairs, int64_t npairs, int init_rule, int bland_after,
+                     int nthreads, double *dist, int32_t *status, long long *pivots,
+                     long long *bland) {
     job_t J;
     memset(&J, 0, sizeof(J));
     J.d = d; J.offA = offA; J.xA = xA; J.wA = wA; J.nA = nA;
     J.offB = offB; J.xB = xB; J.wB = wB; J.nB = nB;
-    J.init = init_rule; J.mode = 0; J.pairs = pairs; J.npairs = npairs;
-    J.dist = dist; J.status = status; J.pivots = pivots;
+    J.init = init_rule; J.bland_after = bland_after; J.mode = 0; J.pairs = pairs;
+    J.npairs = npairs;
+    J.dist = dist; J.status = status; J.pivots = pivots; J.bland = bland;
     J.max_t = max_support(offA, nA); J.max_s = max_support(offB, nB);
     for (int64_t k = 0; k < npairs; ++k)
         if (pairs[2 * k] < 0 || pairs[2 * k] >= nA || pairs[2 * k + 1] < 0 ||
@@ -578,13 +592,14 @@ int oracle_emd_batch(int d, const int64_t *offA, const double *xA, const double 
 int oracle_assign(int d, const int64_t *offX, const double *xX, const double *wX, int64_t nX,
                   const int64_t *offZ, const double *xZ, const double *wZ, int64_t nZ,
                   int init_rule, int nthreads, int32_t *labels, double *best, double *all,
-                  int32_t *status, long long *pivots) {
+                  int32_t *status, long long *pivots, long long *bland) {
     job_t J;
     memset(&J, 0, sizeof(J));
     J.d = d; J.offA = offX; J.xA = xX; J.wA = wX; J.nA = nX;
     J.offB = offZ; J.xB = xZ; J.wB = wZ; J.nB = nZ;
     J.init = init_rule; J.mode = 1;
-    J.dist = all; J.status = status; J.pivots = pivots; J.labels = labels; J.best = best;
+    J.dist = all; J.status = status; J.pivots = pivots; J.bland = bland; J.labels = labels;
+    J.best = best;
     J.max_t = max_support(offX, nX); J.max_s = max_support(offZ, nZ);
     if (J.max_t < 1) J.max_t = 1;
     if (J.max_s < 1) J.max_s = 1;
@@ -593,13 +608,13 @@ int oracle_assign(int d, const int64_t *offX, const double *xX, const double *wX
 
 int oracle_pairwise(int d, const int64_t *offX, const double *xX, const double *wX, int64_t nX,
                     int init_rule, int nthreads, double *condensed, int32_t *status,
-                    long long *pivots) {
+                    long long *pivots, long long *bland) {
     job_t J;
     memset(&J, 0, sizeof(J));
     J.d = d; J.offA = offX; J.xA = xX; J.wA = wX; J.nA = nX;
     J.offB = offX; J.xB = xX; J.wB = wX; J.nB = nX;
     J.init = init_rule; J.mode = 2;
-    J.dist = condensed; J.status = status; J.pivots = pivots;
+    J.dist = condensed; J.status = status; J.pivots = pivots; J.bland = bland;
     J.max_t = max_support(offX, nX); J.max_s = J.max_t;
     if (J.max_t < 1) { J.max_t = 1; J.max_s = 1; }
     return run_jobs(&J, nX * (nX - 1) / 2, nthreads);

@@ -3,14 +3,14 @@
 
 Written from Sec. 2 of the paper, level by level:
 
-  Step 1  segmentation (Sec. 2.3): starting from one segment holding every
+  Step 1  segmentation (Sec. 2.2): starting from one segment holding every
           object of the level, a segment with more than tau objects is split
           in two by constrained D2-clustering with two centroids, until no
           segment is larger than tau.  A split depends only on the segment it
           splits, so splitting every oversize segment in the same round gives
           the segments that splitting the largest one first would give.
   Step 2  each segment mu is clustered on its own into k_mu = ceil(n_mu / e)
-          groups (tau = c e, Sec. 2.6) by weighted D2-clustering (Eq. (3),
+          groups (tau = c e, Sec. 2.5) by weighted D2-clustering (Eq. (3),
           (4)); the centroid weights are held uniform (the constrained
           update), since the full update with free centroid weights is not
           part of this code.

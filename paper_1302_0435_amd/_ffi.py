@@ -18,7 +18,7 @@ D2_INIT_AUTO, D2_INIT_NWC, D2_INIT_VOGEL, D2_INIT_LCM = 0, 1, 2, 3
 D2_SCHED_AUTO, D2_SCHED_PLAIN = 0, 1
 D2_FLAG_EAGER = 1
 (D2_PAIR_OK, D2_PAIR_BAD_WEIGHTS, D2_PAIR_TOO_LARGE, D2_PAIR_PIVOT_CAP, D2_PAIR_BAD_POINTS,
- D2_PAIR_UNLABELLED) = range(6)
+ D2_PAIR_UNLABELLED, D2_PAIR_INTERNAL) = range(7)
 WHICH_COST_TILES, WHICH_EMD_BATCH, WHICH_ASSIGN, WHICH_PAIRWISE, WHICH_UPDATE, WHICH_MULTI = range(6)
 
 # Every function the header declares (checked against the header by the tests).
@@ -39,7 +39,7 @@ class d2_opts(ctypes.Structure):
     _fields_ = [("cost_mode", ctypes.c_int32), ("init", ctypes.c_int32),
                 ("max_pivots", ctypes.c_int32), ("want_sqrt", ctypes.c_int32),
                 ("opt_tol", ctypes.c_double), ("schedule", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("bland_after", ctypes.c_int32)]
 
 
 class LibraryMissing(RuntimeError):
@@ -70,7 +70,7 @@ def lib():
     L.d2_workspace_bytes.argtypes = [P, ctypes.c_int, S, S, I64, O]
     L.d2_workspace_bytes.restype = SZ
     L.d2_cost_tiles.argtypes = [P, S, S, P, I64, I32, P, P, P, SZ, P]
-    L.d2_emd_batch.argtypes = [P, S, S, P, I64, O, P, P, P, P, P, P, P, SZ, P]
+    L.d2_emd_batch.argtypes = [P, S, S, P, I64, O, P, P, P, P, P, P, P, P, SZ, P]
     L.d2_assign.argtypes = [P, S, S, O, P, P, P, P, P, SZ, P]
     L.d2_pairwise.argtypes = [P, S, O, P, P, P, SZ, P]
     L.d2_tune_pairwise.argtypes = [P, S, O, P, P, P, SZ, P, ctypes.POINTER(ctypes.c_double)]

@@ -98,10 +98,11 @@ class Opts:
     opt_tol: float = 0.0
     schedule: int = _ffi.D2_SCHED_AUTO
     flags: int = 0
+    bland_after: int = 0
 
     def c(self) -> _ffi.d2_opts:
         return _ffi.d2_opts(self.cost_mode, self.init, self.max_pivots, self.want_sqrt,
-                            self.opt_tol, self.schedule, self.flags)
+                            self.opt_tol, self.schedule, self.flags, self.bland_after)
 
 
 class Handle:
@@ -191,8 +192,11 @@ def _offsets_of(sizes: torch.Tensor) -> torch.Tensor:
 
 
 def d2_emd_batch(h: Handle, A: DeviceSet, B: DeviceSet, pairs: torch.Tensor,
-                 opts: Optional[Opts] = None, want_plan: bool = False, want_duals: bool = False):
-    """dist[m], status[m], and (plan, plan_offsets), (duals, dual_offsets) when asked."""
+                 opts: Optional[Opts] = None, want_plan: bool = False, want_duals: bool = False,
+                 want_pivots: bool = False):
+    """dist[m], status[m], and (plan, plan_offsets), (duals, dual_offsets) when asked;
+    with ``want_pivots`` a fifth item, pivots[m, 2] int32 (pivots taken, of which
+    under Bland's rule)."""
     opts = opts or Opts()
     dev = _dev(h)
     pairs = pairs.to(device=dev, dtype=torch.int64).reshape(-1, 2).contiguous()
@@ -210,12 +214,15 @@ def d2_emd_batch(h: Handle, A: DeviceSet, B: DeviceSet, pairs: torch.Tensor,
             dual_off = _offsets_of(sa + sb)
             duals = torch.empty(int(dual_off[-1].item()) if m else 0, dtype=torch.float64,
                                 device=dev)
+    piv = torch.empty((m, 2), dtype=torch.int32, device=dev) if want_pivots else None
     ws, nbytes = _workspace(h, _ffi.WHICH_EMD_BATCH, A, B, m, opts)
     a, b, o = A.c(), B.c(), opts.c()
     check(_ffi.lib().d2_emd_batch(h.ptr, ctypes.byref(a), ctypes.byref(b), _ptr(pairs), m,
                                   ctypes.byref(o), _ptr(dist), _ptr(plan_off), _ptr(plan),
-                                  _ptr(dual_off), _ptr(duals), _ptr(status), _ptr(ws), nbytes,
-                                  _stream(dev)), "d2_emd_batch")
+                                  _ptr(dual_off), _ptr(duals), _ptr(status), _ptr(piv), _ptr(ws),
+                                  nbytes, _stream(dev)), "d2_emd_batch")
+    if want_pivots:
+        return dist, status, (plan, plan_off), (duals, dual_off), piv
     return dist, status, (plan, plan_off), (duals, dual_off)
 
 

@@ -84,10 +84,12 @@ d2_status opts_ok(const d2_opts *o, KOpts &k) {
     if (!(o->opt_tol >= 0.0) || !isfinite(o->opt_tol) || o->opt_tol >= 1.0) return D2_EINVAL;
     if (o->schedule != D2_SCHED_AUTO && o->schedule != D2_SCHED_PLAIN) return D2_EINVAL;
     if (o->flags & ~D2_FLAG_EAGER) return D2_EINVAL;
+    if (o->bland_after < 0) return D2_EINVAL;
     k.init = o->init == D2_INIT_NWC ? d2::kStartNWC : o->init == D2_INIT_VOGEL ? d2::kStartVogel : d2::kStartLCM;
     k.max_pivots = o->max_pivots;
     k.want_sqrt = o->want_sqrt;
     k.cost_mode = o->cost_mode;
+    k.bland_after = o->bland_after;
     k.tol = o->opt_tol > 0.0 ? o->opt_tol : 1e-14;
     return D2_OK;
 }
@@ -140,6 +142,7 @@ void key_set(uint64_t *k, int &n, const d2_set *s) {
 void key_opts(uint64_t *k, int &n, const KOpts &o) {
     k[n++] = ((uint64_t)(uint32_t)o.init << 32) | (uint32_t)o.max_pivots;
     k[n++] = ((uint64_t)(uint32_t)o.want_sqrt << 32) | (uint32_t)o.cost_mode;
+    k[n++] = (uint64_t)(uint32_t)o.bland_after;
     uint64_t t;
     memcpy(&t, &o.tol, sizeof(t));
     k[n++] = t;
@@ -320,8 +323,8 @@ d2_status d2_cost_tiles(d2_handle *h, const d2_set *A, const d2_set *B, const in
 d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int64_t *pairs,
                        int64_t npairs, const d2_opts *opts, double *dist,
                        const int64_t *plan_offsets, double *plan, const int64_t *dual_offsets,
-                       double *duals, int32_t *pair_status, void *ws, size_t ws_bytes,
-                       void *stream) {
+                       double *duals, int32_t *pair_status, int32_t *pivots, void *ws,
+                       size_t ws_bytes, void *stream) {
     if (!h || npairs < 0) return D2_EINVAL;
     if (!set_ok(A) || !set_ok(B)) return D2_EINVAL;
     if (A->d != B->d || A->dtype != B->dtype) return D2_EINVAL;
@@ -339,14 +342,15 @@ d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int
         if (npairs > 0 && (!ws || ws_bytes < (size_t)(grid * elems) * sizeof(double))) return D2_EWORKSPACE;
         if ((st = bind_device(h)) != D2_OK) return st;
         hipError_t e = d2::launch_emd_wg(ctx(h, (hipStream_t)stream), kset(A), kset(B), pairs, npairs, k, ms(A),
-                                         ms(B), dist, plan_offsets, plan, dual_offsets, duals, pair_status, ws);
+                                         ms(B), dist, plan_offsets, plan, dual_offsets, duals, pair_status, pivots,
+                                         ws);
         return e == hipSuccess ? D2_OK : D2_EHIP;
     }
     if ((st = bind_device(h)) != D2_OK) return st;
     const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(ms(A), ms(B));
     hipError_t e = d2::launch_emd_pairs(ctx(h, (hipStream_t)stream), cls, kset(A), kset(B), pairs,
                                         npairs, k, dist, plan_offsets, plan, dual_offsets, duals,
-                                        pair_status);
+                                        pair_status, pivots);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 

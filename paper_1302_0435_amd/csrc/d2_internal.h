@@ -18,6 +18,7 @@ struct KOpts {
     int max_pivots;  // 0 = max(50 t s, 100)
     int want_sqrt;
     int cost_mode;
+    int bland_after; // degenerate-pivot run that switches to Bland's rule (0 = 2 (t + s))
     double tol;      // relative optimality tolerance
 };
 
@@ -65,7 +66,7 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
 hipError_t launch_emd_pairs(const LaunchCtx &c, int cls, const KSet &A, const KSet &B,
                             const int64_t *pairs, int64_t npairs, const KOpts &o, double *dist,
                             const int64_t *plan_off, double *plan, const int64_t *dual_off,
-                            double *duals, int32_t *status);
+                            double *duals, int32_t *status, int32_t *pivots);
 
 struct PairwisePlan {
     bool plain, binned;
@@ -85,7 +86,7 @@ int wg_max_support();
 void wg_plan(int64_t npairs, int tmax, int smax, int cu_count, int64_t *grid, int64_t *slab_elems);
 hipError_t launch_emd_wg(const LaunchCtx &c, const KSet &A, const KSet &B, const int64_t *pairs, int64_t npairs,
                          const KOpts &o, int tmax, int smax, double *dist, const int64_t *plan_off, double *plan,
-                         const int64_t *dual_off, double *duals, int32_t *status, void *ws);
+                         const int64_t *dual_off, double *duals, int32_t *status, int32_t *pivots, void *ws);
 size_t wg_assign_bytes(int64_t n, int64_t K, int tmax, int smax, int cu_count);
 hipError_t launch_assign_wg(const LaunchCtx &c, const KSet &X, const KSet &Z, const KOpts &o, int tmax, int smax,
                             int32_t *labels, double *best, double *all, int32_t *row_status, void *ws);

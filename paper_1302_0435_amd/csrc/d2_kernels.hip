@@ -190,7 +190,8 @@ __global__ void k_assign_reduce(int64_t n, int64_t chunks, const double *ws_best
 template <int CLS, typename TIn, int START>
 __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_emd_pairs(
     KSet A, KSet B, const int64_t *pairs, int64_t npairs, KOpts o, double *dist,
-    const int64_t *plan_off, double *plan, const int64_t *dual_off, double *duals, int32_t *status) {
+    const int64_t *plan_off, double *plan, const int64_t *dual_off, double *duals, int32_t *status,
+    int32_t *pivots) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
     __shared__ GroupMem<G, GS> mem[NG];
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_
     const int64_t stride = (int64_t)gridDim.x * NG;
     for (int64_t k = (int64_t)blockIdx.x * NG + g; k < npairs; k += stride) {
         const int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
-        int st;
+        int st, npiv = 0, nbland = 0;
         double val = __builtin_nan("");
         if (i < 0 || i >= A.n || j < 0 || j >= B.n) {
             st = kTooLarge;
@@ -209,6 +210,8 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_
             PairView pv = orient(A, i, B, j, (int)sizeof(TIn));
             SolveOut r = solve_pair<G, GS, LT, TIn, START>(mem[g], tiles[g], N, pv, A.d, o, l, gbase);
             st = r.status;
+            npiv = r.pivots;
+            nbland = r.bland_pivots;
             if (st == kOk) {
                 val = r.d2;
                 if (plan || duals)
@@ -219,6 +222,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_
         if (l == 0) {
             dist[k] = val;
             if (status) status[k] = st;
+            if (pivots) { pivots[2 * k] = npiv; pivots[2 * k + 1] = nbland; }
         }
     }
 }
@@ -728,14 +732,15 @@ struct EmdRun {
     const int64_t *pairs; int64_t npairs;
     const KOpts &o;
     double *dist; const int64_t *plan_off; double *plan; const int64_t *dual_off; double *duals;
-    int32_t *status;
+    int32_t *status, *pivots;
     template <int C, typename TIn, int V>
     hipError_t run() {
         const int NG = ShapeCfg<C>::groups;
         int64_t grid = (npairs + NG - 1) / NG;
         if (grid > (1LL << 30)) grid = 1LL << 30;
         hipLaunchKernelGGL((k_emd_pairs<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
-                           c.stream, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status);
+                           c.stream, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status,
+                           pivots);
         return hipGetLastError();
     }
 };
@@ -743,9 +748,9 @@ struct EmdRun {
 hipError_t launch_emd_pairs(const LaunchCtx &c, int cls, const KSet &A, const KSet &B,
                             const int64_t *pairs, int64_t npairs, const KOpts &o, double *dist,
                             const int64_t *plan_off, double *plan, const int64_t *dual_off,
-                            double *duals, int32_t *status) {
+                            double *duals, int32_t *status, int32_t *pivots) {
     if (npairs == 0) return hipSuccess;
-    EmdRun r{c, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status};
+    EmdRun r{c, A, B, pairs, npairs, o, dist, plan_off, plan, dual_off, duals, status, pivots};
     return dispatch_class(cls, A.dtype == D2_F32, o.init, r);
 }
 

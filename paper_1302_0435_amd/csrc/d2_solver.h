@@ -52,7 +52,7 @@
 
 namespace d2 {
 
-enum { kOk = 0, kBadWeights = 1, kTooLarge = 2, kPivotCap = 3, kBadPoints = 4 };
+enum { kOk = 0, kBadWeights = 1, kTooLarge = 2, kPivotCap = 3, kBadPoints = 4, kInternal = 6 };
 constexpr int kNoKey = 0x7fffffff;
 
 // ------------------------------------------------------------------ masks
@@ -403,6 +403,8 @@ __device__ __forceinline__ unsigned long long ordered_bits(double x) {
 struct SolveOut {
     int status;
     double d2;
+    int pivots;        // simplex pivots taken
+    int bland_pivots;  // of which under Bland's rule
 };
 
 // Solve the LP of one oriented pair with the G lanes of this group.  On
@@ -420,7 +422,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
                                                const PairView &pv, int d, const KOpts &o, int l, int gbase,
                                                const float *ctile = nullptr, const double *gcost = nullptr,
                                                int64_t grs = 0, int64_t gcs = 0) {
-    SolveOut out{kOk, __builtin_nan("")};
+    SolveOut out{kOk, __builtin_nan(""), 0, 0};
     const int T = pv.T, S = pv.S;
     if (T < 1 || S < 1 || T > G || S > GS) { out.status = kTooLarge; return out; }
     const bool hasR = l < T, hasC = l < S;
@@ -582,7 +584,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         int rounds = 0;
 #pragma unroll 1
         for (;;) {
-            if (++rounds > T + S) { out.status = kPivotCap; return out; }
+            if (++rounds > T + S) { out.status = kInternal; return out; }
             const int nr = __popcll((uint64_t)rowon), nc = __popcll((uint64_t)colon);
             if (nr == 1) {
                 const int a = __ffsll((long long)(uint64_t)rowon) - 1;
@@ -854,7 +856,8 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     const long long cap = o.max_pivots > 0 ? (long long)o.max_pivots
                                            : (50LL * T * S > 100 ? 50LL * T * S : 100LL);
     long long pivots = 0;
-    int degenerate_run = 0;
+    int degenerate_run = 0, bland_pivots = 0;
+    const int bland_after = o.bland_after > 0 ? o.bland_after : 2 * (T + S);
     bool bland = false, fresh = true;
 #pragma unroll 1
     for (;;) {
@@ -920,7 +923,12 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
             fresh = true;
             continue;
         }
-        if (pivots >= cap) { out.status = kPivotCap; return out; }
+        if (pivots >= cap) {
+            out.status = kPivotCap;
+            out.pivots = (int)pivots;
+            out.bland_pivots = bland_pivots;
+            return out;
+        }
         const int er = kidx >> 6, ec = kidx & 63;
         if (l == er) { M.bc_r = best; M.bc_c = bestC; }
         wsync();
@@ -1011,9 +1019,10 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         if (l == lr) N.bas &= ~((decltype(N.bas))1 << lc);
         wsync();
         ++pivots;
+        bland_pivots += bland ? 1 : 0;
         fresh = false;
         if (theta == 0.0) {
-            if (++degenerate_run >= 2 * (T + S)) bland = true;
+            if (++degenerate_run >= bland_after) bland = true;
         } else {
             degenerate_run = 0;
             bland = false;
@@ -1028,6 +1037,8 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
 #pragma unroll 4
     for (int n = 0; n < G + GS; ++n) sum += M.u.fin.obj[n];
     out.d2 = o.want_sqrt ? sqrt(sum) : sum;
+    out.pivots = (int)pivots;
+    out.bland_pivots = bland_pivots;
     wsync();
     return out;
 }

@@ -27,7 +27,8 @@
 // The start is the least-cost one (north-west corner under D2_INIT_NWC),
 // built directly as a tree.  Every loop has a bound: pivots by the cap,
 // tree walks by t + s steps, jumping by a fixed round count (a tree that
-// does not resolve ends the pair with the pivot-cap status).
+// does not resolve, or a tree walk that fails its checks, ends the pair
+// with the internal-error status, kept apart from the pivot cap).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -46,7 +47,7 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kChunk = 2048;          // cells per pricing block
 constexpr int kPer = kChunk / kThreads;   // cells of a block per thread
 constexpr int kBatch = 8;             // of which loaded together
-enum { kWOk = 0, kWBadWeights = 1, kWTooLarge = 2, kWPivotCap = 3, kWBadPoints = 4 };
+enum { kWOk = 0, kWBadWeights = 1, kWTooLarge = 2, kWPivotCap = 3, kWBadPoints = 4, kWInternal = 6 };
 
 // LDS of one workgroup for supports up to CAP atoms per side.
 template <int CAP>
@@ -287,9 +288,10 @@ __device__ __forceinline__ void wg_pair(int mode, const int64_t *pairs, int64_t 
 template <typename TIn, int CAP>
 __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, const int64_t *pairs,
                                                       int64_t ncols, int64_t npairs, KOpts o, double *slabs,
-                                                      int64_t slab_elems, int chunk, double *dist,
+                                                      int64_t slab_elems, double *dist,
                                                       const int64_t *plan_off, double *plan,
-                                                      const int64_t *dual_off, double *duals, int32_t *status) {
+                                                      const int64_t *dual_off, double *duals, int32_t *status,
+                                                      int32_t *pivots_out) {
     constexpr int kNodes = 2 * CAP;
     constexpr int kJumpRounds = CAP <= 256 ? 10 : CAP <= 512 ? 11 : 12;   // ceil(log2(2 CAP)) + 1
     // the first rounds resolve every node of depth < 2^kFirstRounds; the rest
@@ -306,6 +308,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
             a0 = A.off[i]; b0 = B.off[j];
             t = A.off[i + 1] - a0; s = B.off[j + 1] - b0;
         }
+        if (tid == 0 && pivots_out) { pivots_out[2 * k] = 0; pivots_out[2 * k + 1] = 0; }
         if (t < 1 || s < 1 || t > CAP || s > CAP || t * s > slab_elems) {   // uniform
             if (tid == 0) { dist[k] = __builtin_nan(""); if (status) status[k] = kWTooLarge; }
             continue;
@@ -392,7 +395,8 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
         int64_t cap = o.max_pivots > 0 ? o.max_pivots : 50LL * T * S;
         if (cap < 100) cap = 100;
         int64_t pivots = 0;
-        int streak = 0;   // wave 0 only
+        int streak = 0, bland_pivots = 0;   // wave 0 only
+        const int bland_after = o.bland_after > 0 ? o.bland_after : 2 * V;
         int buf = 0;
         for (;;) {
             // potentials and depths by pointer jumping
@@ -418,19 +422,23 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                 }
             }
             buf = kJumpRounds & 1;   // extra rounds only copy resolved nodes
-            // pricing by blocks: cells in chunks of `chunk`, from where the
+            // pricing by blocks: cells in chunks of kChunk, from where the
             // last search stopped and wrapping; the most negative reduced cost
             // of the first chunk holding one below -delta enters (lowest cell
             // on ties), and the pair is optimal once a full cycle of chunks
             // holds none.  Under Bland's rule one chunk covers every cell from
-            // cell 0 and the lowest cell below -delta enters.
+            // cell 0 and the lowest cell below -delta enters.  Basic cells
+            // never enter: the jumping sums reach a tree edge's potentials in
+            // another order than its cost, so its reduced cost is a rounding
+            // residue rather than exactly 0, and a small tolerance could let
+            // it through (the check runs only on candidates below -delta).
             const bool bland = M.bland != 0;
             const int TS = T * S;
             int unresolved = 0;
             for (int x = tid; x < V; x += kThreads) unresolved |= M.anc[buf][x] >= 0;
             if (unresolved) M.bad = 1;   // benign race: every writer stores 1
             int pos = bland ? 0 : M.scan;
-            const int width = bland ? TS : chunk;
+            const int width = bland ? TS : kChunk;
             double bv = -delta;
             int bi = INT32_MAX;
             for (int scanned = 0, rb = 0; scanned < TS; rb ^= 1) {   // >= 1 cell a pass
@@ -457,7 +465,11 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                             if (cc[e] >= 0) {
                                 const int c = cc[e], a = c / S, b = c - a * S;
                                 const double r = cv[e] - M.off[buf][a] - M.off[buf][T + b];
-                                if (r < -delta && better(r, c, best, bc, false)) { best = r; bc = c; }
+                                if (r < -delta && better(r, c, best, bc, false) && M.par[a] != T + b &&
+                                    M.par[T + b] != a) {
+                                    best = r;
+                                    bc = c;
+                                }
                             }
                         }
                     }
@@ -465,7 +477,11 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                     for (int q = tid; q < n; q += kThreads) {
                         const int a = q / S, b = q - a * S;   // one pass from cell 0
                         const double r = C[q] - M.off[buf][a] - M.off[buf][T + b];
-                        if (r < -delta && better(r, q, best, bc, true)) { best = r; bc = q; }
+                        if (r < -delta && better(r, q, best, bc, true) && M.par[a] != T + b &&
+                            M.par[T + b] != a) {
+                            best = r;
+                            bc = q;
+                        }
                     }
                 }
                 int unused = 0;
@@ -488,7 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                 // the re-hang spread over the lanes
                 const int lane = tid;
                 int stop = 0, stat = -1;
-                if (M.bad) { stat = kWPivotCap; stop = 1; }
+                if (M.bad) { stat = kWInternal; stop = 1; }
                 else if (bi == INT32_MAX) stop = 1;
                 else if (pivots >= cap) { stat = kWPivotCap; stop = 1; }
                 else {
@@ -518,7 +534,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                         ++nb; y = M.par[y];
                         ok = x >= 0 && y >= 0 && na < kNodes && nb < kNodes;
                     }
-                    if (!ok || x != y || na + nb < 3) { stat = kWPivotCap; stop = 1; }
+                    if (!ok || x != y || na + nb < 3) { stat = kWInternal; stop = 1; }
                     else {
                         // ratio test over the edges at odd distance from either
                         // end: least flow, then lowest cell (unique)
@@ -566,8 +582,9 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                             M.par[top] = (int16_t)other;
                         }
                         ++pivots;
+                        bland_pivots += bland ? 1 : 0;
                         if (theta == 0.0) {
-                            if (++streak >= 2 * V && lane == 0) M.bland = 1;
+                            if (++streak >= bland_after && lane == 0) M.bland = 1;
                         } else {
                             streak = 0;
                             if (lane == 0) M.bland = 0;
@@ -591,6 +608,7 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
                     if (M.par[x] >= 0) obj += M.pflow[x] * M.ecost[x];
             dist[k] = M.status == kWOk ? (o.want_sqrt ? sqrt(fmax(obj, 0.0)) : obj) : __builtin_nan("");
             if (status) status[k] = M.status;
+            if (pivots_out) { pivots_out[2 * k] = (int32_t)pivots; pivots_out[2 * k + 1] = bland_pivots; }
         }
         if (M.status == kWOk) {
             if (plan) {
@@ -632,16 +650,15 @@ void wg_plan(int64_t npairs, int tmax, int smax, int cu_count, int64_t *grid, in
 static hipError_t launch_wg(const LaunchCtx &c, const KSet &A, const KSet &B, int mode, const int64_t *pairs,
                             int64_t ncols, int64_t npairs, const KOpts &o, int tmax, int smax, double *dist,
                             const int64_t *plan_off, double *plan, const int64_t *dual_off, double *duals,
-                            int32_t *status, void *ws) {
+                            int32_t *status, int32_t *pivots, void *ws) {
     if (npairs == 0) return hipSuccess;
     int64_t grid, elems;
     wg_plan(npairs, tmax, smax, c.cu_count, &grid, &elems);
     const int top = tmax > smax ? tmax : smax;
-    const int chunk = kChunk;   // the chunk passes take at most kPer cells a thread
 #define D2_WG_LAUNCH(TIN, CAPV)                                                                                  \
     hipLaunchKernelGGL((k_emd_wg<TIN, CAPV>), dim3((unsigned)grid), dim3(kThreads), 0, c.stream, A, B, mode,    \
-                       pairs, ncols, npairs, o, (double *)ws, elems, chunk, dist, plan_off, plan, dual_off, duals, \
-                       status)
+                       pairs, ncols, npairs, o, (double *)ws, elems, dist, plan_off, plan, dual_off, duals,        \
+                       status, pivots)
     if (A.dtype == D2_F32) {
         if (top <= kWgSmall) D2_WG_LAUNCH(float, kWgSmall);
         else if (top <= kWgMid) D2_WG_LAUNCH(float, kWgMid);
@@ -657,9 +674,9 @@ static hipError_t launch_wg(const LaunchCtx &c, const KSet &A, const KSet &B, in
 
 hipError_t launch_emd_wg(const LaunchCtx &c, const KSet &A, const KSet &B, const int64_t *pairs, int64_t npairs,
                          const KOpts &o, int tmax, int smax, double *dist, const int64_t *plan_off, double *plan,
-                         const int64_t *dual_off, double *duals, int32_t *status, void *ws) {
+                         const int64_t *dual_off, double *duals, int32_t *status, int32_t *pivots, void *ws) {
     return launch_wg(c, A, B, kWgPairs, pairs, 0, npairs, o, tmax, smax, dist, plan_off, plan, dual_off, duals,
-                     status, ws);
+                     status, pivots, ws);
 }
 
 namespace {
@@ -719,7 +736,7 @@ hipError_t launch_assign_wg(const LaunchCtx &c, const KSet &X, const KSet &Z, co
     double *m = all ? all : (double *)((char *)ws + slab);
     int32_t *st = (int32_t *)((char *)ws + slab + mat);
     hipError_t e = launch_wg(c, X, Z, kWgCross, nullptr, K, n * K, o, tmax, smax, m, nullptr, nullptr, nullptr,
-                             nullptr, st, ws);
+                             nullptr, st, nullptr, ws);
     if (e != hipSuccess) return e;
     const int64_t g = (n + 3) / 4 < 65536 ? (n + 3) / 4 : 65536;
     hipLaunchKernelGGL(k_wg_argmin, dim3((unsigned)g), dim3(256), 0, c.stream, m, st, n, K, labels, best,
@@ -738,7 +755,7 @@ hipError_t launch_pairwise_wg(const LaunchCtx &c, const KSet &X, const KOpts &o,
                               int32_t *status, void *ws) {
     const int64_t m = X.n * (X.n - 1) / 2;
     return launch_wg(c, X, X, kWgTriangle, nullptr, X.n, m, o, tmax, tmax, condensed, nullptr, nullptr, nullptr,
-                     nullptr, status, ws);
+                     nullptr, status, nullptr, ws);
 }
 
 }  // namespace d2

@@ -14,13 +14,13 @@ once:
 
 Per level:
 
-1. **Segmentation (Sec. 2.3).**  Segments larger than tau are split in two
+1. **Segmentation (Sec. 2.2).**  Segments larger than tau are split in two
    by constrained D2-clustering with two centroids, repeated until none is
    larger.  All oversize segments split in the same round: a split depends
    only on its own segment, so the result is the one the largest-first
    order gives.
 2. **Clustering.**  Every segment is clustered into ceil(n_mu / e) groups
-   (tau = c e, Sec. 2.6) by weighted constrained D2-clustering (Eq. (3),
+   (tau = c e, Sec. 2.5) by weighted constrained D2-clustering (Eq. (3),
    (4) with the centroid weights held uniform).
 3. **Merge.**  The segments' centroids are concatenated in segment order,
    labels are offset (Eq. (5)) and inherited (Eq. (6)), and a centroid's

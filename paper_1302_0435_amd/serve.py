@@ -15,7 +15,10 @@ plus its K distances, label, minimum and status.  The scheduler
     memory, d2_assign against the resident centroids, copy back -- so
     batches on different slots overlap on the device,
   * measures each request's latency from its scheduled arrival time to the
-    device completion of its batch (no coordinated omission).
+    device completion of its batch (no coordinated omission).  Device times
+    are kept against a reference event; the host time at which that event is
+    known to have passed is taken as its place on the host clock, so a
+    latency can only be overstated by that bound, never understated.
 
 The scheduler core is independent of the device: it drives an executor
 object (GpuExecutor here; tests use a scripted one) through submit / poll.
@@ -121,7 +124,9 @@ class Scheduler:
         batch_sizes: List[int] = []
         max_queue = 0
         t0 = clock()
-        self.ex.start()
+        # the executor reports completions against its own origin; `shift`
+        # places that origin on this loop's clock (arrivals count from t0)
+        shift = self.ex.start(clock) - t0
         while True:
             now = clock() - t0
             arrived = int(np.searchsorted(arrivals, now, side="right"))
@@ -131,7 +136,7 @@ class Scheduler:
             for b in list(inflight):
                 t_done = self.ex.poll(b)
                 if t_done is not None:
-                    done_s[b.first:b.first + b.count] = t_done
+                    done_s[b.first:b.first + b.count] = t_done + shift
                     used -= b.nbytes
                     free_slots.append(b.slot)
                     inflight.remove(b)
@@ -224,10 +229,13 @@ class GpuExecutor:
             s["ws"] = torch.empty(max(ws_b, 1), dtype=torch.uint8, device=self.dev)
         self.ref = torch.cuda.Event(enable_timing=True)
 
-    def start(self):
+    def start(self, clock=time.perf_counter) -> float:
+        """Record the reference event on an idle device; return the host time
+        once it has completed (an upper bound on the event's own time)."""
         self.torch.cuda.synchronize(self.dev)
         self.ref.record(self.torch.cuda.current_stream(self.dev))
         self.ref.synchronize()
+        return clock()
 
     def stop(self):
         self.torch.cuda.synchronize(self.dev)
@@ -283,8 +291,9 @@ class ScriptedExecutor:
         self.t0 = None
         self.submitted = []
 
-    def start(self):
+    def start(self, clock=None) -> float:
         self.t0 = self.clock()
+        return self.t0
 
     def stop(self):
         pass

@@ -209,3 +209,26 @@ def sample_pairs(cfg: int, n_rows: int, n_cols: int, count: int, tag: int = 0) -
 def sample_rows(cfg: int, n_rows: int, count: int, tag: int = 0) -> np.ndarray:
     rng = rng_for(cfg, STREAM_SAMPLE, 1000 + tag)
     return np.sort(rng.choice(n_rows, size=min(count, n_rows), replace=False)).astype(np.int64)
+
+
+def make_degenerate(seed: int, n: int, t: int, s: int, d: int = 2, grid: int = 4,
+                    identical_every: int = 4) -> tuple:
+    """A family of highly degenerate transport problems: ``n`` pairs of bags
+    with equal weights (all 1, so with t and s powers of two the normalised
+    weights and every flow are exact binary fractions) and points on the
+    integer grid {0..grid-1}^d (exact costs, many ties).  Every
+    ``identical_every``-th pair is one bag against itself, where every pivot
+    from the north-west corner is degenerate.  Returns (A, B, pairs) with
+    pair k = (k, k)."""
+    rng = np.random.default_rng([SEED, 900, seed, t, s, d])
+    bags_a, bags_b = [], []
+    for k in range(n):
+        xa = rng.integers(0, grid, size=(t, d)).astype(np.float64)
+        if identical_every and k % identical_every == 0 and s == t:
+            xb = xa.copy()
+        else:
+            xb = rng.integers(0, grid, size=(s, d)).astype(np.float64)
+        bags_a.append((xa, np.ones(t)))
+        bags_b.append((xb, np.ones(s)))
+    pairs = np.stack([np.arange(n), np.arange(n)], axis=1).astype(np.int64)
+    return from_bags(bags_a), from_bags(bags_b), pairs

@@ -50,9 +50,9 @@ def test_struct_layout_matches_c(ffi, tmp_path):
 #include <stddef.h>
 #include "d2.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(d2_set), offsetof(d2_set, offsets),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(d2_set), offsetof(d2_set, offsets),
          offsetof(d2_set, points), offsetof(d2_set, weights), offsetof(d2_set, max_support),
-         sizeof(d2_opts), offsetof(d2_opts, opt_tol));
+         sizeof(d2_opts), offsetof(d2_opts, opt_tol), offsetof(d2_opts, bland_after));
   return 0;
 }
 """)
@@ -63,7 +63,7 @@ int main(void) {
                                        check=True).stdout.split()))
     S, O = ffi.d2_set, ffi.d2_opts
     want = [ctypes.sizeof(S), S.offsets.offset, S.points.offset, S.weights.offset,
-            S.max_support.offset, ctypes.sizeof(O), O.opt_tol.offset]
+            S.max_support.offset, ctypes.sizeof(O), O.opt_tol.offset, O.bland_after.offset]
     assert got == want
 
 
@@ -84,7 +84,7 @@ def test_null_handle_is_rejected_without_a_gpu(ffi):
     assert L.d2_assign(None, r(s), r(s), r(o), None, None, None, None, None, 0, None) == ffi.D2_EINVAL
     assert L.d2_pairwise(None, r(s), r(o), None, None, None, 0, None) == ffi.D2_EINVAL
     assert L.d2_emd_batch(None, r(s), r(s), None, 0, r(o), None, None, None, None, None, None,
-                          None, 0, None) == ffi.D2_EINVAL
+                          None, None, 0, None) == ffi.D2_EINVAL
     assert L.d2_cost_tiles(None, r(s), r(s), None, 0, 0, None, None, None, 0, None) == ffi.D2_EINVAL
     assert L.d2_workspace_bytes(None, 2, r(s), r(s), 0, r(o)) == 0
     assert L.d2_create(None, 0) == ffi.D2_EINVAL

@@ -202,7 +202,7 @@ def test_declared_bounds(d2, h):
     rc = d2._ffi.lib().d2_emd_batch(h.ptr, ctypes.byref(a), ctypes.byref(a),
                                     ctypes.c_void_p(pairs.data_ptr()), 1, ctypes.byref(o),
                                     ctypes.c_void_p(dist.data_ptr()), None, None, None, None, None,
-                                    None, 0, None)
+                                    None, None, 0, None)
     assert rc == 3                                           # above D2_MAX_SUPPORT_LARGE
     B = bags(rng, [100], 2)
     Bd = d2.DeviceSet.from_ragged(B, DEV)
@@ -210,7 +210,7 @@ def test_declared_bounds(d2, h):
     rc = d2._ffi.lib().d2_emd_batch(h.ptr, ctypes.byref(b), ctypes.byref(b),
                                     ctypes.c_void_p(pairs.data_ptr()), 1, ctypes.byref(o),
                                     ctypes.c_void_p(dist.data_ptr()), None, None, None, None, None,
-                                    None, 0, None)
+                                    None, None, 0, None)
     assert rc == 2                                           # the workgroup path needs its workspace
 
 

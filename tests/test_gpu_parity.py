@@ -397,3 +397,22 @@ def test_autotuned_pairwise_matches(d2, h):
     n = X.n
     pairs = np.array([(i, j) for i in range(n) for j in range(i + 1, n)])
     assert_close(again.cpu().numpy(), o, pair_tolerance(X, X, pairs))
+
+
+@pytest.mark.parametrize("n", [7, 300])
+def test_duplicate_centroids_take_the_lowest_index(d2, h, n):
+    """Exact ties: centroids repeated at later indices (within one chunk of
+    centroids and across chunks) give bitwise-equal distances, and the label
+    is the first of them, as in the oracle."""
+    X = synth.make_data(1, n=n)
+    Z0 = synth.make_centroids(1, k=20)
+    order = list(range(20)) + [3, 0, 19, 7, 3, 12, 0, 5] * 3   # duplicates after their originals
+    Z = Z0.subset(np.array(order))
+    g_lab, g_best, g_all, g_st = run_assign(d2, h, X, Z)
+    o_lab, o_best, o_all, o_st, _ = oracle.assign(X, Z)
+    assert np.all(g_st == 0)
+    np.testing.assert_array_equal(g_lab, o_lab)
+    first = {j: order.index(j) for j in set(order)}
+    for j, src in enumerate(order):
+        np.testing.assert_array_equal(g_all[:, j], g_all[:, first[src]])
+    assert np.all(g_lab < 20)

@@ -419,3 +419,59 @@ def test_threads_do_not_change_results(oracle_mod):
     r8 = oracle_mod.assign(X, Z, threads=8)
     for a, b in zip(r1, r8):
         assert np.array_equal(a, b)
+
+
+# ---- the Bland anti-cycling branch (a reading: the paper leaves cycling open)
+
+@pytest.mark.parametrize("t", [16, 32, 64])
+@pytest.mark.parametrize("bland_after", [1, 3])
+def test_bland_branch_reaches_the_assignment_optimum(oracle_mod, t, bland_after):
+    """Equal weights on integer grids: the LP optimum is the assignment
+    optimum over C / t (Birkhoff), and the values are exact in binary.  With
+    a short degenerate run before Bland's rule, every pair of the family
+    pivots under it, and still reaches that optimum."""
+    from scipy.optimize import linear_sum_assignment
+    A, B, pairs = synth.make_degenerate(1, 6, t, t)
+    for k in range(pairs.shape[0]):
+        x, p = A.bag(k)
+        y, q = B.bag(k)
+        C = cost(x, y)
+        r, c = linear_sum_assignment(C)
+        want = C[r, c].sum() / t
+        got, _, _, _, piv, bl = oracle_mod.emd_pair(x, p, y, q, stats=True, bland_after=bland_after)
+        assert abs(got - want) <= 1e-12 * max(1.0, want), (k, got, want)
+        assert bl > 0 and piv >= bl, (k, piv, bl)
+        default = oracle_mod.emd_pair(x, p, y, q)
+        assert default[0] == got   # same optimum (exact arithmetic), another pivot path
+
+
+def test_bland_counts_in_the_batch_entry(oracle_mod):
+    """The batch entry reports the same per-pair pivot and Bland counts as
+    single solves, and the default run (2(t+s) degenerate pivots) does not
+    reach Bland's rule on this family."""
+    A, B, pairs = synth.make_degenerate(2, 8, 32, 32)
+    dist, st, piv, bl = oracle_mod.emd_batch_stats(A, B, pairs, bland_after=2)
+    assert np.all(st == 0)
+    for k in range(pairs.shape[0]):
+        x, p = A.bag(k)
+        y, q = B.bag(k)
+        one = oracle_mod.emd_pair(x, p, y, q, stats=True, bland_after=2)
+        assert (one[0], one[4], one[5]) == (dist[k], piv[k], bl[k])
+    assert np.all(bl > 0)
+    _, _, _, bl0 = oracle_mod.emd_batch_stats(A, B, pairs)
+    assert np.all(bl0 == 0)
+
+
+def test_identical_pairs_under_bland_rule_from_the_first_degenerate_pivot(oracle_mod):
+    """With bland_after = 1 on a bag against itself, every pivot from the
+    north-west corner is degenerate (the corner plan is the identity, already
+    optimal at 0), so the first pivot is Dantzig's and every later one is
+    Bland's.  The run ends at exactly 0 with a dual-feasible basis."""
+    for t in (8, 16, 64):
+        A, B, pairs = synth.make_degenerate(3, 1, t, t, identical_every=1)
+        x, p = A.bag(0)
+        got, plan, u, v, piv, bl = oracle_mod.emd_pair(x, p, x, p, stats=True, bland_after=1)
+        assert got == 0.0
+        assert piv >= 1 and bl == piv - 1, (t, piv, bl)
+        C = cost(x, x)
+        assert np.all(C - u[:, None] - v[None, :] >= -1e-14 * C.max())

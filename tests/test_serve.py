@@ -88,3 +88,29 @@ def test_slots_bound_concurrency(slots):
     st, ex = run(arrivals, [5] * 50, lambda c: 0.01, budget=1 << 30, max_batch=5, slots=slots)
     assert sorted({s for _, _, s in ex.submitted}) == list(range(slots))
     assert np.all(~np.isnan(st.done_s))
+
+
+class SlowStartExecutor(ScriptedExecutor):
+    """An executor whose start takes `lag` seconds (like a device
+    synchronisation) before its own time origin."""
+
+    def __init__(self, duration, clock, lag):
+        super().__init__(duration, clock=clock)
+        self.lag = lag
+
+    def start(self, clock=None):
+        self.clock.sleep(self.lag)
+        return super().start(clock)
+
+
+def test_completions_are_placed_on_the_arrival_clock():
+    # requests arrive at 0 and 0.1 s; the executor's origin lies 5 ms after
+    # the loop's t0, so the first request waits for it and completes at
+    # 5 + 10 ms, the second at 100 + 10 ms (plus at most one poll step)
+    clk = VClock()
+    ex = SlowStartExecutor(lambda c: 0.010, clk, 0.005)
+    sch = Scheduler(ex, np.array([3, 3]), 4, 8, 1 << 30, 64, 2)
+    st = sch.run(np.array([0.0, 0.1]), clock=clk, sleep=clk.sleep)
+    lat = st.latencies_ms()
+    assert 15.0 - 1e-9 <= lat[0] <= 15.2
+    assert 10.0 - 1e-9 <= lat[1] <= 10.2
