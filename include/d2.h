@@ -59,8 +59,14 @@ typedef enum {
     D2_EWORKSPACE = 2,   /* ws_bytes below d2_workspace_bytes() for the call     */
     D2_EUNSUPPORTED = 3, /* declared max_support above D2_MAX_SUPPORT, etc.      */
     D2_EHIP = 4,         /* a HIP runtime call or launch failed                  */
-    D2_ENOMEM = 5        /* host allocation failed (handle creation only)        */
+    D2_ENOMEM = 5,       /* host allocation failed (handle creation only)        */
+    D2_ESCRATCH = 6      /* d2_assign_noalloc: the call needs more workspace     *
+                          * than D2_NOALLOC_SCRATCH_BYTES                        */
 } d2_status;
+
+/* Bytes of device scratch each GPU holds for d2_assign_noalloc (32 MiB),
+ * from the first d2_create on it until the process ends. */
+#define D2_NOALLOC_SCRATCH_BYTES (32u << 20)
 
 /* element type of d2_set.points and d2_set.weights (always both the same) */
 enum { D2_F64 = 0, D2_F32 = 1 };
@@ -242,6 +248,24 @@ d2_status d2_emd_cost_batch(d2_handle *h, int64_t nprob, const int64_t *row_offs
 d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opts *opts,
                     int32_t *labels, double *best, double *all, int32_t *row_status, void *ws,
                     size_t ws_bytes, void *stream);
+
+/* d2_assign without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory: code under hipGraph stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as d2_assign with opts->flags treated as
+ * D2_FLAG_EAGER (always enqueued directly, never recorded as a graph).  The
+ * workspace d2_assign would take (d2_workspace_bytes(h, 2, X, Z, 0, opts))
+ * lives in a fixed device array of D2_NOALLOC_SCRATCH_BYTES per GPU instead;
+ * a call needing more returns D2_ESCRATCH and enqueues nothing (C2-like
+ * labelling of 100,000 objects needs under 1 MiB; the BF16 cost mode and
+ * supports above D2_MAX_SUPPORT are beyond it).  The call performs no
+ * hipMalloc/hipFree and no allocating library call.  Every call on one GPU
+ * shares that GPU's array: calls whose stream work overlaps on one GPU
+ * race (serialise them, e.g. on one stream).  Kernels clear what must start
+ * at zero; nothing carries over between calls. */
+d2_status d2_assign_noalloc(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opts *opts,
+                            int32_t *labels, double *best, double *all, int32_t *row_status,
+                            void *stream);
 
 /* Centroid update of constrained D2-clustering (Alg. 2 Step 3*: the update
  * of Alg. 1 with every centroid's weights held fixed), one pass over all

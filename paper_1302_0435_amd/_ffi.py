@@ -11,7 +11,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libd2.so")
 
-D2_OK, D2_EINVAL, D2_EWORKSPACE, D2_EUNSUPPORTED, D2_EHIP, D2_ENOMEM = range(6)
+D2_OK, D2_EINVAL, D2_EWORKSPACE, D2_EUNSUPPORTED, D2_EHIP, D2_ENOMEM, D2_ESCRATCH = range(7)
+D2_NOALLOC_SCRATCH_BYTES = 32 << 20
 D2_F64, D2_F32 = 0, 1
 D2_COST_F64_DIRECT, D2_COST_BF16_MFMA = 0, 1
 D2_INIT_AUTO, D2_INIT_NWC, D2_INIT_VOGEL, D2_INIT_LCM = 0, 1, 2, 3
@@ -25,7 +26,7 @@ WHICH_COST_TILES, WHICH_EMD_BATCH, WHICH_ASSIGN, WHICH_PAIRWISE, WHICH_UPDATE, W
 EXPORTS = ["d2_create", "d2_destroy", "d2_status_string", "d2_max_support", "d2_version",
            "d2_workspace_bytes", "d2_cost_tiles", "d2_emd_batch", "d2_assign", "d2_pairwise",
            "d2_tune_pairwise", "d2_centroid_update", "d2_emd_cost_batch",
-           "d2_assign_multi", "d2_assign_segmented"]
+           "d2_assign_multi", "d2_assign_segmented", "d2_assign_noalloc"]
 
 
 class d2_set(ctypes.Structure):
@@ -72,6 +73,7 @@ def lib():
     L.d2_cost_tiles.argtypes = [P, S, S, P, I64, I32, P, P, P, SZ, P]
     L.d2_emd_batch.argtypes = [P, S, S, P, I64, O, P, P, P, P, P, P, P, P, SZ, P]
     L.d2_assign.argtypes = [P, S, S, O, P, P, P, P, P, SZ, P]
+    L.d2_assign_noalloc.argtypes = [P, S, S, O, P, P, P, P, P]
     L.d2_pairwise.argtypes = [P, S, O, P, P, P, SZ, P]
     L.d2_tune_pairwise.argtypes = [P, S, O, P, P, P, SZ, P, ctypes.POINTER(ctypes.c_double)]
     L.d2_centroid_update.argtypes = [P, S, S, P, P, O, P, P, P, P, P, P, SZ, P]
@@ -80,7 +82,8 @@ def lib():
     L.d2_emd_cost_batch.argtypes = [P, I64, P, P, P, P, P, P, I32, I32, O, P, P, P, P, P, SZ, P]
     for name in ("d2_create", "d2_destroy", "d2_cost_tiles", "d2_emd_batch", "d2_assign",
                  "d2_pairwise", "d2_max_support", "d2_tune_pairwise", "d2_centroid_update",
-                 "d2_emd_cost_batch", "d2_assign_multi", "d2_assign_segmented"):
+                 "d2_emd_cost_batch", "d2_assign_multi", "d2_assign_segmented",
+                 "d2_assign_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -1,12 +1,15 @@
 // Host side of the C ABI declared in include/d2.h: argument validation,
 // option defaults, work planning, kernel dispatch, hipGraph capture/replay
 // and the schedule autotuner.  Nothing here allocates device memory; every
-// device buffer belongs to the caller.
+// device buffer belongs to the caller, except the fixed scratch array that
+// d2_assign_noalloc uses in place of a workspace (a file-scope __device__
+// array, one copy per GPU, held until the process ends).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -38,13 +41,42 @@ struct TuneEntry {
 struct d2_handle {
     int device;
     int cu_count;
+    void *scratch;                  // this device's copy of `scratch` (device address)
     hipStream_t capture;            // private stream used only to record graphs
     std::vector<GraphEntry> graphs;
     std::vector<TuneEntry> tuned;
     uint64_t clock;
 };
 
+// Workspace of d2_assign_noalloc: the partial minima of split centroid
+// ranges and the support-class sort live here instead of in a caller
+// buffer.  In host code the name stands for a host-side shadow, not device
+// memory: only the address from hipGetSymbolAddress (kept per device in
+// g_scratch) may be handed to kernels.
+static __device__ __align__(256) unsigned char scratch[D2_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr size_t kScratchBytes = (size_t)D2_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices];
+
+// The device address of `scratch` on `device` (current), looked up once per
+// device; nullptr on failure.
+void *scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch[device] = p;
+    }
+    return g_scratch[device];
+}
 
 constexpr size_t kMaxGraphs = 32;
 
@@ -237,6 +269,7 @@ const char *d2_status_string(int code) {
     case D2_EUNSUPPORTED: return "unsupported size or mode";
     case D2_EHIP: return "HIP runtime error";
     case D2_ENOMEM: return "out of host memory";
+    case D2_ESCRATCH: return "call needs more than the fixed scratch of d2_assign_noalloc";
     default: return "unknown status";
     }
 }
@@ -250,10 +283,13 @@ d2_status d2_create(d2_handle **h, int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return D2_EHIP;
     if (hipSetDevice(device) != hipSuccess) return D2_EHIP;
+    void *scr = scratch_on(device);
+    if (!scr) return D2_EHIP;
     d2_handle *p = new (std::nothrow) d2_handle;
     if (!p) return D2_ENOMEM;
     p->device = device;
     p->cu_count = prop.multiProcessorCount;
+    p->scratch = scr;
     p->clock = 0;
     if (hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
         delete p;
@@ -403,6 +439,29 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
     return run_graph(h, 2, key, eager_of(opts), (hipStream_t)stream, [&](hipStream_t s) {
         return d2::launch_assign(ctx(h, s), p, kx, kz, k, labels, best, all, row_status, ws);
     });
+}
+
+d2_status d2_assign_noalloc(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opts *opts,
+                            int32_t *labels, double *best, double *all, int32_t *row_status, void *stream) {
+    if (!h) return D2_EINVAL;
+    d2_status st = pair_sets_ok(X, Z);
+    if (st != D2_OK) return st;
+    KOpts k;
+    if ((st = opts_ok(opts, k)) != D2_OK) return st;
+    if (k.cost_mode == D2_COST_BF16_MFMA && (ms(X) > 32 || ms(Z) > 32)) return D2_EUNSUPPORTED;
+    if (X->n > 0 && (!labels || !best)) return D2_EINVAL;
+    if (X->n > 0 && Z->n < 1) return D2_EINVAL;
+    if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
+    KSet kx = kset(X), kz = kset(Z);
+    d2::AssignPlan p = d2::plan_assign(kx, kz, ms(X), ms(Z), h->cu_count, sched_of(opts), k.cost_mode);
+    if (p.ws_bytes > kScratchBytes) return D2_ESCRATCH;
+    if ((st = bind_device(h)) != D2_OK) return st;
+    if (X->n == 0) return D2_OK;
+    // enqueued directly: recording a graph could allocate
+    return d2::launch_assign(ctx(h, (hipStream_t)stream), p, kx, kz, k, labels, best, all, row_status,
+                             h->scratch) == hipSuccess
+               ? D2_OK
+               : D2_EHIP;
 }
 
 d2_status d2_emd_cost_batch(d2_handle *h, int64_t nprob, const int64_t *row_offsets,

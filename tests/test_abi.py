@@ -71,7 +71,7 @@ def test_constants_and_strings(ffi):
     L = ffi.lib()
     assert L.d2_max_support() == 64
     assert L.d2_version().decode().startswith("d2-mi355x")
-    for code in range(6):
+    for code in range(7):
         assert L.d2_status_string(code).decode() != "unknown status"
     assert L.d2_status_string(99).decode() == "unknown status"
 
