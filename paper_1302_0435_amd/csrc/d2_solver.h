@@ -27,9 +27,9 @@
 //     its old ancestor set inside the subtree and y its deepest ancestor on
 //     the stem (looked up by position along the stem);
 //   * potentials change only inside the moved subtree, by +-r_entering.
-// Potentials are set from the tree as signed sums over ancestor sets at the
-// start and once more before optimality is declared, so rounding drift in
-// the incremental updates cannot end the solve early.
+// Potentials are set from the tree by pointer jumping at the start and once
+// more before optimality is declared, so rounding drift in the incremental
+// updates cannot end the solve early.
 //
 // Group communication: reductions are butterflies over DPP row permutations
 // (16 lanes), plus a swizzle (32) and a lane permute (64); broadcasts go
@@ -172,16 +172,28 @@ __device__ __forceinline__ void group_argmin(double &v, int &k) {
     v = m;
 }
 
-// Maximum of a group-uniform value over the whole wavefront (a scalar), so
-// loops bounded by it branch on the scalar unit.
+template <int J, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (J < N) {
+        f(std::integral_constant<int, J>{});
+        static_for<J + 1, N>(f);
+    }
+}
+
+// Maximum of a group-uniform value over the groups of the wavefront that are
+// executing, as a scalar, so loops bounded by it branch on the scalar unit.
+// A group whose loop has ended is inactive and its registers hold stale
+// values, so only groups present in the active mask count (groups are
+// always active or inactive as a whole).
 template <int G>
 __device__ __forceinline__ int wave_max(int v) {
-    int m = __builtin_amdgcn_readlane(v, 0);
-    if constexpr (G <= 32) m = max(m, __builtin_amdgcn_readlane(v, 32));
-    if constexpr (G == 16) {
-        m = max(m, __builtin_amdgcn_readlane(v, 16));
-        m = max(m, __builtin_amdgcn_readlane(v, 48));
-    }
+    const uint64_t act = __ballot(1);
+    int m = 0;
+    static_for<0, 64 / G>([&](auto k) {
+        constexpr int b = decltype(k)::value * G;
+        const int x = __builtin_amdgcn_readlane(v, b);
+        m = ((act >> b) & 1ull) ? max(m, x) : m;
+    });
     return m;
 }
 
@@ -192,11 +204,19 @@ __device__ __forceinline__ uint64_t group_bits(bool p, int gbase) {
     return (b >> gbase) & gm;
 }
 
-template <int J, int N, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (J < N) {
-        f(std::integral_constant<int, J>{});
-        static_for<J + 1, N>(f);
+
+// f(integral_constant<int, N>) for the least N in {Q, 2Q, .., MAX} with
+// N >= n.  With a wave-uniform n the choice is a few scalar branches and the
+// body runs fully unrolled over N items, so loops over a pair's columns stop
+// near its support instead of running to the shape's capacity (a plain
+// guard inside an unrolled loop is turned into predicated selects).
+template <int MAX, int Q, int N = Q, typename F>
+__device__ __forceinline__ void up_to(int n, F &&f) {
+    if constexpr (N >= MAX) {
+        f(std::integral_constant<int, MAX>{});
+    } else {
+        if (n <= N) f(std::integral_constant<int, N>{});
+        else up_to<MAX, Q, N + Q>(n, f);
     }
 }
 
@@ -206,6 +226,10 @@ __device__ __forceinline__ void static_for(F &&f) {
 // shape, 4 for the others, whose register budgets are tighter (measured).
 template <int G>
 constexpr int stage_k() { return G == 32 ? 8 : 4; }
+
+// The widest shape keeps columns [0, kSplitCols) of its cost row in
+// registers and the rest in an LDS tile (TileHalf below).
+constexpr int kSplitCols = 32;
 
 template <int G, int GS>
 struct GroupMem {
@@ -217,8 +241,7 @@ struct GroupMem {
     union {
         struct { double pw[G]; double qw[GS]; double P[G]; double Q[GS]; double colcpar[GS];
                  int colpar[GS]; int kind[2 * G]; int lastpos[2 * G]; } init;
-        struct { int jmp[2 * G]; Mask<G> anc[2 * G]; } jump;
-        struct { double g[2 * G]; } pot;
+        struct { int jmp[2 * G]; Mask<G> anc[2 * G]; double off[2 * G]; } jump;
         struct { int newpar[2 * G]; int stemtab[2 * G]; double newflow[2 * G];
                  double newcpar[2 * G]; } piv;
         struct { double obj[2 * G]; double colflow[GS]; int colpar[GS]; } fin;
@@ -233,10 +256,9 @@ template <int G, int GS>
 struct Tile { double C[GS][G + 1]; };
 struct NoTile { char pad; };
 
-// The widest shape keeps columns [0, kSplitCols) of its cost row in
-// registers and the rest in this LDS tile (column-major, C[b - kSplitCols][a]),
-// which halves the LDS a pair needs and lets two wavefronts share a SIMD.
-constexpr int kSplitCols = 32;
+// The widest shape's LDS tile of columns [kSplitCols, GS) (column-major,
+// C[b - kSplitCols][a]), which halves the LDS a pair needs and lets two
+// wavefronts share a SIMD.
 template <int G, int GS>
 struct TileHalf { double C[GS - kSplitCols][G]; };
 template <typename T> struct IsTileHalf : std::false_type {};
@@ -328,67 +350,76 @@ __device__ __forceinline__ double cost_pick(const NodeState<G, GS, LT> &N, const
 
 // ------------------------------------------------------------ potentials
 
-// u, v from the tree: with sign(n) = (-1)^depth(n), the potential of node x
-// is sign(x) * sum over its ancestors n != root of sign(n) * cpar(n), which
-// unrolls u_a + v_b = C_ab along the path to the root.  The sum runs over
-// node indices in order (rows, then columns).  Also refreshes the LDS
-// mirrors read when pricing and when broadcasting the entering cell.
-template <int G, int GS, bool LT>
-__device__ __forceinline__ void set_potentials(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int l, int T, int S) {
+// Potentials (and, with MASKS, ancestor masks) from the parent pointers by
+// pointer jumping.  A tree edge joins node x to its parent with the cost
+// cpar(x) of their cell, and u_a + v_b = C_ab there gives
+// pot(x) = cpar(x) - pot(parent(x)), with pot(root) = 0.  Every node keeps a
+// target t(x) (first its parent), the parity of the path from x up to t(x)
+// and an offset o(x) such that pot(x) = o(x) + (-1)^parity pot(t(x)).  A
+// round replaces t(x) by t(t(x)) and folds o(t(x)) into o(x); after
+// ceil(log2 2G) rounds every target is the root and pot(x) = o(x).  The order
+// of the additions follows the tree alone, so every group width computes the
+// same bits.  Also refreshes the LDS mirrors read when pricing and when
+// broadcasting the entering cell.
+template <int G, int GS, bool LT, bool MASKS>
+__device__ __forceinline__ void tree_jump(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int l, int T, int S) {
     const bool hasR = l < T, hasC = l < S;
-    const double sR = ((N.ancR.popc() - 1) & 1) ? -1.0 : 1.0;
-    const double sC = ((N.ancC.popc() - 1) & 1) ? -1.0 : 1.0;
-    M.u.pot.g[l] = (hasR && N.parR >= 0) ? sR * N.cparR : 0.0;
-    if (l < GS) M.u.pot.g[G + l] = (hasC && N.parC >= 0) ? sC * N.cparC : 0.0;
-    wsync();
-    double sumR = 0.0, sumC = 0.0;
-#pragma unroll 4
-    for (int n = 0; n < G + GS; ++n) {
-        const double gv = M.u.pot.g[n];
-        sumR += N.ancR.has(n) ? gv : 0.0;
-        sumC += N.ancC.has(n) ? gv : 0.0;
+    const int idR = l, idC = G + l;
+    const bool pR = hasR && N.parR >= 0, pC = hasC && N.parC >= 0;
+    constexpr int kOdd = 1 << 30;   // parity bit beside the target index
+    int jR = pR ? (G + N.parR) | kOdd : idR;
+    int jC = pC ? N.parC | kOdd : idC;
+    double oR = pR ? N.cparR : 0.0, oC = pC ? N.cparC : 0.0;
+    Mask<G> aR = hasR ? Mask<G>::node(idR) : Mask<G>::none();
+    Mask<G> aC = hasC ? Mask<G>::node(idC) : Mask<G>::none();
+    M.u.jump.jmp[idR] = jR;
+    M.u.jump.jmp[idC] = jC;
+    M.u.jump.off[idR] = oR;
+    M.u.jump.off[idC] = oC;
+    if constexpr (MASKS) {
+        M.u.jump.anc[idR] = aR;
+        M.u.jump.anc[idC] = aC;
     }
-    N.potR = sR * sumR;
-    N.potC = sC * sumC;
+    wsync();
+#pragma unroll 1
+    for (int k = 0; k < Steps<G>::n + 1; ++k) {
+        const int tR = jR & (kOdd - 1), tC = jC & (kOdd - 1);
+        const int nR = M.u.jump.jmp[tR], nC = M.u.jump.jmp[tC];
+        const double xR = M.u.jump.off[tR], xC = M.u.jump.off[tC];
+        Mask<G> mR, mC;
+        if constexpr (MASKS) {
+            mR = M.u.jump.anc[tR];
+            mC = M.u.jump.anc[tC];
+        }
+        wsync();
+        oR = (jR & kOdd) ? oR - xR : oR + xR;
+        oC = (jC & kOdd) ? oC - xC : oC + xC;
+        jR = nR ^ (jR & kOdd);
+        jC = nC ^ (jC & kOdd);
+        M.u.jump.jmp[idR] = jR;
+        M.u.jump.jmp[idC] = jC;
+        M.u.jump.off[idR] = oR;
+        M.u.jump.off[idC] = oC;
+        if constexpr (MASKS) {
+            aR = aR | mR;
+            aC = aC | mC;
+            M.u.jump.anc[idR] = aR;
+            M.u.jump.anc[idC] = aC;
+        }
+        wsync();
+    }
+    N.potR = hasR ? oR : 0.0;
+    N.potC = hasC ? oC : 0.0;
+    if constexpr (MASKS) {
+        N.ancR = aR;
+        N.ancC = aC;
+    }
     M.ancRm[l] = N.ancR;
     if (l < GS) {
         if (hasC) M.vpot[l] = N.potC;
         M.ancCm[l] = N.ancC;
     }
     wsync();
-}
-
-// Ancestor masks from parent pointers by pointer jumping (Vogel's tree).
-template <int G, int GS, bool LT>
-__device__ __forceinline__ void anc_by_jumping(GroupMem<G, GS> &M, NodeState<G, GS, LT> &N, int l, int T, int S) {
-    const bool hasR = l < T, hasC = l < S;
-    const int idR = l, idC = G + l;
-    int jR = (hasR && N.parR >= 0) ? G + N.parR : idR;
-    int jC = (hasC && N.parC >= 0) ? N.parC : idC;
-    Mask<G> aR = hasR ? Mask<G>::node(idR) : Mask<G>::none();
-    Mask<G> aC = hasC ? Mask<G>::node(idC) : Mask<G>::none();
-    M.u.jump.jmp[idR] = jR;
-    M.u.jump.jmp[idC] = jC;
-    M.u.jump.anc[idR] = aR;
-    M.u.jump.anc[idC] = aC;
-    wsync();
-#pragma unroll 1
-    for (int k = 0; k < Steps<G>::n + 1; ++k) {
-        int nR = M.u.jump.jmp[jR], nC = M.u.jump.jmp[jC];
-        Mask<G> xR = M.u.jump.anc[jR], xC = M.u.jump.anc[jC];
-        wsync();
-        aR = aR | xR;
-        aC = aC | xC;
-        jR = nR;
-        jC = nC;
-        M.u.jump.jmp[idR] = jR;
-        M.u.jump.jmp[idC] = jC;
-        M.u.jump.anc[idR] = aR;
-        M.u.jump.anc[idC] = aC;
-        wsync();
-    }
-    N.ancR = aR;
-    N.ancC = aC;
 }
 
 // ------------------------------------------------------------ one solve
@@ -434,11 +465,16 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     M.u.init.pw[l] = pr;
     if (l < GS) M.u.init.qw[l] = pc;
     wsync();
+    // Loops over rows or columns stop at the largest support in the wave
+    // (wave-uniform, so they branch on the scalar unit); cells beyond a
+    // pair's own support hold +inf or zero and change nothing.
+    const int Tw = wave_max<G>(T);
+    const int Sw = wave_max<G>(S);
     double sumr = 0.0, sumc = 0.0;
 #pragma unroll 4
-    for (int a = 0; a < G; ++a) sumr += M.u.init.pw[a];   // zeros beyond the support add nothing
+    for (int a = 0; a < Tw; ++a) sumr += M.u.init.pw[a];   // zeros beyond the support add nothing
 #pragma unroll 4
-    for (int b = 0; b < GS; ++b) sumc += M.u.init.qw[b];
+    for (int b = 0; b < Sw; ++b) sumc += M.u.init.qw[b];
     const bool badsum = !(sumr > 0.0) || !(sumc > 0.0) || !isfinite(sumr) || !isfinite(sumc);
     if (group_bits<G>(badw || badsum, gbase) != 0ull) { out.status = kBadWeights; return out; }
     pr = pr / sumr;
@@ -450,7 +486,6 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     // column and read back by every row lane as a broadcast.  The narrow
     // shapes accumulate straight into the register row; the LDS-tile shape
     // goes in blocks of 16 columns.
-    const int Sw = wave_max<G>(S);
     if constexpr (GIVEN) {
 #pragma unroll
         for (int j = 0; j < GS; ++j) {
@@ -540,13 +575,15 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     }
     double cmax = 0.0;
     bool finite = true;
+    up_to<GS, GS / 4>(Sw, [&](auto nc) {
 #pragma unroll
-    for (int j = 0; j < GS; ++j) {
-        const bool live = hasR && j < S;
-        const double c = cost_at<G, GS, LT>(N, tile, l, j);
-        finite = finite & (!live | isfinite(c));
-        cmax = live ? fmax(cmax, GIVEN ? fabs(c) : c) : cmax;
-    }
+        for (int j = 0; j < decltype(nc)::value; ++j) {
+            const bool live = hasR && j < S;
+            const double c = cost_at<G, GS, LT>(N, tile, l, j);
+            finite = finite & (!live | isfinite(c));
+            cmax = live ? fmax(cmax, GIVEN ? fabs(c) : c) : cmax;
+        }
+    });
     if (group_bits<G>(!finite, gbase) != 0ull) { out.status = kBadPoints; return out; }
     cmax = group_max<G>(cmax);
     const double delta = o.tol * cmax;
@@ -572,13 +609,15 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         LMask colon = (LMask)((S == 64) ? ~0ull : ((1ull << S) - 1ull));
         double m1 = INFINITY;
         int j1 = 0;
+        up_to<GS, GS / 4>(Sw, [&](auto nc) {
 #pragma unroll
-        for (int j = 0; j < GS; ++j) {   // +inf beyond the support
-            const double c = cost_at<G, GS, LT>(N, tile, l, j);
-            const bool lt = c < m1;
-            m1 = lt ? c : m1;
-            j1 = lt ? j : j1;
-        }
+            for (int j = 0; j < decltype(nc)::value; ++j) {   // +inf beyond the support
+                const double c = cost_at<G, GS, LT>(N, tile, l, j);
+                const bool lt = c < m1;
+                m1 = lt ? c : m1;
+                j1 = lt ? j : j1;
+            }
+        });
         // Every round closes at least one line, so T + S - 2 rounds suffice;
         // the bound makes termination unconditional.
         int rounds = 0;
@@ -590,7 +629,8 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
                 const int a = __ffsll((long long)(uint64_t)rowon) - 1;
                 if (l == a) {
 #pragma unroll
-                    for (int j = 0; j < GS; ++j) M.u.lcm.lastrow[j] = cost_at<G, GS, LT>(N, tile, l, j);
+                    for (int j = 0; j < GS; ++j)
+                        if (j < Sw) M.u.lcm.lastrow[j] = cost_at<G, GS, LT>(N, tile, l, j);
                 }
                 wsync();
                 if (hasC && ((colon >> l) & 1u)) {
@@ -654,13 +694,14 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
             if (hasR && ((rowon >> l) & 1u) && ((cshut >> j1) & 1u)) {
                 m1 = INFINITY;
                 j1 = 0;
+                up_to<GS, GS / 4>(Sw, [&](auto nc) {
 #pragma unroll
-                for (int j = 0; j < GS; ++j) {
-                    const double c = ((colon >> j) & 1u) ? cost_at<G, GS, LT>(N, tile, l, j) : INFINITY;
-                    const bool lt = c < m1;
-                    m1 = lt ? c : m1;
-                    j1 = lt ? j : j1;
-                }
+                    for (int j = 0; j < decltype(nc)::value; ++j) {
+                        const bool lt = ((colon >> j) & 1u) && cost_at<G, GS, LT>(N, tile, l, j) < m1;
+                        m1 = lt ? cost_at<G, GS, LT>(N, tile, l, j) : m1;
+                        j1 = lt ? j : j1;
+                    }
+                });
             }
         }
         wsync();
@@ -669,9 +710,9 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0u;
 #pragma unroll
         for (int c = 0; c < GS; ++c)
-            if (hasR && c < S && M.u.init.colpar[c] == l) N.bas |= (decltype(N.bas))1 << c;
+            if (c < Sw && hasR && c < S && M.u.init.colpar[c] == l) N.bas |= (decltype(N.bas))1 << c;
         wsync();
-        anc_by_jumping<G, GS, LT>(M, N, l, T, S);
+        tree_jump<G, GS, LT, true>(M, N, l, T, S);
     } else if constexpr (START == kStartVogel) {
         // Vogel: close, one per round, the line whose two cheapest open cells
         // differ most (ties: rows first, lower index), filling its cheapest
@@ -755,9 +796,9 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0u;
 #pragma unroll
         for (int c = 0; c < GS; ++c)
-            if (hasR && c < S && M.u.init.colpar[c] == l) N.bas |= (decltype(N.bas))1 << c;
+            if (c < Sw && hasR && c < S && M.u.init.colpar[c] == l) N.bas |= (decltype(N.bas))1 << c;
         wsync();
-        anc_by_jumping<G, GS, LT>(M, N, l, T, S);
+        tree_jump<G, GS, LT, true>(M, N, l, T, S);
     } else {
         // North-west corner, all nodes at once.  With inclusive prefix sums
         // P_a of p and Q_b of q, the corner walk moves down after row a when
@@ -771,9 +812,9 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         wsync();
         double Pl = 0.0, Ql = 0.0;
 #pragma unroll 4
-        for (int a = 0; a < G; ++a) Pl += (a <= l) ? M.u.init.pw[a] : 0.0;
+        for (int a = 0; a < Tw; ++a) Pl += (a <= l) ? M.u.init.pw[a] : 0.0;
 #pragma unroll 4
-        for (int b = 0; b < GS; ++b) Ql += (b <= l) ? M.u.init.qw[b] : 0.0;
+        for (int b = 0; b < Sw; ++b) Ql += (b <= l) ? M.u.init.qw[b] : 0.0;
         M.u.init.P[l] = Pl;
         if (l < GS) M.u.init.Q[l] = Ql;
         wsync();
@@ -783,7 +824,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
             const double start = M.u.init.P[l - 1];
             int b = 0;
 #pragma unroll 4
-            for (int j = 0; j < GS - 1; ++j) {
+            for (int j = 0; j < Sw - 1; ++j) {
                 const double qb = M.u.init.Q[j];
                 b += (j <= S - 2 && qb < start) ? 1 : 0;
             }
@@ -802,7 +843,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
             if (l >= 1) {
                 start = M.u.init.Q[l - 1];
 #pragma unroll 4
-                for (int i = 0; i < G - 1; ++i) {
+                for (int i = 0; i < Tw - 1; ++i) {
                     const double pa = M.u.init.P[i];
                     a += (i <= T - 2 && pa <= start) ? 1 : 0;
                 }
@@ -825,7 +866,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         N.bas = (hasR && N.parR >= 0) ? (1ull << N.parR) : 0u;
 #pragma unroll
         for (int c = 0; c < GS; ++c) {
-            if (hasR && c < S && M.u.init.colpar[c] == l) {
+            if (c < Sw && hasR && c < S && M.u.init.colpar[c] == l) {
                 N.bas |= (decltype(N.bas))1 << c;
                 M.u.init.colcpar[c] = cost_at<G, GS, LT>(N, tile, l, c);
             }
@@ -840,7 +881,13 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         wsync();
         Mask<G> aR = Mask<G>::node(l), aC = Mask<G>::node(G + l);
 #pragma unroll 4
-        for (int n = 0; n < G + GS; ++n) {
+        for (int n = 0; n < Tw; ++n) {
+            const int lp = M.u.init.lastpos[n];
+            if (lp < idxR) aR = aR | Mask<G>::node(n);
+            if (lp < idxC) aC = aC | Mask<G>::node(n);
+        }
+#pragma unroll 4
+        for (int n = G; n < G + Sw; ++n) {
             const int lp = M.u.init.lastpos[n];
             if (lp < idxR) aR = aR | Mask<G>::node(n);
             if (lp < idxC) aC = aC | Mask<G>::node(n);
@@ -849,9 +896,8 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         N.ancC = hasC ? aC : Mask<G>::none();
         if (hasC) N.cparC = M.u.init.colcpar[l];
         wsync();
+        tree_jump<G, GS, LT, false>(M, N, l, T, S);
     }
-
-    set_potentials<G, GS, LT>(M, N, l, T, S);
 
     const long long cap = o.max_pivots > 0 ? (long long)o.max_pivots
                                            : (50LL * T * S > 100 ? 50LL * T * S : 100LL);
@@ -919,7 +965,7 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
         if (kidx == kNoKey) {
             if (fresh) break;
             // Recompute the potentials from the tree before concluding.
-            set_potentials<G, GS, LT>(M, N, l, T, S);
+            tree_jump<G, GS, LT, false>(M, N, l, T, S);
             fresh = true;
             continue;
         }
@@ -1035,7 +1081,9 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
     wsync();
     double sum = 0.0;
 #pragma unroll 4
-    for (int n = 0; n < G + GS; ++n) sum += M.u.fin.obj[n];
+    for (int n = 0; n < Tw; ++n) sum += M.u.fin.obj[n];
+#pragma unroll 4
+    for (int n = G; n < G + Sw; ++n) sum += M.u.fin.obj[n];
     out.d2 = o.want_sqrt ? sqrt(sum) : sum;
     out.pivots = (int)pivots;
     out.bland_pivots = bland_pivots;
