@@ -75,6 +75,66 @@ class _Ragged:
         return self.points[a:b], self.weights[a:b]
 
 
+def split_positions(n: int, U: _Uniforms):
+    """The two starting objects of a binary split of a segment of n > 1
+    objects (positions within the segment): position floor(u n), then
+    position floor(u' (n - 1)) among the n - 1 others, in increasing order."""
+    a = int(math.floor(U.next() * n))
+    rest = [x for x in range(n) if x != a]
+    b = rest[int(math.floor(U.next() * (n - 1)))]
+    return a, b
+
+
+def segment_positions(n: int, e: int, U: _Uniforms):
+    """The starting objects of a segment of n objects clustered into
+    k_mu = ceil(n / e) groups (tau = c e): the first k_mu entries of a
+    partial Fisher-Yates shuffle of 0..n-1, step q swapping entry q with entry
+    q + floor(u (n - q))."""
+    kmu = int(math.ceil(n / e))
+    pos = list(range(n))
+    for q in range(kmu):
+        r = q + int(math.floor(U.next() * (n - q)))
+        pos[q], pos[r] = pos[r], pos[q]
+    return pos[:kmu]
+
+
+def split_sides(S, labels, first):
+    """The two halves of a binary split: the members labelled with the
+    split's first centroid, then the rest, each in increasing index; when
+    either side is empty, the segment is halved in index order instead."""
+    S = np.asarray(S, dtype=np.int64)
+    A = S[np.asarray(labels)[S] == first]
+    B = S[np.asarray(labels)[S] != first]
+    if len(A) == 0 or len(B) == 0:
+        A, B = S[:len(S) // 2], S[len(S) // 2:]
+    return A, B
+
+
+def merge_level(segs, zoff, labels, omega, C):
+    """Step 3 of Alg. 3 for one level.  Segment mu's centroids are
+    zoff[mu] .. zoff[mu+1] of the level's centroid list, which concatenates
+    the segments' centroids in segment order, so a member's label already
+    carries the offset |Z^(mu-1)| of Eq. (5).  Centroids without members are
+    dropped and the kept ones renumbered in order (keep[new] = old index).
+    Returns (keep, the level label of every object Ct, the new weights as
+    member-weight sums, and the inherited labels C' = Ct[C] of the original
+    objects, Eq. (6))."""
+    n = len(labels)
+    keep = []
+    Ct = np.full(n, -1, dtype=np.int64)
+    for mu, S in enumerate(segs):
+        S = np.asarray(S, dtype=np.int64)
+        for j in range(int(zoff[mu]), int(zoff[mu + 1])):
+            members = S[np.asarray(labels)[S] == j]
+            if len(members):
+                Ct[members] = len(keep)
+                keep.append(j)
+    new_omega = np.zeros(len(keep))
+    for i in range(n):
+        new_omega[Ct[i]] += omega[i]
+    return keep, Ct, new_omega, Ct[np.asarray(C, dtype=np.int64)]
+
+
 def _centroids_from(G, picks):
     """Centroids made of the picked objects' atoms with uniform weights."""
     pts, wts, off = [], [], [0]
@@ -160,9 +220,7 @@ def hierarchy(X, tau: int, e: int, k: int, uniforms, rounds: int = 3, passes: in
             picks = []
             for q in big:
                 S = segs[q]
-                a = int(math.floor(U.next() * len(S)))
-                rest = [x for x in range(len(S)) if x != a]
-                b = rest[int(math.floor(U.next() * (len(S) - 1)))]
+                a, b = split_positions(len(S), U)
                 picks.append([S[a], S[b]])
             _, zoff, labels = _cluster(G, omega, [segs[q] for q in big], picks, rounds, passes, init)
             new = []
@@ -171,38 +229,16 @@ def hierarchy(X, tau: int, e: int, k: int, uniforms, rounds: int = 3, passes: in
                     new.append(S)
                     continue
                 mu = big.index(q)
-                first = int(zoff[mu])
-                A = S[labels[S] == first]
-                B = S[labels[S] != first]
-                if len(A) == 0 or len(B) == 0:
-                    A, B = S[:len(S) // 2], S[len(S) // 2:]
+                A, B = split_sides(S, labels, int(zoff[mu]))
                 new += [A, B]
             segs = new
         # Step 2: each segment into ceil(n_mu / e) clusters
-        picks = []
-        for S in segs:
-            kmu = int(math.ceil(len(S) / e))
-            pos = list(range(len(S)))
-            for q in range(kmu):
-                r = q + int(math.floor(U.next() * (len(S) - q)))
-                pos[q], pos[r] = pos[r], pos[q]
-            picks.append([S[p] for p in pos[:kmu]])
+        picks = [[S[p] for p in segment_positions(len(S), e, U)] for S in segs]
         Z, zoff, labels = _cluster(G, omega, segs, picks, rounds, passes, init)
         if labels.min() < 0:
             raise RuntimeError("a transport problem failed")
         # Step 3: merge in segment order (Eq. (5)), inherit labels (Eq. (6))
-        keep = []
-        Ct = np.full(G.n, -1, dtype=np.int64)
-        for mu, S in enumerate(segs):
-            for j in range(int(zoff[mu]), int(zoff[mu + 1])):
-                members = S[labels[S] == j]
-                if len(members):
-                    Ct[members] = len(keep)
-                    keep.append(j)
-        new_omega = np.zeros(len(keep))
-        for i in range(G.n):
-            new_omega[Ct[i]] += omega[i]
-        C = Ct[C]
+        keep, Ct, new_omega, C = merge_level(segs, zoff, labels, omega, C)
         pts = [Z.bag(j)[0] for j in keep]
         wts = [Z.bag(j)[1] for j in keep]
         off = np.concatenate([[0], np.cumsum([p.shape[0] for p in pts])])

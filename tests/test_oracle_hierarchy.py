@@ -104,3 +104,51 @@ def test_identical_objects_fall_back_to_halving(oracle_mod):
     assert levels[0]["segments"] == 4           # 130 -> 65 + 65 -> 4 x 32/33
     assert omega.sum() == 130
     np.testing.assert_allclose(pts, 1.0 * np.array([[1.0, 2.0]] * pts.shape[0]))
+
+
+# ---- hand-derived steps of Alg. 3 (tests/golden/hierarchy_steps.json)
+
+import json as _json
+import os
+
+_STEPS = _json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hierarchy_steps.json")))
+
+
+@pytest.mark.parametrize("case", _STEPS["split_positions"], ids=lambda c: f"n{c['n']}")
+def test_split_positions_golden(case):
+    from oracle import hierarchy as H
+    U = H._Uniforms(case["u"])
+    assert list(H.split_positions(case["n"], U)) == case["want"], case["derivation"]
+    assert U.k == 2
+
+
+@pytest.mark.parametrize("case", _STEPS["segment_positions"], ids=lambda c: f"n{c['n']}e{c['e']}")
+def test_segment_positions_golden(case):
+    from oracle import hierarchy as H
+    U = H._Uniforms(case["u"])
+    assert H.segment_positions(case["n"], case["e"], U) == case["want"], case["derivation"]
+    assert U.k == len(case["want"])   # one uniform per group, ceil(n / e) groups
+
+
+@pytest.mark.parametrize("case", _STEPS["split_sides"], ids=lambda c: str(c["first"]))
+def test_split_sides_golden(case):
+    from oracle import hierarchy as H
+    labels = np.full(max(case["S"]) + 1, -1)
+    for i, lab in case["labels"].items():
+        labels[int(i)] = lab
+    A, B = H.split_sides(np.array(case["S"]), labels, case["first"])
+    assert [list(A), list(B)] == case["want"], case["derivation"]
+
+
+@pytest.mark.parametrize("case", _STEPS["merge_level"], ids=lambda c: "two_segments")
+def test_merge_level_golden(case):
+    """Eq. (5) offsets, the drop of a cluster without members, member-sum
+    weights and the inheritance of Eq. (6), against the written-out case."""
+    from oracle import hierarchy as H
+    keep, Ct, omega, C = H.merge_level([np.array(s) for s in case["segs"]], case["zoff"],
+                                       np.array(case["labels"]), np.array(case["omega"], float),
+                                       np.array(case["C"]))
+    assert keep == case["want_keep"], case["derivation"]
+    assert list(Ct) == case["want_Ct"], case["derivation"]
+    assert list(omega) == case["want_omega"], case["derivation"]
+    assert list(C) == case["want_C"], case["derivation"]
