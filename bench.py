@@ -8,6 +8,13 @@ Dirichlet(0.5) weights, FP32 storage) against 512 centroids of support 16,
 51.2M LPs per step.  Inputs are resident in HBM before the timed region.
 Prints one JSON line.
 
+The default run also checks every row of configuration 2 against the
+oracle (the oracle's time over all of them is the CPU baseline), and adds a
+short serving leg of configuration 5 (Poisson queries against 1,024 resident
+centroids: p50/p99 latency at 10k queries/s, the served capacity under
+overload, parity of served results, and the plain per-pair solver on the
+same queries).
+
 Other workloads: --config 1 (200 x 10, d=3), --config 3 (50,000 x 256,
 d=128), --config 4 (one segment's pairwise matrix, 4,096 objects, d=16,
 8.4M pairs); --config 5 runs the serving loop (see paper_1302_0435_amd.serve).
@@ -253,9 +260,10 @@ class AssignWorkload:
                 "t_range": list(s["t_range"]), "s": s["s"], "inputs": s["dtype"],
                 "pairs_per_step": self.pairs}
 
-    def cpu_baseline(self, target_s, init_oracle):
+    def cpu_baseline(self, target_s, init_oracle, all_rows=False):
         """The oracle timed on this host's cores on a bounded sample of rows
-        (all centroids per row); also checks the device results for those rows."""
+        (all centroids per row), or on every row with ``all_rows``; also checks
+        the device results for those rows."""
         import oracle
         import synth
         from tests.parity import coupling_cost
@@ -263,21 +271,25 @@ class AssignWorkload:
         g_labels = self.out[0].cpu().numpy()
         g_best = self.out[1].cpu().numpy()
         threads = oracle.default_threads()
-        rows = synth.sample_rows(self.cfg, X.n, min(64, X.n), tag=1)
-        t0 = time.perf_counter()
-        oracle.assign(X.subset(rows), Z, init=init_oracle, threads=threads, want_all=False)
-        rate = len(rows) * Z.n / max(time.perf_counter() - t0, 1e-6)
-        n_rows = int(min(X.n, max(16, target_s * rate / Z.n)))
-        rows = synth.sample_rows(self.cfg, X.n, n_rows, tag=2)
-        sub = X.subset(rows)
+        if all_rows:
+            rows = np.arange(X.n)
+        else:
+            rows = synth.sample_rows(self.cfg, X.n, min(64, X.n), tag=1)
+            t0 = time.perf_counter()
+            oracle.assign(X.subset(rows), Z, init=init_oracle, threads=threads, want_all=False)
+            rate = len(rows) * Z.n / max(time.perf_counter() - t0, 1e-6)
+            n_rows = int(min(X.n, max(16, target_s * rate / Z.n)))
+            rows = synth.sample_rows(self.cfg, X.n, n_rows, tag=2)
+        sub = X.subset(rows) if not all_rows else X
         t0 = time.perf_counter()
         o_lab, o_best, _, o_st, _ = oracle.assign(sub, Z, init=init_oracle, threads=threads,
                                                   want_all=False)
         dt = time.perf_counter() - t0
         base = {"value": len(rows) * Z.n / dt, "unit": "distances/s", "cores": threads,
                 "kind": "oracle",
-                "sample": f"{len(rows)} seeded rows x all {Z.n} centroids ({len(rows) * Z.n} LPs), "
-                          f"{dt:.1f} s, {'Vogel' if init_oracle else 'north-west-corner'} start",
+                "sample": f"{'all' if all_rows else 'seeded'} {len(rows)} rows x all {Z.n} centroids "
+                          f"({len(rows) * Z.n} LPs), {dt:.1f} s, "
+                          f"{'Vogel' if init_oracle else 'north-west-corner'} start",
                 "cpu_model": _cpu_model()}
         if self.cost_mode == 1:
             # BF16 ground cost: report its error against the FP64 oracle
@@ -834,6 +846,74 @@ def make_pool(n_pool: int):
     return serve.QueryPool(q.offsets, q.points.astype(np.float64), q.weights.astype(np.float64))
 
 
+def serve_leg(d2, rates=(10000.0, 50000.0), duration=2.0, n_pool=4000, check=160):
+    """A short serving run of configuration 5 beside the default workload:
+    Poisson streams of queries (d=32, supports 4..64) against the 1,024
+    resident centroids of support 32, at a sustainable rate and an overloaded
+    one (whose distances/s is the served form's capacity); the served results
+    of the first queries checked against the oracle; and the plain per-pair
+    solver (one wavefront per pair in input order, north-west corner, no
+    binning, no graph) over the same queries for comparison."""
+    import torch
+    import oracle
+    import synth
+    from paper_1302_0435_amd import serve
+    from tests.parity import coupling_cost
+    Z = synth.make_centroids(5)
+    Zd = d2.DeviceSet.from_ragged(Z, "cuda:0")
+    pool = make_pool(n_pool)
+    legs = []
+    for rate in rates:
+        arrivals = synth.arrivals(5, rate, duration)
+        req_idx = np.arange(arrivals.size) % pool.n
+        ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, 4, 512)
+        sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, 256 << 20, 512, 4)
+        sch.run(np.array([0.0]))          # warm the kernels outside the measured run
+        st = sch.run(arrivals)
+        summ = st.summary(Z.n)
+        summ["rate_qps"] = rate
+        legs.append(summ)
+        del ex
+        torch.cuda.synchronize()
+    # parity of served results: a separate short run that keeps every result
+    # (copying results out on the host would slow the measured runs)
+    arrivals = synth.arrivals(5, rates[0], duration)[:check]
+    req_idx = np.arange(arrivals.size) % pool.n
+    ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, 4, 512, keep_results=True)
+    serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, 256 << 20, 512, 4).run(arrivals)
+    kept = dict(ex.results)
+    del ex
+    P = synth.RaggedSet(pool.offsets, pool.points, pool.weights)
+    q = [r for r in range(min(check, pool.n)) if r in kept]
+    o_lab, o_best, o_all, _, _ = oracle.assign(P.subset(q), Z, threads=oracle_threads())
+    fails = 0
+    for i, r in enumerate(q):
+        g_lab, g_best, g_all, g_st = kept[r]
+        x, w = P.bag(r)
+        floor = np.array([1e-14 * coupling_cost(x, w, *Z.bag(j)) for j in range(Z.n)])
+        bad = ~(np.abs(g_all - o_all[i]) <= np.maximum(1e-10 * np.abs(o_all[i]), floor))
+        if g_st != 0 or bad.any() or (g_lab != o_lab[i] and
+                                      o_all[i, g_lab] - o_all[i, o_lab[i]] > max(1e-10 * abs(o_best[i]),
+                                                                                   floor[o_lab[i]])):
+            fails += 1
+    # the plain per-pair solver on the same queries
+    sub = P.subset(np.arange(min(1000, pool.n)))
+    Xs = d2.DeviceSet.from_ragged(sub, "cuda:0")
+    h = d2.Handle(0)
+    opts = d2.Opts(init=d2.D2_INIT_NWC, schedule=d2.D2_SCHED_PLAIN, flags=d2.D2_FLAG_EAGER)
+    dt = _timed(lambda: d2.d2_assign(h, Xs, Zd, opts))
+    plain = sub.n * Z.n / dt
+    cap = legs[-1]["distances_per_s"]
+    return {"workload": synth.CONFIGS[5]["name"], "k": Z.n, "duration_s_per_rate": duration,
+            "slots": 4, "max_batch": 512, "budget_mib": 256, "rates": legs,
+            "p50_ms": legs[0]["p50_ms"], "p99_ms": legs[0]["p99_ms"], "p99_rate_qps": rates[0],
+            "saturated_distances_per_s": cap,
+            "plain_solver": {"value": plain, "unit": "distances/s",
+                             "sample": f"first {sub.n} queries x all {Z.n} centroids, one launch"},
+            "served_over_plain": cap / plain,
+            "parity_checked_queries": len(q), "parity_failures": fails}
+
+
 def run_serving(argv) -> int:
     """Configuration 5: Poisson query streams against 1,024 resident centroids
     of support 32 (d=32), one run per rate; reports p50/p99 latency and
@@ -913,6 +993,10 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=None, help="override object count (testing)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sampled-parity", action="store_true",
+                    help="configuration 2: check a timed sample of rows instead of all of them")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="configuration 2: skip the short serving leg of configuration 5")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling the "
                          "HBM byte counters), then exit")
@@ -1017,9 +1101,21 @@ def main(argv=None) -> int:
         plain = w.plain_baseline()
         plain["speedup_of_value"] = out["value"] / plain["value"]
         out["plain_solver"] = plain
+    default_c2 = args.n is None and args.op == "assign" and args.config == 2 and args.cost == "f64"
+    if default_c2 and not args.no_serve:
+        # the serving form beside the headline: p50/p99 latency and capacity
+        # of configuration 5, against the plain per-pair solver
+        sv = serve_leg(d2)
+        out["p50_ms"] = sv["p50_ms"]
+        out["p99_ms"] = sv["p99_ms"]
+        out["serving"] = sv
     if not args.no_cpu_baseline:
         # the oracle has the north-west-corner and Vogel starts
-        out["cpu_baseline"] = w.cpu_baseline(args.cpu_seconds, 1 if init == d2.D2_INIT_VOGEL else 0)
+        ib = 1 if init == d2.D2_INIT_VOGEL else 0
+        if default_c2 and not args.sampled_parity:
+            out["cpu_baseline"] = w.cpu_baseline(args.cpu_seconds, ib, all_rows=True)
+        else:
+            out["cpu_baseline"] = w.cpu_baseline(args.cpu_seconds, ib)
     print(json.dumps(out), flush=True)
     return 0
 

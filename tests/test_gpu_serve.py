@@ -11,20 +11,23 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def test_serving_results_alone_equal_mix():
+@pytest.mark.parametrize("k,n_pool,n_req,max_batch,alone_every,oracle_every", [
+    (48, 90, 360, 48, 7, 9),
+    (1024, 24, 96, 16, 5, 8),      # the serving workload's resident centroid count
+])
+def test_serving_results_alone_equal_mix(k, n_pool, n_req, max_batch, alone_every, oracle_every):
     if not torch.cuda.is_available():
         pytest.fail("GPU tests selected but no GPU is visible")
     import paper_1302_0435_amd as d2
     from paper_1302_0435_amd import serve
-    Z = synth.make_centroids(5, k=48)
+    Z = synth.make_centroids(5, k=k)
     Zd = d2.DeviceSet.from_ragged(Z, "cuda:0")
-    q = synth.make_data(5, n=90)
+    q = synth.make_data(5, n=n_pool)
     pool = serve.QueryPool(q.offsets, q.points.astype(np.float64), q.weights.astype(np.float64))
-    n_req = 360
     arrivals = np.sort(np.random.default_rng(3).uniform(0.0, 0.05, n_req))
     req_idx = np.arange(n_req) % pool.n
-    ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, slots=3, max_batch=48, keep_results=True)
-    sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, 1 << 28, 48, 3)
+    ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, slots=3, max_batch=max_batch, keep_results=True)
+    sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, 1 << 28, max_batch, 3)
     st = sch.run(arrivals)
     assert np.all(~np.isnan(st.done_s))
     assert max(st.batch_sizes) > 1
@@ -35,7 +38,7 @@ def test_serving_results_alone_equal_mix():
     # alone: each pool entry as a one-request call
     h = d2.Handle(0)
     P = synth.RaggedSet(pool.offsets, pool.points, pool.weights)
-    for q in range(0, pool.n, 7):
+    for q in range(0, pool.n, alone_every):
         one = P.subset([q])
         lab, best, allv, stt = d2.d2_assign(h, d2.DeviceSet.from_ragged(one, "cuda:0"), Zd,
                                             want_all=True)
@@ -43,9 +46,14 @@ def test_serving_results_alone_equal_mix():
         assert np.array_equal(allv.cpu().numpy()[0], ex.results[q][2])
         assert int(lab.cpu().numpy()[0]) == ex.results[q][0]
     # and the oracle agrees
-    sub = P.subset(list(range(0, pool.n, 9)))
+    picked = list(range(0, pool.n, oracle_every))
+    sub = P.subset(picked)
     o_lab, o_best, o_all, _, _ = oracle.assign(sub, Z)
-    g_all = np.stack([ex.results[q][2] for q in range(0, pool.n, 9)])
+    g_all = np.stack([ex.results[q][2] for q in picked])
     floor = np.array([[1e-14 * coupling_cost(*sub.bag(i), *Z.bag(j)) for j in range(Z.n)]
                       for i in range(sub.n)])
     assert_close(g_all, o_all, floor)
+    g_lab = np.array([ex.results[q][0] for q in picked])
+    assert np.array_equal(g_lab, o_lab) or all(
+        o_all[i, g_lab[i]] - o_all[i, o_lab[i]] <= max(1e-10 * abs(o_all[i, o_lab[i]]), floor[i].min())
+        for i in range(len(picked)))
