@@ -30,6 +30,10 @@ Readings where the paper is silent:
     status 5; a member of weight omega = 0 costs and moves nothing and is
     left out of the LP;
   * an atom that receives no mass keeps its coordinates, with weight 0;
+  * a flow or weight of the Step 1 solution at or below FLOW_EPS = 1e-14 (of
+    the unit mass every member carries) is rounding noise of a zero and is
+    set to 0 before Steps 2-3, so an atom left without mass by the exact
+    solution is not moved to a mean of noise;
   * a cluster without members keeps its atoms and weights.
 """
 from __future__ import annotations
@@ -37,6 +41,7 @@ from __future__ import annotations
 import numpy as np
 
 LABEL_OUT_OF_RANGE = 5
+FLOW_EPS = 1e-14
 
 
 def _pivot(T, basis, k, q):
@@ -192,6 +197,7 @@ def free_update(X, Z, labels, weights=None):
         c, A, b, layout = cluster_lp(groups[j], z)
         value, x = lp_simplex(c, A, b)
         eps1[j] = value
+        x = np.where(x > FLOW_EPS, x, 0.0)
         pz = x[len(c) - s:]
         # Step 2: omega- and flow-weighted means (Eq. (2), Eq. (4))
         num = np.zeros_like(z)
