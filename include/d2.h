@@ -166,8 +166,9 @@ const char *d2_version(void);
  * `which` is 0 = d2_cost_tiles, 1 = d2_emd_batch, 2 = d2_assign,
  * 3 = d2_pairwise, 4 = d2_centroid_update (A = X, B = Z), 5 =
  * d2_assign_multi (A, B = the arrays of per-type sets, npairs = the number of
- * types); `npairs` is the pair count for 0 and 1, ignored for 2-4; B may be
- * NULL for d2_pairwise. */
+ * types), 6 = d2_centroid_update_free (A = X, B = Z, npairs = max_members);
+ * `npairs` is the pair count for 0 and 1, ignored for 2-4; B may be NULL for
+ * d2_pairwise. */
 size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set *B,
                           int64_t npairs, const d2_opts *opts);
 
@@ -306,6 +307,57 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
                              const double *obj_weights, const d2_opts *opts, double *z_new,
                              double *eps_step1, double *eps_step3, int32_t *counts,
                              int32_t *obj_status, void *ws, size_t ws_bytes, void *stream);
+
+/* One pass of the centroid update of Alg. 1 with the centroid weights free
+ * (Sec. 1.1, Steps 1-3), for every cluster j = 0..K-1 at once.
+ *   Step 1  with cluster j's atoms fixed, the linear program of Eq. (1)
+ *           (weighted as in Eq. (3)) over the centroid weights p_z and every
+ *           member's transport plan: minimise sum_i omega_i sum w |z - v|^2
+ *           subject to each member's plan having the member's weights as row
+ *           sums and p_z as column sums, sum p_z = 1.  The members share p_z,
+ *           so the cluster is one program, solved exactly by a revised
+ *           simplex (one workgroup per cluster);
+ *   Step 2  every atom moves to the omega-and-flow-weighted mean of the
+ *           member atoms matched to it (Eq. (4));
+ *   Step 3  the objective with the moved atoms and the same plans.
+ * Unlike d2_centroid_update (Alg. 2, weights fixed), this changes the weights.
+ *   labels[n], obj_weights[n]  as for d2_centroid_update; a member of weight
+ *                  0 takes no part (it costs and moves nothing).
+ *   max_members    host bound on the members of one cluster that enter the
+ *                  program (>= 1).  A cluster with more labelled members
+ *                  is left unchanged with status D2_PAIR_TOO_LARGE for it and
+ *                  its members.  The workspace grows with
+ *                  (max_members (max_support(X) + max_support(Z) - 1) + 1)^2.
+ *   z_new          device FP64 [Z.offsets[K]][d], not overlapping Z.points:
+ *                  the moved atoms; an atom that receives no mass keeps its
+ *                  coordinates (its new weight is 0).
+ *   w_new          device FP64 [Z.offsets[K]], not overlapping Z.weights:
+ *                  the new weights p_z (summing to 1 per solved cluster).  A
+ *                  cluster without members, or whose program was not solved,
+ *                  keeps its atoms and weights in z_new, w_new.
+ *   eps_step1[K], eps_step3[K]  device FP64, nullable: the Step 1 optimum and
+ *                  the Step 3 objective; 0 for a cluster without members, NaN
+ *                  for one whose program was not solved.
+ *   counts[K]      device int32, nullable: members that entered the program.
+ *   obj_status[n]  device int32, nullable: D2_PAIR_OK, D2_PAIR_BAD_WEIGHTS
+ *                  (the object's or its omega's weights invalid: left out),
+ *                  D2_PAIR_UNLABELLED, or its cluster's status when that is
+ *                  not D2_PAIR_OK.
+ *   cluster_status[K]  device int32, nullable: D2_PAIR_OK, D2_PAIR_TOO_LARGE,
+ *                  D2_PAIR_PIVOT_CAP (opts->max_pivots, 0 = max(50 m, 100)
+ *                  pivots for a program of m rows) or D2_PAIR_INTERNAL (the
+ *                  basis matrix lost rank numerically).
+ * Workspace: d2_workspace_bytes(h, 6, X, Z, max_members, opts) bytes
+ * (required).  opts->bland_after applies to degenerate pivots as in the
+ * transport solver (0 = 2 m); opts->opt_tol and want_sqrt are ignored: a
+ * reduced cost counts as negative below -1e-13 max C.  Sums run in a fixed
+ * order, so repeated calls give identical bits.  FP64 direct cost only.
+ * D2_EUNSUPPORTED when one cluster's slab would exceed 8 GiB. */
+d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *labels,
+                                  const double *obj_weights, int32_t max_members, const d2_opts *opts,
+                                  double *z_new, double *w_new, double *eps_step1, double *eps_step3,
+                                  int32_t *counts, int32_t *obj_status, int32_t *cluster_status, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 /* Nearest-centroid labelling within segments (Alg. 3 Step 2, where each
  * segment of the data is clustered on its own): object i is compared only

@@ -302,6 +302,44 @@ def d2_centroid_update(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch.Tens
     return z_new, eps1, eps3, counts, status
 
 
+def d2_centroid_update_free(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch.Tensor,
+                            opts: Optional[Opts] = None, weights: Optional[torch.Tensor] = None,
+                            max_members: Optional[int] = None):
+    """One pass of the centroid update of Alg. 1 with free centroid weights
+    (Steps 1-3; object weights as in Eq. (3)-(4)).
+
+    max_members bounds the members of one cluster (None: the largest count
+    among the labels, read back once).  Returns z_new [Z.offsets[K], d] f64,
+    w_new [Z.offsets[K]] f64, eps_step1 [K], eps_step3 [K] f64, counts [K],
+    obj_status [n], cluster_status [K] int32 (see d2_centroid_update_free in
+    d2.h)."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    labels = labels.to(device=dev, dtype=torch.int32).contiguous()
+    if weights is not None:
+        weights = weights.to(device=dev, dtype=torch.float64).contiguous()
+    K = Z.n
+    if max_members is None:
+        inr = labels[(labels >= 0) & (labels < K)].to(torch.int64)
+        max_members = int(torch.bincount(inr, minlength=1).max().item()) if inr.numel() else 1
+    max_members = max(1, int(max_members))
+    z_new = torch.empty((int(Z.points.shape[0]), Z.d), dtype=torch.float64, device=dev)
+    w_new = torch.empty(int(Z.points.shape[0]), dtype=torch.float64, device=dev)
+    eps1 = torch.empty(K, dtype=torch.float64, device=dev)
+    eps3 = torch.empty(K, dtype=torch.float64, device=dev)
+    counts = torch.empty(K, dtype=torch.int32, device=dev)
+    status = torch.empty(X.n, dtype=torch.int32, device=dev)
+    cstatus = torch.empty(K, dtype=torch.int32, device=dev)
+    ws, nbytes = _workspace(h, _ffi.WHICH_UPDATE_FREE, X, Z, max_members, opts)
+    x, z, o = X.c(), Z.c(), opts.c()
+    check(_ffi.lib().d2_centroid_update_free(h.ptr, ctypes.byref(x), ctypes.byref(z), _ptr(labels),
+                                             _ptr(weights), max_members, ctypes.byref(o),
+                                             _ptr(z_new), _ptr(w_new), _ptr(eps1), _ptr(eps3),
+                                             _ptr(counts), _ptr(status), _ptr(cstatus), _ptr(ws),
+                                             nbytes, _stream(dev)), "d2_centroid_update_free")
+    return z_new, w_new, eps1, eps3, counts, status, cstatus
+
+
 def constrained_d2(h: Handle, X: DeviceSet, Z: DeviceSet, opts: Optional[Opts] = None,
                    max_rounds: int = 20, max_passes: int = 10, rtol: float = 1e-9):
     """Constrained D2-clustering (Alg. 2 with Step 3* in place of Step 3).

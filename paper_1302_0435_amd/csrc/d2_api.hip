@@ -58,6 +58,9 @@ static __device__ __align__(256) unsigned char scratch[D2_NOALLOC_SCRATCH_BYTES]
 namespace {
 
 constexpr size_t kScratchBytes = (size_t)D2_NOALLOC_SCRATCH_BYTES;
+// Largest per-cluster slab of the free-weight update (dense basis matrix and
+// its inverse for max_members (xmax + zmax - 1) + 1 rows): 8 GiB.
+constexpr size_t kMaxFreeSlab = (size_t)8 << 30;
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void *g_scratch[kMaxDevices];
@@ -327,6 +330,12 @@ size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set
     }
     if (which == 3) return d2::plan_pairwise(kset(A), ms(A), sched).ws_bytes;
     if (which == 4 && B && set_ok(B)) return d2::update_ws_bytes(A->n, B->n, A->d, ms(A), ms(B));
+    if (which == 6 && B && set_ok(B)) {
+        if (npairs < 1 || npairs > INT32_MAX ||
+            d2::update_free_slab_bytes((int)npairs, ms(A), ms(B), A->d) > kMaxFreeSlab)
+            return 0;
+        return d2::update_free_ws_bytes(A->n, B->n, A->d, ms(A), ms(B), (int)npairs, h->cu_count, nullptr);
+    }
     if (which == 5 && B) {
         d2::AssignPlan plans[kMaxTypes];
         size_t ab = 0;
@@ -513,6 +522,33 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
     const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(ms(X), ms(Z));
     hipError_t e = d2::launch_update(ctx(h, (hipStream_t)stream), cls, kset(X), kset(Z), ms(X), ms(Z), k,
                                      labels, obj_weights, z_new, eps_step1, eps_step3, counts, obj_status, ws);
+    return e == hipSuccess ? D2_OK : D2_EHIP;
+}
+
+d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *labels,
+                                  const double *obj_weights, int32_t max_members, const d2_opts *opts,
+                                  double *z_new, double *w_new, double *eps_step1, double *eps_step3,
+                                  int32_t *counts, int32_t *obj_status, int32_t *cluster_status, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    if (!h) return D2_EINVAL;
+    d2_status st = pair_sets_ok(X, Z);
+    if (st != D2_OK) return st;
+    KOpts k;
+    if ((st = opts_ok(opts, k)) != D2_OK) return st;
+    if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
+    if (max_members < 1) return D2_EINVAL;
+    if (X->n > 0 && !labels) return D2_EINVAL;
+    if (Z->n > 0 && (!z_new || !w_new)) return D2_EINVAL;
+    if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
+    if (Z->n > 0 && ((const void *)z_new == Z->points || (const void *)w_new == Z->weights)) return D2_EINVAL;
+    if (d2::update_free_slab_bytes(max_members, ms(X), ms(Z), X->d) > kMaxFreeSlab) return D2_EUNSUPPORTED;
+    const size_t need = d2::update_free_ws_bytes(X->n, Z->n, X->d, ms(X), ms(Z), max_members, h->cu_count, nullptr);
+    if (!ws || ws_bytes < need) return D2_EWORKSPACE;
+    if ((st = bind_device(h)) != D2_OK) return st;
+    if (X->n == 0 && Z->n == 0) return D2_OK;
+    hipError_t e = d2::launch_update_free(ctx(h, (hipStream_t)stream), kset(X), kset(Z), ms(X), ms(Z),
+                                          max_members, k, labels, obj_weights, z_new, w_new, eps_step1, eps_step3,
+                                          counts, obj_status, cluster_status, ws);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 

@@ -114,6 +114,16 @@ hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet 
                          const KOpts &o, const int32_t *labels, const double *obj_weights, double *z_new,
                          double *eps1, double *eps3, int32_t *counts, int32_t *obj_status, void *ws);
 
+// Centroid update with free centroid weights (Alg. 1 Steps 1-3): the bytes
+// of one cluster's slab, the whole workspace (grid returned), and the enqueue.
+size_t update_free_slab_bytes(int max_members, int xmax, int zmax, int d);
+size_t update_free_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax, int max_members, int cu_count,
+                            int64_t *grid_out);
+hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, int xmax, int zmax,
+                              int max_members, const KOpts &o, const int32_t *labels, const double *obj_weights,
+                              double *z_new, double *w_new, double *eps1, double *eps3, int32_t *counts,
+                              int32_t *obj_status, int32_t *cluster_status, void *ws);
+
 // Labelling within segments: object i against the centroids
 // zoff[seg[i]] .. zoff[seg[i]+1] of Z only.
 hipError_t launch_assign_seg(const LaunchCtx &c, int cls, const KSet &X, const KSet &Z, const KOpts &o,

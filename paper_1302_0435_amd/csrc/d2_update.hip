@@ -610,4 +610,637 @@ hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet 
     return hipGetLastError();
 }
 
+
+// ================================================= free centroid weights
+//
+// Alg. 1 Step 1 with the centroid weights free: for every cluster, the LP of
+// Eq. (1) over the weights p_z of its s atoms and every member's matching,
+// with the member's weight omega of Eq. (3) on its costs.  Members of one
+// cluster are coupled through p_z, so the LP does not separate; it is solved
+// whole by a revised simplex, one workgroup per cluster:
+//   rows     member k's atom a (sum_r w = p_k(a)), then the coupling rows
+//            sum_a w(k, ., r) - p_z(r) = 0: all s of member 0's, s - 1 of
+//            each later member's (the last is implied: every member's rows
+//            give sum_r p_z(r) = 1, so the mass row and one coupling row per
+//            later member are dependent and dropped); m = sum t + n (s - 1) + 1;
+//   columns  w(k, a, r) for every member, atom and centroid atom (two unit
+//            entries), then p_z(r) (-1 in member r's coupling rows);
+//   start    member 0 sends each atom to its cheapest centroid atom, which
+//            fixes p_z (all s weights basic); every later member is the
+//            north-west corner from its weights to p_z.  The basis matrix is
+//            block triangular with non-singular blocks, so it is a basis;
+//   pivots   explicit inverse of the basis: y = c_B B^-1, Dantzig's entering
+//            column (Bland's after a run of degenerate pivots), the column
+//            B^-1 a_q, the ratio test (least ratio, then lowest variable),
+//            and the rank-one update of B^-1; B^-1 is rebuilt by Gauss-Jordan
+//            elimination with partial pivoting every kRefactor pivots and
+//            before optimality is declared; values of the solution at or
+//            below kFlowEps are rounding noise of zeros and set to 0;
+//   Step 2   each atom moves to the omega-and-flow-weighted mean of the
+//            member atoms matched to it (Eq. (4)); Step 3 evaluates the
+//            objective with the moved atoms and the same matchings.
+// The dense arrays of a cluster (B, B^-1, costs, solution) live in the
+// workgroup's slab of the workspace, sized for the caller's bound on the
+// members of one cluster.  Every reduction runs in a fixed order.
+
+namespace {
+
+constexpr int kFreeThreads = 256;
+constexpr int kRefactor = 64;
+constexpr double kFreeTol = 1e-13;     // reduced costs above -kFreeTol max|c| count as >= 0
+constexpr double kPivTol = 1e-9;       // least |entry| of B^-1 a_q taken in the ratio test
+constexpr double kFlowEps = 1e-14;     // flows at or below this (of a unit mass) are zeros
+enum { kFOk = 0, kFBadWeights = 1, kFTooLarge = 2, kFPivotCap = 3, kFInternal = 6 };
+
+struct FreeDims {
+    int nmax, xmax, zmax, d;
+    int64_t mmax, vmax;
+    size_t slab;
+};
+
+FreeDims free_dims(int nmax, int xmax, int zmax, int d) {
+    FreeDims f;
+    f.nmax = nmax > 0 ? nmax : 1;
+    f.xmax = xmax > 0 ? xmax : 1;
+    f.zmax = zmax > 0 ? zmax : 1;
+    f.d = d;
+    f.mmax = (int64_t)f.nmax * (f.xmax + f.zmax - 1) + 1;
+    f.vmax = (int64_t)f.zmax * f.nmax * f.xmax + f.zmax;
+    f.slab = 2 * align256((size_t)f.mmax * f.mmax * 8) + 2 * align256((size_t)f.vmax * 8) + align256((size_t)f.vmax) +
+             5 * align256((size_t)f.mmax * 8) + align256((size_t)f.mmax * 4) + align256((size_t)(f.nmax + 1) * 4) +
+             3 * align256((size_t)f.nmax * 8);
+    return f;
+}
+
+struct FreeSlab {
+    double *B, *Binv, *cost, *x, *xB, *y, *alpha, *b, *prow;
+    int8_t *basic;
+    int32_t *basis, *T;
+    int64_t *obj;
+    double *om, *isum;
+};
+
+__host__ __device__ inline FreeSlab free_slab(char *base, const FreeDims &f) {
+    FreeSlab s;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { char *q = base + off; off += (bytes + 255) & ~(size_t)255; return q; };
+    s.B = (double *)take((size_t)f.mmax * f.mmax * 8);
+    s.Binv = (double *)take((size_t)f.mmax * f.mmax * 8);
+    s.cost = (double *)take((size_t)f.vmax * 8);
+    s.x = (double *)take((size_t)f.vmax * 8);
+    s.basic = (int8_t *)take((size_t)f.vmax);
+    s.xB = (double *)take((size_t)f.mmax * 8);
+    s.y = (double *)take((size_t)f.mmax * 8);
+    s.alpha = (double *)take((size_t)f.mmax * 8);
+    s.b = (double *)take((size_t)f.mmax * 8);
+    s.prow = (double *)take((size_t)f.mmax * 8);
+    s.basis = (int32_t *)take((size_t)f.mmax * 4);
+    s.T = (int32_t *)take((size_t)(f.nmax + 1) * 4);
+    s.obj = (int64_t *)take((size_t)f.nmax * 8);
+    s.om = (double *)take((size_t)f.nmax * 8);
+    s.isum = (double *)take((size_t)f.nmax * 8);
+    return s;
+}
+
+struct FreeShared {
+    double rv[kFreeThreads / 64];
+    int ri[kFreeThreads / 64];
+    int n, s, m, nvar, nw, stat, q, p, fresh, done, bland;
+    double cmax, delta, theta;
+};
+
+// Block-wide (value, key) minimum, lowest key among equal values; keys of
+// INT32_MAX are no candidates.  Every thread receives the result.
+__device__ __forceinline__ void free_argmin(FreeShared &sh, double &v, int &k) {
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int ok = __shfl_xor(k, off, 64);
+        if (ov < v || (ov == v && ok < k)) { v = ov; k = ok; }
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { sh.rv[w] = v; sh.ri[w] = k; }
+    __syncthreads();
+    v = sh.rv[0];
+    k = sh.ri[0];
+    for (int q = 1; q < kFreeThreads / 64; ++q)
+        if (sh.rv[q] < v || (sh.rv[q] == v && sh.ri[q] < k)) { v = sh.rv[q]; k = sh.ri[q]; }
+}
+
+__device__ __forceinline__ double free_max(FreeShared &sh, double v) {
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh.rv[w] = v;
+    __syncthreads();
+    double m = sh.rv[0];
+    for (int q = 1; q < kFreeThreads / 64; ++q) m = fmax(m, sh.rv[q]);
+    return m;
+}
+
+// Row of member k's coupling constraint for atom r, or -1 (dropped).
+__device__ __forceinline__ int free_colrow(int sumt, int s, int k, int r) {
+    if (k == 0) return sumt + r;
+    if (r == s - 1) return -1;
+    return sumt + s + (k - 1) * (s - 1) + r;
+}
+
+// Member of variable v < nw (binary search over the atom offsets T).
+__device__ __forceinline__ int free_member(const int32_t *T, int n, int s, int v) {
+    const int atom = v / s;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T[mid] <= atom) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Rebuild B from the basis, B^-1 by Gauss-Jordan with partial pivoting, and
+// x_B = B^-1 b.  Returns false when a pivot is (numerically) zero.
+__device__ bool free_refactor(FreeShared &sh, const FreeSlab &S) {
+    const int m = sh.m, n = sh.n, s = sh.s, nw = sh.nw, sumt = S.T[n];
+    const int tid = threadIdx.x;
+    for (int64_t e = tid; e < (int64_t)m * m; e += kFreeThreads) {
+        S.B[e] = 0.0;
+        S.Binv[e] = (e / m == e % m) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = tid; j < m; j += kFreeThreads) {   // column j of B: the basis variable's column
+        const int v = S.basis[j];
+        if (v < nw) {
+            const int k = free_member(S.T, n, s, v);
+            const int a = v / s - S.T[k], r = v % s;
+            S.B[(int64_t)(S.T[k] + a) * m + j] = 1.0;
+            const int cr = free_colrow(sumt, s, k, r);
+            if (cr >= 0) S.B[(int64_t)cr * m + j] = 1.0;
+        } else {
+            const int r = v - nw;
+            for (int k = 0; k < n; ++k) {
+                const int cr = free_colrow(sumt, s, k, r);
+                if (cr >= 0) S.B[(int64_t)cr * m + j] = -1.0;
+            }
+        }
+    }
+    __syncthreads();
+    for (int c = 0; c < m; ++c) {
+        double v = -1.0;
+        int k = INT32_MAX;
+        for (int i = c + tid; i < m; i += kFreeThreads) {
+            const double a = fabs(S.B[(int64_t)i * m + c]);
+            if (a > v || (a == v && i < k)) { v = a; k = i; }
+        }
+        // largest |entry| (lowest row on ties): argmin of the negation
+        double nv = -v;
+        free_argmin(sh, nv, k);
+        if (!(-nv > 1e-12)) return false;
+        const int pr = k;
+        if (pr != c)
+            for (int j = tid; j < m; j += kFreeThreads) {
+                const double t1 = S.B[(int64_t)c * m + j];
+                S.B[(int64_t)c * m + j] = S.B[(int64_t)pr * m + j];
+                S.B[(int64_t)pr * m + j] = t1;
+                const double t2 = S.Binv[(int64_t)c * m + j];
+                S.Binv[(int64_t)c * m + j] = S.Binv[(int64_t)pr * m + j];
+                S.Binv[(int64_t)pr * m + j] = t2;
+            }
+        __syncthreads();
+        const double piv = S.B[(int64_t)c * m + c];
+        __syncthreads();
+        for (int j = tid; j < m; j += kFreeThreads) {
+            S.B[(int64_t)c * m + j] /= piv;
+            S.Binv[(int64_t)c * m + j] /= piv;
+        }
+        for (int i = tid; i < m; i += kFreeThreads) S.alpha[i] = S.B[(int64_t)i * m + c];   // factors, read first
+        __syncthreads();
+        for (int64_t e = tid; e < (int64_t)m * m; e += kFreeThreads) {
+            const int i = (int)(e / m), j = (int)(e % m);
+            if (i == c) continue;
+            const double f = S.alpha[i];
+            if (f != 0.0) {
+                S.B[e] -= f * S.B[(int64_t)c * m + j];
+                S.Binv[e] -= f * S.Binv[(int64_t)c * m + j];
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < m; i += kFreeThreads) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc = fma(S.Binv[(int64_t)i * m + j], S.b[j], acc);
+        S.xB[i] = acc < 0.0 ? 0.0 : acc;
+    }
+    __syncthreads();
+    return true;
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOpts o, const int64_t *pre,
+                                                             const int64_t *perm, int64_t tiles, FreeDims f,
+                                                             char *slabs, const double *objw, double *z_new,
+                                                             double *w_new, double *eps1, double *eps3,
+                                                             int32_t *counts, int32_t *obj_status,
+                                                             int32_t *cluster_status) {
+    __shared__ FreeShared sh;
+    const int tid = threadIdx.x;
+    const FreeSlab S = free_slab(slabs + (size_t)blockIdx.x * f.slab, f);
+    const int d = X.d;
+    for (int64_t j = blockIdx.x; j < Z.n; j += gridDim.x) {
+        const int64_t pb = pre[j * tiles], pe = pre[(j + 1) * tiles];
+        const int64_t z0 = Z.off[j];
+        const int s = (int)(Z.off[j + 1] - z0);
+        // centroid outputs default to the input (kept when the LP is not solved)
+        for (int64_t e = tid; e < (int64_t)s * d; e += kFreeThreads)
+            z_new[z0 * d + e] = ldw<TIn>(Z.pts, z0 * d + e);
+        for (int r = tid; r < s; r += kFreeThreads) w_new[z0 + r] = ldw<TIn>(Z.w, z0 + r);
+        // members: validate weights (thread per member), then compact in order
+        const int64_t nall = pe - pb;
+        if (tid == 0) { sh.stat = kFOk; sh.n = 0; }
+        __syncthreads();
+        if (nall > f.nmax || s < 1 || s > f.zmax) {
+            for (int64_t q = pb + tid; q < pe; q += kFreeThreads)
+                if (obj_status) obj_status[perm[q]] = kFTooLarge;
+            if (tid == 0) {
+                if (eps1) eps1[j] = __builtin_nan("");
+                if (eps3) eps3[j] = __builtin_nan("");
+                if (counts) counts[j] = 0;
+                if (cluster_status) cluster_status[j] = kFTooLarge;
+            }
+            __syncthreads();
+            continue;
+        }
+        for (int64_t q = pb + tid; q < pe; q += kFreeThreads) {
+            const int64_t i = perm[q];
+            const int64_t a0 = X.off[i];
+            const int64_t t = X.off[i + 1] - a0;
+            const double om = objw ? objw[i] : 1.0;
+            double sum = 0.0;
+            bool bad = !(isfinite(om) && om >= 0.0) || t < 1 || t > f.xmax;
+            for (int64_t a = 0; a < t && !bad; ++a) {
+                const double w = ldw<TIn>(X.w, a0 + a);
+                bad = !(isfinite(w) && w >= 0.0);
+                sum += w;
+            }
+            bad = bad || !(sum > 0.0) || !isfinite(sum);
+            if (obj_status) obj_status[i] = bad ? (t > f.xmax ? kFTooLarge : kFBadWeights) : kFOk;
+            S.isum[q - pb] = bad ? -1.0 : (om > 0.0 ? 1.0 / sum : 0.0);
+            S.om[q - pb] = om;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int n = 0, acc = 0;
+            for (int64_t q = 0; q < nall; ++q) {
+                if (!(S.isum[q] > 0.0)) continue;   // invalid, or omega = 0: no part in the LP
+                const int64_t i = perm[pb + q];
+                S.obj[n] = i;
+                S.om[n] = S.om[q];
+                S.isum[n] = S.isum[q];
+                S.T[n] = acc;
+                acc += (int)(X.off[i + 1] - X.off[i]);
+                ++n;
+            }
+            S.T[n] = acc;
+            sh.n = n;
+            sh.s = s;
+            sh.m = acc + n * (s - 1) + 1;
+            sh.nw = s * acc;
+            sh.nvar = s * acc + s;
+        }
+        __syncthreads();
+        const int n = sh.n, m = sh.m, nw = sh.nw, nvar = sh.nvar, sumt = S.T[n];
+        if (n == 0) {
+            if (tid == 0) {
+                if (eps1) eps1[j] = 0.0;
+                if (eps3) eps3[j] = 0.0;
+                if (counts) counts[j] = 0;
+                if (cluster_status) cluster_status[j] = kFOk;
+            }
+            __syncthreads();
+            continue;
+        }
+        // costs omega_k |z_r - v_ka|^2 (direct form, coordinates ascending)
+        double cm = 0.0;
+        for (int v = tid; v < nvar; v += kFreeThreads) {
+            double c = 0.0;
+            if (v < nw) {
+                const int k = free_member(S.T, n, s, v);
+                const int a = v / s - S.T[k], r = v % s;
+                const int64_t xa = (X.off[S.obj[k]] + a) * d, zr = (z0 + r) * d;
+                double acc = 0.0;
+                for (int qd = 0; qd < d; ++qd) {
+                    const double diff = ldw<TIn>(X.pts, xa + qd) - ldw<TIn>(Z.pts, zr + qd);
+                    acc = fma(diff, diff, acc);
+                }
+                c = S.om[k] * acc;
+            }
+            S.cost[v] = c;
+            S.basic[v] = 0;
+            cm = fmax(cm, fabs(c));
+        }
+        cm = free_max(sh, cm);
+        if (tid == 0) { sh.cmax = cm; sh.delta = kFreeTol * cm; }
+        for (int i = tid; i < m; i += kFreeThreads) {   // right-hand sides: member weights, then zeros
+            double bv = 0.0;
+            if (i < sumt) {
+                const int k = free_member(S.T, n, 1, i);
+                bv = ldw<TIn>(X.w, X.off[S.obj[k]] + (i - S.T[k])) * S.isum[k];
+            }
+            S.b[i] = bv;
+        }
+        __syncthreads();
+        // the structured starting basis (serial: O(sum t + n s) steps)
+        if (tid == 0) {
+            int nb = 0;
+            const int t0 = S.T[1] - S.T[0];
+            for (int a = 0; a < t0; ++a) {   // member 0: cheapest atom, lowest on ties
+                int rb = 0;
+                for (int r = 1; r < s; ++r)
+                    if (S.cost[a * s + r] < S.cost[a * s + rb]) rb = r;
+                S.basis[nb++] = a * s + rb;
+                S.prow[a] = rb;   // scratch: chosen atom
+            }
+            for (int r = 0; r < s; ++r) S.y[r] = 0.0;   // scratch: p_z
+            for (int a = 0; a < t0; ++a) S.y[(int)S.prow[a]] += S.b[a];
+            for (int r = 0; r < s; ++r) S.basis[nb++] = nw + r;
+            for (int k = 1; k < n; ++k) {
+                const int tk = S.T[k + 1] - S.T[k];
+                int a = 0, r = 0;
+                double ra = S.b[S.T[k]], rc = S.y[0];
+                for (int step = 0; step < tk + s; ++step) {
+                    S.basis[nb++] = s * (S.T[k] + a) + r;
+                    const double fl = fmin(ra, rc);
+                    ra -= fl;
+                    rc -= fl;
+                    if (a == tk - 1 && r == s - 1) break;
+                    if ((ra <= rc && a < tk - 1) || r == s - 1) { ++a; ra = S.b[S.T[k] + a]; }
+                    else { ++r; rc = S.y[r]; }
+                }
+            }
+            sh.stat = nb == m ? kFOk : kFInternal;
+            for (int q = 0; q < nb && q < m; ++q) S.basic[S.basis[q]] = 1;
+        }
+        __syncthreads();
+        if (sh.stat == kFOk && !free_refactor(sh, S) && tid == 0) sh.stat = kFInternal;
+        __syncthreads();
+        // the simplex
+        const int64_t cap = o.max_pivots > 0 ? o.max_pivots : (50LL * m > 100 ? 50LL * m : 100LL);
+        const int bland_after = o.bland_after > 0 ? o.bland_after : 2 * m;
+        int64_t pivots = 0;
+        int streak = 0, since = 0;
+        if (tid == 0) { sh.fresh = 1; sh.bland = 0; }
+        __syncthreads();
+        while (sh.stat == kFOk) {
+            // y = c_B B^-1
+            for (int i = tid; i < m; i += kFreeThreads) {
+                double acc = 0.0;
+                for (int jj = 0; jj < m; ++jj) acc = fma(S.cost[S.basis[jj]], S.Binv[(int64_t)jj * m + i], acc);
+                S.y[i] = acc;
+            }
+            __syncthreads();
+            // pricing: Dantzig (least reduced cost, lowest variable), or
+            // Bland (lowest variable below -delta)
+            const bool bl = sh.bland != 0;
+            const double delta = sh.delta;
+            double bv = INFINITY;
+            int bq = INT32_MAX;
+            for (int v = tid; v < nvar; v += kFreeThreads) {
+                if (S.basic[v]) continue;
+                double dv;
+                if (v < nw) {
+                    const int k = free_member(S.T, n, s, v);
+                    const int a = v / s - S.T[k], r = v % s;
+                    const int cr = free_colrow(sumt, s, k, r);
+                    dv = S.cost[v] - S.y[S.T[k] + a] - (cr >= 0 ? S.y[cr] : 0.0);
+                } else {
+                    const int r = v - nw;
+                    double acc = 0.0;
+                    for (int k = 0; k < n; ++k) {
+                        const int cr = free_colrow(sumt, s, k, r);
+                        if (cr >= 0) acc += S.y[cr];
+                    }
+                    dv = acc;   // 0 - y . a with a = -1 on the coupling rows
+                }
+                if (!(dv < -delta)) continue;
+                const double key = bl ? 0.0 : dv;
+                if (key < bv || (key == bv && v < bq)) { bv = key; bq = v; }
+            }
+            free_argmin(sh, bv, bq);
+            if (bq == INT32_MAX) {
+                if (sh.fresh) break;   // optimal with freshly factored B^-1
+                __syncthreads();
+                if (!free_refactor(sh, S)) { if (tid == 0) sh.stat = kFInternal; __syncthreads(); break; }
+                if (tid == 0) sh.fresh = 1;
+                since = 0;
+                __syncthreads();
+                continue;
+            }
+            if (pivots >= cap) { if (tid == 0) sh.stat = kFPivotCap; __syncthreads(); break; }
+            // alpha = B^-1 a_q
+            const int q = bq;
+            for (int i = tid; i < m; i += kFreeThreads) {
+                double acc = 0.0;
+                if (q < nw) {
+                    const int k = free_member(S.T, n, s, q);
+                    const int a = q / s - S.T[k], r = q % s;
+                    const int cr = free_colrow(sumt, s, k, r);
+                    acc = S.Binv[(int64_t)i * m + S.T[k] + a] + (cr >= 0 ? S.Binv[(int64_t)i * m + cr] : 0.0);
+                } else {
+                    const int r = q - nw;
+                    for (int k = 0; k < n; ++k) {
+                        const int cr = free_colrow(sumt, s, k, r);
+                        if (cr >= 0) acc -= S.Binv[(int64_t)i * m + cr];
+                    }
+                }
+                S.alpha[i] = acc;
+            }
+            __syncthreads();
+            // ratio test: least x_B / alpha over alpha > kPivTol, then lowest variable
+            double tv = INFINITY;
+            int tk = INT32_MAX;
+            for (int i = tid; i < m; i += kFreeThreads) {
+                const double al = S.alpha[i];
+                if (al > kPivTol) {
+                    const double r = S.xB[i] / al;
+                    const int key = S.basis[i];
+                    if (r < tv || (r == tv && key < tk)) { tv = r; tk = key; }
+                }
+            }
+            free_argmin(sh, tv, tk);
+            if (tk == INT32_MAX) { if (tid == 0) sh.stat = kFInternal; __syncthreads(); break; }
+            // the row holding variable tk
+            if (tid == 0) {
+                int pr = -1;
+                for (int i = 0; i < m; ++i) if (S.basis[i] == tk) { pr = i; break; }
+                sh.p = pr;
+                sh.theta = tv > 0.0 ? tv : 0.0;
+            }
+            __syncthreads();
+            const int pr = sh.p;
+            if (pr < 0) { __syncthreads(); if (tid == 0) sh.stat = kFInternal; __syncthreads(); break; }
+            const double theta = sh.theta, ap = S.alpha[pr];
+            for (int jj = tid; jj < m; jj += kFreeThreads) S.prow[jj] = S.Binv[(int64_t)pr * m + jj] / ap;
+            __syncthreads();
+            for (int64_t e = tid; e < (int64_t)m * m; e += kFreeThreads) {
+                const int i = (int)(e / m), jj = (int)(e % m);
+                S.Binv[e] = i == pr ? S.prow[jj] : S.Binv[e] - S.alpha[i] * S.prow[jj];
+            }
+            for (int i = tid; i < m; i += kFreeThreads) {
+                const double xv = i == pr ? theta : S.xB[i] - theta * S.alpha[i];
+                S.xB[i] = xv < 0.0 ? 0.0 : xv;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                S.basic[S.basis[pr]] = 0;
+                S.basic[q] = 1;
+                S.basis[pr] = q;
+                sh.fresh = 0;
+                if (theta == 0.0) {
+                    if (++streak >= bland_after) sh.bland = 1;
+                } else {
+                    streak = 0;
+                    sh.bland = 0;
+                }
+            }
+            ++pivots;
+            if (++since >= kRefactor) {
+                __syncthreads();
+                if (!free_refactor(sh, S)) { if (tid == 0) sh.stat = kFInternal; __syncthreads(); break; }
+                if (tid == 0) sh.fresh = 1;
+                since = 0;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        const int st = sh.stat;
+        if (st != kFOk) {
+            for (int k = tid; k < n; k += kFreeThreads)
+                if (obj_status) obj_status[S.obj[k]] = st;
+            if (tid == 0) {
+                if (eps1) eps1[j] = __builtin_nan("");
+                if (eps3) eps3[j] = __builtin_nan("");
+                if (counts) counts[j] = 0;
+                if (cluster_status) cluster_status[j] = st;
+            }
+            __syncthreads();
+            continue;
+        }
+        // the solution, densely
+        for (int v = tid; v < nvar; v += kFreeThreads) S.x[v] = 0.0;
+        __syncthreads();
+        for (int i = tid; i < m; i += kFreeThreads) S.x[S.basis[i]] = S.xB[i] > kFlowEps ? S.xB[i] : 0.0;
+        __syncthreads();
+        for (int r = tid; r < s; r += kFreeThreads) w_new[z0 + r] = S.x[nw + r];
+        // Step 1 value, in variable order
+        if (tid == 0) {
+            double v1 = 0.0;
+            for (int v = 0; v < nw; ++v) v1 = fma(S.cost[v], S.x[v], v1);
+            if (eps1) eps1[j] = v1;
+            if (counts) counts[j] = n;
+            if (cluster_status) cluster_status[j] = kFOk;
+        }
+        // Step 2: each atom to the omega-and-flow-weighted mean (Eq. (4)),
+        // members and atoms in order; an atom with no mass stays
+        for (int e = tid; e < s * d; e += kFreeThreads) {
+            const int r = e / d, qd = e % d;
+            double num = 0.0, den = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const int tk2 = S.T[k + 1] - S.T[k];
+                const int64_t xa = X.off[S.obj[k]];
+                double nk = 0.0, dk = 0.0;
+                for (int a = 0; a < tk2; ++a) {
+                    const double wv = S.x[s * (S.T[k] + a) + r];
+                    nk = fma(wv, ldw<TIn>(X.pts, (xa + a) * d + qd), nk);
+                    dk += wv;
+                }
+                num = fma(S.om[k], nk, num);
+                den = fma(S.om[k], dk, den);
+            }
+            if (den > 0.0) z_new[(z0 + r) * d + qd] = num / den;
+        }
+        __syncthreads();
+        // Step 3: the objective with the moved atoms and the same matchings
+        if (tid == 0) {
+            double v3 = 0.0;
+            for (int v = 0; v < nw; ++v) {
+                const double wv = S.x[v];
+                if (wv == 0.0) continue;
+                const int k = free_member(S.T, n, s, v);
+                const int a = v / s - S.T[k], r = v % s;
+                const int64_t xa = (X.off[S.obj[k]] + a) * d;
+                double acc = 0.0;
+                for (int qd = 0; qd < d; ++qd) {
+                    const double diff = ldw<TIn>(X.pts, xa + qd) - z_new[(z0 + r) * d + qd];
+                    acc = fma(diff, diff, acc);
+                }
+                v3 = fma(S.om[k] * wv, acc, v3);
+            }
+            if (eps3) eps3[j] = v3;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t update_free_slab_bytes(int max_members, int xmax, int zmax, int d) {
+    return free_dims(max_members, xmax, zmax, d).slab;
+}
+
+size_t update_free_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax, int max_members, int cu_count,
+                            int64_t *grid_out) {
+    const UpdDims u = upd_dims(n, K, d, xmax, zmax);
+    const FreeDims f = free_dims(max_members, xmax, zmax, d);
+    int64_t grid = (int64_t)(cu_count > 0 ? cu_count : 256) * 2;
+    const int64_t fit = (int64_t)((size_t)1 << 30) / (int64_t)f.slab;
+    if (grid > fit) grid = fit;
+    if (grid > K) grid = K;
+    if (grid < 1) grid = 1;
+    if (grid_out) *grid_out = grid;
+    // grouping arrays (counts, block sums, order) then the slabs
+    return align256((size_t)u.entries * 8) + align256((size_t)u.sblocks * 8) + align256((size_t)(n > 0 ? n : 1) * 8) +
+           align256((size_t)(n > 0 ? n : 1) * 4) + (size_t)grid * f.slab;
+}
+
+hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, int xmax, int zmax,
+                              int max_members, const KOpts &o, const int32_t *labels, const double *obj_weights,
+                              double *z_new, double *w_new, double *eps1, double *eps3, int32_t *counts,
+                              int32_t *obj_status, int32_t *cluster_status, void *ws) {
+    const UpdDims u = upd_dims(X.n, Z.n, X.d, xmax, zmax);
+    const FreeDims f = free_dims(max_members, xmax, zmax, X.d);
+    int64_t grid = 1;
+    update_free_ws_bytes(X.n, Z.n, X.d, xmax, zmax, max_members, c.cu_count, &grid);
+    char *p = (char *)ws;
+    int64_t *cnt = (int64_t *)p;
+    p += align256((size_t)u.entries * 8);
+    int64_t *bsum = (int64_t *)p;
+    p += align256((size_t)u.sblocks * 8);
+    int64_t *perm = (int64_t *)p;
+    p += align256((size_t)(X.n > 0 ? X.n : 1) * 8);
+    int32_t *skey = (int32_t *)p;
+    p += align256((size_t)(X.n > 0 ? X.n : 1) * 4);
+    char *slabs = p;
+    const unsigned wave_blocks = (unsigned)((u.tiles + 3) / 4);
+    const int64_t fill_grid = (u.entries + 255) / 256 < 4096 ? (u.entries + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_upd_fill, dim3((unsigned)fill_grid), dim3(256), 0, c.stream, cnt, u.entries);
+    if (X.n > 0)
+        hipLaunchKernelGGL(k_upd_count, dim3(wave_blocks), dim3(256), 0, c.stream, labels, X.n, Z.n, u.tiles, cnt,
+                           obj_status);
+    hipLaunchKernelGGL(k_upd_scan_blocks, dim3((unsigned)u.sblocks), dim3(256), 0, c.stream, cnt, u.entries, bsum);
+    hipLaunchKernelGGL(k_upd_scan_top, dim3(1), dim3(1024), 0, c.stream, bsum, u.sblocks);
+    hipLaunchKernelGGL(k_upd_scan_apply, dim3((unsigned)u.sblocks), dim3(256), 0, c.stream, cnt, u.entries, bsum);
+    if (X.n > 0)
+        hipLaunchKernelGGL(k_upd_place, dim3(wave_blocks), dim3(256), 0, c.stream, labels, X.n, Z.n, u.tiles, cnt,
+                           perm, skey);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || Z.n == 0) return e;
+    if (X.dtype == D2_F32)
+        hipLaunchKernelGGL(k_free_solve<float>, dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream, X, Z, o, cnt,
+                           perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts, obj_status,
+                           cluster_status);
+    else
+        hipLaunchKernelGGL(k_free_solve<double>, dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream, X, Z, o, cnt,
+                           perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts, obj_status,
+                           cluster_status);
+    return hipGetLastError();
+}
+
 }  // namespace d2
