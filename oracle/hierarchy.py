@@ -11,9 +11,9 @@ Written from Sec. 2 of the paper, level by level:
           the segments that splitting the largest one first would give.
   Step 2  each segment mu is clustered on its own into k_mu = ceil(n_mu / e)
           groups (tau = c e, Sec. 2.5) by weighted D2-clustering (Eq. (3),
-          (4)); the centroid weights are held uniform (the constrained
-          update), since the full update with free centroid weights is not
-          part of this code.
+          (4)): Alg. 1's centroid update with the centroid weights free
+          (``free_update``); ``update="constrained"`` holds them at their
+          starting values instead (Alg. 2's Step 3*).
   Step 3  the segments' centroids are concatenated in segment order, every
           object's level label is offset by the centroids before its segment
           (Eq. (5)), each original object inherits the label of its ancestor
@@ -27,6 +27,10 @@ Readings where the paper is silent:
     floor(u' (|S| - 1)) among the others; a segment's k_mu picks are a
     partial Fisher-Yates shuffle of its positions;
   * an initial centroid is the picked object's atoms with uniform weights;
+  * the binary splits of Step 1 use the constrained update (the paper's
+    segmentation is constrained D2-clustering with two centroids);
+  * a centroid carries the weights its last update left (free weights,
+    zeros included) into the next level, where it is an object;
   * each clustering runs `rounds` rounds of (labelling within segments,
     `passes` passes of the weighted update), then labels once more;
   * a split that leaves one side empty falls back to halving the segment in
@@ -44,6 +48,7 @@ import math
 import numpy as np
 
 from . import INIT_NWC, emd_batch
+from .free_update import free_update
 from .update import centroid_update
 
 
@@ -177,10 +182,11 @@ def assign_segmented(X, Z, seg, zoff, init: int = INIT_NWC):
     return labels, best, status
 
 
-def _cluster(G, omega, segs, picks, rounds, passes, init):
-    """Weighted constrained D2-clustering of every segment in `segs` at once,
-    segment mu starting from the objects picks[mu].  Returns (centroid
-    ragged set, its segment offsets, final labels over G, -1 outside)."""
+def _cluster(G, omega, segs, picks, rounds, passes, init, free=False):
+    """Weighted D2-clustering of every segment in `segs` at once, segment mu
+    starting from the objects picks[mu]; the centroid weights are free
+    (Alg. 1) when `free`, else held (constrained).  Returns (centroid ragged
+    set, its segment offsets, final labels over G, -1 outside)."""
     pts, wts, off = [], [], [0]
     zoff = [0]
     for p in picks:
@@ -197,16 +203,23 @@ def _cluster(G, omega, segs, picks, rounds, passes, init):
     for _ in range(rounds):
         labels, _, _ = assign_segmented(G, Z, seg, zoff, init)
         for _ in range(passes):
-            z_new, _, _, _ = centroid_update(G, Z, labels, init=init, weights=omega)
-            Z = _Ragged(Z.offsets, z_new, Z.weights)
+            if free:
+                z_new, p_new, _, _, _ = free_update(G, Z, labels, omega)
+                Z = _Ragged(Z.offsets, z_new, p_new)
+            else:
+                z_new, _, _, _ = centroid_update(G, Z, labels, init=init, weights=omega)
+                Z = _Ragged(Z.offsets, z_new, Z.weights)
     labels, _, _ = assign_segmented(G, Z, seg, zoff, init)
     return Z, np.asarray(zoff), labels
 
 
 def hierarchy(X, tau: int, e: int, k: int, uniforms, rounds: int = 3, passes: int = 2,
-              init: int = INIT_NWC, max_levels: int = 16):
+              init: int = INIT_NWC, max_levels: int = 16, update: str = "free"):
     """Returns (centroids as (offsets, points, weights), labels of X, levels)
-    with levels a list of dicts (objects, segments, centroids)."""
+    with levels a list of dicts (objects, segments, centroids).  ``update``:
+    "free" (Alg. 1 in Step 2, the paper's) or "constrained"."""
+    if update not in ("free", "constrained"):
+        raise ValueError("update is 'free' or 'constrained'")
     U = _Uniforms(uniforms)
     G = _Ragged(X.offsets, X.points, X.weights)
     omega = np.ones(G.n)
@@ -234,7 +247,7 @@ def hierarchy(X, tau: int, e: int, k: int, uniforms, rounds: int = 3, passes: in
             segs = new
         # Step 2: each segment into ceil(n_mu / e) clusters
         picks = [[S[p] for p in segment_positions(len(S), e, U)] for S in segs]
-        Z, zoff, labels = _cluster(G, omega, segs, picks, rounds, passes, init)
+        Z, zoff, labels = _cluster(G, omega, segs, picks, rounds, passes, init, free=update == "free")
         if labels.min() < 0:
             raise RuntimeError("a transport problem failed")
         # Step 3: merge in segment order (Eq. (5)), inherit labels (Eq. (6))
