@@ -347,6 +347,8 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
  *                  D2_PAIR_PIVOT_CAP (opts->max_pivots, 0 = max(50 m, 100)
  *                  pivots for a program of m rows) or D2_PAIR_INTERNAL (the
  *                  basis matrix lost rank numerically).
+ *   cluster_pivots[K]  device int32, nullable: simplex pivots of each
+ *                  cluster's program (0 where none was solved).
  * Workspace: d2_workspace_bytes(h, 6, X, Z, max_members, opts) bytes
  * (required).  opts->bland_after applies to degenerate pivots as in the
  * transport solver (0 = 2 m); opts->opt_tol and want_sqrt are ignored: a
@@ -356,8 +358,8 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
 d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *labels,
                                   const double *obj_weights, int32_t max_members, const d2_opts *opts,
                                   double *z_new, double *w_new, double *eps_step1, double *eps_step3,
-                                  int32_t *counts, int32_t *obj_status, int32_t *cluster_status, void *ws,
-                                  size_t ws_bytes, void *stream);
+                                  int32_t *counts, int32_t *obj_status, int32_t *cluster_status,
+                                  int32_t *cluster_pivots, void *ws, size_t ws_bytes, void *stream);
 
 /* Nearest-centroid labelling within segments (Alg. 3 Step 2, where each
  * segment of the data is clustered on its own): object i is compared only

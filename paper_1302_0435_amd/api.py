@@ -304,7 +304,7 @@ def d2_centroid_update(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch.Tens
 
 def d2_centroid_update_free(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch.Tensor,
                             opts: Optional[Opts] = None, weights: Optional[torch.Tensor] = None,
-                            max_members: Optional[int] = None):
+                            max_members: Optional[int] = None, want_pivots: bool = False):
     """One pass of the centroid update of Alg. 1 with free centroid weights
     (Steps 1-3; object weights as in Eq. (3)-(4)).
 
@@ -312,7 +312,8 @@ def d2_centroid_update_free(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch
     among the labels, read back once).  Returns z_new [Z.offsets[K], d] f64,
     w_new [Z.offsets[K]] f64, eps_step1 [K], eps_step3 [K] f64, counts [K],
     obj_status [n], cluster_status [K] int32 (see d2_centroid_update_free in
-    d2.h)."""
+    d2.h); with ``want_pivots`` also the simplex pivots of each cluster
+    [K] int32."""
     opts = opts or Opts()
     dev = _dev(h)
     labels = labels.to(device=dev, dtype=torch.int32).contiguous()
@@ -330,13 +331,16 @@ def d2_centroid_update_free(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch
     counts = torch.empty(K, dtype=torch.int32, device=dev)
     status = torch.empty(X.n, dtype=torch.int32, device=dev)
     cstatus = torch.empty(K, dtype=torch.int32, device=dev)
+    piv = torch.empty(K, dtype=torch.int32, device=dev) if want_pivots else None
     ws, nbytes = _workspace(h, _ffi.WHICH_UPDATE_FREE, X, Z, max_members, opts)
     x, z, o = X.c(), Z.c(), opts.c()
     check(_ffi.lib().d2_centroid_update_free(h.ptr, ctypes.byref(x), ctypes.byref(z), _ptr(labels),
                                              _ptr(weights), max_members, ctypes.byref(o),
                                              _ptr(z_new), _ptr(w_new), _ptr(eps1), _ptr(eps3),
-                                             _ptr(counts), _ptr(status), _ptr(cstatus), _ptr(ws),
-                                             nbytes, _stream(dev)), "d2_centroid_update_free")
+                                             _ptr(counts), _ptr(status), _ptr(cstatus), _ptr(piv),
+                                             _ptr(ws), nbytes, _stream(dev)), "d2_centroid_update_free")
+    if want_pivots:
+        return z_new, w_new, eps1, eps3, counts, status, cstatus, piv
     return z_new, w_new, eps1, eps3, counts, status, cstatus
 
 

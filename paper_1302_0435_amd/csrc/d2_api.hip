@@ -58,8 +58,8 @@ static __device__ __align__(256) unsigned char scratch[D2_NOALLOC_SCRATCH_BYTES]
 namespace {
 
 constexpr size_t kScratchBytes = (size_t)D2_NOALLOC_SCRATCH_BYTES;
-// Largest per-cluster slab of the free-weight update (dense basis matrix and
-// its inverse for max_members (xmax + zmax - 1) + 1 rows): 8 GiB.
+// Largest per-cluster slab of the free-weight update (the dense inverse of a
+// basis of max_members (xmax + zmax - 1) + 1 rows): 8 GiB.
 constexpr size_t kMaxFreeSlab = (size_t)8 << 30;
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
@@ -528,8 +528,8 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
 d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z, const int32_t *labels,
                                   const double *obj_weights, int32_t max_members, const d2_opts *opts,
                                   double *z_new, double *w_new, double *eps_step1, double *eps_step3,
-                                  int32_t *counts, int32_t *obj_status, int32_t *cluster_status, void *ws,
-                                  size_t ws_bytes, void *stream) {
+                                  int32_t *counts, int32_t *obj_status, int32_t *cluster_status,
+                                  int32_t *cluster_pivots, void *ws, size_t ws_bytes, void *stream) {
     if (!h) return D2_EINVAL;
     d2_status st = pair_sets_ok(X, Z);
     if (st != D2_OK) return st;
@@ -548,7 +548,7 @@ d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z
     if (X->n == 0 && Z->n == 0) return D2_OK;
     hipError_t e = d2::launch_update_free(ctx(h, (hipStream_t)stream), kset(X), kset(Z), ms(X), ms(Z),
                                           max_members, k, labels, obj_weights, z_new, w_new, eps_step1, eps_step3,
-                                          counts, obj_status, cluster_status, ws);
+                                          counts, obj_status, cluster_status, cluster_pivots, ws);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 

@@ -629,33 +629,114 @@ hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet 
 //            fixes p_z (all s weights basic); every later member is the
 //            north-west corner from its weights to p_z.  The basis matrix is
 //            block triangular with non-singular blocks, so it is a basis;
-//   pivots   explicit inverse of the basis: y = c_B B^-1, Dantzig's entering
-//            column (Bland's after a run of degenerate pivots), the column
+//   pivots   explicit inverse of the basis: Dantzig's entering column
+//            (Bland's after a run of degenerate pivots), the column
 //            B^-1 a_q, the ratio test (least ratio, then lowest variable),
-//            and the rank-one update of B^-1; B^-1 is rebuilt by Gauss-Jordan
-//            elimination with partial pivoting every kRefactor pivots and
-//            before optimality is declared; values of the solution at or
-//            below kFlowEps are rounding noise of zeros and set to 0;
+//            the rank-one update of B^-1 and of the duals y = c_B B^-1
+//            (y += d_q times the new pivot row); B^-1, x_B and y are rebuilt
+//            from the identity by pivoting the basis columns in, each onto
+//            its largest untaken entry, every kRefactor pivots and before
+//            optimality is declared; values of
+//            the solution at or below kFlowEps are rounding noise of zeros
+//            and set to 0;
 //   Step 2   each atom moves to the omega-and-flow-weighted mean of the
 //            member atoms matched to it (Eq. (4)); Step 3 evaluates the
 //            objective with the moved atoms and the same matchings.
-// The dense arrays of a cluster (B, B^-1, costs, solution) live in the
-// workgroup's slab of the workspace, sized for the caller's bound on the
-// members of one cluster.  Every reduction runs in a fixed order.
+// B^-1 (m x m), the costs and the solution live in the workgroup's
+// slab of the workspace, sized for the caller's bound on the members of one
+// cluster; the vectors of length m and the member tables live in LDS when
+// they fit in kFreeLds bytes, else in the slab.  Sums run in a fixed order.
 
 namespace {
 
-constexpr int kFreeThreads = 256;
-constexpr int kRefactor = 64;
+constexpr int kFreeThreads = 512;
+constexpr int kFreeWaves = kFreeThreads / 64;
+constexpr int kRefactor = 256;
 constexpr double kFreeTol = 1e-13;     // reduced costs above -kFreeTol max|c| count as >= 0
-constexpr double kPivTol = 1e-9;       // least |entry| of B^-1 a_q taken in the ratio test
+constexpr double kPivTol = 1e-9;       // least entry of B^-1 a_q taken in the ratio test
 constexpr double kFlowEps = 1e-14;     // flows at or below this (of a unit mass) are zeros
+constexpr size_t kFreeLds = 60 * 1024; // dynamic LDS for the vectors, when they fit
 enum { kFOk = 0, kFBadWeights = 1, kFTooLarge = 2, kFPivotCap = 3, kFInternal = 6 };
 
+// Vectors of one cluster's program (length m unless noted).
+struct FreeVec {
+    double *y, *alpha, *xB, *prow, *b, *cB;
+    double *om, *isum;    // [nmax] member weight omega, 1 / (sum of its weights)
+    int64_t *obj;         // [nmax] member object
+    int32_t *basis;       // variable of each basis position
+    int32_t *nbasis;      // the basis being rebuilt by a reinversion
+    int32_t *T;           // [nmax + 1] first row (atom) of each member
+    int32_t *amem;        // [nmax xmax] member of each row (atom)
+    int32_t *tt;          // [nmax] support of each member before compaction
+    uint32_t *basic;      // [vmax / 32] bit v set for basic variables
+    int8_t *taken;        // rows already given a basis column by a reinversion
+    int16_t *rlist;       // rows a rank-one update changes (ascending)
+    int16_t *clist;       // columns it changes (ascending)
+};
+
+// Byte offsets of the vectors inside their block (LDS or the slab).
+struct FreeLayout {
+    size_t y, alpha, xB, prow, b, cB, om, isum, obj, basis, nbasis, T, amem, tt, basic, taken, rlist, clist, total;
+};
+
+FreeLayout free_layout(int64_t nmax, int64_t amax, int64_t mmax, int64_t vmax) {
+    FreeLayout l;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t q = off;
+        off += (bytes + 15) & ~(size_t)15;
+        return q;
+    };
+    l.y = take((size_t)mmax * 8);
+    l.alpha = take((size_t)mmax * 8);
+    l.xB = take((size_t)mmax * 8);
+    l.prow = take((size_t)mmax * 8);
+    l.b = take((size_t)mmax * 8);
+    l.cB = take((size_t)mmax * 8);
+    l.om = take((size_t)nmax * 8);
+    l.isum = take((size_t)nmax * 8);
+    l.obj = take((size_t)nmax * 8);
+    l.basis = take((size_t)mmax * 4);
+    l.nbasis = take((size_t)mmax * 4);
+    l.T = take((size_t)(nmax + 1) * 4);
+    l.amem = take((size_t)amax * 4);
+    l.tt = take((size_t)nmax * 4);
+    l.basic = take((size_t)((vmax + 31) / 32) * 4);
+    l.taken = take((size_t)mmax);
+    l.rlist = take((size_t)mmax * 2);
+    l.clist = take((size_t)mmax * 2);
+    l.total = off;
+    return l;
+}
+
+__device__ __forceinline__ FreeVec free_vec(char *base, const FreeLayout &l) {
+    FreeVec v;
+    v.y = (double *)(base + l.y);
+    v.alpha = (double *)(base + l.alpha);
+    v.xB = (double *)(base + l.xB);
+    v.prow = (double *)(base + l.prow);
+    v.b = (double *)(base + l.b);
+    v.cB = (double *)(base + l.cB);
+    v.om = (double *)(base + l.om);
+    v.isum = (double *)(base + l.isum);
+    v.obj = (int64_t *)(base + l.obj);
+    v.basis = (int32_t *)(base + l.basis);
+    v.nbasis = (int32_t *)(base + l.nbasis);
+    v.T = (int32_t *)(base + l.T);
+    v.amem = (int32_t *)(base + l.amem);
+    v.tt = (int32_t *)(base + l.tt);
+    v.basic = (uint32_t *)(base + l.basic);
+    v.taken = (int8_t *)(base + l.taken);
+    v.rlist = (int16_t *)(base + l.rlist);
+    v.clist = (int16_t *)(base + l.clist);
+    return v;
+}
+
 struct FreeDims {
-    int nmax, xmax, zmax, d;
-    int64_t mmax, vmax;
-    size_t slab;
+    int nmax, xmax, zmax, d, lds;
+    int64_t mmax, vmax, amax;
+    size_t vec, slab;
+    FreeLayout lay;
 };
 
 FreeDims free_dims(int nmax, int xmax, int zmax, int d) {
@@ -664,49 +745,23 @@ FreeDims free_dims(int nmax, int xmax, int zmax, int d) {
     f.xmax = xmax > 0 ? xmax : 1;
     f.zmax = zmax > 0 ? zmax : 1;
     f.d = d;
-    f.mmax = (int64_t)f.nmax * (f.xmax + f.zmax - 1) + 1;
-    f.vmax = (int64_t)f.zmax * f.nmax * f.xmax + f.zmax;
-    f.slab = 2 * align256((size_t)f.mmax * f.mmax * 8) + 2 * align256((size_t)f.vmax * 8) + align256((size_t)f.vmax) +
-             5 * align256((size_t)f.mmax * 8) + align256((size_t)f.mmax * 4) + align256((size_t)(f.nmax + 1) * 4) +
-             3 * align256((size_t)f.nmax * 8);
+    f.amax = (int64_t)f.nmax * f.xmax;
+    f.mmax = f.amax + (int64_t)f.nmax * (f.zmax - 1) + 1;
+    f.vmax = (int64_t)f.zmax * f.amax + f.zmax;
+    f.lay = free_layout(f.nmax, f.amax, f.mmax, f.vmax);
+    f.vec = f.lay.total;
+    f.lds = f.vec <= kFreeLds;
+    f.slab = align256((size_t)f.mmax * f.mmax * 8 + (size_t)f.vmax * 8 * 2 + (f.lds ? 0 : f.vec));
+    if (f.mmax > 32767) f.slab = SIZE_MAX;   // row and column lists are 16-bit
     return f;
 }
 
-struct FreeSlab {
-    double *B, *Binv, *cost, *x, *xB, *y, *alpha, *b, *prow;
-    int8_t *basic;
-    int32_t *basis, *T;
-    int64_t *obj;
-    double *om, *isum;
-};
-
-__host__ __device__ inline FreeSlab free_slab(char *base, const FreeDims &f) {
-    FreeSlab s;
-    size_t off = 0;
-    auto take = [&](size_t bytes) { char *q = base + off; off += (bytes + 255) & ~(size_t)255; return q; };
-    s.B = (double *)take((size_t)f.mmax * f.mmax * 8);
-    s.Binv = (double *)take((size_t)f.mmax * f.mmax * 8);
-    s.cost = (double *)take((size_t)f.vmax * 8);
-    s.x = (double *)take((size_t)f.vmax * 8);
-    s.basic = (int8_t *)take((size_t)f.vmax);
-    s.xB = (double *)take((size_t)f.mmax * 8);
-    s.y = (double *)take((size_t)f.mmax * 8);
-    s.alpha = (double *)take((size_t)f.mmax * 8);
-    s.b = (double *)take((size_t)f.mmax * 8);
-    s.prow = (double *)take((size_t)f.mmax * 8);
-    s.basis = (int32_t *)take((size_t)f.mmax * 4);
-    s.T = (int32_t *)take((size_t)(f.nmax + 1) * 4);
-    s.obj = (int64_t *)take((size_t)f.nmax * 8);
-    s.om = (double *)take((size_t)f.nmax * 8);
-    s.isum = (double *)take((size_t)f.nmax * 8);
-    return s;
-}
-
 struct FreeShared {
-    double rv[kFreeThreads / 64];
-    int ri[kFreeThreads / 64];
-    int n, s, m, nvar, nw, stat, q, p, fresh, done, bland;
-    double cmax, delta, theta;
+    double rv[kFreeWaves];
+    int ri[kFreeWaves];
+    int cr[kFreeWaves], cc[kFreeWaves];
+    int n, m, stat, p, fresh, bland;
+    double delta, dq;
 };
 
 // Block-wide (value, key) minimum, lowest key among equal values; keys of
@@ -717,25 +772,34 @@ __device__ __forceinline__ void free_argmin(FreeShared &sh, double &v, int &k) {
         const int ok = __shfl_xor(k, off, 64);
         if (ov < v || (ov == v && ok < k)) { v = ov; k = ok; }
     }
-    const int w = threadIdx.x >> 6;
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) { sh.rv[w] = v; sh.ri[w] = k; }
+    if ((threadIdx.x & 63) == 0) { sh.rv[threadIdx.x >> 6] = v; sh.ri[threadIdx.x >> 6] = k; }
     __syncthreads();
     v = sh.rv[0];
     k = sh.ri[0];
-    for (int q = 1; q < kFreeThreads / 64; ++q)
+    for (int q = 1; q < kFreeWaves; ++q)
         if (sh.rv[q] < v || (sh.rv[q] == v && sh.ri[q] < k)) { v = sh.rv[q]; k = sh.ri[q]; }
 }
 
 __device__ __forceinline__ double free_max(FreeShared &sh, double v) {
     for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    const int w = threadIdx.x >> 6;
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh.rv[w] = v;
+    if ((threadIdx.x & 63) == 0) sh.rv[threadIdx.x >> 6] = v;
     __syncthreads();
     double m = sh.rv[0];
-    for (int q = 1; q < kFreeThreads / 64; ++q) m = fmax(m, sh.rv[q]);
+    for (int q = 1; q < kFreeWaves; ++q) m = fmax(m, sh.rv[q]);
     return m;
+}
+
+// Block-wide sum in a fixed order (the same bits on every run).
+__device__ __forceinline__ double free_sum(FreeShared &sh, double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh.rv[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = sh.rv[0];
+    for (int q = 1; q < kFreeWaves; ++q) t += sh.rv[q];
+    return t;
 }
 
 // Row of member k's coupling constraint for atom r, or -1 (dropped).
@@ -745,104 +809,174 @@ __device__ __forceinline__ int free_colrow(int sumt, int s, int k, int r) {
     return sumt + s + (k - 1) * (s - 1) + r;
 }
 
-// Member of variable v < nw (binary search over the atom offsets T).
-__device__ __forceinline__ int free_member(const int32_t *T, int n, int s, int v) {
-    const int atom = v / s;
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (T[mid] <= atom) lo = mid; else hi = mid - 1;
+// Reduced cost of variable v under the duals y.
+__device__ __forceinline__ double free_reduced(const FreeVec &V, const double *cost, int v, int n, int s,
+                                               int nw, int sumt) {
+    if (v < nw) {
+        const int atom = v / s, r = v - atom * s;
+        const int cr = free_colrow(sumt, s, V.amem[atom], r);
+        return cost[v] - V.y[atom] - (cr >= 0 ? V.y[cr] : 0.0);
     }
-    return lo;
+    const int r = v - nw;
+    double acc = V.y[sumt + r];   // 0 - y . a, a = -1 on every kept coupling row of atom r
+    if (r < s - 1)
+        for (int k = 1; k < n; ++k) acc += V.y[sumt + s + (k - 1) * (s - 1) + r];
+    return acc;
 }
 
-// Rebuild B from the basis, B^-1 by Gauss-Jordan with partial pivoting, and
-// x_B = B^-1 b.  Returns false when a pivot is (numerically) zero.
-__device__ bool free_refactor(FreeShared &sh, const FreeSlab &S) {
-    const int m = sh.m, n = sh.n, s = sh.s, nw = sh.nw, sumt = S.T[n];
-    const int tid = threadIdx.x;
-    for (int64_t e = tid; e < (int64_t)m * m; e += kFreeThreads) {
-        S.B[e] = 0.0;
-        S.Binv[e] = (e / m == e % m) ? 1.0 : 0.0;
+// alpha = B^-1 a_v (thread per row).
+__device__ __forceinline__ void free_ftran(const FreeVec &V, const double *Binv, int v, int m, int n, int s,
+                                           int nw, int sumt) {
+    if (v < nw) {
+        const int atom = v / s, r = v - atom * s;
+        const int cr = free_colrow(sumt, s, V.amem[atom], r);
+        for (int i = threadIdx.x; i < m; i += kFreeThreads) {
+            const double *row = Binv + (int64_t)i * m;
+            V.alpha[i] = row[atom] + (cr >= 0 ? row[cr] : 0.0);
+        }
+    } else {
+        const int r = v - nw;
+        for (int i = threadIdx.x; i < m; i += kFreeThreads) {
+            const double *row = Binv + (int64_t)i * m;
+            double acc = -row[sumt + r];
+            if (r < s - 1)
+                for (int k = 1; k < n; ++k) acc -= row[sumt + s + (k - 1) * (s - 1) + r];
+            V.alpha[i] = acc;
+        }
+    }
+}
+
+// B^-1 <- E B^-1 for the pivot on row pr: row pr becomes prow (the old row
+// over alpha_pr), every other row i with alpha_i != 0 loses alpha_i prow;
+// only the columns where prow is non-zero change.  The rows and columns
+// that change are first listed in ascending order (wave ballots); then
+// each wave takes kEtaRows listed rows at a time and reads kEtaCols chunks
+// of 64 listed columns of them before writing any, so the loads overlap.
+constexpr int kEtaRows = 4, kEtaCols = 4;
+__device__ __forceinline__ void free_eta(FreeShared &sh, const FreeVec &V, double *Binv, int m, int pr) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int nr = 0, nc = 0;
+    for (int base = 0; base < m; base += kFreeThreads) {
+        const int i = base + tid;
+        const bool rin = i < m && (V.alpha[i] != 0.0 || i == pr);
+        const bool cin = i < m && V.prow[i] != 0.0;
+        const uint64_t rb = __ballot(rin), cb = __ballot(cin);
+        __syncthreads();   // the previous round's counts have been read
+        if (lane == 0) {
+            sh.cr[wv] = __builtin_popcountll(rb);
+            sh.cc[wv] = __builtin_popcountll(cb);
+        }
+        __syncthreads();
+        int ro = nr, co = nc;
+        for (int w = 0; w < kFreeWaves; ++w) {
+            if (w < wv) { ro += sh.cr[w]; co += sh.cc[w]; }
+            nr += sh.cr[w];
+            nc += sh.cc[w];
+        }
+        if (rin) V.rlist[ro + __builtin_popcountll(rb & lanes_below())] = (int16_t)i;
+        if (cin) V.clist[co + __builtin_popcountll(cb & lanes_below())] = (int16_t)i;
     }
     __syncthreads();
-    for (int j = tid; j < m; j += kFreeThreads) {   // column j of B: the basis variable's column
-        const int v = S.basis[j];
-        if (v < nw) {
-            const int k = free_member(S.T, n, s, v);
-            const int a = v / s - S.T[k], r = v % s;
-            S.B[(int64_t)(S.T[k] + a) * m + j] = 1.0;
-            const int cr = free_colrow(sumt, s, k, r);
-            if (cr >= 0) S.B[(int64_t)cr * m + j] = 1.0;
-        } else {
-            const int r = v - nw;
-            for (int k = 0; k < n; ++k) {
-                const int cr = free_colrow(sumt, s, k, r);
-                if (cr >= 0) S.B[(int64_t)cr * m + j] = -1.0;
+    for (int g = wv * kEtaRows; g < nr; g += kFreeWaves * kEtaRows) {
+        int rows[kEtaRows];
+        double als[kEtaRows];
+#pragma unroll
+        for (int r = 0; r < kEtaRows; ++r) {
+            rows[r] = g + r < nr ? V.rlist[g + r] : -1;
+            als[r] = rows[r] >= 0 ? V.alpha[rows[r]] : 0.0;
+        }
+        for (int c0 = 0; c0 < nc; c0 += 64 * kEtaCols) {
+            int col[kEtaCols];
+            double pv[kEtaCols], bv[kEtaRows][kEtaCols];
+#pragma unroll
+            for (int u = 0; u < kEtaCols; ++u) {
+                const int jc = c0 + u * 64 + lane;
+                col[u] = jc < nc ? V.clist[jc] : -1;
+                pv[u] = col[u] >= 0 ? V.prow[col[u]] : 0.0;
+#pragma unroll
+                for (int r = 0; r < kEtaRows; ++r)
+                    bv[r][u] = (col[u] >= 0 && rows[r] >= 0 && rows[r] != pr)
+                                   ? Binv[(int64_t)rows[r] * m + col[u]] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < kEtaRows; ++r) {
+                if (rows[r] < 0) continue;
+                double *row = Binv + (int64_t)rows[r] * m;
+#pragma unroll
+                for (int u = 0; u < kEtaCols; ++u)
+                    if (col[u] >= 0) row[col[u]] = rows[r] == pr ? pv[u] : bv[r][u] - als[r] * pv[u];
             }
         }
     }
+}
+
+// Rebuild B^-1 from the basis by pivoting its columns in, one by one, from
+// the identity (each onto the untaken row of largest |entry|, the lowest on
+// ties), then x_B = B^-1 b, c_B and y = c_B B^-1.  Returns false when a
+// column has no usable pivot (the basis lost rank numerically).
+__device__ __forceinline__ bool free_refactor(FreeShared &sh, const FreeVec &V, double *Binv, const double *cost,
+                                              int m, int n, int s, int nw) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int sumt = V.T[n];
+    for (int i = wv; i < m; i += kFreeWaves)
+        for (int j = lane; j < m; j += 64) Binv[(int64_t)i * m + j] = i == j ? 1.0 : 0.0;
+    for (int i = tid; i < m; i += kFreeThreads) V.taken[i] = 0;
     __syncthreads();
     for (int c = 0; c < m; ++c) {
-        double v = -1.0;
-        int k = INT32_MAX;
-        for (int i = c + tid; i < m; i += kFreeThreads) {
-            const double a = fabs(S.B[(int64_t)i * m + c]);
-            if (a > v || (a == v && i < k)) { v = a; k = i; }
+        const int v = V.basis[c];
+        free_ftran(V, Binv, v, m, n, s, nw, sumt);
+        __syncthreads();
+        double bv = 1.0;
+        int br = INT32_MAX;
+        for (int i = tid; i < m; i += kFreeThreads) {
+            if (V.taken[i]) continue;
+            const double a = -fabs(V.alpha[i]);
+            if (a < bv || (a == bv && i < br)) { bv = a; br = i; }
         }
-        // largest |entry| (lowest row on ties): argmin of the negation
-        double nv = -v;
-        free_argmin(sh, nv, k);
-        if (!(-nv > 1e-12)) return false;
-        const int pr = k;
-        if (pr != c)
-            for (int j = tid; j < m; j += kFreeThreads) {
-                const double t1 = S.B[(int64_t)c * m + j];
-                S.B[(int64_t)c * m + j] = S.B[(int64_t)pr * m + j];
-                S.B[(int64_t)pr * m + j] = t1;
-                const double t2 = S.Binv[(int64_t)c * m + j];
-                S.Binv[(int64_t)c * m + j] = S.Binv[(int64_t)pr * m + j];
-                S.Binv[(int64_t)pr * m + j] = t2;
-            }
+        free_argmin(sh, bv, br);
+        if (!(-bv > 1e-12) || br == INT32_MAX) return false;
+        const double ap = V.alpha[br];
+        for (int j = tid; j < m; j += kFreeThreads) V.prow[j] = Binv[(int64_t)br * m + j] / ap;
         __syncthreads();
-        const double piv = S.B[(int64_t)c * m + c];
-        __syncthreads();
-        for (int j = tid; j < m; j += kFreeThreads) {
-            S.B[(int64_t)c * m + j] /= piv;
-            S.Binv[(int64_t)c * m + j] /= piv;
-        }
-        for (int i = tid; i < m; i += kFreeThreads) S.alpha[i] = S.B[(int64_t)i * m + c];   // factors, read first
-        __syncthreads();
-        for (int64_t e = tid; e < (int64_t)m * m; e += kFreeThreads) {
-            const int i = (int)(e / m), j = (int)(e % m);
-            if (i == c) continue;
-            const double f = S.alpha[i];
-            if (f != 0.0) {
-                S.B[e] -= f * S.B[(int64_t)c * m + j];
-                S.Binv[e] -= f * S.Binv[(int64_t)c * m + j];
-            }
+        free_eta(sh, V, Binv, m, br);
+        if (tid == 0) {
+            V.taken[br] = 1;
+            V.nbasis[br] = v;
         }
         __syncthreads();
     }
     for (int i = tid; i < m; i += kFreeThreads) {
+        V.basis[i] = V.nbasis[i];
+        V.cB[i] = cost[V.nbasis[i]];
         double acc = 0.0;
-        for (int j = 0; j < m; ++j) acc = fma(S.Binv[(int64_t)i * m + j], S.b[j], acc);
-        S.xB[i] = acc < 0.0 ? 0.0 : acc;
+        const double *row = Binv + (int64_t)i * m;
+        for (int j = 0; j < m; ++j) acc = fma(row[j], V.b[j], acc);
+        V.xB[i] = acc < 0.0 ? 0.0 : acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += kFreeThreads) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc = fma(V.cB[j], Binv[(int64_t)j * m + i], acc);
+        V.y[i] = acc;
     }
     __syncthreads();
     return true;
 }
 
-template <typename TIn>
+template <typename TIn, bool L>
 __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOpts o, const int64_t *pre,
                                                              const int64_t *perm, int64_t tiles, FreeDims f,
                                                              char *slabs, const double *objw, double *z_new,
                                                              double *w_new, double *eps1, double *eps3,
                                                              int32_t *counts, int32_t *obj_status,
-                                                             int32_t *cluster_status) {
+                                                             int32_t *cluster_status, int32_t *cluster_pivots) {
+    extern __shared__ __align__(16) char free_lds[];
     __shared__ FreeShared sh;
     const int tid = threadIdx.x;
-    const FreeSlab S = free_slab(slabs + (size_t)blockIdx.x * f.slab, f);
+    double *Binv = (double *)(slabs + (size_t)blockIdx.x * f.slab);
+    double *cost = Binv + f.mmax * f.mmax;
+    double *x = cost + f.vmax;
+    const FreeVec V = free_vec(L ? free_lds : (char *)(x + f.vmax), f.lay);
     const int d = X.d;
     for (int64_t j = blockIdx.x; j < Z.n; j += gridDim.x) {
         const int64_t pb = pre[j * tiles], pe = pre[(j + 1) * tiles];
@@ -852,10 +986,7 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
         for (int64_t e = tid; e < (int64_t)s * d; e += kFreeThreads)
             z_new[z0 * d + e] = ldw<TIn>(Z.pts, z0 * d + e);
         for (int r = tid; r < s; r += kFreeThreads) w_new[z0 + r] = ldw<TIn>(Z.w, z0 + r);
-        // members: validate weights (thread per member), then compact in order
         const int64_t nall = pe - pb;
-        if (tid == 0) { sh.stat = kFOk; sh.n = 0; }
-        __syncthreads();
         if (nall > f.nmax || s < 1 || s > f.zmax) {
             for (int64_t q = pb + tid; q < pe; q += kFreeThreads)
                 if (obj_status) obj_status[perm[q]] = kFTooLarge;
@@ -864,10 +995,12 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
                 if (eps3) eps3[j] = __builtin_nan("");
                 if (counts) counts[j] = 0;
                 if (cluster_status) cluster_status[j] = kFTooLarge;
+                if (cluster_pivots) cluster_pivots[j] = 0;
             }
             __syncthreads();
             continue;
         }
+        // members: validate (thread per member), then compact in order
         for (int64_t q = pb + tid; q < pe; q += kFreeThreads) {
             const int64_t i = perm[q];
             const int64_t a0 = X.off[i];
@@ -882,216 +1015,182 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
             }
             bad = bad || !(sum > 0.0) || !isfinite(sum);
             if (obj_status) obj_status[i] = bad ? (t > f.xmax ? kFTooLarge : kFBadWeights) : kFOk;
-            S.isum[q - pb] = bad ? -1.0 : (om > 0.0 ? 1.0 / sum : 0.0);
-            S.om[q - pb] = om;
+            V.isum[q - pb] = bad ? -1.0 : (om > 0.0 ? 1.0 / sum : 0.0);
+            V.om[q - pb] = om;
+            V.obj[q - pb] = i;
+            V.tt[q - pb] = (int)t;
         }
         __syncthreads();
         if (tid == 0) {
             int n = 0, acc = 0;
-            for (int64_t q = 0; q < nall; ++q) {
-                if (!(S.isum[q] > 0.0)) continue;   // invalid, or omega = 0: no part in the LP
-                const int64_t i = perm[pb + q];
-                S.obj[n] = i;
-                S.om[n] = S.om[q];
-                S.isum[n] = S.isum[q];
-                S.T[n] = acc;
-                acc += (int)(X.off[i + 1] - X.off[i]);
+            for (int q = 0; q < (int)nall; ++q) {
+                if (!(V.isum[q] > 0.0)) continue;   // invalid, or omega = 0: no part in the LP
+                V.obj[n] = V.obj[q];
+                V.om[n] = V.om[q];
+                V.isum[n] = V.isum[q];
+                V.T[n] = acc;
+                acc += V.tt[q];
                 ++n;
             }
-            S.T[n] = acc;
+            V.T[n] = acc;
             sh.n = n;
-            sh.s = s;
             sh.m = acc + n * (s - 1) + 1;
-            sh.nw = s * acc;
-            sh.nvar = s * acc + s;
+            sh.stat = kFOk;
         }
         __syncthreads();
-        const int n = sh.n, m = sh.m, nw = sh.nw, nvar = sh.nvar, sumt = S.T[n];
+        const int n = sh.n, m = sh.m, sumt = V.T[n], nw = s * sumt, nvar = nw + s;
         if (n == 0) {
             if (tid == 0) {
                 if (eps1) eps1[j] = 0.0;
                 if (eps3) eps3[j] = 0.0;
                 if (counts) counts[j] = 0;
                 if (cluster_status) cluster_status[j] = kFOk;
+                if (cluster_pivots) cluster_pivots[j] = 0;
             }
             __syncthreads();
             continue;
         }
+        // row tables and right-hand sides: the members' normalised weights, then zeros
+        for (int k = tid; k < n; k += kFreeThreads) {
+            const int64_t xa = X.off[V.obj[k]];
+            for (int a = V.T[k]; a < V.T[k + 1]; ++a) {
+                V.amem[a] = k;
+                V.b[a] = ldw<TIn>(X.w, xa + (a - V.T[k])) * V.isum[k];
+            }
+        }
+        for (int i = sumt + tid; i < m; i += kFreeThreads) V.b[i] = 0.0;
+        __syncthreads();
         // costs omega_k |z_r - v_ka|^2 (direct form, coordinates ascending)
         double cm = 0.0;
         for (int v = tid; v < nvar; v += kFreeThreads) {
             double c = 0.0;
             if (v < nw) {
-                const int k = free_member(S.T, n, s, v);
-                const int a = v / s - S.T[k], r = v % s;
-                const int64_t xa = (X.off[S.obj[k]] + a) * d, zr = (z0 + r) * d;
+                const int atom = v / s, r = v - atom * s, k = V.amem[atom];
+                const int64_t xa = (X.off[V.obj[k]] + (atom - V.T[k])) * d, zr = (z0 + r) * d;
                 double acc = 0.0;
                 for (int qd = 0; qd < d; ++qd) {
                     const double diff = ldw<TIn>(X.pts, xa + qd) - ldw<TIn>(Z.pts, zr + qd);
                     acc = fma(diff, diff, acc);
                 }
-                c = S.om[k] * acc;
+                c = V.om[k] * acc;
             }
-            S.cost[v] = c;
-            S.basic[v] = 0;
+            cost[v] = c;
             cm = fmax(cm, fabs(c));
         }
+        for (int w = tid; w < (nvar + 31) / 32; w += kFreeThreads) V.basic[w] = 0u;
         cm = free_max(sh, cm);
-        if (tid == 0) { sh.cmax = cm; sh.delta = kFreeTol * cm; }
-        for (int i = tid; i < m; i += kFreeThreads) {   // right-hand sides: member weights, then zeros
-            double bv = 0.0;
-            if (i < sumt) {
-                const int k = free_member(S.T, n, 1, i);
-                bv = ldw<TIn>(X.w, X.off[S.obj[k]] + (i - S.T[k])) * S.isum[k];
-            }
-            S.b[i] = bv;
+        // the structured starting basis: member 0's atoms at their cheapest
+        // centroid atom (lowest on ties), thread per atom; then, serially, the
+        // weights they fix and the other members' north-west corners
+        const int t0 = V.T[1];
+        for (int a = tid; a < t0; a += kFreeThreads) {
+            int rb = 0;
+            for (int r = 1; r < s; ++r)
+                if (cost[a * s + r] < cost[a * s + rb]) rb = r;
+            V.basis[a] = a * s + rb;
         }
         __syncthreads();
-        // the structured starting basis (serial: O(sum t + n s) steps)
         if (tid == 0) {
-            int nb = 0;
-            const int t0 = S.T[1] - S.T[0];
-            for (int a = 0; a < t0; ++a) {   // member 0: cheapest atom, lowest on ties
-                int rb = 0;
-                for (int r = 1; r < s; ++r)
-                    if (S.cost[a * s + r] < S.cost[a * s + rb]) rb = r;
-                S.basis[nb++] = a * s + rb;
-                S.prow[a] = rb;   // scratch: chosen atom
-            }
-            for (int r = 0; r < s; ++r) S.y[r] = 0.0;   // scratch: p_z
-            for (int a = 0; a < t0; ++a) S.y[(int)S.prow[a]] += S.b[a];
-            for (int r = 0; r < s; ++r) S.basis[nb++] = nw + r;
+            sh.delta = kFreeTol * cm;
+            int nb = t0;
+            double *pz = V.prow;   // scratch: the weights member 0 fixes
+            for (int r = 0; r < s; ++r) pz[r] = 0.0;
+            for (int a = 0; a < t0; ++a) pz[V.basis[a] - a * s] += V.b[a];
+            for (int r = 0; r < s; ++r) V.basis[nb++] = nw + r;
             for (int k = 1; k < n; ++k) {
-                const int tk = S.T[k + 1] - S.T[k];
+                const int tk = V.T[k + 1] - V.T[k];
                 int a = 0, r = 0;
-                double ra = S.b[S.T[k]], rc = S.y[0];
+                double ra = V.b[V.T[k]], rc = pz[0];
                 for (int step = 0; step < tk + s; ++step) {
-                    S.basis[nb++] = s * (S.T[k] + a) + r;
+                    V.basis[nb++] = s * (V.T[k] + a) + r;
                     const double fl = fmin(ra, rc);
                     ra -= fl;
                     rc -= fl;
                     if (a == tk - 1 && r == s - 1) break;
-                    if ((ra <= rc && a < tk - 1) || r == s - 1) { ++a; ra = S.b[S.T[k] + a]; }
-                    else { ++r; rc = S.y[r]; }
+                    if ((ra <= rc && a < tk - 1) || r == s - 1) { ++a; ra = V.b[V.T[k] + a]; }
+                    else { ++r; rc = pz[r]; }
                 }
             }
             sh.stat = nb == m ? kFOk : kFInternal;
-            for (int q = 0; q < nb && q < m; ++q) S.basic[S.basis[q]] = 1;
+            for (int q = 0; q < nb && q < m; ++q) V.basic[V.basis[q] >> 5] |= 1u << (V.basis[q] & 31);
+            sh.fresh = 1;
+            sh.bland = 0;
         }
         __syncthreads();
-        if (sh.stat == kFOk && !free_refactor(sh, S) && tid == 0) sh.stat = kFInternal;
+        if (sh.stat == kFOk && !free_refactor(sh, V, Binv, cost, m, n, s, nw) && tid == 0) sh.stat = kFInternal;
         __syncthreads();
         // the simplex
         const int64_t cap = o.max_pivots > 0 ? o.max_pivots : (50LL * m > 100 ? 50LL * m : 100LL);
         const int bland_after = o.bland_after > 0 ? o.bland_after : 2 * m;
+        const double delta = sh.delta;
         int64_t pivots = 0;
         int streak = 0, since = 0;
-        if (tid == 0) { sh.fresh = 1; sh.bland = 0; }
-        __syncthreads();
         while (sh.stat == kFOk) {
-            // y = c_B B^-1
-            for (int i = tid; i < m; i += kFreeThreads) {
-                double acc = 0.0;
-                for (int jj = 0; jj < m; ++jj) acc = fma(S.cost[S.basis[jj]], S.Binv[(int64_t)jj * m + i], acc);
-                S.y[i] = acc;
-            }
-            __syncthreads();
             // pricing: Dantzig (least reduced cost, lowest variable), or
             // Bland (lowest variable below -delta)
             const bool bl = sh.bland != 0;
-            const double delta = sh.delta;
             double bv = INFINITY;
             int bq = INT32_MAX;
             for (int v = tid; v < nvar; v += kFreeThreads) {
-                if (S.basic[v]) continue;
-                double dv;
-                if (v < nw) {
-                    const int k = free_member(S.T, n, s, v);
-                    const int a = v / s - S.T[k], r = v % s;
-                    const int cr = free_colrow(sumt, s, k, r);
-                    dv = S.cost[v] - S.y[S.T[k] + a] - (cr >= 0 ? S.y[cr] : 0.0);
-                } else {
-                    const int r = v - nw;
-                    double acc = 0.0;
-                    for (int k = 0; k < n; ++k) {
-                        const int cr = free_colrow(sumt, s, k, r);
-                        if (cr >= 0) acc += S.y[cr];
-                    }
-                    dv = acc;   // 0 - y . a with a = -1 on the coupling rows
-                }
+                if ((V.basic[v >> 5] >> (v & 31)) & 1u) continue;
+                const double dv = free_reduced(V, cost, v, n, s, nw, sumt);
                 if (!(dv < -delta)) continue;
                 const double key = bl ? 0.0 : dv;
                 if (key < bv || (key == bv && v < bq)) { bv = key; bq = v; }
             }
             free_argmin(sh, bv, bq);
             if (bq == INT32_MAX) {
-                if (sh.fresh) break;   // optimal with freshly factored B^-1
+                if (sh.fresh) break;   // optimal with a freshly rebuilt B^-1
                 __syncthreads();
-                if (!free_refactor(sh, S)) { if (tid == 0) sh.stat = kFInternal; __syncthreads(); break; }
+                if (!free_refactor(sh, V, Binv, cost, m, n, s, nw)) {
+                    if (tid == 0) sh.stat = kFInternal;
+                    __syncthreads();
+                    break;
+                }
                 if (tid == 0) sh.fresh = 1;
                 since = 0;
                 __syncthreads();
                 continue;
             }
             if (pivots >= cap) { if (tid == 0) sh.stat = kFPivotCap; __syncthreads(); break; }
-            // alpha = B^-1 a_q
+            // alpha = B^-1 a_q, and d_q
             const int q = bq;
-            for (int i = tid; i < m; i += kFreeThreads) {
-                double acc = 0.0;
-                if (q < nw) {
-                    const int k = free_member(S.T, n, s, q);
-                    const int a = q / s - S.T[k], r = q % s;
-                    const int cr = free_colrow(sumt, s, k, r);
-                    acc = S.Binv[(int64_t)i * m + S.T[k] + a] + (cr >= 0 ? S.Binv[(int64_t)i * m + cr] : 0.0);
-                } else {
-                    const int r = q - nw;
-                    for (int k = 0; k < n; ++k) {
-                        const int cr = free_colrow(sumt, s, k, r);
-                        if (cr >= 0) acc -= S.Binv[(int64_t)i * m + cr];
-                    }
-                }
-                S.alpha[i] = acc;
-            }
+            if (tid == 0) sh.dq = free_reduced(V, cost, q, n, s, nw, sumt);
+            free_ftran(V, Binv, q, m, n, s, nw, sumt);
             __syncthreads();
-            // ratio test: least x_B / alpha over alpha > kPivTol, then lowest variable
+            // ratio test: least x_B / alpha over alpha > kPivTol, then lowest
+            // variable; the winning thread names the row
             double tv = INFINITY;
-            int tk = INT32_MAX;
+            int tk = INT32_MAX, ti = -1;
             for (int i = tid; i < m; i += kFreeThreads) {
-                const double al = S.alpha[i];
+                const double al = V.alpha[i];
                 if (al > kPivTol) {
-                    const double r = S.xB[i] / al;
-                    const int key = S.basis[i];
-                    if (r < tv || (r == tv && key < tk)) { tv = r; tk = key; }
+                    const double r = V.xB[i] / al;
+                    const int key = V.basis[i];
+                    if (r < tv || (r == tv && key < tk)) { tv = r; tk = key; ti = i; }
                 }
             }
+            const int my_k = tk, my_i = ti;
             free_argmin(sh, tv, tk);
             if (tk == INT32_MAX) { if (tid == 0) sh.stat = kFInternal; __syncthreads(); break; }
-            // the row holding variable tk
-            if (tid == 0) {
-                int pr = -1;
-                for (int i = 0; i < m; ++i) if (S.basis[i] == tk) { pr = i; break; }
-                sh.p = pr;
-                sh.theta = tv > 0.0 ? tv : 0.0;
-            }
+            if (my_k == tk) sh.p = my_i;
             __syncthreads();
             const int pr = sh.p;
-            if (pr < 0) { __syncthreads(); if (tid == 0) sh.stat = kFInternal; __syncthreads(); break; }
-            const double theta = sh.theta, ap = S.alpha[pr];
-            for (int jj = tid; jj < m; jj += kFreeThreads) S.prow[jj] = S.Binv[(int64_t)pr * m + jj] / ap;
+            const double theta = tv > 0.0 ? tv : 0.0, ap = V.alpha[pr], dq = sh.dq;
+            for (int jj = tid; jj < m; jj += kFreeThreads) V.prow[jj] = Binv[(int64_t)pr * m + jj] / ap;
             __syncthreads();
-            for (int64_t e = tid; e < (int64_t)m * m; e += kFreeThreads) {
-                const int i = (int)(e / m), jj = (int)(e % m);
-                S.Binv[e] = i == pr ? S.prow[jj] : S.Binv[e] - S.alpha[i] * S.prow[jj];
-            }
+            free_eta(sh, V, Binv, m, pr);
             for (int i = tid; i < m; i += kFreeThreads) {
-                const double xv = i == pr ? theta : S.xB[i] - theta * S.alpha[i];
-                S.xB[i] = xv < 0.0 ? 0.0 : xv;
+                const double xv = i == pr ? theta : V.xB[i] - theta * V.alpha[i];
+                V.xB[i] = xv < 0.0 ? 0.0 : xv;
+                V.y[i] = fma(dq, V.prow[i], V.y[i]);
             }
             __syncthreads();
             if (tid == 0) {
-                S.basic[S.basis[pr]] = 0;
-                S.basic[q] = 1;
-                S.basis[pr] = q;
+                V.basic[V.basis[pr] >> 5] &= ~(1u << (V.basis[pr] & 31));
+                V.basic[q >> 5] |= 1u << (q & 31);
+                V.basis[pr] = q;
+                V.cB[pr] = cost[q];
                 sh.fresh = 0;
                 if (theta == 0.0) {
                     if (++streak >= bland_after) sh.bland = 1;
@@ -1103,7 +1202,11 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
             ++pivots;
             if (++since >= kRefactor) {
                 __syncthreads();
-                if (!free_refactor(sh, S)) { if (tid == 0) sh.stat = kFInternal; __syncthreads(); break; }
+                if (!free_refactor(sh, V, Binv, cost, m, n, s, nw)) {
+                    if (tid == 0) sh.stat = kFInternal;
+                    __syncthreads();
+                    break;
+                }
                 if (tid == 0) sh.fresh = 1;
                 since = 0;
             }
@@ -1113,67 +1216,67 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
         const int st = sh.stat;
         if (st != kFOk) {
             for (int k = tid; k < n; k += kFreeThreads)
-                if (obj_status) obj_status[S.obj[k]] = st;
+                if (obj_status) obj_status[V.obj[k]] = st;
             if (tid == 0) {
                 if (eps1) eps1[j] = __builtin_nan("");
                 if (eps3) eps3[j] = __builtin_nan("");
                 if (counts) counts[j] = 0;
                 if (cluster_status) cluster_status[j] = st;
+                if (cluster_pivots) cluster_pivots[j] = (int32_t)pivots;
             }
             __syncthreads();
             continue;
         }
         // the solution, densely
-        for (int v = tid; v < nvar; v += kFreeThreads) S.x[v] = 0.0;
+        for (int v = tid; v < nvar; v += kFreeThreads) x[v] = 0.0;
         __syncthreads();
-        for (int i = tid; i < m; i += kFreeThreads) S.x[S.basis[i]] = S.xB[i] > kFlowEps ? S.xB[i] : 0.0;
+        for (int i = tid; i < m; i += kFreeThreads) x[V.basis[i]] = V.xB[i] > kFlowEps ? V.xB[i] : 0.0;
         __syncthreads();
-        for (int r = tid; r < s; r += kFreeThreads) w_new[z0 + r] = S.x[nw + r];
-        // Step 1 value, in variable order
-        if (tid == 0) {
-            double v1 = 0.0;
-            for (int v = 0; v < nw; ++v) v1 = fma(S.cost[v], S.x[v], v1);
-            if (eps1) eps1[j] = v1;
-            if (counts) counts[j] = n;
-            if (cluster_status) cluster_status[j] = kFOk;
-        }
+        for (int r = tid; r < s; r += kFreeThreads) w_new[z0 + r] = x[nw + r];
+        // Step 1 value
+        double p1 = 0.0;
+        for (int v = tid; v < nw; v += kFreeThreads) p1 = fma(cost[v], x[v], p1);
+        const double v1 = free_sum(sh, p1);
         // Step 2: each atom to the omega-and-flow-weighted mean (Eq. (4)),
         // members and atoms in order; an atom with no mass stays
         for (int e = tid; e < s * d; e += kFreeThreads) {
-            const int r = e / d, qd = e % d;
+            const int r = e / d, qd = e - r * d;
             double num = 0.0, den = 0.0;
             for (int k = 0; k < n; ++k) {
-                const int tk2 = S.T[k + 1] - S.T[k];
-                const int64_t xa = X.off[S.obj[k]];
+                const int64_t xa = X.off[V.obj[k]];
                 double nk = 0.0, dk = 0.0;
-                for (int a = 0; a < tk2; ++a) {
-                    const double wv = S.x[s * (S.T[k] + a) + r];
-                    nk = fma(wv, ldw<TIn>(X.pts, (xa + a) * d + qd), nk);
-                    dk += wv;
+                for (int a = V.T[k]; a < V.T[k + 1]; ++a) {
+                    const double wv2 = x[s * a + r];
+                    nk = fma(wv2, ldw<TIn>(X.pts, (xa + (a - V.T[k])) * d + qd), nk);
+                    dk += wv2;
                 }
-                num = fma(S.om[k], nk, num);
-                den = fma(S.om[k], dk, den);
+                num = fma(V.om[k], nk, num);
+                den = fma(V.om[k], dk, den);
             }
             if (den > 0.0) z_new[(z0 + r) * d + qd] = num / den;
         }
         __syncthreads();
         // Step 3: the objective with the moved atoms and the same matchings
-        if (tid == 0) {
-            double v3 = 0.0;
-            for (int v = 0; v < nw; ++v) {
-                const double wv = S.x[v];
-                if (wv == 0.0) continue;
-                const int k = free_member(S.T, n, s, v);
-                const int a = v / s - S.T[k], r = v % s;
-                const int64_t xa = (X.off[S.obj[k]] + a) * d;
-                double acc = 0.0;
-                for (int qd = 0; qd < d; ++qd) {
-                    const double diff = ldw<TIn>(X.pts, xa + qd) - z_new[(z0 + r) * d + qd];
-                    acc = fma(diff, diff, acc);
-                }
-                v3 = fma(S.om[k] * wv, acc, v3);
+        double p3 = 0.0;
+        for (int v = tid; v < nw; v += kFreeThreads) {
+            const double wv2 = x[v];
+            if (wv2 == 0.0) continue;
+            const int atom = v / s, r = v - atom * s, k = V.amem[atom];
+            const int64_t xa = (X.off[V.obj[k]] + (atom - V.T[k])) * d;
+            double acc = 0.0;
+            for (int qd = 0; qd < d; ++qd) {
+                const double diff = ldw<TIn>(X.pts, xa + qd) - z_new[(z0 + r) * d + qd];
+                acc = fma(diff, diff, acc);
             }
+            p3 = fma(V.om[k] * wv2, acc, p3);
+        }
+        const double v3 = free_sum(sh, p3);
+        if (tid == 0) {
+            if (eps1) eps1[j] = v1;
             if (eps3) eps3[j] = v3;
+            if (counts) counts[j] = n;
+            if (cluster_status) cluster_status[j] = kFOk;
+            if (cluster_pivots) cluster_pivots[j] = (int32_t)pivots;
         }
         __syncthreads();
     }
@@ -1189,13 +1292,14 @@ size_t update_free_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax, int
                             int64_t *grid_out) {
     const UpdDims u = upd_dims(n, K, d, xmax, zmax);
     const FreeDims f = free_dims(max_members, xmax, zmax, d);
+    // two workgroups per CU, the slabs within 4 GiB
     int64_t grid = (int64_t)(cu_count > 0 ? cu_count : 256) * 2;
-    const int64_t fit = (int64_t)((size_t)1 << 30) / (int64_t)f.slab;
+    const int64_t fit = (int64_t)(((size_t)4 << 30) / f.slab);
     if (grid > fit) grid = fit;
     if (grid > K) grid = K;
     if (grid < 1) grid = 1;
     if (grid_out) *grid_out = grid;
-    // grouping arrays (counts, block sums, order) then the slabs
+    // grouping arrays (counts, block sums, order, keys) then the slabs
     return align256((size_t)u.entries * 8) + align256((size_t)u.sblocks * 8) + align256((size_t)(n > 0 ? n : 1) * 8) +
            align256((size_t)(n > 0 ? n : 1) * 4) + (size_t)grid * f.slab;
 }
@@ -1203,7 +1307,7 @@ size_t update_free_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax, int
 hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, int xmax, int zmax,
                               int max_members, const KOpts &o, const int32_t *labels, const double *obj_weights,
                               double *z_new, double *w_new, double *eps1, double *eps3, int32_t *counts,
-                              int32_t *obj_status, int32_t *cluster_status, void *ws) {
+                              int32_t *obj_status, int32_t *cluster_status, int32_t *cluster_pivots, void *ws) {
     const UpdDims u = upd_dims(X.n, Z.n, X.d, xmax, zmax);
     const FreeDims f = free_dims(max_members, xmax, zmax, X.d);
     int64_t grid = 1;
@@ -1232,14 +1336,26 @@ hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, 
                            perm, skey);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || Z.n == 0) return e;
-    if (X.dtype == D2_F32)
-        hipLaunchKernelGGL(k_free_solve<float>, dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream, X, Z, o, cnt,
-                           perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts, obj_status,
-                           cluster_status);
-    else
-        hipLaunchKernelGGL(k_free_solve<double>, dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream, X, Z, o, cnt,
-                           perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts, obj_status,
-                           cluster_status);
+    const size_t lds = f.lds ? f.vec : 0;
+    if (X.dtype == D2_F32) {
+        if (f.lds)
+            hipLaunchKernelGGL((k_free_solve<float, true>), dim3((unsigned)grid), dim3(kFreeThreads), lds, c.stream,
+                               X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
+                               obj_status, cluster_status, cluster_pivots);
+        else
+            hipLaunchKernelGGL((k_free_solve<float, false>), dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream,
+                               X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
+                               obj_status, cluster_status, cluster_pivots);
+    } else {
+        if (f.lds)
+            hipLaunchKernelGGL((k_free_solve<double, true>), dim3((unsigned)grid), dim3(kFreeThreads), lds, c.stream,
+                               X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
+                               obj_status, cluster_status, cluster_pivots);
+        else
+            hipLaunchKernelGGL((k_free_solve<double, false>), dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream,
+                               X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
+                               obj_status, cluster_status, cluster_pivots);
+    }
     return hipGetLastError();
 }
 

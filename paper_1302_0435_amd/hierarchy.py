@@ -9,8 +9,10 @@ once:
 
 * ``d2_assign_segmented`` labels each object among its own segment's
   centroids;
-* ``d2_centroid_update`` with object weights moves every centroid by
-  Eq. (4).
+* ``d2_centroid_update_free`` with object weights solves Alg. 1's Step 1
+  program for every cluster (the centroid weights free) and moves every
+  centroid by Eq. (4); the binary splits use ``d2_centroid_update`` (the
+  centroid weights held).
 
 Per level:
 
@@ -20,11 +22,13 @@ Per level:
    only on its own segment, so the result is the one the largest-first
    order gives.
 2. **Clustering.**  Every segment is clustered into ceil(n_mu / e) groups
-   (tau = c e, Sec. 2.5) by weighted constrained D2-clustering (Eq. (3),
-   (4) with the centroid weights held uniform).
+   (tau = c e, Sec. 2.5) by weighted D2-clustering: Alg. 1 with Eq. (3),
+   (4), the centroid weights free (``update="constrained"`` holds them at
+   their starting values instead).
 3. **Merge.**  The segments' centroids are concatenated in segment order,
    labels are offset (Eq. (5)) and inherited (Eq. (6)), and a centroid's
-   weight is the sum of its members' weights.  The hierarchy stops at the
+   weight is the sum of its members' weights.  A centroid becomes an object
+   of the next level with the atom weights its last update left.  The hierarchy stops at the
    first level with at most k centroids.
 
 The random choices (initial centroids) consume a caller-given stream of
@@ -47,7 +51,8 @@ from typing import Optional
 import numpy as np
 import torch
 
-from .api import DeviceSet, Handle, Opts, d2_assign_segmented, d2_centroid_update
+from .api import (DeviceSet, Handle, Opts, d2_assign_segmented, d2_centroid_update,
+                  d2_centroid_update_free)
 
 
 class _Stream:
@@ -64,25 +69,31 @@ class _Stream:
         return float(self._u[self._k - 1])
 
 
-def _gather(G: DeviceSet, g_off: np.ndarray, objs) -> tuple:
-    """A centroid set made of the atoms of objects `objs` of G (in that
-    order) with uniform weights; returns (DeviceSet, host offsets)."""
+def _gather(G: DeviceSet, g_off: np.ndarray, objs, keep_weights: bool = False) -> tuple:
+    """A set made of the atoms of objects `objs` of G (in that order), with
+    uniform weights or, with `keep_weights`, G's own; returns (DeviceSet,
+    host offsets)."""
     objs = np.asarray(objs, dtype=np.int64)
     sizes = g_off[1:][objs] - g_off[:-1][objs]
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     # atom rows of the picked objects, object after object
     rows = np.repeat(g_off[:-1][objs] - off[:-1], sizes) + np.arange(int(off[-1]), dtype=np.int64)
-    w = np.repeat(1.0 / np.maximum(sizes, 1), sizes)
     dev = G.points.device
-    pts = G.points.index_select(0, torch.as_tensor(rows, device=dev))
-    Z = DeviceSet(torch.as_tensor(off, device=dev), pts.contiguous(),
-                  torch.as_tensor(w, device=dev), int(sizes.max()) if len(objs) else 1)
+    rows_d = torch.as_tensor(rows, device=dev)
+    pts = G.points.index_select(0, rows_d)
+    if keep_weights:
+        w = G.weights.to(pts.dtype).index_select(0, rows_d)
+    else:
+        w = torch.as_tensor(np.repeat(1.0 / np.maximum(sizes, 1), sizes), device=dev)
+    Z = DeviceSet(torch.as_tensor(off, device=dev), pts.contiguous(), w.contiguous(),
+                  int(sizes.max()) if len(objs) else 1)
     return Z, off
 
 
-def _count(stats, G, g_off, z_off, segments, starts, rounds, passes):
+def _count(stats, G, g_off, z_off, segments, starts, rounds, passes, free):
     """Adds the LPs this clustering solves, and their pivot-free FP64 work
-    (3 t s d + 3 t s each), to `stats`."""
+    (3 t s d + 3 t s per member and centroid), to `stats`.  A free update
+    solves one program per cluster, a constrained one one per member."""
     t = (g_off[1:] - g_off[:-1]).astype(np.float64)
     s = (z_off[1:] - z_off[:-1]).astype(np.float64)
     d = G.d
@@ -97,7 +108,7 @@ def _count(stats, G, g_off, z_off, segments, starts, rounds, passes):
         "lps_label": float(((rounds + 1) * n_seg * k_seg).sum()),
         "flops_label": float(((rounds + 1) * t_seg * s_sum * (3 * d + 3)).sum()),
         # update: every member against one centroid (bounded by the largest)
-        "lps_update": float((rounds * passes * n_seg).sum()),
+        "lps_update": float((rounds * passes * (k_seg if free else n_seg)).sum()),
         "flops_update": float((rounds * passes * t_seg * s_max * (3 * d + 3)).sum()),
     }
     add["lps"] = add["lps_label"] + add["lps_update"]
@@ -106,14 +117,16 @@ def _count(stats, G, g_off, z_off, segments, starts, rounds, passes):
         stats[key] = stats.get(key, 0.0) + v
 
 
-def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts, stats=None):
-    """Weighted constrained D2-clustering of every segment at once; segment
-    mu starts from its objects starts[mu].  Returns (centroids, their host
-    offsets, the centroid range of each segment, labels over G)."""
+def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts, stats=None,
+                      free=False):
+    """Weighted D2-clustering of every segment at once, the centroid weights
+    free (Alg. 1) when `free`, else held; segment mu starts from its objects
+    starts[mu].  Returns (centroids, their host offsets, the centroid range
+    of each segment, labels over G)."""
     order = [o for s in starts for o in s]
     Z, z_off = _gather(G, g_off, order)
     if stats is not None:
-        _count(stats, G, g_off, z_off, segments, starts, rounds, passes)
+        _count(stats, G, g_off, z_off, segments, starts, rounds, passes, free)
     zseg = np.concatenate([[0], np.cumsum([len(s) for s in starts])]).astype(np.int64)
     seg = np.full(G.n, -1, dtype=np.int32)
     if segments:
@@ -122,24 +135,37 @@ def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts
     dev = G.points.device
     seg_d = torch.as_tensor(seg, device=dev)
     zseg_d = torch.as_tensor(zseg, device=dev)
+    worst = torch.zeros((), dtype=torch.int32, device=dev)
     for _ in range(rounds):
         labels, _, _ = d2_assign_segmented(h, G, Z, seg_d, zseg_d, opts)
         for _ in range(passes):
-            z_new = d2_centroid_update(h, G, Z, labels, opts, weights=omega)[0]
-            Z = Z.with_points(z_new)
+            if free:
+                z_new, w_new, _, _, _, _, cst = d2_centroid_update_free(h, G, Z, labels, opts,
+                                                                        weights=omega)
+                if cst.numel():
+                    worst = torch.maximum(worst, cst.max())
+                Z = DeviceSet(Z.offsets, z_new, w_new, Z.max_support)
+            else:
+                z_new = d2_centroid_update(h, G, Z, labels, opts, weights=omega)[0]
+                Z = Z.with_points(z_new)
     labels, _, _ = d2_assign_segmented(h, G, Z, seg_d, zseg_d, opts)
+    if int(worst.item()) != 0:
+        raise RuntimeError(f"a cluster's centroid program failed (status {int(worst.item())})")
     return Z, z_off, zseg, labels.cpu().numpy()
 
 
 def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
                     rounds: int = 3, passes: int = 2, opts: Optional[Opts] = None,
-                    max_levels: int = 16, stats: Optional[dict] = None):
+                    max_levels: int = 16, stats: Optional[dict] = None, update: str = "free"):
     """Alg. 3 on one GPU.  Returns (centroids as a DeviceSet, labels of X as
     a host int32 array, their weights, per-level statistics).  `stats`, when
     given, receives the count of LPs solved ("lps") and their pivot-free
-    FP64 work ("flops"; the update's is bounded by the largest centroid)."""
+    FP64 work ("flops"; the update's is bounded by the largest centroid).
+    ``update``: "free" (Alg. 1 in Step 2, the paper's) or "constrained"."""
     if tau < 2 or e < 1 or k < 1:
         raise ValueError("need tau >= 2, e >= 1 and k >= 1")
+    if update not in ("free", "constrained"):
+        raise ValueError("update is 'free' or 'constrained'")
     if X.n < 1:
         raise ValueError("no objects to cluster")
     opts = opts or Opts()
@@ -184,7 +210,7 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
                 pos[q], pos[r] = pos[r], pos[q]
             starts.append([int(S[p]) for p in pos[:math.ceil(S.size / e)]])
         Z, z_off, zseg, labels = _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes,
-                                                   opts, stats)
+                                                   opts, stats, free=update == "free")
         if labels.min() < 0:
             raise RuntimeError("an object's transport problem failed; check its weights and points")
         # Step 3: merge (Eq. (5)), weights, inheritance (Eq. (6))
@@ -199,7 +225,7 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
         C = level_label[C]
         levels.append({"objects": G.n, "segments": len(segments), "centroids": len(kept),
                        "max_segment": int(max(S.size for S in segments))})
-        G, g_off = _gather(Z, z_off, kept)   # the same uniform weights the centroids carry
+        G, g_off = _gather(Z, z_off, kept, keep_weights=True)
         omega = torch.as_tensor(new_w, device=G.points.device)
         if len(kept) <= k or len(kept) == levels[-1]["objects"]:
             break

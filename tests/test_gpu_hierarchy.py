@@ -5,10 +5,12 @@ oracle on the same seeded inputs:
   the pair rule, statuses equal;
 * the weighted centroid update (Eq. (4)): moved atoms within 1e-10 of the
   coordinate scale, objectives at the summed pair rule;
-* the hierarchical driver (hierarchical_d2) against the oracle's: the same
-  segments and centroid counts per level, the same final labels and
-  weights, centroids within 1e-10 of the coordinate scale.  Both consume
-  the same seeded stream of uniforms.
+* the hierarchical driver (hierarchical_d2) against the oracle's, with
+  Alg. 1's free-weight update in Step 2 (the paper's) and with the
+  constrained one: the same segments and centroid counts per level, the
+  same final labels and object weights, centroid atoms within 1e-10 of the
+  coordinate scale and atom weights within 1e-9.  Both consume the same
+  seeded stream of uniforms.
 """
 import numpy as np
 import pytest
@@ -99,8 +101,9 @@ def blobs(rng, n_per, centres, spread=0.05):
     return synth.from_bags(bags)
 
 
+@pytest.mark.parametrize("update", ["free", "constrained"])
 @pytest.mark.parametrize("case", ["blobs", "config1_mixture"])
-def test_hierarchy_matches_oracle(d2, h, case):
+def test_hierarchy_matches_oracle(d2, h, case, update):
     rng = np.random.default_rng(63)
     if case == "blobs":
         centres = [np.array([0.0, 0.0]), np.array([50.0, 0.0]), np.array([0.0, 50.0]),
@@ -112,15 +115,17 @@ def test_hierarchy_matches_oracle(d2, h, case):
         X = synth.make_data(1, n=300)
         tau, e, k = 40, 4, 6
     U = synth.rng_for(1, synth.STREAM_SAMPLE, 64).random(20000)
-    Zg, lab_g, w_g, lv_g = d2.hierarchical_d2(h, d2.DeviceSet.from_ragged(X, DEV), tau, e, k, U)
+    Zg, lab_g, w_g, lv_g = d2.hierarchical_d2(h, d2.DeviceSet.from_ragged(X, DEV), tau, e, k, U,
+                                              update=update)
     torch.cuda.synchronize()
-    (off, pts, wts), lab_o, lv_o, w_o = o_hierarchy(X, tau, e, k, U)
+    (off, pts, wts), lab_o, lv_o, w_o = o_hierarchy(X, tau, e, k, U, update=update)
     assert lv_g == lv_o
     np.testing.assert_array_equal(lab_g, lab_o)
     np.testing.assert_array_equal(w_g, w_o)
     np.testing.assert_array_equal(Zg.offsets.cpu().numpy(), off)
     scale = float(np.abs(X.points).max())
     assert np.abs(Zg.points.cpu().numpy() - pts).max() <= REL * scale
+    assert np.abs(Zg.weights.cpu().numpy() - wts).max() <= 1e-9
     assert lv_g[-1]["centroids"] <= k
     assert all(lv["max_segment"] <= tau for lv in lv_g)
 
