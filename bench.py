@@ -36,15 +36,14 @@ if ROOT not in sys.path:
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 # Committed rocprofv3 summaries of each workload's dominant kernel, keyed by
-# (configuration, cost mode); the MFMA cost kernel of the BF16 mode has one
-# of its own.
+# (configuration, cost mode).  The BF16 mode's MFMA cost tiles are computed
+# inside its labelling kernel.
 PROFILES = {
     (2, "f64"): "k_assign_cls0_f32_c2_100k_x512.txt",
     (3, "f64"): "k_assign_cls1_f32_c3_50k_x256_d128.txt",
-    (3, "bf16"): "k_assign_cls1_f32_c3_bf16_tiles.txt",
+    (3, "bf16"): "k_assign_bf16_f32_c3_50k_x256_d128.txt",
     (4, "f64"): "k_pairwise_q_cls2_f64_c4_4096.txt",
 }
-MFMA_PROFILES = {(3, "bf16"): "k_cost_bf16_assign_f32_c3_50k_x256_d128.txt"}
 # the centroid update's dominant kernel (--op update), keyed by configuration
 UPDATE_PROFILES = {2: "k_upd_solve_cls0_f32_c2_100k_x512.txt"}
 # the given-cost LP kernel (--op cost), configuration 2 shapes
@@ -129,11 +128,6 @@ def profile_counters(cfg: int, cost: str, op: str = "assign"):
            "valu_issue_busy": float(kv["valu_issue_busy_fraction"]),
            "lds_util_percent": float(kv["lds_util_percent"]),
            "profile_avg_ms": float(kv["avg_duration_ns"]) / 1e6}
-    mk = _read_profile(MFMA_PROFILES.get((cfg, cost), ""))
-    if mk and mk.get("kernel_source_sha256_16") == kernel_sha():
-        out["mfma"] = {"kernel": mk["_kernel"], "bf16_tflops": float(mk["mfma_bf16_tflops"]),
-                       "peak_tflops": 2500.0, "mfma_util_percent": float(mk["mfma_util_percent"]),
-                       "avg_ms": float(mk["avg_duration_ns"]) / 1e6}
     return out
 
 
@@ -981,7 +975,8 @@ def main(argv=None) -> int:
                     help="starting basis (auto: the library default, least cost)")
     ap.add_argument("--schedule", choices=["auto", "plain"], default="auto")
     ap.add_argument("--cost", choices=["f64", "bf16"], default="f64",
-                    help="ground-cost arithmetic (bf16: MFMA tiles, supports <= 32)")
+                    help="ground-cost arithmetic (bf16: MFMA cost tiles fused into the "
+                         "labelling kernel, supports <= 32)")
     ap.add_argument("--tune", action="store_true", help="autotune the pairwise schedule first")
     ap.add_argument("--op", choices=["assign", "update", "cost", "multi", "hierarchy", "large"],
                     default="assign",
@@ -1094,8 +1089,6 @@ def main(argv=None) -> int:
         },
         "failed_pairs_or_rows": w.failed(),
     }
-    if prof and "mfma" in prof:
-        out["roofline"]["mfma_cost_kernel"] = prof["mfma"]
     if args.n is None and args.op == "assign":
         out["end_to_end_with_copies"] = w.end_to_end()
         plain = w.plain_baseline()

@@ -240,8 +240,10 @@ d2_status d2_emd_cost_batch(d2_handle *h, int64_t nprob, const int64_t *row_offs
  * for every object i of X, D^2 to every centroid j of Z, then
  * labels[i] = argmin_j (ties: lowest j), best[i] = the minimum.  all[n][K]
  * (nullable) receives every D^2; row_status[n] (nullable) the worst pair
- * status of the row.  With D2_COST_BF16_MFMA the workspace also holds the
- * cost tiles of a block of rows (4 KiB per pair, at most 1 GiB).  When a
+ * status of the row.  With D2_COST_BF16_MFMA each wavefront computes the
+ * cost tiles of the two pairs it solves with MFMA and keeps them in
+ * registers: no tile is written to memory and none enters the workspace.
+ * When a
  * declared max_support exceeds D2_MAX_SUPPORT (up to D2_MAX_SUPPORT_LARGE),
  * every pair runs on the workgroup simplex of d2_emd_batch and the
  * workspace also holds the n x K distance matrix and its statuses; such a
@@ -258,8 +260,8 @@ d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opt
  * workspace d2_assign would take (d2_workspace_bytes(h, 2, X, Z, 0, opts))
  * lives in a fixed device array of D2_NOALLOC_SCRATCH_BYTES per GPU instead;
  * a call needing more returns D2_ESCRATCH and enqueues nothing (C2-like
- * labelling of 100,000 objects needs under 1 MiB; the BF16 cost mode and
- * supports above D2_MAX_SUPPORT are beyond it).  The call performs no
+ * labelling of 100,000 objects needs under 1 MiB; supports above
+ * D2_MAX_SUPPORT are beyond it).  The call performs no
  * hipMalloc/hipFree and no allocating library call.  Every call on one GPU
  * shares that GPU's array: calls whose stream work overlaps on one GPU
  * race (serialise them, e.g. on one stream).  Kernels clear what must start

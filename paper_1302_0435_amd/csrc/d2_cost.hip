@@ -57,7 +57,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_
         // uniform over the group; the declared bounds size the caller's plan
         if (t >= 1 && s >= 1 && t <= max_rows && s <= max_cols)
             r = solve_pair<G, GS, LT, double, START, TileT, true>(mem[g], tiles[g], N, pv, 1, o, l, gbase,
-                                                                  nullptr, cost + moff[k], grs, gcs);
+                                                                  cost + moff[k], grs, gcs);
         if (r.status == kOk && plan)
             write_certificate<G, GS, LT>(mem[g], N, pv, l, plan + plan_off[k], nullptr);
         if (l == 0) {

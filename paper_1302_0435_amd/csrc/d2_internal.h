@@ -54,8 +54,7 @@ struct AssignPlan {
     int single_class;
     int zmax;
     int64_t chunks, per_chunk;
-    int64_t bf16_rows;   // rows per block of BF16 cost tiles
-    size_t part_bytes, sort_bytes, tile_bytes, ws_bytes;
+    size_t part_bytes, sort_bytes, frag_bytes, ws_bytes;
 };
 AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_count, int schedule,
                        int cost_mode);

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_
     KSet X, KSet Z, KOpts o, const int64_t *perm, const int64_t *bounds, int cls_lo_idx,
     int64_t row_begin, int64_t row_end, int64_t chunks, int64_t per_chunk, int32_t *labels,
     double *best, double *all, int32_t *row_status, double *ws_best, int32_t *ws_label,
-    int32_t *ws_status, const float *tiles) {
+    int32_t *ws_status) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
     __shared__ GroupMem<G, GS> mem[NG];
@@ -132,8 +132,7 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_
         for (int64_t j = j0 + g; j < j1; j += NG) {
             NodeState<G, GS, LT> N;
             PairView pv = orient(X, i, Z, j, (int)sizeof(TIn));
-            const float *ct = tiles ? tiles + ((r - row_begin) * K + j) * 1024 : nullptr;
-            SolveOut res = solve_pair<G, GS, LT, TIn, START>(mem[g], ltile[g], N, pv, X.d, o, l, gbase, ct);
+            SolveOut res = solve_pair<G, GS, LT, TIn, START>(mem[g], ltile[g], N, pv, X.d, o, l, gbase);
             if (res.status != kOk) {
                 worst = res.status > worst ? res.status : worst;
                 res.d2 = __builtin_nan("");
@@ -373,7 +372,6 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kBfSteps = 16;      // MFMA k-steps (8 coordinates each) held in registers
-constexpr int kBfCentroids = 8;   // centroids per wavefront item, sharing the row's operands
 
 __device__ __forceinline__ unsigned short f32_to_bf16(float f) {  // round to nearest even
     unsigned int u = __float_as_uint(f);
@@ -460,53 +458,190 @@ __device__ __forceinline__ void bf16_epilogue(const f32x16 &acc, float rowN, flo
     wsync();
 }
 
-// Tiles of rows [r0, r1) against every centroid, oriented like the solver
-// (rows = the larger support, ties: the object), row-major 32 x 32 FP32 at
-// tiles + ((r - r0) K + j) 1024.  One wavefront per (row, block of
-// kBfCentroids centroids); with d <= 8 kBfSteps the row's fragments and
-// norms stay in registers across the block.
+// The centroids as BF16 MFMA fragments, once per call (d <= 8 kBfSteps):
+// fragment m of lane l of centroid j at zf[(j kBfSteps + m) 64 + l] (the
+// layout bf16_frags forms), and the squared norms of its atoms (from the
+// same rounded values) at zn[32 j + atom].  One wavefront per centroid.
 template <typename TIn>
-__global__ __launch_bounds__(256) void k_cost_bf16_assign(KSet X, KSet Z, int64_t r0, int64_t r1,
-                                                          float *tiles) {
-    __shared__ float lds[4][32];
-    const int w = threadIdx.x >> 6;
-    const int d = X.d;
-    const int64_t K = Z.n, nblk = (K + kBfCentroids - 1) / kBfCentroids, items = (r1 - r0) * nblk;
-    const bool cache = d <= 8 * kBfSteps;
-    for (int64_t it = (int64_t)blockIdx.x * 4 + w; it < items; it += (int64_t)gridDim.x * 4) {
-        const int64_t i = r0 + it / nblk, j0 = (it % nblk) * kBfCentroids;
-        const int64_t j1 = j0 + kBfCentroids < K ? j0 + kBfCentroids : K;
-        const int64_t a0 = X.off[i];
-        const int t = (int)(X.off[i + 1] - a0);
-        if (t < 1 || t > 32) continue;
-        const TIn *px = (const TIn *)X.pts + a0 * d;
-        bf16x4 fx[kBfSteps];
-        float nx = 0.f;
-        if (cache) {
-            bf16_frags<TIn>(px, t, d, 0, fx, nx);
-            nx += __shfl_xor(nx, 32, 64);
-        }
-        for (int64_t j = j0; j < j1; ++j) {
-            const int64_t b0 = Z.off[j];
-            const int s = (int)(Z.off[j + 1] - b0);
-            if (s < 1 || s > 32) continue;
-            const TIn *pz = (const TIn *)Z.pts + b0 * d;
-            const bool sw = t < s;
-            f32x16 acc = {};
-            float ny = 0.f, nxj = 0.f;
-            for (int kc = 0; kc < d; kc += 8 * kBfSteps) {
-                if (!cache) bf16_frags<TIn>(px, t, d, kc, fx, nxj);
-                bf16x4 fz[kBfSteps];
-                bf16_frags<TIn>(pz, s, d, kc, fz, ny);
-                const int steps = (d - kc + 7) / 8;
-                if (sw) bf16_mma(fz, fx, steps, acc);
-                else bf16_mma(fx, fz, steps, acc);
+__global__ __launch_bounds__(256) void k_bf16_centroid_frags(KSet Z, bf16x4 *zf, float *zn) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); j < Z.n; j += (int64_t)gridDim.x * 4) {
+        const int64_t b0 = Z.off[j];
+        const int s = (int)(Z.off[j + 1] - b0);
+        bf16x4 f[kBfSteps];
+        float nz = 0.f;
+        bf16_frags<TIn>((const TIn *)Z.pts + b0 * Z.d, s >= 1 && s <= 32 ? s : 0, Z.d, 0, f, nz);
+#pragma unroll
+        for (int m = 0; m < kBfSteps; ++m) zf[(j * kBfSteps + m) * 64 + lane] = f[m];
+        nz += __shfl_xor(nz, 32, 64);
+        if (lane < 32) zn[j * 32 + lane] = nz;
+    }
+}
+
+// One pair's cost tile, transposed: A = the column atoms, B = the row atoms,
+// so accumulator j of lane l holds row (l mod 32), column 8 (j div 4) +
+// 4 (l div 32) + (j mod 4).  With CACHED (d <= 8 kBfSteps) the object's
+// fragments and atom norms come from LDS (xf, xn) and the centroid's from
+// the per-call fragments (zf, zn); otherwise both sides are formed here.
+// `rown` receives the squared norm of row atom (l mod 32); the column norms
+// go to cn[0..32).  All 64 lanes take part.
+template <typename TIn, bool CACHED>
+__device__ __forceinline__ void bf16_tile_rows(const PairView &pv, int d, const bf16x4 (*xf)[64],
+                                               const float *xn, const bf16x4 *zf, const float *zn,
+                                               f32x16 &acc, float &rown, float *cn) {
+    const int lane = threadIdx.x & 63;
+    if constexpr (CACHED) {
+        // X is the column side when the pair is swapped (rows = the centroid)
+        const bool xcol = pv.swapped;
+        const int steps = (d + 7) / 8;
+#pragma unroll
+        for (int m = 0; m < kBfSteps; ++m) {
+            if (m < steps) {
+                const bf16x4 fz = zf[m * 64 + lane], fx = xf[m][lane];
+                acc = xcol ? __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(fx, fz, acc, 0, 0, 0)
+                           : __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(fz, fx, acc, 0, 0, 0);
             }
-            ny += __shfl_xor(ny, 32, 64);
-            if (!cache) nxj += __shfl_xor(nxj, 32, 64);
-            const float nxv = cache ? nx : nxj;
-            bf16_epilogue(acc, sw ? ny : nxv, sw ? nxv : ny, tiles + ((i - r0) * K + j) * 1024, lds[w]);
         }
+        const float nx = xn[lane & 31], nz = zn[lane & 31];
+        if (lane < 32) cn[lane] = xcol ? nx : nz;
+        rown = xcol ? nz : nx;
+    } else {
+        float ncol = 0.f, nrow = 0.f;
+        for (int kc = 0; kc < d; kc += 8 * kBfSteps) {
+            bf16x4 fc[kBfSteps], fr[kBfSteps];
+            bf16_frags<TIn>((const TIn *)pv.xc, pv.S, d, kc, fc, ncol);
+            bf16_frags<TIn>((const TIn *)pv.xr, pv.T, d, kc, fr, nrow);
+            bf16_mma(fc, fr, (d - kc + 7) / 8, acc);
+        }
+        ncol += __shfl_xor(ncol, 32, 64);
+        nrow += __shfl_xor(nrow, 32, 64);
+        if (lane < 32) cn[lane] = ncol;
+        rown = nrow;
+    }
+}
+
+// BF16 cost mode: the labelling of k_assign in the 32-lane shape, each
+// wavefront computing the cost tiles of its two pairs with MFMA right
+// before solving them, so no tile leaves the chip.  The row's object is
+// rounded to BF16 fragments once per item, into LDS, and the centroids'
+// fragments were formed once per call (k_bf16_centroid_frags) when d <= 8
+// kBfSteps.  Wave w takes
+// centroids j0 + 2w (its first group) and j0 + 2w + 1 (its second), then
+// steps by the workgroup's group count.  The tiles come out transposed
+// (bf16_tile_rows): lane l holds half of row (l mod 32) of pair (l div 32)
+// and half of the same row of the other pair, so one exchange with lane
+// l ^ 32 gives every lane its whole cost row, written straight into the
+// solver's register row: C = max(0, |row|^2 + |col|^2 - 2 acc).
+template <typename TIn, int START, bool CACHED>
+__global__ __launch_bounds__(ShapeCfg<1>::threads, ShapeCfg<1>::occ) void k_assign_bf16(
+    KSet X, KSet Z, KOpts o, int64_t chunks, int64_t per_chunk, int32_t *labels, double *best, double *all,
+    int32_t *row_status, double *ws_best, int32_t *ws_label, int32_t *ws_status, const bf16x4 *zfrag,
+    const float *znorm) {
+    constexpr int G = ShapeCfg<1>::G, GS = ShapeCfg<1>::GS, NG = ShapeCfg<1>::groups;
+    constexpr bool LT = ShapeCfg<1>::LT;
+    static_assert(G == 32 && GS == 32 && !LT, "two pairs of up to 32 atoms per wavefront");
+    __shared__ GroupMem<G, GS> mem[NG];
+    __shared__ TileOf<1, START> ltile[NG];
+    __shared__ float cnorm[NG][32];
+    __shared__ bf16x4 xfrag[kBfSteps][64];
+    __shared__ float xnorm[32];
+    __shared__ double red_v[NG];
+    __shared__ int red_i[NG], red_s[NG];
+    const int tid = threadIdx.x;
+    const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
+    const int w = tid >> 6, h = (tid >> 5) & 1;
+    const int d = X.d;
+    const int64_t total = X.n * chunks;
+    const int64_t K = Z.n;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int64_t i = item / chunks, ch = item % chunks;
+        const int64_t j0 = ch * per_chunk;
+        const int64_t j1 = j0 + per_chunk < K ? j0 + per_chunk : K;
+        const int64_t a0 = X.off[i];
+        const int tx = (int)(X.off[i + 1] - a0);
+        const bool xc = CACHED && tx >= 1 && tx <= 32;
+        if (xc && w == 0) {
+            bf16x4 f[kBfSteps];
+            float nx = 0.f;
+            bf16_frags<TIn>((const TIn *)X.pts + a0 * d, tx, d, 0, f, nx);
+#pragma unroll
+            for (int m = 0; m < kBfSteps; ++m) xfrag[m][tid] = f[m];
+            nx += __shfl_xor(nx, 32, 64);
+            if (tid < 32) xnorm[tid] = nx;
+        }
+        __syncthreads();
+        double bv = INFINITY;
+        int bj = kNoKey, worst = kOk;
+        for (int64_t jp = j0 + 2 * w; jp < j1; jp += NG) {   // wave-uniform
+            const bool hasB = jp + 1 < j1;
+            const PairView pa = orient(X, i, Z, jp, (int)sizeof(TIn));
+            const PairView pb = hasB ? orient(X, i, Z, jp + 1, (int)sizeof(TIn)) : pa;
+            const bool okA = pa.T >= 1 && pa.S >= 1 && pa.T <= 32 && pa.S <= 32;
+            const bool okB = hasB && pb.T >= 1 && pb.S >= 1 && pb.T <= 32 && pb.S <= 32;
+            f32x16 accA = {}, accB = {};
+            float rnA = 0.f, rnB = 0.f;
+            // (with CACHED, a pair is only solved when the object's fragments are in LDS)
+            if (okA && (!CACHED || xc))
+                bf16_tile_rows<TIn, CACHED>(pa, d, xfrag, xnorm, zfrag + jp * kBfSteps * 64, znorm + jp * 32,
+                                            accA, rnA, cnorm[2 * w]);
+            if (okB && (!CACHED || xc))
+                bf16_tile_rows<TIn, CACHED>(pb, d, xfrag, xnorm, zfrag + (jp + 1) * kBfSteps * 64,
+                                            znorm + (jp + 1) * 32, accB, rnB, cnorm[2 * w + 1]);
+            wsync();
+            // lane l keeps its own pair's half row; the other half comes from
+            // lane l ^ 32, which holds it for the pair it does not solve
+            NodeState<G, GS, LT> N;
+            const PairView pv = h ? pb : pa;
+            const bool hasR = l < pv.T;
+            const float rn = h ? rnB : rnA;
+            const float *cn = cnorm[g];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const float own = h ? accB[q] : accA[q];
+                const float got = __shfl_xor(h ? accA[q] : accB[q], 32, 64);
+                const float lo = h ? got : own;   // column 8 (q div 4) + (q mod 4)
+                const float hi = h ? own : got;   // column 8 (q div 4) + 4 + (q mod 4)
+                const int c0 = 8 * (q >> 2) + (q & 3), c1 = c0 + 4;
+                const float v0 = (rn + cn[c0]) - 2.f * lo, v1 = (rn + cn[c1]) - 2.f * hi;
+                // NaN passes through the clamp, to be flagged by the solver
+                N.crow[c0] = (hasR && c0 < pv.S) ? (double)(v0 < 0.f ? 0.f : v0) : INFINITY;
+                N.crow[c1] = (hasR && c1 < pv.S) ? (double)(v1 < 0.f ? 0.f : v1) : INFINITY;
+            }
+            wsync();   // the column norms are read before the next round writes them
+            const int64_t j = jp + h;
+            if (h == 0 || hasB) {
+                SolveOut res = solve_pair<G, GS, LT, TIn, START>(mem[g], ltile[g], N, pv, d, o, l, gbase, nullptr,
+                                                                 0, 0, true);
+                if (res.status != kOk) {
+                    worst = res.status > worst ? res.status : worst;
+                    res.d2 = __builtin_nan("");
+                } else if (res.d2 < bv || (res.d2 == bv && (int)j < bj)) {
+                    bv = res.d2;
+                    bj = (int)j;
+                }
+                if (all && l == 0) all[i * K + j] = res.d2;
+            }
+        }
+        if (l == 0) { red_v[g] = bv; red_i[g] = bj; red_s[g] = worst; }
+        __syncthreads();
+        if (tid == 0) {
+            double v = INFINITY;
+            int jj = kNoKey, st = kOk;
+            for (int q = 0; q < NG; ++q) {
+                if (red_v[q] < v || (red_v[q] == v && red_i[q] < jj)) { v = red_v[q]; jj = red_i[q]; }
+                st = red_s[q] > st ? red_s[q] : st;
+            }
+            if (chunks == 1) {
+                labels[i] = st == kOk ? jj : -1;
+                best[i] = st == kOk ? v : __builtin_nan("");
+                if (row_status) row_status[i] = st;
+            } else {
+                ws_best[i * chunks + ch] = v;
+                ws_label[i * chunks + ch] = jj;
+                ws_status[i * chunks + ch] = st;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -593,25 +728,12 @@ AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_
     // classes the rows can fall in: rows of support 1..xmax against zmax
     const int cmin = class_for(1, zmax), cmax = class_for(xmax, zmax);
     p.binned = !p.plain && !p.bf16 && cmin != cmax;
-    p.single_class = p.plain ? 3 : cmax;
+    // BF16 mode: the fused kernel in the 32-lane shape (supports <= 32)
+    p.single_class = p.plain ? 3 : (p.bf16 ? 1 : cmax);
     const int NG = class_groups(p.single_class);
     const int64_t K = Z.n > 0 ? Z.n : 1;
     const int64_t target = (int64_t)(cu_count > 0 ? cu_count : 256) * 8;
-    // BF16 mode: cost tiles (32 x 32 FP32 per pair) for a block of rows at
-    // a time, at most 1 GiB of them; the simplex launch runs per block.
-    p.bf16_rows = 0;
-    p.tile_bytes = 0;
-    if (p.bf16) {
-        const int64_t per_row = K * 1024 * (int64_t)sizeof(float);
-        int64_t rows = (1LL << 30) / per_row;
-        if (rows < 1) rows = 1;
-        if (rows > X.n) rows = X.n > 0 ? X.n : 1;
-        p.bf16_rows = rows;
-        p.tile_bytes = (size_t)rows * per_row;
-    }
-    const int64_t rows_per_launch = p.bf16 ? p.bf16_rows : X.n;
-    int64_t chunks = rows_per_launch > 0 ? (2 * target + rows_per_launch - 1) / rows_per_launch : 1;
-    if (!p.bf16) chunks = X.n > 0 ? (target + X.n - 1) / X.n : 1;
+    int64_t chunks = X.n > 0 ? (target + X.n - 1) / X.n : 1;
     // XCD-aware split.  Workgroups are dealt to the 8 XCDs round-robin by
     // index, and item = row * chunks + chunk, so with a multiple of 8 chunks
     // every workgroup of one XCD works on the same eighth of the centroids,
@@ -620,7 +742,7 @@ AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_
     // d) are more than a quarter of one L2.
     const size_t zbytes = (size_t)K * (size_t)(zmax > 0 ? zmax : 1) * (size_t)(Z.d > 0 ? Z.d : 1) *
                           (Z.dtype == D2_F32 ? 4u : 8u);
-    if (!p.bf16 && zbytes > kXcdSplitBytes) chunks = ((chunks + kXcds - 1) / kXcds) * kXcds;
+    if (zbytes > kXcdSplitBytes) chunks = ((chunks + kXcds - 1) / kXcds) * kXcds;
     const int64_t max_chunks = (K + NG - 1) / NG;
     if (chunks > max_chunks) chunks = max_chunks;
     if (chunks < 1) chunks = 1;
@@ -628,7 +750,9 @@ AssignPlan plan_assign(const KSet &X, const KSet &Z, int xmax, int zmax, int cu_
     p.per_chunk = (K + chunks - 1) / chunks;
     p.part_bytes = chunks > 1 ? (size_t)X.n * chunks * (sizeof(double) + 2 * sizeof(int32_t)) : 0;
     p.sort_bytes = p.binned ? sort_ws_bytes(X.n) : 0;
-    p.ws_bytes = p.part_bytes + p.sort_bytes + p.tile_bytes;
+    // BF16 mode: the centroids as MFMA fragments (8 KiB each) and atom norms
+    p.frag_bytes = (p.bf16 && Z.d <= 8 * kBfSteps) ? (size_t)K * (kBfSteps * 64 * 8 + 32 * 4) : 0;
+    p.ws_bytes = p.part_bytes + p.sort_bytes + p.frag_bytes;
     p.zmax = zmax;
     return p;
 }
@@ -644,12 +768,28 @@ struct AssignRun {
     int cls_idx;
     int64_t grid;
     int64_t row_begin, row_end;
-    const float *tiles;
+    const bf16x4 *zfrag;
+    const float *znorm;
     template <int C, typename TIn, int V>
     hipError_t run() {
-        hipLaunchKernelGGL((k_assign<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
-                           c.stream, X, Z, o, perm, bounds, cls_idx, row_begin, row_end, p.chunks,
-                           p.per_chunk, labels, best, all, row_status, wb, wl, wsn, tiles);
+        if (p.bf16) {
+            if constexpr (C == 1) {
+                if (zfrag)
+                    hipLaunchKernelGGL((k_assign_bf16<TIn, V, true>), dim3((unsigned)grid),
+                                       dim3(ShapeCfg<1>::threads), 0, c.stream, X, Z, o, p.chunks, p.per_chunk,
+                                       labels, best, all, row_status, wb, wl, wsn, zfrag, znorm);
+                else
+                    hipLaunchKernelGGL((k_assign_bf16<TIn, V, false>), dim3((unsigned)grid),
+                                       dim3(ShapeCfg<1>::threads), 0, c.stream, X, Z, o, p.chunks, p.per_chunk,
+                                       labels, best, all, row_status, wb, wl, wsn, zfrag, znorm);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        } else {
+            hipLaunchKernelGGL((k_assign<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
+                               c.stream, X, Z, o, perm, bounds, cls_idx, row_begin, row_end, p.chunks,
+                               p.per_chunk, labels, best, all, row_status, wb, wl, wsn);
+        }
         return hipGetLastError();
     }
 };
@@ -669,30 +809,26 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
     }
     hipError_t e = hipSuccess;
     const int64_t items = X.n * p.chunks;
-    if (p.bf16) {
-        // BF16 cost tiles for a block of rows, then the simplex on them
-        float *tiles = (float *)((char *)ws + p.part_bytes);
-        for (int64_t r0 = 0; r0 < X.n && e == hipSuccess; r0 += p.bf16_rows) {
-            const int64_t r1 = r0 + p.bf16_rows < X.n ? r0 + p.bf16_rows : X.n;
-            const int64_t items = (r1 - r0) * ((Z.n + kBfCentroids - 1) / kBfCentroids);
-            const int64_t cg = (items + 3) / 4 < 65536 ? (items + 3) / 4 : 65536;
+    if (!p.binned) {
+        const bf16x4 *zfrag = nullptr;
+        const float *znorm = nullptr;
+        if (p.frag_bytes > 0) {
+            bf16x4 *zf = (bf16x4 *)((char *)ws + p.part_bytes + p.sort_bytes);
+            float *zn = (float *)(zf + Z.n * kBfSteps * 64);
+            const int64_t fg = (Z.n + 3) / 4 < 65536 ? (Z.n + 3) / 4 : 65536;
             if (f32)
-                hipLaunchKernelGGL(k_cost_bf16_assign<float>, dim3((unsigned)cg), dim3(256), 0, c.stream,
-                                   X, Z, r0, r1, tiles);
+                hipLaunchKernelGGL(k_bf16_centroid_frags<float>, dim3((unsigned)fg), dim3(256), 0, c.stream, Z,
+                                   zf, zn);
             else
-                hipLaunchKernelGGL(k_cost_bf16_assign<double>, dim3((unsigned)cg), dim3(256), 0, c.stream,
-                                   X, Z, r0, r1, tiles);
-            if ((e = hipGetLastError()) != hipSuccess) break;
-            const int64_t it = (r1 - r0) * p.chunks;
-            const int64_t grid = it < (1LL << 30) ? it : (1LL << 30);
-            AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, nullptr, nullptr, 0,
-                        grid, r0, r1, tiles};
-            e = dispatch_class(p.single_class, f32, start, r);
+                hipLaunchKernelGGL(k_bf16_centroid_frags<double>, dim3((unsigned)fg), dim3(256), 0, c.stream, Z,
+                                   zf, zn);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            zfrag = zf;
+            znorm = zn;
         }
-    } else if (!p.binned) {
         const int64_t grid = items < (1LL << 30) ? items : (1LL << 30);
         AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, nullptr, nullptr, 0, grid,
-                    0, X.n, nullptr};
+                    0, X.n, zfrag, znorm};
         e = dispatch_class(p.single_class, f32, start, r);
     } else {
         void *sws = (char *)ws + p.part_bytes;
@@ -713,7 +849,7 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
             const int64_t grid = (int64_t)(c.cu_count > 0 ? c.cu_count : 256) * 16;
             const int64_t g2 = items < grid ? (items > 0 ? items : 1) : grid;
             AssignRun r{c, p, X, Z, o, labels, best, all, row_status, wb, wl, wsn, hs.perm, hs.bounds,
-                        cls, g2, 0, X.n, nullptr};
+                        cls, g2, 0, X.n, nullptr, nullptr};
             e = dispatch_class(cls, f32, start, r);
         }
     }

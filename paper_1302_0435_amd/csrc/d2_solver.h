@@ -441,8 +441,9 @@ struct SolveOut {
 // Solve the LP of one oriented pair with the G lanes of this group.  On
 // return every lane holds the same SolveOut; N holds the optimal basis tree
 // and potentials (valid when status == kOk).
-// `ctile`, when given, is this pair's cost tile already computed (row-major,
-// 32 columns, oriented like the pair); otherwise costs come from the points.
+// With `costs_set` the caller has already put the pair's costs into N (the
+// register row, +inf beyond the support, oriented like the pair);
+// otherwise costs come from the points.
 //
 // GIVEN: the costs are the caller's FP64 matrix `gcost` instead of points:
 // row l, column j of the oriented pair is gcost[l * grs + j * gcs].  Such
@@ -451,8 +452,8 @@ struct SolveOut {
 template <int G, int GS, bool LT, typename TIn, int START, typename TileT, bool GIVEN = false>
 __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, NodeState<G, GS, LT> &N,
                                                const PairView &pv, int d, const KOpts &o, int l, int gbase,
-                                               const float *ctile = nullptr, const double *gcost = nullptr,
-                                               int64_t grs = 0, int64_t gcs = 0) {
+                                               const double *gcost = nullptr, int64_t grs = 0, int64_t gcs = 0,
+                                               bool costs_set = false) {
     SolveOut out{kOk, __builtin_nan(""), 0, 0};
     const int T = pv.T, S = pv.S;
     if (T < 1 || S < 1 || T > G || S > GS) { out.status = kTooLarge; return out; }
@@ -492,14 +493,8 @@ __device__ __forceinline__ SolveOut solve_pair(GroupMem<G, GS> &M, TileT &tile, 
             const double c = (hasR && j < S) ? gcost[(int64_t)l * grs + (int64_t)j * gcs] : INFINITY;
             put_cost<G, GS, LT>(N, tile, l, j, c);
         }
-    } else if (ctile) {
-        if constexpr (GS <= 32) {
-#pragma unroll
-            for (int j = 0; j < GS; ++j) {
-                const double c = (hasR && j < S) ? (double)ctile[l * 32 + j] : INFINITY;
-                put_cost<G, GS, LT>(N, tile, l, j, c);
-            }
-        }
+    } else if (costs_set) {
+        // already in N
     } else {
         const TIn *xr = (const TIn *)pv.xr + (int64_t)l * d;
         const TIn *yc = (const TIn *)pv.xc + (int64_t)l * d;

@@ -85,12 +85,17 @@ def test_noalloc_matches_assign_on_two_calls(d2, h):
 
 
 def test_noalloc_rejects_calls_beyond_the_scratch(d2, h):
-    # BF16 cost tiles need up to 1 GiB of workspace: refused, nothing enqueued
+    # 300,000 one-atom rows against centroids large enough (2 MiB of points)
+    # to be split into 8 ranges by XCD: the partial minima (16 B per row and
+    # range, 38.4 MB) exceed the scratch, so the call is refused and nothing
+    # is enqueued
     rng = np.random.default_rng(4243)
-    X = bags(rng, 4000, 32, 16)
-    Z = bags(rng, 256, 32, 16)
+    n = 300_000
+    X = synth.RaggedSet(np.arange(n + 1, dtype=np.int64), rng.normal(size=(n, 16)), np.ones(n))
+    Z = synth.RaggedSet(np.arange(0, 16 * 1024 + 1, 16, dtype=np.int64), rng.normal(size=(16 * 1024, 16)),
+                        np.ones(16 * 1024))
     Xd, Zd = d2.DeviceSet.from_ragged(X, DEV), d2.DeviceSet.from_ragged(Z, DEV)
-    opts = d2.Opts(cost_mode=1)
+    opts = d2.Opts()
     assert d2.d2_workspace_bytes(h, 2, Xd, Zd, 0, opts) > d2._ffi.D2_NOALLOC_SCRATCH_BYTES
     rc, lab, _, _, _ = noalloc(d2, h, Xd, Zd, opts, want_all=False)
     assert rc == d2._ffi.D2_ESCRATCH
