@@ -723,15 +723,17 @@ class HierarchyWorkload:
                 "update_lps_per_step": self.stats.get("lps_update"), "inputs": s["dtype"]}
 
     def cpu_baseline(self, target_s, init_oracle):
-        """The oracle's hierarchy on the first 1,600 objects of the workload;
-        the device driver runs on the same objects and its labels are
-        compared.  The sample is fixed rather than sized by time: beyond a
-        few thousand objects a one-ulp change in a moved atom can flip a
-        near-tie and the whole later trajectory with it (the oracle against
-        itself, perturbed by one ulp, disagrees on 3,049 of 3,200 labels)."""
+        """The oracle's hierarchy on the first 320 objects of the workload
+        (about 20 s: its Step 2 solves every cluster's free-weight program
+        with a dense tableau); the device driver runs on the same objects
+        and its labels are compared.  The sample is fixed rather than sized
+        by time: beyond a few thousand objects a one-ulp change in a moved
+        atom can flip a near-tie and the whole later trajectory with it (the
+        oracle against itself, perturbed by one ulp, disagrees on 3,049 of
+        3,200 labels)."""
         from oracle.hierarchy import hierarchy
         import torch
-        sub = self.X.subset(np.arange(min(1600, self.X.n)))
+        sub = self.X.subset(np.arange(min(320, self.X.n)))
         t0 = time.perf_counter()
         (off, pts, wts), lab_o, lv_o, w_o = hierarchy(sub, self.tau, self.e, self.k, self.U,
                                                      init=init_oracle)

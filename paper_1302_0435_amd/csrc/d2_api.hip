@@ -245,15 +245,21 @@ d2_status multi_plans(d2_handle *h, int ntypes, const d2_set *X, const d2_set *Z
     return D2_OK;
 }
 
+d2::Schedule default_schedule() {
+    d2::Schedule s;
+    for (int c = 0; c < 4; ++c) { s.blocks_per_cu[c] = 4; s.chunk[c] = 4; s.tile[c] = 128; }
+    s.blocks_per_cu[3] = 8;   // one-wave workgroups, two per SIMD
+    s.edge[0] = 16;
+    s.edge[1] = 32;
+    return s;
+}
+
 d2::Schedule schedule_for(d2_handle *h, const d2_set *X, const KOpts &k) {
     for (auto &t : h->tuned)
         if (t.n == X->n && t.d == X->d && t.dtype == X->dtype && t.max_support == X->max_support &&
             t.init == k.init)
             return t.sch;
-    d2::Schedule s;
-    for (int c = 0; c < 4; ++c) { s.blocks_per_cu[c] = 4; s.chunk[c] = 4; }
-    s.blocks_per_cu[3] = 8;   // one-wave workgroups, two per SIMD
-    return s;
+    return default_schedule();
 }
 
 }  // namespace
@@ -633,7 +639,10 @@ d2_status d2_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double
     key[n++] = (uint64_t)(uintptr_t)pair_status;
     key[n++] = (uint64_t)(uintptr_t)ws;
     key[n++] = (uint64_t)sched_of(opts);
-    for (int c = 0; c < 4; ++c) key[n++] = ((uint64_t)(uint32_t)sch.blocks_per_cu[c] << 32) | (uint32_t)sch.chunk[c];
+    for (int c = 0; c < 4; ++c)
+        key[n++] = ((uint64_t)(uint32_t)sch.blocks_per_cu[c] << 42) | ((uint64_t)(uint32_t)sch.chunk[c] << 21) |
+                   (uint32_t)sch.tile[c];
+    key[n++] = ((uint64_t)(uint32_t)sch.edge[0] << 32) | (uint32_t)sch.edge[1];
     return run_graph(h, 3, key, eager_of(opts), (hipStream_t)stream, [&](hipStream_t s) {
         return d2::launch_pairwise(ctx(h, s), p, kx, k, condensed, pair_status, ws, sch);
     });
@@ -656,30 +665,63 @@ d2_status d2_tune_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, d
     if ((st = bind_device(h)) != D2_OK) return st;
     if (X->n < 2) { if (best_ms) *best_ms = 0.0; return D2_OK; }
     hipStream_t s = (hipStream_t)stream;
-    // Candidate schedules: persistent workgroups per CU x work-queue chunk;
-    // each candidate is applied to every class at once and timed as a whole.
+    // The classes run one after another, so each is tuned on its own launch
+    // (the sort plus that class): persistent workgroups per CU x work-queue
+    // chunk x tile width, coordinate by coordinate from the defaults.  Then
+    // the bin edges of classes 0 and 1 (moving objects of support just below
+    // an edge into the next, wider shape), timed on the whole call.
     static const int kBlocks[] = {2, 4, 8};
-    static const int kChunk[] = {1, 8};
+    static const int kChunk[] = {1, 4, 16};
+    static const int kTile[] = {32, 128, 512};
+    static const int kEdge0[] = {16, 12, 8};
+    static const int kEdge1[] = {32, 24};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return D2_EHIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return D2_EHIP; }
-    float best = 1e30f;
-    d2::Schedule best_sch;
-    for (int c = 0; c < 4; ++c) { best_sch.blocks_per_cu[c] = 4; best_sch.chunk[c] = 4; }
     hipError_t e = hipSuccess;
-    for (int bi = 0; bi < 3 && e == hipSuccess; ++bi) {
-        for (int ci = 0; ci < 2 && e == hipSuccess; ++ci) {
-            d2::Schedule sch;
-            for (int c = 0; c < 4; ++c) { sch.blocks_per_cu[c] = kBlocks[bi]; sch.chunk[c] = kChunk[ci]; }
-            e = hipEventRecord(e0, s);
-            if (e == hipSuccess) e = d2::launch_pairwise(ctx(h, s), p, kx, k, condensed, pair_status, ws, sch);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms_ = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms_, e0, e1);
-            if (e == hipSuccess && ms_ < best) { best = ms_; best_sch = sch; }
+    auto timed = [&](const d2::Schedule &sch, int only) -> float {
+        float ms_ = 1e30f;
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = d2::launch_pairwise(ctx(h, s), p, kx, k, condensed, pair_status, ws, sch, only);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms_, e0, e1);
+        return e == hipSuccess ? ms_ : 1e30f;
+    };
+    d2::Schedule best_sch = default_schedule();
+    for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+        float bc = timed(best_sch, c);
+        for (int bi = 0; bi < 3; ++bi) {
+            d2::Schedule t = best_sch;
+            t.blocks_per_cu[c] = kBlocks[bi];
+            const float m = timed(t, c);
+            if (m < bc) { bc = m; best_sch = t; }
+        }
+        for (int ci = 0; ci < 3; ++ci) {
+            d2::Schedule t = best_sch;
+            t.chunk[c] = kChunk[ci];
+            const float m = timed(t, c);
+            if (m < bc) { bc = m; best_sch = t; }
+        }
+        for (int ti = 0; ti < 3; ++ti) {
+            d2::Schedule t = best_sch;
+            t.tile[c] = kTile[ti];
+            const float m = timed(t, c);
+            if (m < bc) { bc = m; best_sch = t; }
         }
     }
+    float best = timed(best_sch, -1);
+    for (int a0 = 0; a0 < 3 && e == hipSuccess; ++a0)
+        for (int a1 = 0; a1 < 2 && e == hipSuccess; ++a1) {
+            d2::Schedule t = best_sch;
+            t.edge[0] = kEdge0[a0];
+            t.edge[1] = kEdge1[a1];
+            if (t.edge[0] == best_sch.edge[0] && t.edge[1] == best_sch.edge[1]) continue;
+            const float m = timed(t, -1);
+            if (m < best) { best = m; best_sch = t; }
+        }
+    // the condensed output holds the chosen schedule's full result
+    if (e == hipSuccess) best = timed(best_sch, -1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return D2_EHIP;

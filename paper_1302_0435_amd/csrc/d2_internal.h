@@ -39,8 +39,10 @@ struct LaunchCtx {
 
 // Persistent-kernel schedule per support class (chosen by the autotuner).
 struct Schedule {
-    int blocks_per_cu[4];
-    int chunk[4];
+    int blocks_per_cu[4];   // persistent workgroups per CU, per support class
+    int chunk[4];           // pairs taken per work-queue grab
+    int tile[4];            // a positions per tile of the class's walk (0: 128)
+    int edge[2];            // support bin edges of classes 0 and 1 (<= 16, <= 32)
 };
 
 // Support class of a pair with these (declared) maximum supports.
@@ -74,7 +76,8 @@ struct PairwisePlan {
 };
 PairwisePlan plan_pairwise(const KSet &X, int xmax, int schedule);
 hipError_t launch_pairwise(const LaunchCtx &c, const PairwisePlan &p, const KSet &X, const KOpts &o,
-                           double *condensed, int32_t *status, void *ws, const Schedule &sch);
+                           double *condensed, int32_t *status, void *ws, const Schedule &sch,
+                           int only_class = -1);
 
 hipError_t launch_cost_tiles(const LaunchCtx &c, const KSet &A, const KSet &B,
                              const int64_t *pairs, int64_t npairs, int cost_mode, double *tiles,

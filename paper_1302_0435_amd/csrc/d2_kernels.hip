@@ -31,7 +31,8 @@ __device__ __forceinline__ int support_bucket(const int64_t *off, int64_t i) {
 
 // ------------------------------------------------------ support sorting
 
-// ws layout (all int64): hist[66] | cursor[66] | bounds[8] | counters[4] | perm[n]
+// ws layout (all int64): hist[66] | cursor[66] | bounds[8] | counters[32] | perm[n]
+// (work-queue counters: one per support class and XCD)
 struct SortWS {
     int64_t *hist, *cursor, *bounds;
     unsigned long long *counters;
@@ -45,18 +46,18 @@ __device__ __forceinline__ SortWS sort_ws(void *ws) {
     s.cursor = p + 66;
     s.bounds = p + 132;
     s.counters = (unsigned long long *)(p + 140);
-    s.perm = p + 144;
+    s.perm = p + 172;
     return s;
 }
 
-size_t sort_ws_bytes(int64_t n) { return (size_t)(144 + (n > 0 ? n : 0)) * sizeof(int64_t); }
+size_t sort_ws_bytes(int64_t n) { return (size_t)(172 + (n > 0 ? n : 0)) * sizeof(int64_t); }
 
 __global__ void k_sort_init(void *ws) {
     SortWS s = sort_ws(ws);
     const int t = threadIdx.x;
     if (t < 66) { s.hist[t] = 0; s.cursor[t] = 0; }
     if (t < 8) s.bounds[t] = 0;
-    if (t < 4) s.counters[t] = 0ull;
+    if (t < 32) s.counters[t] = 0ull;
 }
 
 __global__ void k_sort_hist(KSet X, void *ws) {
@@ -68,10 +69,11 @@ __global__ void k_sort_hist(KSet X, void *ws) {
 
 // Exclusive prefix over buckets, and class boundaries: bounds[c] = number of
 // sorted objects whose class is <= c (class is monotone in the support).
-// mode 0 (pairwise): class by the support alone (<= 16, <= 32, larger).
+// mode 0 (pairwise): class by the support alone (<= e0, <= e1, larger; the
+// bin edges e0 <= 16 and e1 <= 32 keep every class within its shape).
 // mode 1 (labelling against centroids of support <= smax): class of the
 // pair (max(t, smax), min(t, smax)).
-__global__ void k_sort_scan(void *ws, int64_t n, int mode, int smax) {
+__global__ void k_sort_scan(void *ws, int64_t n, int mode, int smax, int e0, int e1) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     SortWS s = sort_ws(ws);
     int64_t acc = 0;
@@ -79,7 +81,7 @@ __global__ void k_sort_scan(void *ws, int64_t n, int mode, int smax) {
     for (int t = 0; t < 66; ++t) {
         s.cursor[t] = acc;
         const int64_t T = t > smax ? t : smax, S = t < smax ? t : smax;
-        const int c = mode == 0 ? (t <= 16 ? 0 : (t <= 32 ? 1 : 2)) : class_of(T, S);
+        const int c = mode == 0 ? (t <= e0 ? 0 : (t <= e1 ? 1 : 2)) : class_of(T, S);
         const int64_t h = s.hist[t];
         acc += h;
         for (int k = c; k < 4; ++k) le[k] += h;
@@ -233,40 +235,92 @@ __device__ __forceinline__ int64_t condensed_index(int64_t n, int64_t i, int64_t
     return i * n - i * (i + 1) / 2 + (j - i - 1);
 }
 
-// k -> (a, b), a < b, in column-major order over a triangle: b(b-1)/2 + a.
-__device__ __forceinline__ void tri_colmajor(int64_t k, int64_t &a, int64_t &b) {
-    int64_t bb = (int64_t)floor((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
-    while (bb * (bb - 1) / 2 > k) --bb;
-    while ((bb + 1) * bb / 2 <= k) ++bb;
-    b = bb;
-    a = k - bb * (bb - 1) / 2;
-}
+// The pairs of one support class, in sorted-object positions: every (a, b)
+// with a in [A0, A1), b in [B0, B1) and a < b.
+//   class 0: both in [0, n16); class 1: b in [n16, n32), any a < b;
+//   class 2: a in [0, n32), b in [n32, n); class 3: both in [n32, n).
+struct Region {
+    int64_t A0, A1, B0, B1;
+};
 
-// Pair items of one support class, in sorted-object positions (a < b):
-//   class 0: triangle over [0, n16); class 1: b in [n16, n32), a < b;
-//   class 2: a in [0, n32), b in [n32, n); class 3: triangle over [n32, n).
-__device__ __forceinline__ int64_t class_items(int cls, int64_t n16, int64_t n32, int64_t n) {
+__device__ __forceinline__ Region class_region(int cls, int64_t n16, int64_t n32, int64_t n) {
     switch (cls) {
-    case 0: return n16 * (n16 - 1) / 2;
-    case 1: return n32 * (n32 - 1) / 2 - n16 * (n16 - 1) / 2;
-    case 2: return n32 * (n - n32);
-    default: return (n - n32) * (n - n32 - 1) / 2;
+    case 0: return Region{0, n16, 0, n16};
+    case 1: return Region{0, n32, n16, n32};
+    case 2: return Region{0, n32, n32, n};
+    default: return Region{n32, n, n32, n};
     }
 }
 
-__device__ __forceinline__ void class_item(int cls, int64_t k, int64_t n16, int64_t n32, int64_t &a,
-                                           int64_t &b) {
-    switch (cls) {
-    case 0: tri_colmajor(k, a, b); break;
-    case 1: tri_colmajor(k + n16 * (n16 - 1) / 2, a, b); break;
-    case 2: b = n32 + k / n32; a = k % n32; break;
-    default: tri_colmajor(k, a, b); a += n32; b += n32; break;
-    }
+// Items are walked tile by tile: a tile holds `ta` consecutive a positions
+// (at most 64 tiles per class), and within a tile b runs outermost, so
+// consecutive items share their b object and a tile's a objects are reused
+// while it is worked on.  Pairs of tile [a0, a1): for b from
+// bs = max(B0, a0 + 1) on, the a in [a0, min(a1, b)).
+__device__ __forceinline__ int64_t tile_width(const Region &R, int tile) {
+    const int64_t span = R.A1 - R.A0;
+    const int64_t min_w = (span + 63) / 64;
+    const int64_t w = tile > 0 ? tile : 128;
+    return w > min_w ? w : (min_w > 0 ? min_w : 1);
 }
+
+__device__ __forceinline__ int64_t tri2(int64_t m) { return m > 1 ? m * (m - 1) / 2 : 0; }
+
+__device__ __forceinline__ void tile_counts(const Region &R, int64_t a0, int64_t a1, int64_t &c1, int64_t &c2) {
+    const int64_t bs = R.B0 > a0 + 1 ? R.B0 : a0 + 1;
+    const int64_t e1 = a1 < R.B1 ? a1 : R.B1;
+    c1 = e1 > bs ? tri2(e1 - a0) - tri2(bs - a0) : 0;   // b < a1: b - a0 pairs each
+    const int64_t b2 = bs > a1 ? bs : a1;
+    c2 = R.B1 > b2 ? (R.B1 - b2) * (a1 - a0) : 0;        // b >= a1: the whole tile each
+}
+
+__device__ __forceinline__ int64_t region_items(const Region &R, int64_t w) {
+    int64_t total = 0;
+    for (int64_t a0 = R.A0; a0 < R.A1; a0 += w) {
+        int64_t c1, c2;
+        tile_counts(R, a0, a0 + w < R.A1 ? a0 + w : R.A1, c1, c2);
+        total += c1 + c2;
+    }
+    return total;
+}
+
+__device__ __forceinline__ void region_item(const Region &R, int64_t w, int64_t k, int64_t &a, int64_t &b) {
+    for (int64_t a0 = R.A0; a0 < R.A1; a0 += w) {
+        const int64_t a1 = a0 + w < R.A1 ? a0 + w : R.A1;
+        int64_t c1, c2;
+        tile_counts(R, a0, a1, c1, c2);
+        if (k >= c1 + c2) { k -= c1 + c2; continue; }
+        const int64_t bs = R.B0 > a0 + 1 ? R.B0 : a0 + 1;
+        if (k < c1) {
+            // largest m = b - a0 with tri2(m) <= k + tri2(bs - a0)
+            const int64_t key = k + tri2(bs - a0);
+            int64_t m = (int64_t)floor((1.0 + sqrt(1.0 + 8.0 * (double)key)) * 0.5);
+            while (m > 0 && tri2(m) > key) --m;
+            while (tri2(m + 1) <= key) ++m;
+            b = a0 + m;
+            a = a0 + (key - tri2(m));
+        } else {
+            const int64_t r = k - c1, ww = a1 - a0;
+            const int64_t b2 = bs > a1 ? bs : a1;
+            b = b2 + r / ww;
+            a = a0 + r % ww;
+        }
+        return;
+    }
+    a = 0;
+    b = 0;
+}
+
+// One support class of the pairwise matrix.  The class's items are split
+// into kXcdQueues contiguous ranges with a work-queue counter each; a
+// workgroup drains the range of its own XCD first (workgroups are dealt to
+// the XCDs round-robin by index), then helps the others, so each XCD works
+// on a few tiles at a time and their objects stay in its L2.
+constexpr int kXcdQueues = 8;
 
 template <int CLS, typename TIn, int START>
 __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_pairwise_q(
-    KSet X, KOpts o, void *ws, int cls, int chunk, double *out, int32_t *status) {
+    KSet X, KOpts o, void *ws, int cls, int chunk, int tile, double *out, int32_t *status) {
     constexpr int G = ShapeCfg<CLS>::G, GS = ShapeCfg<CLS>::GS, NG = ShapeCfg<CLS>::groups;
     constexpr bool LT = ShapeCfg<CLS>::LT;
     __shared__ GroupMem<G, GS> mem[NG];
@@ -275,28 +329,37 @@ __global__ __launch_bounds__(ShapeCfg<CLS>::threads, ShapeCfg<CLS>::occ) void k_
     const int g = tid / G, l = tid % G, gbase = (tid & 63) & ~(G - 1);
     SortWS s = sort_ws(ws);
     const int64_t n = X.n, n16 = s.bounds[0], n32 = s.bounds[1];
-    const int64_t items = class_items(cls, n16, n32, n);
+    const Region R = class_region(cls, n16, n32, n);
+    const int64_t w = tile_width(R, tile);
+    const int64_t items = region_items(R, w);
     GroupMem<G, GS> &M = mem[g];
+    const int home = (int)(blockIdx.x % kXcdQueues);
 #pragma unroll 1
-    for (;;) {
-        if (l == 0) M.grab = (long long)atomicAdd(&s.counters[cls], (unsigned long long)chunk);
-        wsync();
-        const int64_t base = M.grab;
-        wsync();
-        if (base >= items) break;
-        const int64_t end = base + chunk < items ? base + chunk : items;
-        for (int64_t k = base; k < end; ++k) {
-            int64_t a, b;
-            class_item(cls, k, n16, n32, a, b);
-            const int64_t pi = s.perm[a], pj = s.perm[b];
-            const int64_t lo = pi < pj ? pi : pj, hi = pi < pj ? pj : pi;
-            NodeState<G, GS, LT> N;
-            PairView pv = orient(X, lo, X, hi, (int)sizeof(TIn));
-            SolveOut r = solve_pair<G, GS, LT, TIn, START>(M, tiles[g], N, pv, X.d, o, l, gbase);
-            if (l == 0) {
-                const int64_t idx = condensed_index(n, lo, hi);
-                out[idx] = r.status == kOk ? r.d2 : __builtin_nan("");
-                if (status) status[idx] = r.status;
+    for (int q = 0; q < kXcdQueues; ++q) {
+        const int x = (home + q) % kXcdQueues;
+        const int64_t lo = items * x / kXcdQueues, hi = items * (x + 1) / kXcdQueues;
+#pragma unroll 1
+        for (;;) {
+            if (l == 0)
+                M.grab = (long long)atomicAdd(&s.counters[cls * kXcdQueues + x], (unsigned long long)chunk);
+            wsync();
+            const int64_t base = lo + M.grab;
+            wsync();
+            if (base >= hi) break;
+            const int64_t end = base + chunk < hi ? base + chunk : hi;
+            for (int64_t k = base; k < end; ++k) {
+                int64_t a, b;
+                region_item(R, w, k, a, b);
+                const int64_t pi = s.perm[a], pj = s.perm[b];
+                const int64_t lo2 = pi < pj ? pi : pj, hi2 = pi < pj ? pj : pi;
+                NodeState<G, GS, LT> N;
+                PairView pv = orient(X, lo2, X, hi2, (int)sizeof(TIn));
+                SolveOut r = solve_pair<G, GS, LT, TIn, START>(M, tiles[g], N, pv, X.d, o, l, gbase);
+                if (l == 0) {
+                    const int64_t idx = condensed_index(n, lo2, hi2);
+                    out[idx] = r.status == kOk ? r.d2 : __builtin_nan("");
+                    if (status) status[idx] = r.status;
+                }
             }
         }
     }
@@ -836,12 +899,12 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
         {
             int64_t *q = (int64_t *)sws;
             hs.hist = q; hs.cursor = q + 66; hs.bounds = q + 132;
-            hs.counters = (unsigned long long *)(q + 140); hs.perm = q + 144;
+            hs.counters = (unsigned long long *)(q + 140); hs.perm = q + 172;
         }
         const int sb = (int)((X.n + 255) / 256 < 1024 ? (X.n + 255) / 256 : 1024);
         hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(128), 0, c.stream, sws);
         hipLaunchKernelGGL(k_sort_hist, dim3(sb), dim3(256), 0, c.stream, X, sws);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, c.stream, sws, X.n, 1, p.zmax);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, c.stream, sws, X.n, 1, p.zmax, 16, 32);
         hipLaunchKernelGGL(k_sort_scatter, dim3(sb), dim3(256), 0, c.stream, X, sws);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // every class a row can fall in; kernels of empty classes exit at once
@@ -918,18 +981,18 @@ struct PairwisePlainRun {
 
 struct PairwiseQRun {
     const LaunchCtx &c;
-    const KSet &X; const KOpts &o; void *ws; int cls; int chunk; int64_t grid;
+    const KSet &X; const KOpts &o; void *ws; int cls; int chunk; int tile; int64_t grid;
     double *out; int32_t *status;
     template <int C, typename TIn, int V>
     hipError_t run() {
         hipLaunchKernelGGL((k_pairwise_q<C, TIn, V>), dim3((unsigned)grid), dim3(ShapeCfg<C>::threads), 0,
-                           c.stream, X, o, ws, cls, chunk, out, status);
+                           c.stream, X, o, ws, cls, chunk, tile, out, status);
         return hipGetLastError();
     }
 };
 
 hipError_t launch_pairwise(const LaunchCtx &c, const PairwisePlan &p, const KSet &X, const KOpts &o,
-                           double *condensed, int32_t *status, void *ws, const Schedule &sch) {
+                           double *condensed, int32_t *status, void *ws, const Schedule &sch, int only_class) {
     if (X.n < 2) return hipSuccess;
     const bool f32 = X.dtype == D2_F32;
     const int start = o.init;
@@ -940,14 +1003,18 @@ hipError_t launch_pairwise(const LaunchCtx &c, const PairwisePlan &p, const KSet
     const int sb = (int)((X.n + 255) / 256 < 1024 ? (X.n + 255) / 256 : 1024);
     hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(128), 0, c.stream, ws);
     hipLaunchKernelGGL(k_sort_hist, dim3(sb), dim3(256), 0, c.stream, X, ws);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, c.stream, ws, X.n, 0, 0);
+    const int e0 = sch.edge[0] >= 1 && sch.edge[0] <= 16 ? sch.edge[0] : 16;
+    const int e1 = sch.edge[1] >= e0 && sch.edge[1] <= 32 ? sch.edge[1] : 32;
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, c.stream, ws, X.n, 0, 0, e0, e1);
     hipLaunchKernelGGL(k_sort_scatter, dim3(sb), dim3(256), 0, c.stream, X, ws);
     hipError_t e = hipGetLastError();
-    // classes 0..3; empty ones exit at once
+    // classes 0..3 (or the one asked for); empty ones exit at once
     for (int cls = 0; cls < 4 && e == hipSuccess; ++cls) {
+        if (only_class >= 0 && cls != only_class) continue;
         const int per_cu = sch.blocks_per_cu[cls] > 0 ? sch.blocks_per_cu[cls] : 4;
         const int64_t grid = (int64_t)(c.cu_count > 0 ? c.cu_count : 256) * per_cu;
-        PairwiseQRun r{c, X, o, ws, cls, sch.chunk[cls] > 0 ? sch.chunk[cls] : 4, grid, condensed, status};
+        PairwiseQRun r{c, X, o, ws, cls, sch.chunk[cls] > 0 ? sch.chunk[cls] : 4, sch.tile[cls], grid,
+                       condensed, status};
         e = dispatch_class(cls, f32, start, r);
     }
     return e;
