@@ -53,8 +53,10 @@ COST_PROFILES = {2: "k_emd_cost_cls0_c2_shapes_2m.txt"}
 MULTI_PROFILES = {2: "k_assign_cls0_f32_c2_multi_type_all.txt"}
 # the workgroup simplex on supports beyond 64 (--op large)
 LARGE_PROFILES = {2: "k_emd_wg_f64_large_96_192.txt"}
-# the hierarchy's labelling-within-segments kernel (--op hierarchy)
-HIER_PROFILES = {2: "k_assign_seg_cls0_f64_c2_hierarchy_100k.txt"}
+# the hierarchy's dominant kernel (--op hierarchy): the free-weight centroid
+# update of Step 2 (its labelling kernel has a summary of its own,
+# k_assign_seg_cls0_f64_c2_hierarchy_100k.txt)
+HIER_PROFILES = {2: "k_free_solve_f64_c2_hierarchy_100k.txt"}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
                for f in ("d2_solver.h", "d2_shapes.h", "d2_kernels.hip")]
 UPDATE_SRCS = [os.path.join(ROOT, "paper_1302_0435_amd", "csrc", f)
@@ -109,7 +111,7 @@ def profile_counters(cfg: int, cost: str, op: str = "assign"):
         sha = kernel_sha(COST_SRCS)
     elif op == "hierarchy":
         kv = _read_profile(HIER_PROFILES.get(cfg, ""))
-        sha = kernel_sha(SEG_SRCS)
+        sha = kernel_sha(UPDATE_SRCS)
     elif op == "multi":
         kv = _read_profile(MULTI_PROFILES.get(cfg, ""))
         sha = kernel_sha()

@@ -408,8 +408,8 @@ d2_status d2_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, double
 /* Schedule autotuner for d2_pairwise (synchronous: waits for the stream).
  * Tunes each support class on its own launch, one setting at a time from
  * the defaults: persistent workgroups per CU (2, 4, 8), pairs per
- * work-queue grab (1, 4, 16) and tile width of the class's walk (32, 128,
- * 512 objects); then the support bin edges of classes 0 and 1 ({16, 12, 8}
+ * work-queue grab (1, 4, 16) and tile width of the class's walk (128, 512,
+ * 2048 objects); then the support bin edges of classes 0 and 1 ({16, 12, 8}
  * x {32, 24}) on whole calls.  Keeps the fastest schedule for this workload
  * shape (n, d, dtype, max_support, start rule) in the handle and writes the
  * time of a whole call with it to *best_ms.  Later d2_pairwise calls of the

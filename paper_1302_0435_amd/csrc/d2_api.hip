@@ -247,7 +247,7 @@ d2_status multi_plans(d2_handle *h, int ntypes, const d2_set *X, const d2_set *Z
 
 d2::Schedule default_schedule() {
     d2::Schedule s;
-    for (int c = 0; c < 4; ++c) { s.blocks_per_cu[c] = 4; s.chunk[c] = 4; s.tile[c] = 128; }
+    for (int c = 0; c < 4; ++c) { s.blocks_per_cu[c] = 4; s.chunk[c] = 4; s.tile[c] = 512; }
     s.blocks_per_cu[3] = 8;   // one-wave workgroups, two per SIMD
     s.edge[0] = 16;
     s.edge[1] = 32;
@@ -672,7 +672,7 @@ d2_status d2_tune_pairwise(d2_handle *h, const d2_set *X, const d2_opts *opts, d
     // an edge into the next, wider shape), timed on the whole call.
     static const int kBlocks[] = {2, 4, 8};
     static const int kChunk[] = {1, 4, 16};
-    static const int kTile[] = {32, 128, 512};
+    static const int kTile[] = {128, 512, 2048};
     static const int kEdge0[] = {16, 12, 8};
     static const int kEdge1[] = {32, 24};
     hipEvent_t e0, e1;

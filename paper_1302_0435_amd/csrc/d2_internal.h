@@ -41,7 +41,7 @@ struct LaunchCtx {
 struct Schedule {
     int blocks_per_cu[4];   // persistent workgroups per CU, per support class
     int chunk[4];           // pairs taken per work-queue grab
-    int tile[4];            // a positions per tile of the class's walk (0: 128)
+    int tile[4];            // a positions per tile of the class's walk (default 512)
     int edge[2];            // support bin edges of classes 0 and 1 (<= 16, <= 32)
 };
 
