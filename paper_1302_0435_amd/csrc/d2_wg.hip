@@ -431,72 +431,94 @@ __global__ __launch_bounds__(kThreads) void k_emd_wg(KSet A, KSet B, int mode, c
             // never enter: the jumping sums reach a tree edge's potentials in
             // another order than its cost, so its reduced cost is a rounding
             // residue rather than exactly 0, and a small tolerance could let
-            // it through (the check runs only on candidates below -delta).
+            // it through.  The chosen cell is checked once; a basic one joins
+            // a short skip list (this pricing only) and the search runs again,
+            // with the check inside the scan once the list is full.
             const bool bland = M.bland != 0;
             const int TS = T * S;
             int unresolved = 0;
             for (int x = tid; x < V; x += kThreads) unresolved |= M.anc[buf][x] >= 0;
             if (unresolved) M.bad = 1;   // benign race: every writer stores 1
-            int pos = bland ? 0 : M.scan;
+            int pos = 0;
             const int width = bland ? TS : kChunk;
             double bv = -delta;
             int bi = INT32_MAX;
-            for (int scanned = 0, rb = 0; scanned < TS; rb ^= 1) {   // >= 1 cell a pass
-                const int n = min(width, TS - scanned);
-                double best = -delta;
-                int bc = INT32_MAX;
-                if (!bland) {
-                    // a chunk: at most kPer cells a thread, their loads issued
-                    // together (a cell past the chunk reads cell 0, unused)
+            int sk0 = -1, sk1 = -1, sk2 = -1, sk3 = -1;   // skipped basic cells (uniform)
+            bool checked = false;
+            for (;;) {
+                pos = bland ? 0 : M.scan;
+                bv = -delta;
+                bi = INT32_MAX;
+                for (int scanned = 0, rb = 0; scanned < TS; rb ^= 1) {   // >= 1 cell a pass
+                    const int n = min(width, TS - scanned);
+                    double best = -delta;
+                    int bc = INT32_MAX;
+                    if (!bland) {
+                        // a chunk: at most kPer cells a thread, their loads issued
+                        // together (a cell past the chunk reads cell 0, unused)
 #pragma unroll
-                    for (int e0 = 0; e0 < kPer; e0 += kBatch) {
-                        double cv[kBatch];
-                        int cc[kBatch];
+                        for (int e0 = 0; e0 < kPer; e0 += kBatch) {
+                            double cv[kBatch];
+                            int cc[kBatch];
 #pragma unroll
-                        for (int e = 0; e < kBatch; ++e) {
-                            const int q = tid + (e0 + e) * kThreads;
-                            int c = pos + q;
-                            if (c >= TS) c -= TS;
-                            cc[e] = q < n ? c : -1;
-                            cv[e] = C[q < n ? c : 0];
-                        }
+                            for (int e = 0; e < kBatch; ++e) {
+                                const int q = tid + (e0 + e) * kThreads;
+                                int c = pos + q;
+                                if (c >= TS) c -= TS;
+                                cc[e] = q < n ? c : -1;
+                                cv[e] = C[q < n ? c : 0];
+                            }
 #pragma unroll
-                        for (int e = 0; e < kBatch; ++e) {
-                            if (cc[e] >= 0) {
-                                const int c = cc[e], a = c / S, b = c - a * S;
-                                const double r = cv[e] - M.off[buf][a] - M.off[buf][T + b];
-                                if (r < -delta && better(r, c, best, bc, false) && M.par[a] != T + b &&
-                                    M.par[T + b] != a) {
-                                    best = r;
-                                    bc = c;
+                            for (int e = 0; e < kBatch; ++e) {
+                                if (cc[e] >= 0) {
+                                    const int c = cc[e], a = c / S, b = c - a * S;
+                                    const double r = cv[e] - M.off[buf][a] - M.off[buf][T + b];
+                                    if (r < -delta && better(r, c, best, bc, false) && c != sk0 && c != sk1 &&
+                                        c != sk2 && c != sk3 &&
+                                        (!checked || (M.par[a] != T + b && M.par[T + b] != a))) {
+                                        best = r;
+                                        bc = c;
+                                    }
                                 }
                             }
                         }
-                    }
-                } else {
-                    for (int q = tid; q < n; q += kThreads) {
-                        const int a = q / S, b = q - a * S;   // one pass from cell 0
-                        const double r = C[q] - M.off[buf][a] - M.off[buf][T + b];
-                        if (r < -delta && better(r, q, best, bc, true) && M.par[a] != T + b &&
-                            M.par[T + b] != a) {
-                            best = r;
-                            bc = q;
+                    } else {
+                        for (int q = tid; q < n; q += kThreads) {
+                            const int a = q / S, b = q - a * S;   // one pass from cell 0
+                            const double r = C[q] - M.off[buf][a] - M.off[buf][T + b];
+                            if (r < -delta && better(r, q, best, bc, true) && q != sk0 && q != sk1 && q != sk2 &&
+                                q != sk3 && (!checked || (M.par[a] != T + b && M.par[T + b] != a))) {
+                                best = r;
+                                bc = q;
+                            }
                         }
                     }
-                }
-                int unused = 0;
-                wave_best(best, bc, unused, bland);
-                if ((tid & 63) == 0) { M.rv[rb * kWaves + (tid >> 6)] = best; M.ri[rb * kWaves + (tid >> 6)] = bc; }
-                __syncthreads();   // two result banks: the next pass writes the other
-                for (int w = 0; w < kWaves; ++w)
-                    if (better(M.rv[rb * kWaves + w], M.ri[rb * kWaves + w], bv, bi, bland)) {
-                        bv = M.rv[rb * kWaves + w];
-                        bi = M.ri[rb * kWaves + w];
+                    int unused = 0;
+                    wave_best(best, bc, unused, bland);
+                    if ((tid & 63) == 0) {
+                        M.rv[rb * kWaves + (tid >> 6)] = best;
+                        M.ri[rb * kWaves + (tid >> 6)] = bc;
                     }
-                scanned += n;
-                pos += n;
-                if (pos >= TS) pos -= TS;
-                if (bi != INT32_MAX) break;
+                    __syncthreads();   // two result banks: the next pass writes the other
+                    for (int w = 0; w < kWaves; ++w)
+                        if (better(M.rv[rb * kWaves + w], M.ri[rb * kWaves + w], bv, bi, bland)) {
+                            bv = M.rv[rb * kWaves + w];
+                            bi = M.ri[rb * kWaves + w];
+                        }
+                    scanned += n;
+                    pos += n;
+                    if (pos >= TS) pos -= TS;
+                    if (bi != INT32_MAX) break;
+                }
+                if (bi == INT32_MAX || checked) break;
+                const int ea = bi / S, eb = bi - ea * S;
+                if (M.par[ea] != T + eb && M.par[T + eb] != ea) break;   // not a tree edge
+                if (sk0 < 0) sk0 = bi;
+                else if (sk1 < 0) sk1 = bi;
+                else if (sk2 < 0) sk2 = bi;
+                else if (sk3 < 0) sk3 = bi;
+                else checked = true;
+                __syncthreads();   // every thread has read the result banks before they are reused
             }
             if (tid < 64) {
                 // wave 0 pivots: every lane takes the tree walk in step (one
