@@ -351,6 +351,22 @@ d2_status d2_centroid_update(d2_handle *h, const d2_set *X, const d2_set *Z, con
  *                  basis matrix lost rank numerically).
  *   cluster_pivots[K]  device int32, nullable: simplex pivots of each
  *                  cluster's program (0 where none was solved).
+ *   basis_io       device int32 [K][basis_stride], nullable: starting bases
+ *                  kept between calls.  Row j holds m, the row count of a
+ *                  basis of cluster j's program, then its m basic variables
+ *                  (w(k, a, r) numbered s (T_k + a) + r with members k in
+ *                  increasing object index and T_k their first atom, then
+ *                  p_z(r) as s sum(t) + r), or -1.  On entry a row whose m
+ *                  equals this call's, whose variables are distinct and in
+ *                  range, whose basis matrix has full rank and whose
+ *                  solution is feasible starts that cluster's simplex (a
+ *                  later pass over the same members: only the costs have
+ *                  changed); any other row is ignored.  On return every
+ *                  solved cluster's row holds its optimal basis (when
+ *                  m + 1 <= basis_stride), the others -1.  Fill with -1
+ *                  before the first call.  A warm start only changes the
+ *                  pivot path: with several optimal solutions it may end at
+ *                  another one than a cold start.
  * Workspace: d2_workspace_bytes(h, 6, X, Z, max_members, opts) bytes
  * (required).  opts->bland_after applies to degenerate pivots as in the
  * transport solver (0 = 2 m); opts->opt_tol and want_sqrt are ignored: a
@@ -361,7 +377,8 @@ d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z
                                   const double *obj_weights, int32_t max_members, const d2_opts *opts,
                                   double *z_new, double *w_new, double *eps_step1, double *eps_step3,
                                   int32_t *counts, int32_t *obj_status, int32_t *cluster_status,
-                                  int32_t *cluster_pivots, void *ws, size_t ws_bytes, void *stream);
+                                  int32_t *cluster_pivots, int32_t *basis_io, int64_t basis_stride, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 /* Nearest-centroid labelling within segments (Alg. 3 Step 2, where each
  * segment of the data is clustered on its own): object i is compared only

@@ -79,7 +79,7 @@ def lib():
     L.d2_pairwise.argtypes = [P, S, O, P, P, P, SZ, P]
     L.d2_tune_pairwise.argtypes = [P, S, O, P, P, P, SZ, P, ctypes.POINTER(ctypes.c_double)]
     L.d2_centroid_update.argtypes = [P, S, S, P, P, O, P, P, P, P, P, P, SZ, P]
-    L.d2_centroid_update_free.argtypes = [P, S, S, P, P, I32, O, P, P, P, P, P, P, P, P, P, SZ, P]
+    L.d2_centroid_update_free.argtypes = [P, S, S, P, P, I32, O, P, P, P, P, P, P, P, P, P, I64, P, SZ, P]
     L.d2_assign_segmented.argtypes = [P, S, S, P, I64, P, O, P, P, P, P]
     L.d2_assign_multi.argtypes = [P, I32, S, S, O, P, P, P, P, P, SZ, P]
     L.d2_emd_cost_batch.argtypes = [P, I64, P, P, P, P, P, P, I32, I32, O, P, P, P, P, P, SZ, P]

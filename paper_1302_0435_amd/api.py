@@ -304,7 +304,8 @@ def d2_centroid_update(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch.Tens
 
 def d2_centroid_update_free(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch.Tensor,
                             opts: Optional[Opts] = None, weights: Optional[torch.Tensor] = None,
-                            max_members: Optional[int] = None, want_pivots: bool = False):
+                            max_members: Optional[int] = None, want_pivots: bool = False,
+                            basis: Optional[torch.Tensor] = None):
     """One pass of the centroid update of Alg. 1 with free centroid weights
     (Steps 1-3; object weights as in Eq. (3)-(4)).
 
@@ -313,7 +314,8 @@ def d2_centroid_update_free(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch
     w_new [Z.offsets[K]] f64, eps_step1 [K], eps_step3 [K] f64, counts [K],
     obj_status [n], cluster_status [K] int32 (see d2_centroid_update_free in
     d2.h); with ``want_pivots`` also the simplex pivots of each cluster
-    [K] int32."""
+    [K] int32.  ``basis`` (device int32 [K, stride], see free_basis_buffer)
+    carries each cluster's optimal basis to the next call as its start."""
     opts = opts or Opts()
     dev = _dev(h)
     labels = labels.to(device=dev, dtype=torch.int32).contiguous()
@@ -333,15 +335,29 @@ def d2_centroid_update_free(h: Handle, X: DeviceSet, Z: DeviceSet, labels: torch
     cstatus = torch.empty(K, dtype=torch.int32, device=dev)
     piv = torch.empty(K, dtype=torch.int32, device=dev) if want_pivots else None
     ws, nbytes = _workspace(h, _ffi.WHICH_UPDATE_FREE, X, Z, max_members, opts)
+    if basis is not None:
+        if basis.dtype != torch.int32 or basis.dim() != 2 or basis.shape[0] != K or not basis.is_contiguous():
+            raise ValueError("basis must be a contiguous int32 [K, stride] tensor")
+    stride = int(basis.shape[1]) if basis is not None else 0
     x, z, o = X.c(), Z.c(), opts.c()
     check(_ffi.lib().d2_centroid_update_free(h.ptr, ctypes.byref(x), ctypes.byref(z), _ptr(labels),
                                              _ptr(weights), max_members, ctypes.byref(o),
                                              _ptr(z_new), _ptr(w_new), _ptr(eps1), _ptr(eps3),
                                              _ptr(counts), _ptr(status), _ptr(cstatus), _ptr(piv),
-                                             _ptr(ws), nbytes, _stream(dev)), "d2_centroid_update_free")
+                                             _ptr(basis), stride, _ptr(ws), nbytes, _stream(dev)),
+          "d2_centroid_update_free")
     if want_pivots:
         return z_new, w_new, eps1, eps3, counts, status, cstatus, piv
     return z_new, w_new, eps1, eps3, counts, status, cstatus
+
+
+def free_basis_buffer(X: DeviceSet, Z: DeviceSet, max_members: int) -> torch.Tensor:
+    """Starting-basis rows for d2_centroid_update_free, all -1 (no kept
+    basis): one row per centroid, wide enough for a program of up to
+    max_members members (max_members (max_support(X) + max_support(Z) - 1)
+    + 1 rows, plus the count)."""
+    stride = int(max_members) * (X.max_support + Z.max_support - 1) + 2
+    return torch.full((Z.n, stride), -1, dtype=torch.int32, device=Z.points.device)
 
 
 def constrained_d2(h: Handle, X: DeviceSet, Z: DeviceSet, opts: Optional[Opts] = None,

@@ -535,7 +535,8 @@ d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z
                                   const double *obj_weights, int32_t max_members, const d2_opts *opts,
                                   double *z_new, double *w_new, double *eps_step1, double *eps_step3,
                                   int32_t *counts, int32_t *obj_status, int32_t *cluster_status,
-                                  int32_t *cluster_pivots, void *ws, size_t ws_bytes, void *stream) {
+                                  int32_t *cluster_pivots, int32_t *basis_io, int64_t basis_stride, void *ws,
+                                  size_t ws_bytes, void *stream) {
     if (!h) return D2_EINVAL;
     d2_status st = pair_sets_ok(X, Z);
     if (st != D2_OK) return st;
@@ -543,6 +544,7 @@ d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z
     if ((st = opts_ok(opts, k)) != D2_OK) return st;
     if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
     if (max_members < 1) return D2_EINVAL;
+    if (basis_io && basis_stride < 2) return D2_EINVAL;
     if (X->n > 0 && !labels) return D2_EINVAL;
     if (Z->n > 0 && (!z_new || !w_new)) return D2_EINVAL;
     if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
@@ -554,7 +556,8 @@ d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z
     if (X->n == 0 && Z->n == 0) return D2_OK;
     hipError_t e = d2::launch_update_free(ctx(h, (hipStream_t)stream), kset(X), kset(Z), ms(X), ms(Z),
                                           max_members, k, labels, obj_weights, z_new, w_new, eps_step1, eps_step3,
-                                          counts, obj_status, cluster_status, cluster_pivots, ws);
+                                          counts, obj_status, cluster_status, cluster_pivots, basis_io,
+                                          basis_stride, ws);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 

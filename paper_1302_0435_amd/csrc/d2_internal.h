@@ -124,7 +124,8 @@ size_t update_free_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax, int
 hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, int xmax, int zmax,
                               int max_members, const KOpts &o, const int32_t *labels, const double *obj_weights,
                               double *z_new, double *w_new, double *eps1, double *eps3, int32_t *counts,
-                              int32_t *obj_status, int32_t *cluster_status, int32_t *cluster_pivots, void *ws);
+                              int32_t *obj_status, int32_t *cluster_status, int32_t *cluster_pivots,
+                              int32_t *basis_io, int64_t basis_stride, void *ws);
 
 // Labelling within segments: object i against the centroids
 // zoff[seg[i]] .. zoff[seg[i]+1] of Z only.

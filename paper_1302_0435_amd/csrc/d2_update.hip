@@ -625,10 +625,12 @@ hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet 
 //            later member are dependent and dropped); m = sum t + n (s - 1) + 1;
 //   columns  w(k, a, r) for every member, atom and centroid atom (two unit
 //            entries), then p_z(r) (-1 in member r's coupling rows);
-//   start    member 0 sends each atom to its cheapest centroid atom, which
-//            fixes p_z (all s weights basic); every later member is the
-//            north-west corner from its weights to p_z.  The basis matrix is
-//            block triangular with non-singular blocks, so it is a basis;
+//   start    a basis the caller kept from an earlier pass over the same
+//            members, when it still is one and is feasible; else member 0
+//            sends each atom to its cheapest centroid atom, which fixes p_z
+//            (all s weights basic), and every later member is the
+//            north-west corner from its weights to p_z.  That basis matrix
+//            is block triangular with non-singular blocks, so it is a basis;
 //   pivots   explicit inverse of the basis: Dantzig's entering column
 //            (Bland's after a run of degenerate pivots), the column
 //            B^-1 a_q, the ratio test (least ratio, then lowest variable),
@@ -655,6 +657,7 @@ constexpr int kRefactor = 256;
 constexpr double kFreeTol = 1e-13;     // reduced costs above -kFreeTol max|c| count as >= 0
 constexpr double kPivTol = 1e-9;       // least entry of B^-1 a_q taken in the ratio test
 constexpr double kFlowEps = 1e-14;     // flows at or below this (of a unit mass) are zeros
+constexpr double kWarmTol = 1e-12;     // a kept basis starts only if B^-1 b >= -kWarmTol
 constexpr size_t kFreeLds = 60 * 1024; // dynamic LDS for the vectors, when they fit
 enum { kFOk = 0, kFBadWeights = 1, kFTooLarge = 2, kFPivotCap = 3, kFInternal = 6 };
 
@@ -760,8 +763,8 @@ struct FreeShared {
     double rv[kFreeWaves];
     int ri[kFreeWaves];
     int cr[kFreeWaves], cc[kFreeWaves];
-    int n, m, stat, p, fresh, bland;
-    double delta, dq;
+    int n, m, stat, p, fresh, bland, warm_ok;
+    double delta, dq, negx;
 };
 
 // Block-wide (value, key) minimum, lowest key among equal values; keys of
@@ -945,6 +948,7 @@ __device__ __forceinline__ bool free_refactor(FreeShared &sh, const FreeVec &V, 
         }
         __syncthreads();
     }
+    double neg = 0.0;
     for (int i = tid; i < m; i += kFreeThreads) {
         V.basis[i] = V.nbasis[i];
         V.cB[i] = cost[V.nbasis[i]];
@@ -952,7 +956,10 @@ __device__ __forceinline__ bool free_refactor(FreeShared &sh, const FreeVec &V, 
         const double *row = Binv + (int64_t)i * m;
         for (int j = 0; j < m; ++j) acc = fma(row[j], V.b[j], acc);
         V.xB[i] = acc < 0.0 ? 0.0 : acc;
+        neg = fmax(neg, -acc);
     }
+    neg = free_max(sh, neg);   // the most negative basic value, before clamping
+    if (tid == 0) sh.negx = neg;
     __syncthreads();
     for (int i = tid; i < m; i += kFreeThreads) {
         double acc = 0.0;
@@ -969,7 +976,8 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
                                                              char *slabs, const double *objw, double *z_new,
                                                              double *w_new, double *eps1, double *eps3,
                                                              int32_t *counts, int32_t *obj_status,
-                                                             int32_t *cluster_status, int32_t *cluster_pivots) {
+                                                             int32_t *cluster_status, int32_t *cluster_pivots,
+                                                             int32_t *basis_io, int64_t bstride) {
     extern __shared__ __align__(16) char free_lds[];
     __shared__ FreeShared sh;
     const int tid = threadIdx.x;
@@ -996,6 +1004,7 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
                 if (counts) counts[j] = 0;
                 if (cluster_status) cluster_status[j] = kFTooLarge;
                 if (cluster_pivots) cluster_pivots[j] = 0;
+                if (basis_io) basis_io[j * bstride] = -1;
             }
             __syncthreads();
             continue;
@@ -1046,6 +1055,7 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
                 if (counts) counts[j] = 0;
                 if (cluster_status) cluster_status[j] = kFOk;
                 if (cluster_pivots) cluster_pivots[j] = 0;
+                if (basis_io) basis_io[j * bstride] = -1;
             }
             __syncthreads();
             continue;
@@ -1079,18 +1089,47 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
         }
         for (int w = tid; w < (nvar + 31) / 32; w += kFreeThreads) V.basic[w] = 0u;
         cm = free_max(sh, cm);
+        // a kept basis of this size (an earlier pass over the same members,
+        // with other atom positions) starts the simplex when its variables
+        // are distinct and in range, it has full rank and its solution is
+        // feasible; otherwise the structured start below
+        bool warm = false;
+        if (basis_io && (int64_t)m + 1 <= bstride && basis_io[j * bstride] == m) {
+            const int32_t *kept = basis_io + j * bstride + 1;
+            for (int i = tid; i < m; i += kFreeThreads) V.basis[i] = kept[i];
+            __syncthreads();
+            if (tid == 0) {
+                int ok = 1;
+                for (int q = 0; q < m && ok; ++q) {
+                    const int v = V.basis[q];
+                    if (v < 0 || v >= nvar || ((V.basic[v >> 5] >> (v & 31)) & 1u)) ok = 0;
+                    else V.basic[v >> 5] |= 1u << (v & 31);
+                }
+                sh.warm_ok = ok;
+                sh.delta = kFreeTol * cm;
+                sh.fresh = 1;
+                sh.bland = 0;
+                sh.stat = kFOk;
+            }
+            __syncthreads();
+            if (sh.warm_ok && free_refactor(sh, V, Binv, cost, m, n, s, nw) && !(sh.negx > kWarmTol)) warm = true;
+            __syncthreads();
+            if (!warm)
+                for (int w = tid; w < (nvar + 31) / 32; w += kFreeThreads) V.basic[w] = 0u;
+            __syncthreads();
+        }
         // the structured starting basis: member 0's atoms at their cheapest
         // centroid atom (lowest on ties), thread per atom; then, serially, the
         // weights they fix and the other members' north-west corners
         const int t0 = V.T[1];
-        for (int a = tid; a < t0; a += kFreeThreads) {
+        for (int a = tid; a < t0 && !warm; a += kFreeThreads) {
             int rb = 0;
             for (int r = 1; r < s; ++r)
                 if (cost[a * s + r] < cost[a * s + rb]) rb = r;
             V.basis[a] = a * s + rb;
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid == 0 && !warm) {
             sh.delta = kFreeTol * cm;
             int nb = t0;
             double *pz = V.prow;   // scratch: the weights member 0 fixes
@@ -1117,7 +1156,8 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
             sh.bland = 0;
         }
         __syncthreads();
-        if (sh.stat == kFOk && !free_refactor(sh, V, Binv, cost, m, n, s, nw) && tid == 0) sh.stat = kFInternal;
+        if (!warm && sh.stat == kFOk && !free_refactor(sh, V, Binv, cost, m, n, s, nw) && tid == 0)
+            sh.stat = kFInternal;
         __syncthreads();
         // the simplex
         const int64_t cap = o.max_pivots > 0 ? o.max_pivots : (50LL * m > 100 ? 50LL * m : 100LL);
@@ -1223,9 +1263,16 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
                 if (counts) counts[j] = 0;
                 if (cluster_status) cluster_status[j] = st;
                 if (cluster_pivots) cluster_pivots[j] = (int32_t)pivots;
+                if (basis_io) basis_io[j * bstride] = -1;
             }
             __syncthreads();
             continue;
+        }
+        // the optimal basis, for a later pass's start
+        if (basis_io) {
+            const bool fits = (int64_t)m + 1 <= bstride;
+            for (int i = tid; i < m && fits; i += kFreeThreads) basis_io[j * bstride + 1 + i] = V.basis[i];
+            if (tid == 0) basis_io[j * bstride] = fits ? m : -1;
         }
         // the solution, densely
         for (int v = tid; v < nvar; v += kFreeThreads) x[v] = 0.0;
@@ -1307,7 +1354,8 @@ size_t update_free_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax, int
 hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, int xmax, int zmax,
                               int max_members, const KOpts &o, const int32_t *labels, const double *obj_weights,
                               double *z_new, double *w_new, double *eps1, double *eps3, int32_t *counts,
-                              int32_t *obj_status, int32_t *cluster_status, int32_t *cluster_pivots, void *ws) {
+                              int32_t *obj_status, int32_t *cluster_status, int32_t *cluster_pivots,
+                              int32_t *basis_io, int64_t basis_stride, void *ws) {
     const UpdDims u = upd_dims(X.n, Z.n, X.d, xmax, zmax);
     const FreeDims f = free_dims(max_members, xmax, zmax, X.d);
     int64_t grid = 1;
@@ -1341,20 +1389,20 @@ hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, 
         if (f.lds)
             hipLaunchKernelGGL((k_free_solve<float, true>), dim3((unsigned)grid), dim3(kFreeThreads), lds, c.stream,
                                X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
-                               obj_status, cluster_status, cluster_pivots);
+                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride);
         else
             hipLaunchKernelGGL((k_free_solve<float, false>), dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream,
                                X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
-                               obj_status, cluster_status, cluster_pivots);
+                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride);
     } else {
         if (f.lds)
             hipLaunchKernelGGL((k_free_solve<double, true>), dim3((unsigned)grid), dim3(kFreeThreads), lds, c.stream,
                                X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
-                               obj_status, cluster_status, cluster_pivots);
+                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride);
         else
             hipLaunchKernelGGL((k_free_solve<double, false>), dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream,
                                X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
-                               obj_status, cluster_status, cluster_pivots);
+                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride);
     }
     return hipGetLastError();
 }

@@ -52,7 +52,7 @@ import numpy as np
 import torch
 
 from .api import (DeviceSet, Handle, Opts, d2_assign_segmented, d2_centroid_update,
-                  d2_centroid_update_free)
+                  d2_centroid_update_free, free_basis_buffer)
 
 
 class _Stream:
@@ -136,12 +136,15 @@ def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts
     seg_d = torch.as_tensor(seg, device=dev)
     zseg_d = torch.as_tensor(zseg, device=dev)
     worst = torch.zeros((), dtype=torch.int32, device=dev)
+    # each cluster's optimal basis starts its next pass (the same members
+    # within a round; a changed membership is detected and starts cold)
+    basis = free_basis_buffer(G, Z, max(len(S) for S in segments)) if free and segments else None
     for _ in range(rounds):
         labels, _, _ = d2_assign_segmented(h, G, Z, seg_d, zseg_d, opts)
         for _ in range(passes):
             if free:
                 z_new, w_new, _, _, _, _, cst = d2_centroid_update_free(h, G, Z, labels, opts,
-                                                                        weights=omega)
+                                                                        weights=omega, basis=basis)
                 if cst.numel():
                     worst = torch.maximum(worst, cst.max())
                 Z = DeviceSet(Z.offsets, z_new, w_new, Z.max_support)

@@ -206,3 +206,40 @@ def test_free_update_repeatable_bits_and_pivot_cap(d2, h):
     assert np.all(capped[5] == 3)
     np.testing.assert_array_equal(capped[1], Z.weights)
     assert np.all(np.isnan(capped[2]))
+
+
+def test_free_update_warm_start_from_kept_bases(d2, h):
+    """A second pass over the same members (moved atoms, so other costs)
+    starts from the first pass's optimal bases: same results as a cold
+    start and as the oracle, in fewer pivots.  Rows that do not fit the
+    program (another membership, garbage) are ignored."""
+    X, Z, labels = make_case(8, K=4, per=8, tlo=3, thi=8, s=6)
+    Xd = d2.DeviceSet.from_ragged(X, DEV)
+    Zd = d2.DeviceSet.from_ragged(Z, DEV)
+    lab = torch.as_tensor(labels, device=DEV)
+    basis = d2.free_basis_buffer(Xd, Zd, 8)
+    first = d2.d2_centroid_update_free(h, Xd, Zd, lab, want_pivots=True, basis=basis)
+    torch.cuda.synchronize()
+    kept = basis.cpu().numpy()
+    assert np.all(kept[:, 0] > 0)
+    # the moved atoms with the new weights: the next pass's centroids
+    Z2 = synth.RaggedSet(Z.offsets, first[0].cpu().numpy(), first[1].cpu().numpy())
+    Z2d = d2.DeviceSet.from_ragged(Z2, DEV)
+    cold = [t.cpu().numpy() for t in d2.d2_centroid_update_free(h, Xd, Z2d, lab, want_pivots=True)]
+    warm = [t.cpu().numpy() for t in d2.d2_centroid_update_free(h, Xd, Z2d, lab, want_pivots=True,
+                                                                basis=basis)]
+    torch.cuda.synchronize()
+    check_unique(X, Z2, labels, warm[:7])
+    for a, b in zip(cold[:7], warm[:7]):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-12)
+    assert warm[7].sum() < cold[7].sum(), (warm[7], cold[7])
+    # another membership with the same kept rows, and garbage rows
+    lab2 = labels.copy()
+    lab2[0], lab2[9] = lab2[9], lab2[0]
+    junk = torch.randint(-5, 10**6, basis.shape, dtype=torch.int32, device=DEV)
+    junk[:, 0] = basis[:, 0]
+    for rows in (basis, junk):
+        got = [t.cpu().numpy() for t in d2.d2_centroid_update_free(
+            h, Xd, Z2d, torch.as_tensor(lab2, device=DEV), basis=rows.clone())]
+        torch.cuda.synchronize()
+        check_unique(X, Z2, lab2, got)
