@@ -166,7 +166,8 @@ const char *d2_version(void);
  * `which` is 0 = d2_cost_tiles, 1 = d2_emd_batch, 2 = d2_assign,
  * 3 = d2_pairwise, 4 = d2_centroid_update (A = X, B = Z), 5 =
  * d2_assign_multi (A, B = the arrays of per-type sets, npairs = the number of
- * types), 6 = d2_centroid_update_free (A = X, B = Z, npairs = max_members);
+ * types), 6 = d2_centroid_update_free (A = X, B = Z, npairs = max_members),
+ * 7 = d2_merge_level (A = Z, B unused, npairs = n);
  * `npairs` is the pair count for 0 and 1, ignored for 2-4; B may be NULL for
  * d2_pairwise. */
 size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set *B,
@@ -379,6 +380,34 @@ d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z
                                   int32_t *counts, int32_t *obj_status, int32_t *cluster_status,
                                   int32_t *cluster_pivots, int32_t *basis_io, int64_t basis_stride, void *ws,
                                   size_t ws_bytes, void *stream);
+
+/* One level's merge (Alg. 3 Step 3, Sec. 2.4).  Z holds the level's
+ * centroids, the segments' centroid ranges concatenated in segment order, so
+ * that labels already carry the offset of Eq. (5).  A centroid with at least
+ * one member is kept; the kept ones are renumbered 0 .. kept-1 in index order
+ * and become the next level's objects:
+ *   labels[n]       device int32, the centroid of each level object; a label
+ *                   outside [0, Z->n) makes the object nobody's member;
+ *   omega[n]        device FP64 object weights, or NULL for all 1;
+ *   C[n0]           device int32, in/out: on entry the level object of each
+ *                   original object, on exit its inherited label (Eq. (6)),
+ *                   the new index of that object's centroid, or -1 when the
+ *                   entry is outside [0, n) or that object has no centroid;
+ *   kept            device int64 (one value), the number of kept centroids;
+ *   new_offsets     device int64 [Z->n + 1]: the first kept+1 entries are the
+ *                   atom offsets of the kept centroids in their new order;
+ *   new_points,     device, Z's dtype, room for Z's atoms (Z->offsets[Z->n]
+ *   new_weights     rows of d values, resp. that many weights): the kept
+ *                   centroids' atoms and atom weights, copied unchanged;
+ *   new_omega       device FP64 [Z->n]: the first kept entries are the kept
+ *                   centroids' weights, each the sum of its members' omega
+ *                   (Eq. (3)), added in increasing member index.
+ * No output may overlap an input.  Workspace: d2_workspace_bytes(h, 7, Z,
+ * NULL, n, NULL) bytes.  Members are grouped by a counting sort with no
+ * atomics, so repeated calls give identical bits. */
+d2_status d2_merge_level(d2_handle *h, const d2_set *Z, int64_t n, const int32_t *labels, const double *omega,
+                         int64_t n0, int32_t *C, int64_t *kept, int64_t *new_offsets, void *new_points,
+                         void *new_weights, double *new_omega, void *ws, size_t ws_bytes, void *stream);
 
 /* Nearest-centroid labelling within segments (Alg. 3 Step 2, where each
  * segment of the data is clustered on its own): object i is compared only

@@ -10,5 +10,5 @@ from ._ffi import (D2_COST_BF16_MFMA, D2_COST_F64_DIRECT, D2_INIT_AUTO, D2_INIT_
 from .api import (DeviceSet, Handle, Opts, d2_assign, d2_assign_into, d2_cost_tiles,  # noqa: F401
                   d2_emd_batch, d2_pairwise, d2_tune_pairwise, d2_workspace_bytes,
                   d2_centroid_update, d2_centroid_update_free, free_basis_buffer, constrained_d2, d2_emd_cost_batch, d2_mm_distance,
-                  d2_assign_multi, d2_assign_segmented)
+                  d2_assign_multi, d2_assign_segmented, d2_merge_level)
 from .hierarchy import hierarchical_d2  # noqa: F401,E402

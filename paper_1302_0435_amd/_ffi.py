@@ -21,14 +21,14 @@ D2_FLAG_EAGER = 1
 (D2_PAIR_OK, D2_PAIR_BAD_WEIGHTS, D2_PAIR_TOO_LARGE, D2_PAIR_PIVOT_CAP, D2_PAIR_BAD_POINTS,
  D2_PAIR_UNLABELLED, D2_PAIR_INTERNAL) = range(7)
 (WHICH_COST_TILES, WHICH_EMD_BATCH, WHICH_ASSIGN, WHICH_PAIRWISE, WHICH_UPDATE, WHICH_MULTI,
- WHICH_UPDATE_FREE) = range(7)
+ WHICH_UPDATE_FREE, WHICH_MERGE) = range(8)
 
 # Every function the header declares (checked against the header by the tests).
 EXPORTS = ["d2_create", "d2_destroy", "d2_status_string", "d2_max_support", "d2_version",
            "d2_workspace_bytes", "d2_cost_tiles", "d2_emd_batch", "d2_assign", "d2_pairwise",
            "d2_tune_pairwise", "d2_centroid_update", "d2_emd_cost_batch",
            "d2_assign_multi", "d2_assign_segmented", "d2_assign_noalloc",
-           "d2_centroid_update_free"]
+           "d2_centroid_update_free", "d2_merge_level"]
 
 
 class d2_set(ctypes.Structure):
@@ -80,13 +80,14 @@ def lib():
     L.d2_tune_pairwise.argtypes = [P, S, O, P, P, P, SZ, P, ctypes.POINTER(ctypes.c_double)]
     L.d2_centroid_update.argtypes = [P, S, S, P, P, O, P, P, P, P, P, P, SZ, P]
     L.d2_centroid_update_free.argtypes = [P, S, S, P, P, I32, O, P, P, P, P, P, P, P, P, P, I64, P, SZ, P]
+    L.d2_merge_level.argtypes = [P, S, I64, P, P, I64, P, P, P, P, P, P, P, SZ, P]
     L.d2_assign_segmented.argtypes = [P, S, S, P, I64, P, O, P, P, P, P]
     L.d2_assign_multi.argtypes = [P, I32, S, S, O, P, P, P, P, P, SZ, P]
     L.d2_emd_cost_batch.argtypes = [P, I64, P, P, P, P, P, P, I32, I32, O, P, P, P, P, P, SZ, P]
     for name in ("d2_create", "d2_destroy", "d2_cost_tiles", "d2_emd_batch", "d2_assign",
                  "d2_pairwise", "d2_max_support", "d2_tune_pairwise", "d2_centroid_update",
                  "d2_emd_cost_batch", "d2_assign_multi", "d2_assign_segmented",
-                 "d2_assign_noalloc", "d2_centroid_update_free"):
+                 "d2_assign_noalloc", "d2_centroid_update_free", "d2_merge_level"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

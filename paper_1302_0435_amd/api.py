@@ -360,6 +360,40 @@ def free_basis_buffer(X: DeviceSet, Z: DeviceSet, max_members: int) -> torch.Ten
     return torch.full((Z.n, stride), -1, dtype=torch.int32, device=Z.points.device)
 
 
+def d2_merge_level(h: Handle, Z: DeviceSet, labels: torch.Tensor, omega: Optional[torch.Tensor],
+                   C: torch.Tensor):
+    """One level's merge of Alg. 3 Step 3 (Eq. (5)-(6)): the centroids of Z
+    with members among the level objects (labels [n]) become the next
+    level's objects, renumbered in index order, each weighted by the sum of
+    its members' omega (None: 1 each); C [n0] (the level object of every
+    original object) is replaced by the inherited labels.  Returns (the next
+    level's objects as a DeviceSet, their weights [kept] f64, the new C
+    [n0] int32, host offsets [kept + 1] int64)."""
+    dev = _dev(h)
+    labels = labels.to(device=dev, dtype=torch.int32).contiguous()
+    if omega is not None:
+        omega = omega.to(device=dev, dtype=torch.float64).contiguous()
+    C = C.to(device=dev, dtype=torch.int32).clone()
+    K = Z.n
+    kept = torch.empty(1, dtype=torch.int64, device=dev)
+    off = torch.empty(K + 1, dtype=torch.int64, device=dev)
+    pts = torch.empty_like(Z.points)
+    wts = torch.empty(int(Z.points.shape[0]), dtype=Z.points.dtype, device=dev)
+    new_omega = torch.empty(max(K, 1), dtype=torch.float64, device=dev)
+    ws, nbytes = _workspace(h, _ffi.WHICH_MERGE, Z, None, labels.numel(), None)
+    z = Z.c()
+    check(_ffi.lib().d2_merge_level(h.ptr, ctypes.byref(z), labels.numel(), _ptr(labels), _ptr(omega),
+                                    C.numel(), _ptr(C), _ptr(kept), _ptr(off), _ptr(pts), _ptr(wts),
+                                    _ptr(new_omega), _ptr(ws), nbytes, _stream(dev)),
+          "d2_merge_level")
+    q = int(kept.item())
+    off_h = off[:q + 1].cpu().numpy()
+    sizes = off_h[1:] - off_h[:-1]
+    na = int(off_h[-1])
+    G = DeviceSet(off[:q + 1].clone(), pts[:na].clone(), wts[:na].clone(), int(sizes.max()) if q else 1)
+    return G, new_omega[:q].clone(), C, off_h
+
+
 def constrained_d2(h: Handle, X: DeviceSet, Z: DeviceSet, opts: Optional[Opts] = None,
                    max_rounds: int = 20, max_passes: int = 10, rtol: float = 1e-9):
     """Constrained D2-clustering (Alg. 2 with Step 3* in place of Step 3).

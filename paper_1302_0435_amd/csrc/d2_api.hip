@@ -342,6 +342,7 @@ size_t d2_workspace_bytes(d2_handle *h, int which, const d2_set *A, const d2_set
             return 0;
         return d2::update_free_ws_bytes(A->n, B->n, A->d, ms(A), ms(B), (int)npairs, h->cu_count, nullptr);
     }
+    if (which == 7) return npairs >= 0 ? d2::merge_ws_bytes(npairs, A->n) : 0;
     if (which == 5 && B) {
         d2::AssignPlan plans[kMaxTypes];
         size_t ab = 0;
@@ -558,6 +559,25 @@ d2_status d2_centroid_update_free(d2_handle *h, const d2_set *X, const d2_set *Z
                                           max_members, k, labels, obj_weights, z_new, w_new, eps_step1, eps_step3,
                                           counts, obj_status, cluster_status, cluster_pivots, basis_io,
                                           basis_stride, ws);
+    return e == hipSuccess ? D2_OK : D2_EHIP;
+}
+
+d2_status d2_merge_level(d2_handle *h, const d2_set *Z, int64_t n, const int32_t *labels, const double *omega,
+                         int64_t n0, int32_t *C, int64_t *kept, int64_t *new_offsets, void *new_points,
+                         void *new_weights, double *new_omega, void *ws, size_t ws_bytes, void *stream) {
+    if (!h || !set_ok(Z) || n < 0 || n0 < 0) return D2_EINVAL;
+    if (Z->n > INT32_MAX) return D2_EUNSUPPORTED;
+    if (!kept || !new_offsets) return D2_EINVAL;
+    if (n > 0 && !labels) return D2_EINVAL;
+    if (n0 > 0 && !C) return D2_EINVAL;
+    if (Z->n > 0 && (!new_points || !new_weights || !new_omega)) return D2_EINVAL;
+    if (Z->n > 0 && (new_points == Z->points || new_weights == Z->weights)) return D2_EINVAL;
+    if (n0 > 0 && n > 0 && (const void *)C == (const void *)labels) return D2_EINVAL;
+    const size_t need = d2::merge_ws_bytes(n, Z->n);
+    if (!ws || ws_bytes < need) return D2_EWORKSPACE;
+    if (bind_device(h) != D2_OK) return D2_EHIP;
+    hipError_t e = d2::launch_merge_level(ctx(h, (hipStream_t)stream), kset(Z), n, labels, omega, n0, C, kept,
+                                          new_offsets, new_points, new_weights, new_omega, ws);
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 

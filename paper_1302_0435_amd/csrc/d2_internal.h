@@ -127,6 +127,13 @@ hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, 
                               int32_t *obj_status, int32_t *cluster_status, int32_t *cluster_pivots,
                               int32_t *basis_io, int64_t basis_stride, void *ws);
 
+// Alg. 3 Step 3 for one level: kept centroids, their weights and atoms,
+// inherited labels.
+size_t merge_ws_bytes(int64_t n, int64_t K);
+hipError_t launch_merge_level(const LaunchCtx &c, const KSet &Z, int64_t n, const int32_t *labels,
+                              const double *omega, int64_t n0, int32_t *C, int64_t *kept, int64_t *new_off,
+                              void *new_points, void *new_weights, double *new_omega, void *ws);
+
 // Labelling within segments: object i against the centroids
 // zoff[seg[i]] .. zoff[seg[i]+1] of Z only.
 hipError_t launch_assign_seg(const LaunchCtx &c, int cls, const KSet &X, const KSet &Z, const KOpts &o,

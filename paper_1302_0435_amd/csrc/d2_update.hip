@@ -1407,4 +1407,132 @@ hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, 
     return hipGetLastError();
 }
 
+// ================================================= merging a level
+//
+// Alg. 3 Step 3 for one level (Sec. 2.4): the centroids with members are
+// kept and renumbered in order (the segments' centroid ranges are
+// consecutive, so this is the offset of Eq. (5)), each kept centroid's
+// weight is the sum of its members' weights (Eq. (3)), its atoms are copied
+// into the next level's object set, and every original object inherits the
+// new label of its level object (Eq. (6)).  Members are grouped by the same
+// counting sort as the update, so the weight sums run in member order.
+
+namespace {
+
+// new_index[j] = kept centroids before j (j = 0..K; new_index[K] = the kept
+// count), then the kept centroids' atom offsets in their new order.
+__global__ __launch_bounds__(1024) void k_merge_index(const int64_t *pre, int64_t K, int64_t tiles,
+                                                       const int64_t *zoff, int64_t *new_index, int64_t *new_off,
+                                                       int64_t *kept) {
+    for (int64_t j = threadIdx.x; j <= K; j += blockDim.x)
+        new_index[j] = (j < K && pre[(j + 1) * tiles] > pre[j * tiles]) ? 1 : 0;
+    __syncthreads();
+    block_exclusive_scan(new_index, K + 1);
+    __syncthreads();
+    const int64_t q = new_index[K];
+    for (int64_t j = threadIdx.x; j < K; j += blockDim.x)
+        if (pre[(j + 1) * tiles] > pre[j * tiles]) new_off[new_index[j]] = zoff[j + 1] - zoff[j];
+    if (threadIdx.x == 0) new_off[q] = 0;
+    __syncthreads();
+    block_exclusive_scan(new_off, q + 1);
+    if (threadIdx.x == 0) *kept = q;
+}
+
+// Kept centroid weights: its members' weights summed in member order.
+__global__ void k_merge_weights(const int64_t *pre, const int64_t *perm, int64_t K, int64_t tiles,
+                                const double *omega, const int64_t *new_index, double *new_omega) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = pre[j * tiles], e = pre[(j + 1) * tiles];
+        if (e <= b) continue;
+        double sum = 0.0;
+        for (int64_t q = b; q < e; ++q) sum += omega ? omega[perm[q]] : 1.0;
+        new_omega[new_index[j]] = sum;
+    }
+}
+
+// Atoms of the kept centroids, in their new order (one wave per centroid).
+template <typename T>
+__global__ void k_merge_gather(const int64_t *zoff, const T *zpts, const T *zw, int d, int64_t K,
+                               const int64_t *pre, int64_t tiles, const int64_t *new_index,
+                               const int64_t *new_off, T *npts, T *nw) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t j = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; j < K;
+         j += (int64_t)gridDim.x * (blockDim.x / 64)) {
+        if (pre[(j + 1) * tiles] <= pre[j * tiles]) continue;
+        const int64_t src = zoff[j], dst = new_off[new_index[j]], s = zoff[j + 1] - zoff[j];
+        for (int64_t e = lane; e < s * d; e += 64) npts[dst * d + e] = zpts[src * d + e];
+        for (int64_t a = lane; a < s; a += 64) nw[dst + a] = zw[src + a];
+    }
+}
+
+// Eq. (6): an original object's new label is that of its level object.
+__global__ void k_merge_inherit(const int32_t *labels, int64_t n, int64_t K, const int64_t *new_index, int32_t *C,
+                                int64_t n0) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n0; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = C[i];
+        const int32_t lab = (c >= 0 && c < n) ? labels[c] : -1;
+        C[i] = (lab >= 0 && lab < K) ? (int32_t)new_index[lab] : -1;
+    }
+}
+
+}  // namespace
+
+size_t merge_ws_bytes(int64_t n, int64_t K) {
+    const UpdDims u = upd_dims(n, K, 1, 1, 1);
+    const int64_t nn = n > 0 ? n : 1;
+    return align256((size_t)u.entries * 8) + align256((size_t)u.sblocks * 8) + align256((size_t)nn * 8) +
+           align256((size_t)nn * 4) + align256((size_t)(K + 1) * 8);
+}
+
+hipError_t launch_merge_level(const LaunchCtx &c, const KSet &Z, int64_t n, const int32_t *labels,
+                              const double *omega, int64_t n0, int32_t *C, int64_t *kept, int64_t *new_off,
+                              void *new_points, void *new_weights, double *new_omega, void *ws) {
+    const int64_t K = Z.n;
+    const UpdDims u = upd_dims(n, K, 1, 1, 1);
+    char *p = (char *)ws;
+    int64_t *cnt = (int64_t *)p;
+    p += align256((size_t)u.entries * 8);
+    int64_t *bsum = (int64_t *)p;
+    p += align256((size_t)u.sblocks * 8);
+    int64_t *perm = (int64_t *)p;
+    p += align256((size_t)(n > 0 ? n : 1) * 8);
+    int32_t *skey = (int32_t *)p;
+    p += align256((size_t)(n > 0 ? n : 1) * 4);
+    int64_t *new_index = (int64_t *)p;
+    const unsigned wave_blocks = (unsigned)((u.tiles + 3) / 4);
+    const int64_t fill_grid = (u.entries + 255) / 256 < 4096 ? (u.entries + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_upd_fill, dim3((unsigned)fill_grid), dim3(256), 0, c.stream, cnt, u.entries);
+    if (n > 0)
+        hipLaunchKernelGGL(k_upd_count, dim3(wave_blocks), dim3(256), 0, c.stream, labels, n, K, u.tiles, cnt,
+                           (int32_t *)nullptr);
+    hipLaunchKernelGGL(k_upd_scan_blocks, dim3((unsigned)u.sblocks), dim3(256), 0, c.stream, cnt, u.entries, bsum);
+    hipLaunchKernelGGL(k_upd_scan_top, dim3(1), dim3(1024), 0, c.stream, bsum, u.sblocks);
+    hipLaunchKernelGGL(k_upd_scan_apply, dim3((unsigned)u.sblocks), dim3(256), 0, c.stream, cnt, u.entries, bsum);
+    if (n > 0)
+        hipLaunchKernelGGL(k_upd_place, dim3(wave_blocks), dim3(256), 0, c.stream, labels, n, K, u.tiles, cnt,
+                           perm, skey);
+    hipLaunchKernelGGL(k_merge_index, dim3(1), dim3(1024), 0, c.stream, cnt, K, u.tiles, Z.off, new_index, new_off,
+                       kept);
+    if (K > 0) {
+        const int64_t g = (K + 255) / 256 < 4096 ? (K + 255) / 256 : 4096;
+        hipLaunchKernelGGL(k_merge_weights, dim3((unsigned)g), dim3(256), 0, c.stream, cnt, perm, K, u.tiles, omega,
+                           new_index, new_omega);
+        const int64_t gw = (K + 3) / 4 < 65536 ? (K + 3) / 4 : 65536;
+        if (Z.dtype == D2_F32)
+            hipLaunchKernelGGL(k_merge_gather<float>, dim3((unsigned)gw), dim3(256), 0, c.stream, Z.off,
+                               (const float *)Z.pts, (const float *)Z.w, Z.d, K, cnt, u.tiles, new_index, new_off,
+                               (float *)new_points, (float *)new_weights);
+        else
+            hipLaunchKernelGGL(k_merge_gather<double>, dim3((unsigned)gw), dim3(256), 0, c.stream, Z.off,
+                               (const double *)Z.pts, (const double *)Z.w, Z.d, K, cnt, u.tiles, new_index,
+                               new_off, (double *)new_points, (double *)new_weights);
+    }
+    if (n0 > 0) {
+        const int64_t g = (n0 + 255) / 256 < 4096 ? (n0 + 255) / 256 : 4096;
+        hipLaunchKernelGGL(k_merge_inherit, dim3((unsigned)g), dim3(256), 0, c.stream, labels, n, K, new_index, C,
+                           n0);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace d2

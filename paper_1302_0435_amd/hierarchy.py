@@ -1,18 +1,19 @@
 """Hierarchical D2-clustering of Alg. 3 on one GPU.
 
 The paper runs each level as three synchronised steps between a master and
-slave processors.  Here the master's work (segment bookkeeping, the merge
-of Eq. (5) and the inheritance of Eq. (6)) is host control over small
-integer arrays.  All distance and update work of the slaves, and of the
-segmentation, runs in the library on the GPU, every segment of a level at
-once:
+slave processors.  Here the master's segment bookkeeping is host control
+over small integer arrays.  All distance and update work of the slaves, the
+segmentation's, and the merge, runs in the library on the GPU, every
+segment of a level at once:
 
 * ``d2_assign_segmented`` labels each object among its own segment's
   centroids;
 * ``d2_centroid_update_free`` with object weights solves Alg. 1's Step 1
   program for every cluster (the centroid weights free) and moves every
   centroid by Eq. (4); the binary splits use ``d2_centroid_update`` (the
-  centroid weights held).
+  centroid weights held);
+* ``d2_merge_level`` keeps the centroids with members, sums their weights
+  and lets every original object inherit its new label.
 
 Per level:
 
@@ -52,7 +53,7 @@ import numpy as np
 import torch
 
 from .api import (DeviceSet, Handle, Opts, d2_assign_segmented, d2_centroid_update,
-                  d2_centroid_update_free, free_basis_buffer)
+                  d2_centroid_update_free, d2_merge_level, free_basis_buffer)
 
 
 class _Stream:
@@ -69,10 +70,10 @@ class _Stream:
         return float(self._u[self._k - 1])
 
 
-def _gather(G: DeviceSet, g_off: np.ndarray, objs, keep_weights: bool = False) -> tuple:
+def _gather(G: DeviceSet, g_off: np.ndarray, objs) -> tuple:
     """A set made of the atoms of objects `objs` of G (in that order), with
-    uniform weights or, with `keep_weights`, G's own; returns (DeviceSet,
-    host offsets)."""
+    uniform weights (the starting centroids of a clustering); returns
+    (DeviceSet, host offsets)."""
     objs = np.asarray(objs, dtype=np.int64)
     sizes = g_off[1:][objs] - g_off[:-1][objs]
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -81,10 +82,7 @@ def _gather(G: DeviceSet, g_off: np.ndarray, objs, keep_weights: bool = False) -
     dev = G.points.device
     rows_d = torch.as_tensor(rows, device=dev)
     pts = G.points.index_select(0, rows_d)
-    if keep_weights:
-        w = G.weights.to(pts.dtype).index_select(0, rows_d)
-    else:
-        w = torch.as_tensor(np.repeat(1.0 / np.maximum(sizes, 1), sizes), device=dev)
+    w = torch.as_tensor(np.repeat(1.0 / np.maximum(sizes, 1), sizes), device=dev)
     Z = DeviceSet(torch.as_tensor(off, device=dev), pts.contiguous(), w.contiguous(),
                   int(sizes.max()) if len(objs) else 1)
     return Z, off
@@ -154,7 +152,7 @@ def _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes, opts
     labels, _, _ = d2_assign_segmented(h, G, Z, seg_d, zseg_d, opts)
     if int(worst.item()) != 0:
         raise RuntimeError(f"a cluster's centroid program failed (status {int(worst.item())})")
-    return Z, z_off, zseg, labels.cpu().numpy()
+    return Z, z_off, zseg, labels
 
 
 def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
@@ -176,7 +174,7 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
     G = X if X.points.dtype == torch.float64 else X.with_points(X.points.double())
     g_off = G.offsets.cpu().numpy()
     omega = torch.ones(G.n, dtype=torch.float64, device=G.points.device)
-    C = np.arange(G.n)
+    C = torch.arange(G.n, dtype=torch.int32, device=G.points.device)
     levels = []
     for _ in range(max_levels):
         # Step 1: segmentation by binary splits
@@ -192,6 +190,7 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
                 starts.append([int(S[a]), int(S[b])])
             _, _, zseg, labels = _cluster_segments(h, G, g_off, omega, [segments[q] for q in split],
                                                    starts, rounds, passes, opts, stats)
+            labels = labels.cpu().numpy()
             out = []
             where = {q: mu for mu, q in enumerate(split)}
             for q, S in enumerate(segments):
@@ -214,22 +213,15 @@ def hierarchical_d2(h: Handle, X: DeviceSet, tau: int, e: int, k: int, uniforms,
             starts.append([int(S[p]) for p in pos[:math.ceil(S.size / e)]])
         Z, z_off, zseg, labels = _cluster_segments(h, G, g_off, omega, segments, starts, rounds, passes,
                                                    opts, stats, free=update == "free")
-        if labels.min() < 0:
+        if int(labels.min().item()) < 0:
             raise RuntimeError("an object's transport problem failed; check its weights and points")
-        # Step 3: merge (Eq. (5)), weights, inheritance (Eq. (6))
-        # centroids with members, in segment order (a segment's centroids
-        # are a contiguous range, so index order is segment order)
-        kept = np.flatnonzero(np.bincount(labels, minlength=int(zseg[-1])) > 0)
-        new_index = np.full(int(zseg[-1]), -1, dtype=np.int64)
-        new_index[kept] = np.arange(len(kept))
-        level_label = new_index[labels]
-        w_host = omega.cpu().numpy()
-        new_w = np.bincount(level_label, weights=w_host, minlength=len(kept))
-        C = level_label[C]
-        levels.append({"objects": G.n, "segments": len(segments), "centroids": len(kept),
+        # Step 3: merge (Eq. (5)), weights, inheritance (Eq. (6)); a
+        # segment's centroids are a contiguous range, so index order is
+        # segment order
+        n_level = G.n
+        G, omega, C, g_off = d2_merge_level(h, Z, labels, omega, C)
+        levels.append({"objects": n_level, "segments": len(segments), "centroids": G.n,
                        "max_segment": int(max(S.size for S in segments))})
-        G, g_off = _gather(Z, z_off, kept, keep_weights=True)
-        omega = torch.as_tensor(new_w, device=G.points.device)
-        if len(kept) <= k or len(kept) == levels[-1]["objects"]:
+        if G.n <= k or G.n == n_level:
             break
-    return G, C.astype(np.int32), omega.cpu().numpy(), levels
+    return G, C.cpu().numpy(), omega.cpu().numpy(), levels
