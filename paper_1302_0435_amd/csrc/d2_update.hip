@@ -628,9 +628,10 @@ hipError_t launch_update(const LaunchCtx &c, int cls, const KSet &X, const KSet 
 //   start    a basis the caller kept from an earlier pass over the same
 //            members, when it still is one and is feasible; else member 0
 //            sends each atom to its cheapest centroid atom, which fixes p_z
-//            (all s weights basic), and every later member is the
-//            north-west corner from its weights to p_z.  That basis matrix
-//            is block triangular with non-singular blocks, so it is a basis;
+//            (all s weights basic), and every later member's transport
+//            problem from its weights to p_z gets a least-cost spanning tree.
+//            That basis matrix is block triangular with non-singular blocks,
+//            so it is a basis;
 //   pivots   explicit inverse of the basis: Dantzig's entering column
 //            (Bland's after a run of degenerate pivots), the column
 //            B^-1 a_q, the ratio test (least ratio, then lowest variable),
@@ -1119,8 +1120,9 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
             __syncthreads();
         }
         // the structured starting basis: member 0's atoms at their cheapest
-        // centroid atom (lowest on ties), thread per atom; then, serially, the
-        // weights they fix and the other members' north-west corners
+        // centroid atom (lowest on ties), thread per atom, and the weights p_z
+        // they fix; then every later member's transport problem from its
+        // weights to p_z by the least-cost rule, thread per member
         const int t0 = V.T[1];
         for (int a = tid; a < t0 && !warm; a += kFreeThreads) {
             int rb = 0;
@@ -1129,29 +1131,55 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
             V.basis[a] = a * s + rb;
         }
         __syncthreads();
+        double *pz = V.prow;   // scratch until the reinversion: the weights member 0 fixes
         if (tid == 0 && !warm) {
             sh.delta = kFreeTol * cm;
-            int nb = t0;
-            double *pz = V.prow;   // scratch: the weights member 0 fixes
             for (int r = 0; r < s; ++r) pz[r] = 0.0;
             for (int a = 0; a < t0; ++a) pz[V.basis[a] - a * s] += V.b[a];
-            for (int r = 0; r < s; ++r) V.basis[nb++] = nw + r;
-            for (int k = 1; k < n; ++k) {
-                const int tk = V.T[k + 1] - V.T[k];
-                int a = 0, r = 0;
-                double ra = V.b[V.T[k]], rc = pz[0];
-                for (int step = 0; step < tk + s; ++step) {
-                    V.basis[nb++] = s * (V.T[k] + a) + r;
-                    const double fl = fmin(ra, rc);
-                    ra -= fl;
-                    rc -= fl;
-                    if (a == tk - 1 && r == s - 1) break;
-                    if ((ra <= rc && a < tk - 1) || r == s - 1) { ++a; ra = V.b[V.T[k] + a]; }
-                    else { ++r; rc = pz[r]; }
+            for (int r = 0; r < s; ++r) V.basis[t0 + r] = nw + r;
+            sh.stat = kFOk;
+        }
+        __syncthreads();
+        // Least cost: the cheapest cell of an open row and an open column
+        // (lowest row, then column, on ties) takes all that its row or column
+        // has left and closes the row when the row runs out first or both do
+        // (unless it is the last open row), else the column.  Each cell
+        // closes a line, so the t + s - 1 cells hold no cycle: a spanning
+        // tree, like the north-west corner's, and the basis stays block
+        // triangular with non-singular blocks.  Remaining masses go to
+        // alpha (rows) and x_B (member k's columns at (k - 1) s), both free
+        // until the reinversion.
+        for (int k = 1 + tid; k < n && !warm; k += kFreeThreads) {
+            const int r0 = V.T[k], tk = V.T[k + 1] - r0;
+            double *remr = V.alpha + r0, *remc = V.xB + (int64_t)(k - 1) * s;
+            for (int a = 0; a < tk; ++a) remr[a] = V.b[r0 + a];
+            for (int r = 0; r < s; ++r) remc[r] = pz[r];
+            uint64_t ron = tk == 64 ? ~0ull : (1ull << tk) - 1ull;
+            uint64_t con = s == 64 ? ~0ull : (1ull << s) - 1ull;
+            int nb = t0 + s + (r0 - t0) + (k - 1) * (s - 1);
+            for (int cell = 0; cell < tk + s - 1; ++cell) {
+                double best = INFINITY;
+                int ba = -1, br = -1;
+                for (uint64_t ra = ron; ra; ra &= ra - 1) {
+                    const int a = __builtin_ctzll(ra);
+                    const double *crow = cost + (int64_t)s * (r0 + a);
+                    for (uint64_t rc = con; rc; rc &= rc - 1) {
+                        const int r = __builtin_ctzll(rc);
+                        if (crow[r] < best || ba < 0) { best = crow[r]; ba = a; br = r; }
+                    }
                 }
+                if (ba < 0) { sh.stat = kFInternal; break; }
+                V.basis[nb++] = s * (r0 + ba) + br;
+                const double fl = fmin(remr[ba], remc[br]);
+                remr[ba] -= fl;
+                remc[br] -= fl;
+                if ((remr[ba] <= remc[br] && __popcll(ron) > 1) || __popcll(con) == 1) ron &= ~(1ull << ba);
+                else con &= ~(1ull << br);
             }
-            sh.stat = nb == m ? kFOk : kFInternal;
-            for (int q = 0; q < nb && q < m; ++q) V.basic[V.basis[q] >> 5] |= 1u << (V.basis[q] & 31);
+        }
+        __syncthreads();
+        if (tid == 0 && !warm && sh.stat == kFOk) {
+            for (int q = 0; q < m; ++q) V.basic[V.basis[q] >> 5] |= 1u << (V.basis[q] & 31);
             sh.fresh = 1;
             sh.bland = 0;
         }
