@@ -766,7 +766,29 @@ struct FreeShared {
     int cr[kFreeWaves], cc[kFreeWaves];
     int n, m, stat, p, fresh, bland, warm_ok;
     double delta, dq, negx;
+    long long next;   // the cluster this workgroup takes next
 };
+
+// The next slot of the launch's queue: clusters go to workgroups as they
+// become free, largest member counts first, so the large programs start
+// early and a workgroup that drew one takes fewer others.  Every thread of
+// the workgroup calls it.
+__device__ __forceinline__ int64_t free_grab(FreeShared &sh, unsigned long long *queue) {
+    __syncthreads();   // every thread is done with the previous cluster's sh.next
+    if (threadIdx.x == 0) sh.next = (long long)atomicAdd(queue, 1ull);
+    __syncthreads();
+    return (int64_t)sh.next;
+}
+
+// Queue order key of cluster j: clusters with more members first (a
+// counting sort on nmax - members, stable in j); counts beyond nmax, which
+// are rejected at once, go first.
+__global__ void k_free_keys(const int64_t *pre, int64_t K, int64_t tiles, int nmax, int32_t *key) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < K; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t members = pre[(j + 1) * tiles] - pre[j * tiles];
+        key[j] = members > nmax ? 0 : (int32_t)(nmax - members);
+    }
+}
 
 // Block-wide (value, key) minimum, lowest key among equal values; keys of
 // INT32_MAX are no candidates.  Every thread receives the result.
@@ -978,7 +1000,8 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
                                                              double *w_new, double *eps1, double *eps3,
                                                              int32_t *counts, int32_t *obj_status,
                                                              int32_t *cluster_status, int32_t *cluster_pivots,
-                                                             int32_t *basis_io, int64_t bstride) {
+                                                             int32_t *basis_io, int64_t bstride,
+                                                             unsigned long long *queue, const int64_t *order) {
     extern __shared__ __align__(16) char free_lds[];
     __shared__ FreeShared sh;
     const int tid = threadIdx.x;
@@ -987,7 +1010,8 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
     double *x = cost + f.vmax;
     const FreeVec V = free_vec(L ? free_lds : (char *)(x + f.vmax), f.lay);
     const int d = X.d;
-    for (int64_t j = blockIdx.x; j < Z.n; j += gridDim.x) {
+    for (int64_t slot = free_grab(sh, queue); slot < Z.n; slot = free_grab(sh, queue)) {
+        const int64_t j = order[slot];
         const int64_t pb = pre[j * tiles], pe = pre[(j + 1) * tiles];
         const int64_t z0 = Z.off[j];
         const int s = (int)(Z.off[j + 1] - z0);
@@ -1359,6 +1383,15 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
 
 }  // namespace
 
+// Workspace of the clusters' queue order (a counting sort of K clusters
+// over nmax + 1 keys).
+size_t free_queue_bytes(int64_t K, int nmax) {
+    const UpdDims q = upd_dims(K, (int64_t)nmax + 1, 1, 1, 1);
+    const int64_t k1 = K > 0 ? K : 1;
+    return align256((size_t)k1 * 4) + align256((size_t)q.entries * 8) + align256((size_t)q.sblocks * 8) +
+           align256((size_t)k1 * 8) + align256((size_t)k1 * 4);
+}
+
 size_t update_free_slab_bytes(int max_members, int xmax, int zmax, int d) {
     return free_dims(max_members, xmax, zmax, d).slab;
 }
@@ -1374,9 +1407,11 @@ size_t update_free_ws_bytes(int64_t n, int64_t K, int d, int xmax, int zmax, int
     if (grid > K) grid = K;
     if (grid < 1) grid = 1;
     if (grid_out) *grid_out = grid;
-    // grouping arrays (counts, block sums, order, keys) then the slabs
+    // grouping arrays (counts, block sums, order, keys), the queue counter
+    // and the clusters' queue order (keys, counts, block sums, order,
+    // sorted keys), then the slabs
     return align256((size_t)u.entries * 8) + align256((size_t)u.sblocks * 8) + align256((size_t)(n > 0 ? n : 1) * 8) +
-           align256((size_t)(n > 0 ? n : 1) * 4) + (size_t)grid * f.slab;
+           align256((size_t)(n > 0 ? n : 1) * 4) + align256(8) + free_queue_bytes(K, f.nmax) + (size_t)grid * f.slab;
 }
 
 hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, int xmax, int zmax,
@@ -1397,10 +1432,25 @@ hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, 
     p += align256((size_t)(X.n > 0 ? X.n : 1) * 8);
     int32_t *skey = (int32_t *)p;
     p += align256((size_t)(X.n > 0 ? X.n : 1) * 4);
+    unsigned long long *queue = (unsigned long long *)p;
+    p += align256(8);
+    const UpdDims q = upd_dims(Z.n, (int64_t)f.nmax + 1, 1, 1, 1);
+    const int64_t k1 = Z.n > 0 ? Z.n : 1;
+    int32_t *qkey = (int32_t *)p;
+    p += align256((size_t)k1 * 4);
+    int64_t *qcnt = (int64_t *)p;
+    p += align256((size_t)q.entries * 8);
+    int64_t *qbsum = (int64_t *)p;
+    p += align256((size_t)q.sblocks * 8);
+    int64_t *order = (int64_t *)p;
+    p += align256((size_t)k1 * 8);
+    int32_t *qskey = (int32_t *)p;
+    p += align256((size_t)k1 * 4);
     char *slabs = p;
     const unsigned wave_blocks = (unsigned)((u.tiles + 3) / 4);
     const int64_t fill_grid = (u.entries + 255) / 256 < 4096 ? (u.entries + 255) / 256 : 4096;
     hipLaunchKernelGGL(k_upd_fill, dim3((unsigned)fill_grid), dim3(256), 0, c.stream, cnt, u.entries);
+    hipLaunchKernelGGL(k_upd_fill, dim3(1), dim3(64), 0, c.stream, (int64_t *)queue, (int64_t)1);
     if (X.n > 0)
         hipLaunchKernelGGL(k_upd_count, dim3(wave_blocks), dim3(256), 0, c.stream, labels, X.n, Z.n, u.tiles, cnt,
                            obj_status);
@@ -1412,25 +1462,42 @@ hipError_t launch_update_free(const LaunchCtx &c, const KSet &X, const KSet &Z, 
                            perm, skey);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || Z.n == 0) return e;
+    // the queue order: clusters by member count, largest first
+    {
+        const unsigned kb = (unsigned)((Z.n + 255) / 256 < 4096 ? (Z.n + 255) / 256 : 4096);
+        hipLaunchKernelGGL(k_free_keys, dim3(kb), dim3(256), 0, c.stream, cnt, Z.n, u.tiles, f.nmax, qkey);
+        const int64_t qfill = (q.entries + 255) / 256 < 4096 ? (q.entries + 255) / 256 : 4096;
+        const unsigned qwave = (unsigned)((q.tiles + 3) / 4);
+        hipLaunchKernelGGL(k_upd_fill, dim3((unsigned)qfill), dim3(256), 0, c.stream, qcnt, q.entries);
+        hipLaunchKernelGGL(k_upd_count, dim3(qwave), dim3(256), 0, c.stream, qkey, Z.n, q.K, q.tiles, qcnt,
+                           (int32_t *)nullptr);
+        hipLaunchKernelGGL(k_upd_scan_blocks, dim3((unsigned)q.sblocks), dim3(256), 0, c.stream, qcnt, q.entries,
+                           qbsum);
+        hipLaunchKernelGGL(k_upd_scan_top, dim3(1), dim3(1024), 0, c.stream, qbsum, q.sblocks);
+        hipLaunchKernelGGL(k_upd_scan_apply, dim3((unsigned)q.sblocks), dim3(256), 0, c.stream, qcnt, q.entries,
+                           qbsum);
+        hipLaunchKernelGGL(k_upd_place, dim3(qwave), dim3(256), 0, c.stream, qkey, Z.n, q.K, q.tiles, qcnt, order,
+                           qskey);
+    }
     const size_t lds = f.lds ? f.vec : 0;
     if (X.dtype == D2_F32) {
         if (f.lds)
             hipLaunchKernelGGL((k_free_solve<float, true>), dim3((unsigned)grid), dim3(kFreeThreads), lds, c.stream,
                                X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
-                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride);
+                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride, queue, order);
         else
             hipLaunchKernelGGL((k_free_solve<float, false>), dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream,
                                X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
-                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride);
+                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride, queue, order);
     } else {
         if (f.lds)
             hipLaunchKernelGGL((k_free_solve<double, true>), dim3((unsigned)grid), dim3(kFreeThreads), lds, c.stream,
                                X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
-                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride);
+                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride, queue, order);
         else
             hipLaunchKernelGGL((k_free_solve<double, false>), dim3((unsigned)grid), dim3(kFreeThreads), 0, c.stream,
                                X, Z, o, cnt, perm, u.tiles, f, slabs, obj_weights, z_new, w_new, eps1, eps3, counts,
-                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride);
+                               obj_status, cluster_status, cluster_pivots, basis_io, basis_stride, queue, order);
     }
     return hipGetLastError();
 }
