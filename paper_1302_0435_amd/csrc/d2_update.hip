@@ -936,6 +936,43 @@ __device__ __forceinline__ void free_eta(FreeShared &sh, const FreeVec &V, doubl
     }
 }
 
+// Whether the current basis and its updated x_B and y already certify the
+// optimum found by pricing, so that no reinversion is needed before it is
+// declared: every row of the program (member rows, every coupling row,
+// sum p_z = 1) holds within kCertTol for x_B scattered into x, and every
+// basic variable's reduced cost is within ctol of 0, so the pricing that
+// found no entering column priced with accurate duals.  x is scratch.
+constexpr double kCertTol = 1e-14;
+__device__ __forceinline__ bool free_certified(FreeShared &sh, const FreeVec &V, const double *cost, double *x,
+                                               int m, int n, int s, int nw, int sumt, double ctol) {
+    const int tid = threadIdx.x, nvar = nw + s;
+    for (int v = tid; v < nvar; v += kFreeThreads) x[v] = 0.0;
+    __syncthreads();
+    for (int i = tid; i < m; i += kFreeThreads) x[V.basis[i]] = V.xB[i];
+    __syncthreads();
+    double pr = 0.0, du = 0.0;
+    for (int a = tid; a < sumt; a += kFreeThreads) {
+        double acc = 0.0;
+        for (int r = 0; r < s; ++r) acc += x[s * a + r];
+        pr = fmax(pr, fabs(acc - V.b[a]));
+    }
+    for (int e = tid; e < n * s; e += kFreeThreads) {
+        const int k = e / s, r = e - k * s;
+        double acc = 0.0;
+        for (int a = V.T[k]; a < V.T[k + 1]; ++a) acc += x[s * a + r];
+        pr = fmax(pr, fabs(acc - x[nw + r]));
+    }
+    if (tid == 0) {
+        double acc = 0.0;
+        for (int r = 0; r < s; ++r) acc += x[nw + r];
+        pr = fmax(pr, fabs(acc - 1.0));
+    }
+    for (int i = tid; i < m; i += kFreeThreads) du = fmax(du, fabs(free_reduced(V, cost, V.basis[i], n, s, nw, sumt)));
+    pr = free_max(sh, pr);
+    du = free_max(sh, du);
+    return pr <= kCertTol && du <= ctol;
+}
+
 // Rebuild B^-1 from the basis by pivoting its columns in, one by one, from
 // the identity (each onto the untaken row of largest |entry|, the lowest on
 // ties), then x_B = B^-1 b, c_B and y = c_B B^-1.  Returns false when a
@@ -1233,6 +1270,8 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
             free_argmin(sh, bv, bq);
             if (bq == INT32_MAX) {
                 if (sh.fresh) break;   // optimal with a freshly rebuilt B^-1
+                // or with an updated one whose vertex and duals check out
+                if (free_certified(sh, V, cost, x, m, n, s, nw, sumt, 1e-2 * delta)) break;
                 __syncthreads();
                 if (!free_refactor(sh, V, Binv, cost, m, n, s, nw)) {
                     if (tid == 0) sh.stat = kFInternal;
