@@ -243,3 +243,42 @@ def test_free_update_warm_start_from_kept_bases(d2, h):
             h, Xd, Z2d, torch.as_tensor(lab2, device=DEV), basis=rows.clone())]
         torch.cuda.synchronize()
         check_unique(X, Z2, lab2, got)
+
+
+def test_free_update_large_programs_in_the_slab(d2, h):
+    """Two clusters of 48 members (m about 1,300 rows), too large for the
+    LDS variant: the slab-resident kernel, past the periodic reinversion
+    (over 256 pivots), against the LP optimum from HiGHS on the oracle's
+    program (scipy's linprog), and the device's weights checked to reach
+    it with fixed-weight transport problems."""
+    from scipy.optimize import linprog
+    from oracle.free_update import cluster_lp
+    X, Z, labels = make_case(9, K=2, per=48, tlo=8, thi=16, s=16, d=8)
+    Xd = d2.DeviceSet.from_ragged(X, DEV)
+    Zd = d2.DeviceSet.from_ragged(Z, DEV)
+    out = d2.d2_centroid_update_free(h, Xd, Zd, torch.as_tensor(labels, device=DEV), want_pivots=True)
+    torch.cuda.synchronize()
+    z, w, e1, e3, cnt, st, cst, piv = [t.cpu().numpy() for t in out]
+    assert np.all(st == 0) and np.all(cst == 0) and np.all(cnt == 48)
+    assert piv.max() > 256, piv
+    for j in range(Z.n):
+        a0, a1 = int(Z.offsets[j]), int(Z.offsets[j + 1])
+        zo = np.asarray(Z.points[a0:a1], np.float64)
+        mem = [i for i in range(X.n) if labels[i] == j]
+        members = []
+        for i in mem:
+            x, p = X.bag(i)
+            p = np.asarray(p, np.float64)
+            members.append((np.asarray(x, np.float64), p / p.sum(), 1.0))
+        c, A, b, _ = cluster_lp(members, zo)
+        ref = linprog(c, A_eq=A, b_eq=b, bounds=(0, None), method="highs")
+        assert ref.status == 0
+        S = scale_S(X, Z, mem, None, j)
+        tol = REL * max(abs(ref.fun), 1e-4 * S)
+        assert abs(e1[j] - ref.fun) <= tol, (j, e1[j], ref.fun)
+        pz = w[a0:a1]
+        assert np.all(pz >= 0.0) and abs(pz.sum() - 1.0) <= 1e-12
+        keep = pz > 0.0
+        total = sum(oracle.emd_pair(*X.bag(i), zo[keep], pz[keep])[0] for i in mem)
+        assert abs(total - ref.fun) <= tol + 1e-12 * abs(ref.fun), (j, total, ref.fun)
+        assert e3[j] <= e1[j] + tol
