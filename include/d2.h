@@ -210,6 +210,23 @@ d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int
                        double *duals, int32_t *pair_status, int32_t *pivots, void *ws,
                        size_t ws_bytes, void *stream);
 
+/* D^2 for an explicit pair list, with each pair's optimal basis: for fixed
+ * centroid atoms the LP of Eq. (1) is a transportation problem (Sec. 1.1),
+ * whose bases are spanning trees of the bipartite graph of the two atom
+ * sets, t_i + s_j - 1 cells.  pairs, dist, opts and pair_status (nullable)
+ * as for d2_emd_batch.  Pair k's cells go to basis_ij + 2 basis_offsets[k]
+ * (int32 (A atom, B atom) per cell, atoms numbered within their objects)
+ * and basis_w + basis_offsets[k] (FP64 flow, in the units of the
+ * normalised weights), sorted by A atom, then B atom, zero-flow
+ * (degenerate) basic cells included; basis_offsets[npairs] (device int64)
+ * is supplied by the caller and must leave t_i + s_j - 1 cells for pair k.
+ * Nothing is written for a pair that failed.  Supports up to
+ * D2_MAX_SUPPORT (else D2_EUNSUPPORTED); FP64 direct cost only; no
+ * workspace. */
+d2_status d2_emd_batch_basis(d2_handle *h, const d2_set *A, const d2_set *B, const int64_t *pairs,
+                             int64_t npairs, const d2_opts *opts, double *dist, const int64_t *basis_offsets,
+                             int32_t *basis_ij, double *basis_w, int32_t *pair_status, void *stream);
+
 /* The transport LP of Eq. (1) over caller-given ground costs, for the MM
  * distance of Eq. (10) (whose ground cost is the matrix of squared Mallows
  * distances between two centroid sets) or any other cost.  Problem k:

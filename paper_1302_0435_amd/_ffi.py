@@ -28,7 +28,7 @@ EXPORTS = ["d2_create", "d2_destroy", "d2_status_string", "d2_max_support", "d2_
            "d2_workspace_bytes", "d2_cost_tiles", "d2_emd_batch", "d2_assign", "d2_pairwise",
            "d2_tune_pairwise", "d2_centroid_update", "d2_emd_cost_batch",
            "d2_assign_multi", "d2_assign_segmented", "d2_assign_noalloc",
-           "d2_centroid_update_free", "d2_merge_level"]
+           "d2_centroid_update_free", "d2_merge_level", "d2_emd_batch_basis"]
 
 
 class d2_set(ctypes.Structure):
@@ -80,6 +80,7 @@ def lib():
     L.d2_tune_pairwise.argtypes = [P, S, O, P, P, P, SZ, P, ctypes.POINTER(ctypes.c_double)]
     L.d2_centroid_update.argtypes = [P, S, S, P, P, O, P, P, P, P, P, P, SZ, P]
     L.d2_centroid_update_free.argtypes = [P, S, S, P, P, I32, O, P, P, P, P, P, P, P, P, P, I64, P, SZ, P]
+    L.d2_emd_batch_basis.argtypes = [P, S, S, P, I64, O, P, P, P, P, P, P]
     L.d2_merge_level.argtypes = [P, S, I64, P, P, I64, P, P, P, P, P, P, P, SZ, P]
     L.d2_assign_segmented.argtypes = [P, S, S, P, I64, P, O, P, P, P, P]
     L.d2_assign_multi.argtypes = [P, I32, S, S, O, P, P, P, P, P, SZ, P]
@@ -87,7 +88,8 @@ def lib():
     for name in ("d2_create", "d2_destroy", "d2_cost_tiles", "d2_emd_batch", "d2_assign",
                  "d2_pairwise", "d2_max_support", "d2_tune_pairwise", "d2_centroid_update",
                  "d2_emd_cost_batch", "d2_assign_multi", "d2_assign_segmented",
-                 "d2_assign_noalloc", "d2_centroid_update_free", "d2_merge_level"):
+                 "d2_assign_noalloc", "d2_centroid_update_free", "d2_merge_level",
+                 "d2_emd_batch_basis"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -226,6 +226,29 @@ def d2_emd_batch(h: Handle, A: DeviceSet, B: DeviceSet, pairs: torch.Tensor,
     return dist, status, (plan, plan_off), (duals, dual_off)
 
 
+def d2_emd_batch_basis(h: Handle, A: DeviceSet, B: DeviceSet, pairs: torch.Tensor,
+                       opts: Optional[Opts] = None):
+    """dist[m], status[m], and each pair's optimal basis: cells [c, 2] int32
+    (A atom, B atom), flows [c] f64 and offsets [m + 1] int64, pair k's
+    t + s - 1 cells at offsets[k] (sorted; see d2_emd_batch_basis in d2.h)."""
+    opts = opts or Opts()
+    dev = _dev(h)
+    pairs = pairs.to(device=dev, dtype=torch.int64).reshape(-1, 2).contiguous()
+    m = int(pairs.shape[0])
+    dist = torch.empty(m, dtype=torch.float64, device=dev)
+    status = torch.empty(m, dtype=torch.int32, device=dev)
+    sa, sb = _pair_sizes(A, B, pairs)
+    off = _offsets_of(sa + sb - 1)
+    cells = int(off[-1].item()) if m else 0
+    ij = torch.full((cells, 2), -1, dtype=torch.int32, device=dev)
+    w = torch.full((cells,), float("nan"), dtype=torch.float64, device=dev)
+    a, b, o = A.c(), B.c(), opts.c()
+    check(_ffi.lib().d2_emd_batch_basis(h.ptr, ctypes.byref(a), ctypes.byref(b), _ptr(pairs), m,
+                                        ctypes.byref(o), _ptr(dist), _ptr(off), _ptr(ij), _ptr(w),
+                                        _ptr(status), _stream(dev)), "d2_emd_batch_basis")
+    return dist, status, ij, w, off
+
+
 def d2_pairwise(h: Handle, X: DeviceSet, opts: Optional[Opts] = None):
     """condensed[n(n-1)/2] f64 (squareform order), status (same shape)."""
     opts = opts or Opts()

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libd2.so")
-SOURCES = ["d2_api.hip", "d2_kernels.hip", "d2_update.hip", "d2_cost.hip", "d2_multi.hip", "d2_seg.hip", "d2_wg.hip"]
+SOURCES = ["d2_api.hip", "d2_kernels.hip", "d2_update.hip", "d2_cost.hip", "d2_multi.hip", "d2_seg.hip", "d2_wg.hip",
+           "d2_basis.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

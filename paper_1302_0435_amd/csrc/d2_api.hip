@@ -406,6 +406,23 @@ d2_status d2_emd_batch(d2_handle *h, const d2_set *A, const d2_set *B, const int
     return e == hipSuccess ? D2_OK : D2_EHIP;
 }
 
+d2_status d2_emd_batch_basis(d2_handle *h, const d2_set *A, const d2_set *B, const int64_t *pairs,
+                             int64_t npairs, const d2_opts *opts, double *dist, const int64_t *basis_offsets,
+                             int32_t *basis_ij, double *basis_w, int32_t *pair_status, void *stream) {
+    if (!h || npairs < 0) return D2_EINVAL;
+    d2_status st = pair_sets_ok(A, B);
+    if (st != D2_OK) return st;
+    KOpts k;
+    if ((st = opts_ok(opts, k)) != D2_OK) return st;
+    if (k.cost_mode != D2_COST_F64_DIRECT) return D2_EUNSUPPORTED;
+    if (npairs > 0 && (!pairs || !dist || !basis_offsets || !basis_ij || !basis_w)) return D2_EINVAL;
+    if ((st = bind_device(h)) != D2_OK) return st;
+    const int cls = sched_of(opts) == D2_SCHED_PLAIN ? 3 : d2::class_for(ms(A), ms(B));
+    hipError_t e = d2::launch_emd_basis(ctx(h, (hipStream_t)stream), cls, kset(A), kset(B), pairs, npairs, k, dist,
+                                        basis_offsets, basis_ij, basis_w, pair_status);
+    return e == hipSuccess ? D2_OK : D2_EHIP;
+}
+
 d2_status d2_assign(d2_handle *h, const d2_set *X, const d2_set *Z, const d2_opts *opts,
                     int32_t *labels, double *best, double *all, int32_t *row_status, void *ws,
                     size_t ws_bytes, void *stream) {

@@ -64,6 +64,10 @@ hipError_t launch_assign(const LaunchCtx &c, const AssignPlan &p, const KSet &X,
                          const KOpts &o, int32_t *labels, double *best, double *all,
                          int32_t *row_status, void *ws);
 
+// Pairs with their optimal bases as sorted (A atom, B atom, flow) cells.
+hipError_t launch_emd_basis(const LaunchCtx &c, int cls, const KSet &A, const KSet &B, const int64_t *pairs,
+                            int64_t npairs, const KOpts &o, double *dist, const int64_t *basis_off,
+                            int32_t *basis_ij, double *basis_w, int32_t *status);
 hipError_t launch_emd_pairs(const LaunchCtx &c, int cls, const KSet &A, const KSet &B,
                             const int64_t *pairs, int64_t npairs, const KOpts &o, double *dist,
                             const int64_t *plan_off, double *plan, const int64_t *dual_off,
