@@ -987,8 +987,9 @@ __device__ __forceinline__ bool free_refactor(FreeShared &sh, const FreeVec &V, 
     __syncthreads();
     for (int c = 0; c < m; ++c) {
         const int v = V.basis[c];
+        // each thread reads back only its own rows of alpha before the
+        // reduction's barriers, so none is needed here
         free_ftran(V, Binv, v, m, n, s, nw, sumt);
-        __syncthreads();
         double bv = 1.0;
         int br = INT32_MAX;
         for (int i = tid; i < m; i += kFreeThreads) {
@@ -999,8 +1000,9 @@ __device__ __forceinline__ bool free_refactor(FreeShared &sh, const FreeVec &V, 
         free_argmin(sh, bv, br);
         if (!(-bv > 1e-12) || br == INT32_MAX) return false;
         const double ap = V.alpha[br];
+        // free_eta lists its own entries first and updates B^-1 only after
+        // its barriers, so row br is read here before any thread writes it
         for (int j = tid; j < m; j += kFreeThreads) V.prow[j] = Binv[(int64_t)br * m + j] / ap;
-        __syncthreads();
         free_eta(sh, V, Binv, m, br);
         if (tid == 0) {
             V.taken[br] = 1;
@@ -1287,8 +1289,7 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
             // alpha = B^-1 a_q, and d_q
             const int q = bq;
             if (tid == 0) sh.dq = free_reduced(V, cost, q, n, s, nw, sumt);
-            free_ftran(V, Binv, q, m, n, s, nw, sumt);
-            __syncthreads();
+            free_ftran(V, Binv, q, m, n, s, nw, sumt);   // own rows only until the next barrier
             // ratio test: least x_B / alpha over alpha > kPivTol, then lowest
             // variable; the winning thread names the row
             double tv = INFINITY;
@@ -1309,8 +1310,7 @@ __global__ __launch_bounds__(kFreeThreads) void k_free_solve(KSet X, KSet Z, KOp
             const int pr = sh.p;
             const double theta = tv > 0.0 ? tv : 0.0, ap = V.alpha[pr], dq = sh.dq;
             for (int jj = tid; jj < m; jj += kFreeThreads) V.prow[jj] = Binv[(int64_t)pr * m + jj] / ap;
-            __syncthreads();
-            free_eta(sh, V, Binv, m, pr);
+            free_eta(sh, V, Binv, m, pr);   // barriers before it writes B^-1 or reads others' entries
             for (int i = tid; i < m; i += kFreeThreads) {
                 const double xv = i == pr ? theta : V.xB[i] - theta * V.alpha[i];
                 V.xB[i] = xv < 0.0 ? 0.0 : xv;
