@@ -659,7 +659,10 @@ constexpr double kFreeTol = 1e-13;     // reduced costs above -kFreeTol max|c| c
 constexpr double kPivTol = 1e-9;       // least entry of B^-1 a_q taken in the ratio test
 constexpr double kFlowEps = 1e-14;     // flows at or below this (of a unit mass) are zeros
 constexpr double kWarmTol = 1e-12;     // a kept basis starts only if B^-1 b >= -kWarmTol
-constexpr size_t kFreeLds = 60 * 1024; // dynamic LDS for the vectors, when they fit
+// Dynamic LDS for the vectors, when they fit: a gfx950 workgroup may hold
+// 160 KiB, and the kernel's registers allow one 512-thread workgroup per CU
+// anyway, so nearly all of it can go to one program.
+constexpr size_t kFreeLds = 150 * 1024;
 enum { kFOk = 0, kFBadWeights = 1, kFTooLarge = 2, kFPivotCap = 3, kFInternal = 6 };
 
 // Vectors of one cluster's program (length m unless noted).

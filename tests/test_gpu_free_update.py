@@ -245,20 +245,28 @@ def test_free_update_warm_start_from_kept_bases(d2, h):
         check_unique(X, Z2, lab2, got)
 
 
-def test_free_update_large_programs_in_the_slab(d2, h):
-    """Two clusters of 48 members (m about 1,300 rows), too large for the
-    LDS variant: the slab-resident kernel, past the periodic reinversion
-    (over 256 pivots), against the LP optimum from HiGHS on the oracle's
-    program (scipy's linprog), and the device's weights checked to reach
-    it with fixed-weight transport problems."""
+@pytest.mark.parametrize("max_members", [None, 100])
+def test_free_update_large_programs(d2, h, max_members):
+    """Two clusters of 48 members (m about 1,300 rows): with the members'
+    own bound the program's vectors fit in LDS; with a bound of 100 they do
+    not and the slab-resident kernel runs.  Both past the periodic
+    reinversion (over 256 pivots), against the LP optimum from HiGHS on the
+    oracle's program (scipy's linprog), and the device's weights checked to
+    reach it with fixed-weight transport problems; the two variants give
+    the same bits."""
     from scipy.optimize import linprog
     from oracle.free_update import cluster_lp
     X, Z, labels = make_case(9, K=2, per=48, tlo=8, thi=16, s=16, d=8)
     Xd = d2.DeviceSet.from_ragged(X, DEV)
     Zd = d2.DeviceSet.from_ragged(Z, DEV)
-    out = d2.d2_centroid_update_free(h, Xd, Zd, torch.as_tensor(labels, device=DEV), want_pivots=True)
+    lab = torch.as_tensor(labels, device=DEV)
+    out = d2.d2_centroid_update_free(h, Xd, Zd, lab, want_pivots=True, max_members=max_members)
     torch.cuda.synchronize()
     z, w, e1, e3, cnt, st, cst, piv = [t.cpu().numpy() for t in out]
+    if max_members is not None:
+        ref_lds = [t.cpu().numpy() for t in d2.d2_centroid_update_free(h, Xd, Zd, lab, want_pivots=True)]
+        for a, b in zip(ref_lds, (z, w, e1, e3, cnt, st, cst, piv)):
+            assert np.array_equal(a, b)
     assert np.all(st == 0) and np.all(cst == 0) and np.all(cnt == 48)
     assert piv.max() > 256, piv
     for j in range(Z.n):
