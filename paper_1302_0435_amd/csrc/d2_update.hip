@@ -767,7 +767,7 @@ struct FreeShared {
     double rv[kFreeWaves];
     int ri[kFreeWaves];
     int cr[kFreeWaves], cc[kFreeWaves];
-    int n, m, stat, p, fresh, bland, warm_ok;
+    int n, m, stat, p, fresh, bland, warm_ok, rfail;
     double delta, dq, negx;
     long long next;   // the cluster this workgroup takes next
 };
@@ -976,6 +976,120 @@ __device__ __forceinline__ bool free_certified(FreeShared &sh, const FreeVec &V,
     return pr <= kCertTol && du <= ctol;
 }
 
+// Orders one wavefront's global and LDS traffic between its own lanes: a
+// workgroup barrier's fences without the barrier.
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Rows up to which the first wave alone rebuilds B^-1: a column of a small
+// program is a few lane steps, which the workgroup barriers of the
+// many-wave rebuild would outweigh.
+constexpr int kWaveRefactor = 192;
+constexpr int kWaveEtaRows = 8;   // rows of a rank-one update whose loads are issued together
+
+// The rebuild of free_refactor (same column order, pivot rule and updates)
+// by wave 0, with wave-level reductions and fences in place of workgroup
+// barriers; the other waves wait at the closing barrier.  Returns, in every
+// thread, whether every column found a usable pivot.
+__device__ __forceinline__ bool free_reinvert_wave(FreeShared &sh, const FreeVec &V, double *Binv, int m, int n,
+                                                   int s, int nw) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int sumt = V.T[n];
+    if (tid < 64) {
+        for (int i = 0; i < m; ++i)
+            for (int j = lane; j < m; j += 64) Binv[(int64_t)i * m + j] = i == j ? 1.0 : 0.0;
+        for (int i = lane; i < m; i += 64) V.taken[i] = 0;
+        wave_fence();
+        int fail = 0;
+        for (int c = 0; c < m; ++c) {
+            const int v = V.basis[c];
+            // alpha = B^-1 a_v, lanes over rows
+            if (v < nw) {
+                const int atom = v / s, r = v - atom * s;
+                const int cr = free_colrow(sumt, s, V.amem[atom], r);
+                for (int i = lane; i < m; i += 64) {
+                    const double *row = Binv + (int64_t)i * m;
+                    V.alpha[i] = row[atom] + (cr >= 0 ? row[cr] : 0.0);
+                }
+            } else {
+                const int r = v - nw;
+                for (int i = lane; i < m; i += 64) {
+                    const double *row = Binv + (int64_t)i * m;
+                    double acc = -row[sumt + r];
+                    if (r < s - 1)
+                        for (int k = 1; k < n; ++k) acc -= row[sumt + s + (k - 1) * (s - 1) + r];
+                    V.alpha[i] = acc;
+                }
+            }
+            // the untaken row of largest |alpha|, lowest on ties
+            double bv = 1.0;
+            int br = INT32_MAX;
+            for (int i = lane; i < m; i += 64) {
+                if (V.taken[i]) continue;
+                const double a = -fabs(V.alpha[i]);
+                if (a < bv || (a == bv && i < br)) { bv = a; br = i; }
+            }
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ov = __shfl_xor(bv, off, 64);
+                const int ok = __shfl_xor(br, off, 64);
+                if (ov < bv || (ov == bv && ok < br)) { bv = ov; br = ok; }
+            }
+            if (!(-bv > 1e-12) || br == INT32_MAX) { fail = 1; break; }
+            wave_fence();   // every lane's alpha is written
+            const double ap = V.alpha[br];
+            for (int j = lane; j < m; j += 64) V.prow[j] = Binv[(int64_t)br * m + j] / ap;
+            wave_fence();
+            // rank-one update: list the rows (alpha != 0, and br) and the
+            // columns (prow != 0) in ascending order by ballots
+            int nr = 0, nc = 0;
+            for (int base = 0; base < m; base += 64) {
+                const int i = base + lane;
+                const bool rin = i < m && (V.alpha[i] != 0.0 || i == br);
+                const bool cin = i < m && V.prow[i] != 0.0;
+                const uint64_t rb = __ballot(rin), cb = __ballot(cin);
+                if (rin) V.rlist[nr + __builtin_popcountll(rb & lanes_below())] = (int16_t)i;
+                if (cin) V.clist[nc + __builtin_popcountll(cb & lanes_below())] = (int16_t)i;
+                nr += __builtin_popcountll(rb);
+                nc += __builtin_popcountll(cb);
+            }
+            wave_fence();
+            for (int g = 0; g < nr; g += kWaveEtaRows) {
+                int rows[kWaveEtaRows];
+                double als[kWaveEtaRows];
+#pragma unroll
+                for (int q = 0; q < kWaveEtaRows; ++q) {
+                    rows[q] = g + q < nr ? V.rlist[g + q] : -1;
+                    als[q] = rows[q] >= 0 ? V.alpha[rows[q]] : 0.0;
+                }
+                for (int c0 = 0; c0 < nc; c0 += 64) {
+                    const int jc = c0 + lane;
+                    const int col = jc < nc ? V.clist[jc] : -1;
+                    const double pv = col >= 0 ? V.prow[col] : 0.0;
+                    double bvals[kWaveEtaRows];
+#pragma unroll
+                    for (int q = 0; q < kWaveEtaRows; ++q)
+                        bvals[q] = (col >= 0 && rows[q] >= 0 && rows[q] != br) ? Binv[(int64_t)rows[q] * m + col] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < kWaveEtaRows; ++q)
+                        if (col >= 0 && rows[q] >= 0)
+                            Binv[(int64_t)rows[q] * m + col] = rows[q] == br ? pv : bvals[q] - als[q] * pv;
+                }
+            }
+            if (lane == 0) {
+                V.taken[br] = 1;
+                V.nbasis[br] = v;
+            }
+            wave_fence();
+        }
+        if (lane == 0) sh.rfail = fail;
+    }
+    __syncthreads();
+    return sh.rfail == 0;
+}
+
 // Rebuild B^-1 from the basis by pivoting its columns in, one by one, from
 // the identity (each onto the untaken row of largest |entry|, the lowest on
 // ties), then x_B = B^-1 b, c_B and y = c_B B^-1.  Returns false when a
@@ -984,11 +1098,13 @@ __device__ __forceinline__ bool free_refactor(FreeShared &sh, const FreeVec &V, 
                                               int m, int n, int s, int nw) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int sumt = V.T[n];
-    for (int i = wv; i < m; i += kFreeWaves)
+    const bool small = m <= kWaveRefactor;
+    if (small && !free_reinvert_wave(sh, V, Binv, m, n, s, nw)) return false;
+    for (int i = wv; i < m && !small; i += kFreeWaves)
         for (int j = lane; j < m; j += 64) Binv[(int64_t)i * m + j] = i == j ? 1.0 : 0.0;
-    for (int i = tid; i < m; i += kFreeThreads) V.taken[i] = 0;
+    for (int i = tid; i < m && !small; i += kFreeThreads) V.taken[i] = 0;
     __syncthreads();
-    for (int c = 0; c < m; ++c) {
+    for (int c = 0; c < m && !small; ++c) {
         const int v = V.basis[c];
         // each thread reads back only its own rows of alpha before the
         // reduction's barriers, so none is needed here
