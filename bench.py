@@ -836,6 +836,91 @@ def oracle_threads():
     return oracle.default_threads()
 
 
+def _pivot_summary(p: np.ndarray) -> dict:
+    p = np.asarray(p, dtype=np.float64)
+    return {"mean": float(p.mean()), "p50": float(np.percentile(p, 50)),
+            "p90": float(np.percentile(p, 90)), "p99": float(np.percentile(p, 99)),
+            "max": int(p.max()), "zero_frac": float((p == 0).mean())}
+
+
+def pivot_work_factor(ts: np.ndarray, ss: np.ndarray, pivots: np.ndarray, d: int) -> float:
+    """Measured work over the pivot-free lower bound: a pair of supports t, s
+    costs 3 t s d for its cost tile and 3 t s per pricing pass, one pass per
+    pivot plus the certifying one."""
+    w = np.asarray(ts, np.float64) * np.asarray(ss, np.float64)
+    p = np.asarray(pivots, np.float64)
+    return float((w * (3 * d + 3 * (p + 1))).sum() / (w * (3 * d + 3)).sum())
+
+
+def pivot_stats(d2, dev, A, B, pairs: np.ndarray, d: int) -> dict:
+    """Pivots per LP on a seeded sample of pairs: the device under its default
+    least-cost start and under the north-west corner, and the oracle under
+    the north-west corner (its starts are the north-west corner and Vogel).
+    Every pivot adds one pricing pass (3 t s operations) to the pivot-free
+    work that the roofline counts; ``work_factor`` is the measured work over
+    that lower bound, weighting each pair by its t s."""
+    import torch
+    import oracle
+    h = d2.Handle(0)
+    Ad, Bd = d2.DeviceSet.from_ragged(A, dev), d2.DeviceSet.from_ragged(B, dev)
+    pt = torch.as_tensor(pairs)
+    dev_piv = {}
+    for name, init in (("lcm", d2.D2_INIT_LCM), ("nwc", d2.D2_INIT_NWC)):
+        dist, st, _, _, piv = d2.d2_emd_batch(h, Ad, Bd, pt, d2.Opts(init=init), want_pivots=True)
+        torch.cuda.synchronize()
+        if int(st.max().item()) != 0:
+            raise RuntimeError(f"pivot sample: device status {int(st.max().item())} under {name}")
+        dev_piv[name] = piv.cpu().numpy()
+    o_d, o_st, o_piv, o_bl = oracle.emd_batch_stats(A, B, pairs, init=oracle.INIT_NWC)
+    ts = np.diff(A.offsets)[pairs[:, 0]]
+    ss = np.diff(B.offsets)[pairs[:, 1]]
+    p_lcm = dev_piv["lcm"][:, 0]
+    return {
+        "pairs": int(pairs.shape[0]),
+        "device_lcm": _pivot_summary(p_lcm),
+        "device_nwc": _pivot_summary(dev_piv["nwc"][:, 0]),
+        "oracle_nwc": _pivot_summary(o_piv),
+        "nwc_same_count_frac": float((dev_piv["nwc"][:, 0] == o_piv).mean()),
+        "bland_pivots": {"device_lcm": int(dev_piv["lcm"][:, 1].sum()),
+                         "device_nwc": int(dev_piv["nwc"][:, 1].sum()), "oracle_nwc": int(o_bl.sum())},
+        "work_factor": pivot_work_factor(ts, ss, p_lcm, d),
+    }
+
+
+def pivot_sample(cfg: int, count: int = 4096):
+    """(A, B, pairs, d) for a configuration's pivot sample: objects against
+    centroids (configurations 1-3, 5: queries against the resident centroids),
+    or object pairs i < j of one segment (configuration 4)."""
+    import synth
+    n = synth.CONFIGS[cfg]["n"]
+    X = synth.make_data(cfg) if 0 < n <= 8192 else synth.make_data(cfg, n=8192)
+    d = int(X.points.shape[1])
+    if cfg == 4:
+        rng = synth.rng_for(cfg, synth.STREAM_SAMPLE, 4242)
+        i = rng.integers(0, X.n, size=4 * count)
+        j = rng.integers(0, X.n, size=4 * count)
+        keep = i < j
+        pairs = np.unique(np.stack([i[keep], j[keep]], axis=1), axis=0)[:count]
+        rng.shuffle(pairs)
+        return X, X, pairs.astype(np.int64), d
+    Z = synth.make_centroids(cfg)
+    return X, Z, synth.sample_pairs(cfg, X.n, Z.n, count, tag=4242), d
+
+
+def run_pivots(argv) -> int:
+    """--op pivots: per-configuration pivot counts, device and oracle."""
+    import paper_1302_0435_amd as d2
+    rows = []
+    for cfg in (1, 2, 3, 4, 5):
+        A, B, pairs, d = pivot_sample(cfg)
+        r = pivot_stats(d2, "cuda:0", A, B, pairs, d)
+        r["config"] = cfg
+        rows.append(r)
+        print(f"config {cfg}: {json.dumps(r)}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "pivots per LP, device and oracle", "configs": rows}), flush=True)
+    return 0
+
+
 def make_pool(n_pool: int):
     """Query pool for the serving workload (configuration 5, stream 1)."""
     import synth
@@ -982,13 +1067,15 @@ def main(argv=None) -> int:
                     help="ground-cost arithmetic (bf16: MFMA cost tiles fused into the "
                          "labelling kernel, supports <= 32)")
     ap.add_argument("--tune", action="store_true", help="autotune the pairwise schedule first")
-    ap.add_argument("--op", choices=["assign", "update", "cost", "multi", "hierarchy", "large"],
+    ap.add_argument("--op", choices=["assign", "update", "cost", "multi", "hierarchy", "large", "pivots"],
                     default="assign",
                     help="update: the constrained D2 centroid update (configurations 1-3); "
                          "cost: LPs over given cost matrices (configuration 2 shapes); "
                          "multi: two-type labelling of Eq. (9) (configuration 2 scale); "
                          "hierarchy: Alg. 3 over a configuration's objects; "
-                         "large: pairs of 96..192 atoms on the workgroup simplex")
+                         "large: pairs of 96..192 atoms on the workgroup simplex; "
+                         "pivots: pivots per LP on a sample of every configuration, device "
+                         "and oracle")
     ap.add_argument("--n", type=int, default=None, help="override object count (testing)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1008,6 +1095,8 @@ def main(argv=None) -> int:
         return 2
     if args.config == 5:
         return run_serving(rest + ["--init", args.init])
+    if args.op == "pivots":
+        return run_pivots(rest)
 
     import torch
     import paper_1302_0435_amd as d2
@@ -1099,6 +1188,17 @@ def main(argv=None) -> int:
         plain["speedup_of_value"] = out["value"] / plain["value"]
         out["plain_solver"] = plain
     default_c2 = args.n is None and args.op == "assign" and args.config == 2 and args.cost == "f64"
+    if args.n is None and args.op == "assign" and args.config in (1, 2, 3) and args.cost == "f64":
+        # pivots on a seeded sample of this workload's pairs (outside the timed
+        # region), and the roofline over the work those pivots add
+        import synth
+        pairs = synth.sample_pairs(args.config, w.X.n, w.Z.n, 4096, tag=4242)
+        pv = pivot_stats(d2, dev, w.X, w.Z, pairs, int(w.X.points.shape[1]))
+        out["pivots"] = pv
+        rf = out["roofline"]
+        rf["work_factor_with_pivots"] = pv["work_factor"]
+        rf["achieved_with_pivots"] = achieved * pv["work_factor"]
+        rf["frac_with_pivots"] = achieved * pv["work_factor"] / FP64_VECTOR_PEAK_TFLOPS
     if default_c2 and not args.no_serve:
         # the serving form beside the headline: p50/p99 latency and capacity
         # of configuration 5, against the plain per-pair solver

@@ -1,0 +1,40 @@
+"""Host-side helpers of bench.py: the seeded pivot samples and the work
+arithmetic that the pivot-weighted roofline uses (no GPU)."""
+import numpy as np
+import pytest
+
+import bench
+import synth
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
+def test_pivot_sample_is_valid_and_seeded(cfg):
+    A, B, pairs, d = bench.pivot_sample(cfg, count=512)
+    assert pairs.ndim == 2 and pairs.shape[1] == 2 and pairs.shape[0] > 0
+    assert pairs.min() >= 0 and pairs[:, 0].max() < A.n and pairs[:, 1].max() < B.n
+    assert d == synth.CONFIGS[cfg]["d"] == A.points.shape[1] == B.points.shape[1]
+    assert np.unique(pairs, axis=0).shape[0] == pairs.shape[0]
+    if cfg == 4:
+        assert np.all(pairs[:, 0] < pairs[:, 1])       # one orientation of each object pair
+    _, _, again, _ = bench.pivot_sample(cfg, count=512)
+    np.testing.assert_array_equal(pairs, again)
+
+
+def test_work_factor_closed_forms():
+    ts, ss = np.array([4, 16, 9]), np.array([16, 16, 2])
+    # no pivots: only the certifying pass, which the lower bound already counts
+    assert bench.pivot_work_factor(ts, ss, np.zeros(3), 8) == pytest.approx(1.0)
+    # P pivots on every pair: (3d + 3(P + 1)) / (3d + 3), whatever the supports
+    for d, p in ((8, 7), (128, 21), (3, 0)):
+        want = (3 * d + 3 * (p + 1)) / (3 * d + 3)
+        assert bench.pivot_work_factor(ts, ss, np.full(3, p), d) == pytest.approx(want)
+    # pairs weigh by t s: one pivot on the 16 x 16 pair alone
+    got = bench.pivot_work_factor(ts, ss, np.array([0, 1, 0]), 1)
+    w = ts * ss
+    assert got == pytest.approx((w.sum() * 6 + w[1] * 3) / (w.sum() * 6))
+
+
+def test_pivot_summary():
+    s = bench._pivot_summary(np.array([0, 0, 2, 4, 10]))
+    assert s["mean"] == pytest.approx(3.2) and s["p50"] == 2.0 and s["max"] == 10
+    assert s["zero_frac"] == pytest.approx(0.4)
