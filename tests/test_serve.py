@@ -114,3 +114,24 @@ def test_completions_are_placed_on_the_arrival_clock():
     lat = st.latencies_ms()
     assert 15.0 - 1e-9 <= lat[0] <= 15.2
     assert 10.0 - 1e-9 <= lat[1] <= 10.2
+
+
+def test_warm_up_leaves_the_measured_run_unchanged():
+    """The warm-up serves a burst and the head of the schedule on the same
+    scheduler; the measured run that follows is the one a fresh scheduler
+    gives (the scheduler keeps no state between runs)."""
+    from paper_1302_0435_amd.serve import warm_up
+    rng = np.random.default_rng(5)
+    arrivals = np.cumsum(rng.exponential(1e-3, size=300))
+    sizes = rng.integers(4, 65, size=300)
+    dur = lambda c: 0.002 + 1e-4 * c
+    fresh, _ = run(arrivals, sizes, dur, budget=1 << 30)
+    clk = VClock()
+    ex = ScriptedExecutor(dur, clock=clk)
+    sch = Scheduler(ex, sizes, 4, 8, 1 << 30, 64, 2)
+    warm_up(sch, arrivals, burst=100, seconds=0.05, clock=clk, sleep=clk.sleep)
+    first = [sub for sub in ex.submitted]
+    assert sum(c for _, c, _ in first) == 100 + int((arrivals < 0.05).sum())
+    clk.t = 0.0      # the same clock phase as the fresh run's
+    st = sch.run(arrivals, clock=clk, sleep=clk.sleep)
+    np.testing.assert_allclose(st.latencies_ms(), fresh.latencies_ms(), rtol=0, atol=1e-6)
