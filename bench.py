@@ -864,14 +864,14 @@ def pivot_stats(d2, dev, A, B, pairs: np.ndarray, d: int) -> dict:
     h = d2.Handle(0)
     Ad, Bd = d2.DeviceSet.from_ragged(A, dev), d2.DeviceSet.from_ragged(B, dev)
     pt = torch.as_tensor(pairs)
-    dev_piv = {}
+    dev_piv, bad = {}, {}
     for name, init in (("lcm", d2.D2_INIT_LCM), ("nwc", d2.D2_INIT_NWC)):
         dist, st, _, _, piv = d2.d2_emd_batch(h, Ad, Bd, pt, d2.Opts(init=init), want_pivots=True)
         torch.cuda.synchronize()
-        if int(st.max().item()) != 0:
-            raise RuntimeError(f"pivot sample: device status {int(st.max().item())} under {name}")
+        bad["device_" + name] = int((st != 0).sum().item())
         dev_piv[name] = piv.cpu().numpy()
     o_d, o_st, o_piv, o_bl = oracle.emd_batch_stats(A, B, pairs, init=oracle.INIT_NWC)
+    bad["oracle_nwc"] = int((o_st != 0).sum())
     ts = np.diff(A.offsets)[pairs[:, 0]]
     ss = np.diff(B.offsets)[pairs[:, 1]]
     p_lcm = dev_piv["lcm"][:, 0]
@@ -881,6 +881,7 @@ def pivot_stats(d2, dev, A, B, pairs: np.ndarray, d: int) -> dict:
         "device_nwc": _pivot_summary(dev_piv["nwc"][:, 0]),
         "oracle_nwc": _pivot_summary(o_piv),
         "nwc_same_count_frac": float((dev_piv["nwc"][:, 0] == o_piv).mean()),
+        "nonzero_status": bad,
         "bland_pivots": {"device_lcm": int(dev_piv["lcm"][:, 1].sum()),
                          "device_nwc": int(dev_piv["nwc"][:, 1].sum()), "oracle_nwc": int(o_bl.sum())},
         "work_factor": pivot_work_factor(ts, ss, p_lcm, d),
