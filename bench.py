@@ -950,7 +950,7 @@ def serve_leg(d2, rates=(10000.0, 50000.0), duration=2.0, n_pool=4000, check=160
     for rate in rates:
         arrivals = synth.arrivals(5, rate, duration)
         req_idx = np.arange(arrivals.size) % pool.n
-        ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, 4, 512)
+        ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, 4, 512, budget_bytes=256 << 20)
         sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, 256 << 20, 512, 4)
         serve.warm_up(sch, arrivals)      # one-time launch costs outside the measured run
         st = sch.run(arrivals)
@@ -963,7 +963,7 @@ def serve_leg(d2, rates=(10000.0, 50000.0), duration=2.0, n_pool=4000, check=160
     # (copying results out on the host would slow the measured runs)
     arrivals = synth.arrivals(5, rates[0], duration)[:check]
     req_idx = np.arange(arrivals.size) % pool.n
-    ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, 4, 512, keep_results=True)
+    ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, 4, 512, keep_results=True, budget_bytes=256 << 20)
     serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, 256 << 20, 512, 4).run(arrivals)
     kept = dict(ex.results)
     del ex
@@ -1027,9 +1027,11 @@ def run_serving(argv) -> int:
         req_idx = np.arange(arrivals.size) % pool.n
         init = {"auto": d2.D2_INIT_AUTO, "nwc": d2.D2_INIT_NWC, "vogel": d2.D2_INIT_VOGEL,
                 "lcm": d2.D2_INIT_LCM}[args.init]
-        ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, args.slots, args.max_batch, init=init)
-        sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n,
-                              int(args.budget_mib * 2**20), args.max_batch, args.slots)
+        budget = int(args.budget_mib * 2**20)
+        ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, args.slots, args.max_batch, init=init,
+                               budget_bytes=budget)
+        sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, budget, args.max_batch,
+                              args.slots)
         serve.warm_up(sch, arrivals)      # one-time launch costs outside the measured run
         st = sch.run(arrivals)
         summ = st.summary(Z.n)

@@ -8,7 +8,10 @@ plus its K distances, label, minimum and status.  The scheduler
 
   * admits requests in arrival order while their footprint fits the HBM
     budget still free and a stream slot is free (requests that do not fit
-    wait; nothing is dropped),
+    wait; nothing is dropped).  The budget is one device buffer: each batch
+    gets a contiguous range of it from a first-fit allocator and gives it
+    back when it completes, so the requests' device memory is the budget,
+    whatever the batch sizes,
   * packs every admitted request that has arrived into one batch
     (continuous batching: a slot that frees up takes whatever is waiting),
   * runs the batch on its own HIP stream -- host-to-device copy from pinned
@@ -67,6 +70,48 @@ class Batch:
     count: int
     nbytes: int
     submit_s: float = 0.0
+    arena_off: int = 0  # start of the batch's range of the budget buffer
+    arena_len: int = 0  # its length (the requests' bytes, the extra offset, alignment)
+
+
+BATCH_EXTRA = 8         # a batch's offsets array has one entry more than requests
+
+
+class Arena:
+    """First-fit allocation of byte ranges of one buffer of ``size`` bytes;
+    lengths are rounded up to ``align``, freed ranges merge with their free
+    neighbours."""
+
+    def __init__(self, size: int, align: int = 256):
+        self.size, self.align = int(size), int(align)
+        self.free = [(0, self.size)] if self.size > 0 else []   # sorted (start, length)
+
+    def need(self, nbytes: int) -> int:
+        return -(-(int(nbytes) + BATCH_EXTRA) // self.align) * self.align
+
+    def largest(self) -> int:
+        return max((n for _, n in self.free), default=0)
+
+    def alloc(self, length: int) -> Optional[int]:
+        for i, (a, n) in enumerate(self.free):
+            if n >= length:
+                if n == length:
+                    del self.free[i]
+                else:
+                    self.free[i] = (a + length, n - length)
+                return a
+        return None
+
+    def release(self, start: int, length: int):
+        self.free.append((start, length))
+        self.free.sort()
+        merged = []
+        for a, n in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == a:
+                merged[-1] = (merged[-1][0], merged[-1][1] + n)
+            else:
+                merged.append((a, n))
+        self.free = merged
 
 
 # ------------------------------------------------------------ scheduler
@@ -104,13 +149,14 @@ class Scheduler:
     """Admission by HBM budget, slots, continuous batching, latency record."""
 
     def __init__(self, executor, sizes: np.ndarray, d: int, k: int, budget_bytes: int,
-                 max_batch: int, slots: int):
+                 max_batch: int, slots: int, align: int = 256):
         self.ex = executor
         self.sizes = sizes          # support size of every request, in arrival order
         self.d, self.k = d, k
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
         self.slots = int(slots)
+        self.align = int(align)
 
     def run(self, arrivals: np.ndarray, clock=time.perf_counter, sleep=time.sleep,
             idle_sleep=50e-6) -> ServeStats:
@@ -119,7 +165,7 @@ class Scheduler:
         done_s = np.full(n, np.nan)
         free_slots = collections.deque(range(self.slots))
         inflight: List[Batch] = []
-        used = 0
+        arena = Arena(self.budget, self.align)
         next_req = 0            # first request not yet admitted
         batch_sizes: List[int] = []
         max_queue = 0
@@ -137,29 +183,31 @@ class Scheduler:
                 t_done = self.ex.poll(b)
                 if t_done is not None:
                     done_s[b.first:b.first + b.count] = t_done + shift
-                    used -= b.nbytes
+                    arena.release(b.arena_off, b.arena_len)
                     free_slots.append(b.slot)
                     inflight.remove(b)
                     progressed = True
             # admit and launch everything that has arrived, within the limits
             while free_slots and next_req < arrived:
                 count, nbytes = 0, 0
+                room = arena.largest()
                 while (next_req + count < arrived and count < self.max_batch and
-                       used + nbytes + fp[next_req + count] <= self.budget):
+                       arena.need(nbytes + fp[next_req + count]) <= room):
                     nbytes += int(fp[next_req + count])
                     count += 1
                 if count == 0:
                     break       # the head request does not fit yet: it waits
-                b = Batch(free_slots.popleft(), next_req, count, nbytes, now)
+                length = arena.need(nbytes)
+                b = Batch(free_slots.popleft(), next_req, count, nbytes, now,
+                          arena.alloc(length), length)
                 self.ex.submit(b)
                 inflight.append(b)
-                used += nbytes
                 next_req += count
                 batch_sizes.append(count)
                 progressed = True
             if next_req >= n and not inflight:
                 break
-            if arrived == n and not inflight and fp[next_req] > self.budget:
+            if arrived == n and not inflight and arena.need(fp[next_req]) > self.budget:
                 break           # budget below one request: it stays queued, unserved
             if not progressed:
                 nxt = arrivals[arrived] - now if arrived < n else idle_sleep
@@ -189,10 +237,17 @@ def warm_up(sch: "Scheduler", arrivals: np.ndarray, burst: int = 512, seconds: f
 
 class GpuExecutor:
     """Runs batches on HIP streams: pinned-host copy in, d2_assign against the
-    resident centroids, copy out.  Completion times come from HIP events."""
+    resident centroids, copy out.  Completion times come from HIP events.
+
+    The requests' device data (points, weights, offsets, K distances, label,
+    minimum, status) live in one buffer of ``budget_bytes``: a batch's arrays
+    are views of the range the scheduler allocated to it (``Batch.arena_off``),
+    so the scheduler's budget is the memory they use.  Each slot also holds
+    the library workspace for ``max_batch`` requests, outside the budget."""
 
     def __init__(self, pool: QueryPool, req_pool_index: np.ndarray, Zd, k: int, slots: int,
-                 max_batch: int, device: int = 0, keep_results: bool = False, init: int = 0):
+                 max_batch: int, device: int = 0, keep_results: bool = False, init: int = 0,
+                 budget_bytes: int = 256 << 20):
         import torch
         from . import api
         self.torch = torch
@@ -207,25 +262,18 @@ class GpuExecutor:
         self.opts = api.Opts(init=init, flags=1)   # eager: batch shapes vary
         tmax = int(pool.sizes().max())
         self.max_batch = max_batch
-        self.max_atoms = max_batch * tmax
         # pinned host copies of the pool
         self.h_pts = torch.from_numpy(np.ascontiguousarray(pool.points)).pin_memory()
         self.h_w = torch.from_numpy(np.ascontiguousarray(pool.weights)).pin_memory()
         self.sizes = pool.sizes()
         self.keep = keep_results
         self.results = {}
+        self.arena = torch.empty(max(int(budget_bytes), 1), dtype=torch.uint8, device=self.dev)
         self.slots = []
         for _ in range(slots):
             s = {
                 "stream": torch.cuda.Stream(device=self.dev),
-                "off": torch.empty(max_batch + 1, dtype=torch.int64, device=self.dev),
                 "h_off": torch.empty(max_batch + 1, dtype=torch.int64).pin_memory(),
-                "pts": torch.empty((self.max_atoms, self.d), dtype=torch.float64, device=self.dev),
-                "w": torch.empty(self.max_atoms, dtype=torch.float64, device=self.dev),
-                "labels": torch.empty(max_batch, dtype=torch.int32, device=self.dev),
-                "best": torch.empty(max_batch, dtype=torch.float64, device=self.dev),
-                "all": torch.empty((max_batch, k), dtype=torch.float64, device=self.dev),
-                "status": torch.empty(max_batch, dtype=torch.int32, device=self.dev),
                 "h_labels": torch.empty(max_batch, dtype=torch.int32).pin_memory(),
                 "h_best": torch.empty(max_batch, dtype=torch.float64).pin_memory(),
                 "h_all": torch.empty((max_batch, k), dtype=torch.float64).pin_memory(),
@@ -234,15 +282,37 @@ class GpuExecutor:
             }
             self.slots.append(s)
         # workspace big enough for any batch of at most max_batch requests
-        probe = api.DeviceSet(self.slots[0]["off"], self.slots[0]["pts"], self.slots[0]["w"], tmax)
+        # (the size depends on the request count and the largest support)
+        p_off = torch.zeros(max_batch + 1, dtype=torch.int64, device=self.dev)
+        p_pts = torch.empty((1, self.d), dtype=torch.float64, device=self.dev)
+        p_w = torch.empty(1, dtype=torch.float64, device=self.dev)
         ws_b = 0
         for nq in range(1, max_batch + 1):
-            probe.offsets = self.slots[0]["off"][:nq + 1]
+            probe = api.DeviceSet(p_off[:nq + 1], p_pts, p_w, tmax)
             ws_b = max(ws_b, api.d2_workspace_bytes(self.h, 2, probe, Zd, 0, self.opts))
+        del p_off, p_pts, p_w
         self.ws_bytes = ws_b
         for s in self.slots:
             s["ws"] = torch.empty(max(ws_b, 1), dtype=torch.uint8, device=self.dev)
         self.ref = torch.cuda.Event(enable_timing=True)
+
+    def _views(self, b: Batch, atoms: int):
+        """The batch's device arrays, carved in order from its arena range."""
+        torch = self.torch
+        c, d, k = b.count, self.d, self.k
+        if b.arena_off < 0 or b.arena_off + b.arena_len > self.arena.numel():
+            raise ValueError("batch range outside the budget buffer")
+        o = b.arena_off
+        out = []
+        for nbytes, dtype in ((atoms * d * 8, torch.float64), (atoms * 8, torch.float64),
+                              ((c + 1) * 8, torch.int64), (c * k * 8, torch.float64),
+                              (c * 8, torch.float64), (c * 4, torch.int32), (c * 4, torch.int32)):
+            out.append(self.arena[o:o + nbytes].view(dtype))
+            o += nbytes
+        if o - b.arena_off != b.nbytes + BATCH_EXTRA or o - b.arena_off > b.arena_len:
+            raise ValueError("batch footprint does not match its requests")
+        pts, w, off, allv, best, labels, status = out
+        return pts.view(atoms, d), w, off, allv.view(c, k), best, labels, status
 
     def start(self, clock=time.perf_counter) -> float:
         """Record the reference event on an idle device; return the host time
@@ -262,26 +332,25 @@ class GpuExecutor:
         sz = self.sizes[ids]
         off = np.zeros(b.count + 1, np.int64)
         np.cumsum(sz, out=off[1:])
+        pts, w, d_off, allv, best, labels, status = self._views(b, int(off[-1]))
         s["h_off"][:b.count + 1].copy_(torch.from_numpy(off))
         with torch.cuda.stream(s["stream"]):
-            s["off"][:b.count + 1].copy_(s["h_off"][:b.count + 1], non_blocking=True)
+            d_off.copy_(s["h_off"][:b.count + 1], non_blocking=True)
             # requests are consecutive pool entries except across the wrap point
             pos = 0
             runs = np.split(ids, np.flatnonzero(np.diff(ids) != 1) + 1)
             for r in runs:
                 a0, a1 = int(self.pool.offsets[r[0]]), int(self.pool.offsets[r[-1] + 1])
-                s["pts"][pos:pos + a1 - a0].copy_(self.h_pts[a0:a1], non_blocking=True)
-                s["w"][pos:pos + a1 - a0].copy_(self.h_w[a0:a1], non_blocking=True)
+                pts[pos:pos + a1 - a0].copy_(self.h_pts[a0:a1], non_blocking=True)
+                w[pos:pos + a1 - a0].copy_(self.h_w[a0:a1], non_blocking=True)
                 pos += a1 - a0
-            Xd = self.api.DeviceSet(s["off"][:b.count + 1], s["pts"][:pos], s["w"][:pos],
-                                    int(sz.max()))
-            self.api.d2_assign_into(self.h, Xd, self.Zd, self.opts, s["labels"][:b.count],
-                                    s["best"][:b.count], s["all"][:b.count], s["status"][:b.count],
+            Xd = self.api.DeviceSet(d_off, pts, w, int(sz.max()))
+            self.api.d2_assign_into(self.h, Xd, self.Zd, self.opts, labels, best, allv, status,
                                     s["ws"], self.ws_bytes)
-            s["h_labels"][:b.count].copy_(s["labels"][:b.count], non_blocking=True)
-            s["h_best"][:b.count].copy_(s["best"][:b.count], non_blocking=True)
-            s["h_all"][:b.count].copy_(s["all"][:b.count], non_blocking=True)
-            s["h_status"][:b.count].copy_(s["status"][:b.count], non_blocking=True)
+            s["h_labels"][:b.count].copy_(labels, non_blocking=True)
+            s["h_best"][:b.count].copy_(best, non_blocking=True)
+            s["h_all"][:b.count].copy_(allv, non_blocking=True)
+            s["h_status"][:b.count].copy_(status, non_blocking=True)
             s["ev"].record(s["stream"])
         s["batch"] = b
 

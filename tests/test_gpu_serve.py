@@ -11,11 +11,15 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("k,n_pool,n_req,max_batch,alone_every,oracle_every", [
-    (48, 90, 360, 48, 7, 9),
-    (1024, 24, 96, 16, 5, 8),      # the serving workload's resident centroid count
+@pytest.mark.parametrize("k,n_pool,n_req,max_batch,alone_every,oracle_every,budget", [
+    (48, 90, 360, 48, 7, 9, 1 << 28),
+    (1024, 24, 96, 16, 5, 8, 1 << 28),      # the serving workload's resident centroid count
+    # a budget of a few requests: batches are cut by the buffer's free ranges,
+    # which the completed batches' ranges return to
+    (48, 90, 360, 48, 7, 9, 6 * (64 * 32 * 8 + 64 * 8 + 8 + 48 * 8 + 16) + 4096),
 ])
-def test_serving_results_alone_equal_mix(k, n_pool, n_req, max_batch, alone_every, oracle_every):
+def test_serving_results_alone_equal_mix(k, n_pool, n_req, max_batch, alone_every, oracle_every,
+                                         budget):
     if not torch.cuda.is_available():
         pytest.fail("GPU tests selected but no GPU is visible")
     import paper_1302_0435_amd as d2
@@ -26,8 +30,9 @@ def test_serving_results_alone_equal_mix(k, n_pool, n_req, max_batch, alone_ever
     pool = serve.QueryPool(q.offsets, q.points.astype(np.float64), q.weights.astype(np.float64))
     arrivals = np.sort(np.random.default_rng(3).uniform(0.0, 0.05, n_req))
     req_idx = np.arange(n_req) % pool.n
-    ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, slots=3, max_batch=max_batch, keep_results=True)
-    sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, 1 << 28, max_batch, 3)
+    ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, slots=3, max_batch=max_batch, keep_results=True,
+                           budget_bytes=budget)
+    sch = serve.Scheduler(ex, pool.sizes()[req_idx], pool.d, Z.n, budget, max_batch, 3)
     st = sch.run(arrivals)
     assert np.all(~np.isnan(st.done_s))
     assert max(st.batch_sizes) > 1

@@ -135,3 +135,53 @@ def test_warm_up_leaves_the_measured_run_unchanged():
     clk.t = 0.0      # the same clock phase as the fresh run's
     st = sch.run(arrivals, clock=clk, sleep=clk.sleep)
     np.testing.assert_allclose(st.latencies_ms(), fresh.latencies_ms(), rtol=0, atol=1e-6)
+
+
+def test_arena_first_fit_and_merging():
+    from paper_1302_0435_amd.serve import Arena, BATCH_EXTRA
+    a = Arena(4096, align=256)
+    assert a.need(1) == 256 and a.need(256 - BATCH_EXTRA) == 256 and a.need(256) == 512
+    x = a.alloc(1024); y = a.alloc(1024); z = a.alloc(2048)
+    assert (x, y, z) == (0, 1024, 2048) and a.largest() == 0 and a.alloc(256) is None
+    a.release(y, 1024)                     # a hole in the middle
+    assert a.largest() == 1024 and a.alloc(2048) is None
+    a.release(x, 1024)                     # merges with the hole
+    assert a.free == [(0, 2048)]
+    a.release(z, 2048)
+    assert a.free == [(0, 4096)]
+
+
+def test_in_flight_batches_hold_disjoint_ranges_of_the_budget():
+    """The budget is one buffer: batches in flight at the same time hold
+    disjoint ranges of it, each large enough for its requests."""
+    from paper_1302_0435_amd.serve import BATCH_EXTRA
+    rng = np.random.default_rng(11)
+    d, k = 8, 16
+    sizes = rng.integers(1, 65, size=400)
+    arrivals = np.cumsum(rng.exponential(2e-4, size=400))
+    budget = 5 * request_bytes(64, d, k) + 1000
+    clk = VClock()
+    ex = ScriptedExecutor(lambda c: 0.001 + 2e-4 * c, clock=clk)
+    held = []
+    orig = ex.submit
+
+    def submit(b):
+        orig(b)
+        held.append(b)
+    ex.submit = submit
+    sch = Scheduler(ex, sizes, d, k, budget, 64, 3)
+    st = sch.run(arrivals, clock=clk, sleep=clk.sleep)
+    assert np.all(~np.isnan(st.done_s))
+    spans = []
+    for b in held:
+        fp = sum(request_bytes(int(t), d, k) for t in sizes[b.first:b.first + b.count])
+        assert b.nbytes == fp and b.arena_len >= fp + BATCH_EXTRA
+        assert 0 <= b.arena_off and b.arena_off + b.arena_len <= budget
+        spans.append((b.submit_s, b.submit_s + 0.001 + 2e-4 * b.count, b.arena_off, b.arena_off + b.arena_len))
+    for i in range(len(spans)):
+        for j in range(i + 1, len(spans)):
+            t0, t1, a0, a1 = spans[i]
+            u0, u1, c0, c1 = spans[j]
+            if t0 < u1 and u0 < t1:          # in flight together
+                assert a1 <= c0 or c1 <= a0
+    assert max(b.count for b in held) > 1
