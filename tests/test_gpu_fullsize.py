@@ -40,7 +40,7 @@ def rows_floor(X, Z, rows, o_lab):
                      for k, i in enumerate(rows)])
 
 
-@pytest.mark.parametrize("cfg,nrows", [(2, 48), (3, 24)])
+@pytest.mark.parametrize("cfg,nrows", [(2, 2048), (3, 256)])
 def test_full_assign_sampled_rows(d2, h, cfg, nrows):
     X = synth.make_data(cfg)
     Z = synth.make_centroids(cfg)
@@ -70,7 +70,7 @@ def test_full_assign_bf16_sampled_rows(d2, h):
     assert st.cpu().numpy().max() == 0
     best = best.cpu().numpy()
     lab = lab.cpu().numpy()
-    rows = synth.sample_rows(3, X.n, 12, tag=8)
+    rows = synth.sample_rows(3, X.n, 96, tag=8)
     sub = X.subset(rows)
     _, _, o_all, _, _ = oracle.assign(sub, Z)
     for k, i in enumerate(rows):
@@ -93,8 +93,8 @@ def test_full_pairwise_sampled_pairs(d2, h):
     st = st.cpu().numpy()
     assert st.max() == 0
     g = out.cpu().numpy()
-    p = synth.sample_pairs(4, n, n, 9000, tag=9)
-    p = p[p[:, 0] < p[:, 1]][:3000]
+    p = synth.sample_pairs(4, n, n, 120000, tag=9)
+    p = p[p[:, 0] < p[:, 1]][:60000]
     i, j = p[:, 0], p[:, 1]
     idx = i * n - i * (i + 1) // 2 + (j - i - 1)
     o, o_st, _ = oracle.emd_batch(X, X, p)
