@@ -908,6 +908,55 @@ def pivot_sample(cfg: int, count: int = 4096):
     return X, Z, synth.sample_pairs(cfg, X.n, Z.n, count, tag=4242), d
 
 
+def other_legs(d2, dev, steps=3, warmup=1, cpu_seconds=2.0) -> list:
+    """Short runs of the other measured workloads beside the default one, so
+    that one run records them all: configuration 1, configuration 3 with the
+    FP64 and the BF16-MFMA cost, configuration 4's pairwise matrix and the
+    hierarchy over configuration 2's objects.  Each is timed like the main
+    step (inputs resident, HIP events), and the labelling and pairwise legs
+    check a seeded sample against the oracle (about ``cpu_seconds`` of it)."""
+    import torch
+    init, sched = d2.D2_INIT_AUTO, d2.D2_SCHED_AUTO
+    makers = [
+        ("c1", lambda: AssignWorkload(1, d2, dev, init, sched)),
+        ("c3_f64", lambda: AssignWorkload(3, d2, dev, init, sched)),
+        ("c3_bf16", lambda: AssignWorkload(3, d2, dev, init, sched, cost_mode=d2.D2_COST_BF16_MFMA)),
+        ("c4", lambda: PairwiseWorkload(4, d2, dev, init, sched)),
+        ("hierarchy_c2", lambda: HierarchyWorkload(2, d2, dev, init, sched)),
+    ]
+    legs = []
+    for name, make in makers:
+        w = make()
+        for _ in range(warmup):
+            w.step()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            w.step()
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        leg = {"leg": name, "config": w.config(), "value": w.pairs * steps / wall,
+               "unit": getattr(w, "unit", "distances/s"), "steps": steps, "warmup": warmup,
+               "ms_per_step": wall / steps * 1e3,
+               "kernel_ms_median": float(np.median([a.elapsed_time(b) for a, b in ev])),
+               "failed_pairs_or_rows": w.failed()}
+        if name != "hierarchy_c2":
+            cb = w.cpu_baseline(cpu_seconds, 0)
+            leg["parity"] = {k: cb[k] for k in ("parity_checked", "parity_failures", "bf16_vs_fp64",
+                                                "sample") if k in cb}
+        legs.append(leg)
+        print(f"leg {name}: {leg['value']:.4g} {leg['unit']}", file=sys.stderr, flush=True)
+        del w
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return legs
+
+
 def run_pivots(argv) -> int:
     """--op pivots: per-configuration pivot counts, device and oracle."""
     import paper_1302_0435_amd as d2
@@ -1086,6 +1135,8 @@ def main(argv=None) -> int:
                     help="configuration 2: check a timed sample of rows instead of all of them")
     ap.add_argument("--no-serve", action="store_true",
                     help="configuration 2: skip the short serving leg of configuration 5")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="configuration 2: skip the short runs of the other workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling the "
                          "HBM byte counters), then exit")
@@ -1209,6 +1260,8 @@ def main(argv=None) -> int:
         out["p50_ms"] = sv["p50_ms"]
         out["p99_ms"] = sv["p99_ms"]
         out["serving"] = sv
+    if default_c2 and not args.no_legs:
+        out["other_workloads"] = other_legs(d2, dev)
     if not args.no_cpu_baseline:
         # the oracle has the north-west-corner and Vogel starts
         ib = 1 if init == d2.D2_INIT_VOGEL else 0
