@@ -836,11 +836,18 @@ def oracle_threads():
     return oracle.default_threads()
 
 
+PIVOT_BINS = [0, 1, 3, 5, 9, 17, 33, 65, 129, 257]   # histogram edges: 0, 1-2, 3-4, 5-8, ...
+
+
 def _pivot_summary(p: np.ndarray) -> dict:
+    """Mean, percentiles and a histogram over power-of-two bins (counts of
+    pairs with 0, 1-2, 3-4, 5-8, ..., 129-256 and more than 256 pivots)."""
     p = np.asarray(p, dtype=np.float64)
+    hist = np.histogram(p, bins=PIVOT_BINS + [np.inf])[0]
     return {"mean": float(p.mean()), "p50": float(np.percentile(p, 50)),
             "p90": float(np.percentile(p, 90)), "p99": float(np.percentile(p, 99)),
-            "max": int(p.max()), "zero_frac": float((p == 0).mean())}
+            "max": int(p.max()), "zero_frac": float((p == 0).mean()),
+            "hist": [int(c) for c in hist]}
 
 
 def pivot_work_factor(ts: np.ndarray, ss: np.ndarray, pivots: np.ndarray, d: int) -> float:

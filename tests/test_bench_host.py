@@ -38,3 +38,7 @@ def test_pivot_summary():
     s = bench._pivot_summary(np.array([0, 0, 2, 4, 10]))
     assert s["mean"] == pytest.approx(3.2) and s["p50"] == 2.0 and s["max"] == 10
     assert s["zero_frac"] == pytest.approx(0.4)
+    # bins 0 | 1-2 | 3-4 | 5-8 | 9-16 | 17-32 | 33-64 | 65-128 | 129-256 | >256
+    assert s["hist"] == [2, 1, 1, 0, 1, 0, 0, 0, 0, 0]
+    h = bench._pivot_summary(np.array([1, 2, 3, 8, 9, 16, 17, 64, 65, 128, 129, 256, 257, 9999]))["hist"]
+    assert h == [0, 2, 1, 1, 2, 1, 1, 2, 2, 2]
