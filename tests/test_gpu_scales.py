@@ -1,0 +1,84 @@
+"""GPU: the lane-group solver at extreme scales, against exact invariants
+and the oracle.
+
+* Scaling every point by a power of two scales every squared cost, every
+  potential and the tolerance by its square, exactly in binary, so the pivot
+  path is the same and D^2 scales by exactly that factor (no overflow or
+  subnormals at the factors used).
+* Very uneven weights (Dirichlet(0.02): most weights many orders of
+  magnitude below the largest) still give the oracle's values.
+Pairs cover every lane-group class (supports up to 64 on both sides)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.parity import assert_close, pair_tolerance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def d2():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests selected but no GPU is visible")
+    import paper_1302_0435_amd as m
+    m._ffi.lib()
+    return m
+
+
+def bags(rng, n, sizes, d, alpha, scale=1.0):
+    out = []
+    for k in range(n):
+        t = int(sizes[k % len(sizes)])
+        x = rng.normal(size=(t, d)) * scale + rng.uniform(-5, 5, size=d)
+        w = rng.dirichlet(np.full(t, alpha))
+        out.append((x, w))
+    return out
+
+
+def emd(d2, A, B, pairs, init):
+    h = d2.Handle(0)
+    dist, st, _, _, piv = d2.d2_emd_batch(h, d2.DeviceSet.from_ragged(A, DEV),
+                                          d2.DeviceSet.from_ragged(B, DEV), torch.as_tensor(pairs),
+                                          d2.Opts(init=init), want_pivots=True)
+    torch.cuda.synchronize()
+    return dist.cpu().numpy(), st.cpu().numpy(), piv.cpu().numpy()
+
+
+def scaled(S, f):
+    return synth.RaggedSet(S.offsets.copy(), S.points * f, S.weights.copy())
+
+
+@pytest.mark.parametrize("init", [1, 3])     # north-west corner, least cost
+def test_power_of_two_scaling_is_exact(d2, init):
+    rng = np.random.default_rng(77)
+    A = synth.from_bags(bags(rng, 24, [5, 16, 20, 32, 40, 64], 6, 0.7))
+    B = synth.from_bags(bags(rng, 24, [8, 16, 30, 33, 64], 6, 0.7))
+    pairs = np.stack(np.meshgrid(np.arange(A.n), np.arange(B.n)), -1).reshape(-1, 2).astype(np.int64)
+    base, st, piv = emd(d2, A, B, pairs, init)
+    assert np.all(st == 0)
+    for k in (-20, 20):
+        f = 2.0 ** k
+        got, st2, piv2 = emd(d2, scaled(A, f), scaled(B, f), pairs, init)
+        assert np.all(st2 == 0)
+        np.testing.assert_array_equal(piv2, piv)
+        np.testing.assert_array_equal(got, base * (f * f))
+
+
+def test_very_uneven_weights_match_oracle(d2):
+    rng = np.random.default_rng(78)
+    A = synth.from_bags(bags(rng, 20, [7, 16, 25, 48, 64], 4, 0.02))
+    B = synth.from_bags(bags(rng, 20, [9, 16, 32, 50, 64], 4, 0.02))
+    assert A.weights.min() < 1e-30            # the law gives weights far below the largest
+    pairs = np.stack(np.meshgrid(np.arange(A.n), np.arange(B.n)), -1).reshape(-1, 2).astype(np.int64)
+    o_d, o_st, _ = oracle.emd_batch(A, B, pairs)
+    assert np.all(o_st == 0)
+    for init in (1, 2, 3):
+        g, st, _ = emd(d2, A, B, pairs, init)
+        assert np.all(st == 0), (init, np.unique(st))
+        assert_close(g, o_d, pair_tolerance(A, B, pairs))
