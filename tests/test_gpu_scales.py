@@ -82,3 +82,46 @@ def test_very_uneven_weights_match_oracle(d2):
         g, st, _ = emd(d2, A, B, pairs, init)
         assert np.all(st == 0), (init, np.unique(st))
         assert_close(g, o_d, pair_tolerance(A, B, pairs))
+
+
+def test_workgroup_simplex_scaling_is_exact(d2):
+    """Supports beyond 64 run on the workgroup simplex; its costs, pointer-
+    jumped potentials and block pricing scale the same way."""
+    rng = np.random.default_rng(79)
+    A = synth.from_bags(bags(rng, 4, [96, 130], 5, 0.7))
+    B = synth.from_bags(bags(rng, 4, [80, 160], 5, 0.7))
+    pairs = np.stack(np.meshgrid(np.arange(A.n), np.arange(B.n)), -1).reshape(-1, 2).astype(np.int64)
+    base, st, piv = emd(d2, A, B, pairs, 3)
+    assert np.all(st == 0)
+    for k in (-20, 20):
+        f = 2.0 ** k
+        got, st2, piv2 = emd(d2, scaled(A, f), scaled(B, f), pairs, 3)
+        assert np.all(st2 == 0)
+        np.testing.assert_array_equal(piv2, piv)
+        np.testing.assert_array_equal(got, base * (f * f))
+
+
+def test_bf16_mode_scaling_is_exact(d2):
+    """BF16-MFMA cost mode: rounding to BF16 commutes with a power-of-two
+    factor, and the FP32 products, norms and sums scale exactly, so every
+    D^2 scales by the factor squared, bit for bit."""
+    rng = np.random.default_rng(80)
+    X = synth.from_bags(bags(rng, 40, [4, 11, 16, 23, 32], 64, 0.7), np.float32)
+    Z = synth.from_bags(bags(rng, 24, [8, 16, 32], 64, 0.7), np.float32)
+    h = d2.Handle(0)
+
+    def run(f):
+        Xs = synth.RaggedSet(X.offsets.copy(), (X.points * np.float32(f)).astype(np.float32), X.weights)
+        Zs = synth.RaggedSet(Z.offsets.copy(), (Z.points * np.float32(f)).astype(np.float32), Z.weights)
+        lab, best, allv, st = d2.d2_assign(h, d2.DeviceSet.from_ragged(Xs, DEV),
+                                           d2.DeviceSet.from_ragged(Zs, DEV),
+                                           d2.Opts(cost_mode=d2.D2_COST_BF16_MFMA), want_all=True)
+        torch.cuda.synchronize()
+        assert int(st.max().item()) == 0
+        return lab.cpu().numpy(), allv.cpu().numpy()
+    lab0, all0 = run(1.0)
+    for k in (-16, 16):
+        f = 2.0 ** k
+        lab, allv = run(f)
+        np.testing.assert_array_equal(lab, lab0)
+        np.testing.assert_array_equal(allv, all0 * (f * f))
