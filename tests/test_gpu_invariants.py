@@ -1,0 +1,102 @@
+"""GPU: invariants of D^2 that hold for any correct solver, on the device's
+own outputs (every lane-group class and the workgroup simplex):
+
+* symmetry: the pair (A_i, B_j) and the pair (B_j, A_i) have the same value,
+  and the returned plans are transposes of each other;
+* atom order: permuting the atoms of either distribution (points with their
+  weights) leaves D^2 unchanged up to rounding;
+* translation: moving both distributions by the same vector leaves D^2
+  unchanged up to rounding."""
+import numpy as np
+import pytest
+
+import synth
+from tests.parity import assert_close, pair_tolerance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def d2():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests selected but no GPU is visible")
+    import paper_1302_0435_amd as m
+    m._ffi.lib()
+    return m
+
+
+def sets(seed, sizes_a, sizes_b, d=4):
+    rng = np.random.default_rng(seed)
+    mk = lambda sizes: synth.from_bags([(rng.normal(size=(t, d)) + rng.uniform(-3, 3, size=d),
+                                         rng.dirichlet(np.ones(t))) for t in sizes])
+    return mk(sizes_a), mk(sizes_b)
+
+
+def emd(d2, A, B, pairs, plan=False):
+    h = d2.Handle(0)
+    out = d2.d2_emd_batch(h, d2.DeviceSet.from_ragged(A, DEV), d2.DeviceSet.from_ragged(B, DEV),
+                          torch.as_tensor(pairs), want_plan=plan)
+    torch.cuda.synchronize()
+    dist, st = out[0].cpu().numpy(), out[1].cpu().numpy()
+    assert np.all(st == 0), np.unique(st)
+    if not plan:
+        return dist
+    plan, off = out[2]
+    return dist, off.cpu().numpy(), plan.cpu().numpy()
+
+
+SIZES = ([3, 16, 16, 30, 41, 64, 100], [5, 16, 20, 32, 64, 64, 130])
+
+
+def all_pairs(A, B):
+    return np.stack(np.meshgrid(np.arange(A.n), np.arange(B.n)), -1).reshape(-1, 2).astype(np.int64)
+
+
+def test_swapping_the_sides_transposes_the_plan(d2):
+    A, B = sets(90, *SIZES)
+    p = all_pairs(A, B)
+    d_ab, off_ab, plan_ab = emd(d2, A, B, p, plan=True)
+    d_ba, off_ba, plan_ba = emd(d2, B, A, p[:, ::-1].copy(), plan=True)
+    assert_close(d_ba, d_ab, pair_tolerance(A, B, p))
+    ta, tb = np.diff(A.offsets), np.diff(B.offsets)
+    for k, (i, j) in enumerate(p):
+        P = plan_ab[off_ab[k]:off_ab[k + 1]].reshape(ta[i], tb[j])
+        Q = plan_ba[off_ba[k]:off_ba[k + 1]].reshape(tb[j], ta[i])
+        # points and weights in general position: the optimal plan is unique,
+        # so the two solves, on different pivot paths, give the same plan
+        np.testing.assert_allclose(Q.T, P, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(P.sum(1), A.bag(i)[1], atol=1e-12)
+        np.testing.assert_allclose(Q.sum(0), A.bag(i)[1], atol=1e-12)
+        np.testing.assert_allclose(P.sum(0), B.bag(j)[1], atol=1e-12)
+        np.testing.assert_allclose(Q.sum(1), B.bag(j)[1], atol=1e-12)
+
+
+def test_atom_order_does_not_matter(d2):
+    A, B = sets(91, *SIZES)
+    rng = np.random.default_rng(92)
+
+    def permuted(S):
+        bags = []
+        for i in range(S.n):
+            x, w = S.bag(i)
+            q = rng.permutation(len(w))
+            bags.append((x[q], w[q]))
+        return synth.from_bags(bags)
+    p = all_pairs(A, B)
+    base = emd(d2, A, B, p)
+    got = emd(d2, permuted(A), permuted(B), p)
+    assert_close(got, base, pair_tolerance(A, B, p))
+
+
+def test_translation_does_not_matter(d2):
+    A, B = sets(93, *SIZES)
+    v = np.array([3.25, -1.5, 0.75, 2.0])
+    moved = lambda S: synth.RaggedSet(S.offsets.copy(), S.points + v, S.weights.copy())
+    p = all_pairs(A, B)
+    base = emd(d2, A, B, p)
+    got = emd(d2, moved(A), moved(B), p)
+    assert_close(got, base, pair_tolerance(A, B, p))
