@@ -6,7 +6,8 @@ own outputs (every lane-group class and the workgroup simplex):
 * atom order: permuting the atoms of either distribution (points with their
   weights) leaves D^2 unchanged up to rounding;
 * translation: moving both distributions by the same vector leaves D^2
-  unchanged up to rounding."""
+  unchanged up to rounding;
+* the triangle inequality of D = sqrt(D^2) over a pairwise matrix."""
 import numpy as np
 import pytest
 
@@ -100,3 +101,28 @@ def test_translation_does_not_matter(d2):
     base = emd(d2, A, B, p)
     got = emd(d2, moved(A), moved(B), p)
     assert_close(got, base, pair_tolerance(A, B, p))
+
+
+def test_triangle_inequality_on_pairwise_distances(d2):
+    """D = sqrt(D^2) is a metric: on a segment's pairwise matrix (supports
+    of every class, up to 100 atoms), D(i,k) <= D(i,j) + D(j,k) for every
+    triple, up to rounding."""
+    rng = np.random.default_rng(94)
+    sizes = rng.choice([1, 4, 9, 16, 23, 32, 40, 64, 100], size=48)
+    X = synth.from_bags([(rng.normal(size=(int(t), 3)) * 0.7 + rng.uniform(-2, 2, size=3),
+                          rng.dirichlet(np.ones(int(t)))) for t in sizes])
+    h = d2.Handle(0)
+    out, st = d2.d2_pairwise(h, d2.DeviceSet.from_ragged(X, DEV))
+    torch.cuda.synchronize()
+    assert int(st.max().item()) == 0
+    c = out.cpu().numpy()
+    n = X.n
+    D2 = np.zeros((n, n))
+    iu = np.triu_indices(n, 1)
+    D2[iu] = c
+    D2 = D2 + D2.T
+    D = np.sqrt(np.maximum(D2, 0.0))
+    lhs = D[:, None, :]                         # D(i, k)
+    rhs = D[:, :, None] + D[None, :, :]         # D(i, j) + D(j, k)
+    slack = rhs - lhs
+    assert slack.min() >= -1e-9 * max(1.0, D.max())
