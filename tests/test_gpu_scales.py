@@ -125,3 +125,27 @@ def test_bf16_mode_scaling_is_exact(d2):
         lab, allv = run(f)
         np.testing.assert_array_equal(lab, lab0)
         np.testing.assert_array_equal(allv, all0 * (f * f))
+
+
+def test_bf16_mode_is_exact_on_small_integer_points(d2):
+    """Integer coordinates in [-8, 8] are exact in BF16, and at d = 64 every
+    product, norm and sum of the FP32 cost stays below 2^24, so the BF16-MFMA
+    cost tile equals the FP64 direct one and the whole solve is the FP64
+    path's, bit for bit."""
+    rng = np.random.default_rng(81)
+
+    def mk(n, sizes):
+        return synth.from_bags([(rng.integers(-8, 9, size=(int(sizes[k % len(sizes)]), 64)).astype(np.float64),
+                                 rng.dirichlet(np.ones(int(sizes[k % len(sizes)]))))
+                                for k in range(n)], np.float32)
+    X, Z = mk(36, [3, 9, 16, 21, 32]), mk(20, [8, 16, 32])
+    h = d2.Handle(0)
+    Xd, Zd = d2.DeviceSet.from_ragged(X, DEV), d2.DeviceSet.from_ragged(Z, DEV)
+    outs = []
+    for mode in (d2.D2_COST_F64_DIRECT, d2.D2_COST_BF16_MFMA):
+        lab, best, allv, st = d2.d2_assign(h, Xd, Zd, d2.Opts(cost_mode=mode), want_all=True)
+        torch.cuda.synchronize()
+        assert int(st.max().item()) == 0
+        outs.append((lab.cpu().numpy(), allv.cpu().numpy()))
+    np.testing.assert_array_equal(outs[1][1], outs[0][1])
+    np.testing.assert_array_equal(outs[1][0], outs[0][0])
