@@ -149,3 +149,23 @@ def test_bf16_mode_is_exact_on_small_integer_points(d2):
         outs.append((lab.cpu().numpy(), allv.cpu().numpy()))
     np.testing.assert_array_equal(outs[1][1], outs[0][1])
     np.testing.assert_array_equal(outs[1][0], outs[0][0])
+
+
+def test_bf16_cost_tiles_are_exact_on_small_integer_points(d2):
+    """The stand-alone cost-tile entry in its BF16-MFMA mode returns the FP64
+    tiles exactly on inputs where its arithmetic is exact (as above)."""
+    rng = np.random.default_rng(82)
+
+    def mk(n, sizes):
+        return synth.from_bags([(rng.integers(-8, 9, size=(int(sizes[k % len(sizes)]), 40)).astype(np.float64),
+                                 rng.dirichlet(np.ones(int(sizes[k % len(sizes)]))))
+                                for k in range(n)], np.float32)
+    A, B = mk(10, [1, 7, 16, 32]), mk(9, [5, 16, 20, 32])      # the BF16 mode's supports (<= 32)
+    pairs = np.stack(np.meshgrid(np.arange(A.n), np.arange(B.n)), -1).reshape(-1, 2).astype(np.int64)
+    h = d2.Handle(0)
+    Ad, Bd = d2.DeviceSet.from_ragged(A, DEV), d2.DeviceSet.from_ragged(B, DEV)
+    f64, off64 = d2.d2_cost_tiles(h, Ad, Bd, torch.as_tensor(pairs), cost_mode=d2.D2_COST_F64_DIRECT)
+    b16, off16 = d2.d2_cost_tiles(h, Ad, Bd, torch.as_tensor(pairs), cost_mode=d2.D2_COST_BF16_MFMA)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(off16.cpu().numpy(), off64.cpu().numpy())
+    np.testing.assert_array_equal(b16.cpu().numpy().astype(np.float64), f64.cpu().numpy())
