@@ -62,3 +62,40 @@ def test_serving_results_alone_equal_mix(k, n_pool, n_req, max_batch, alone_ever
     assert np.array_equal(g_lab, o_lab) or all(
         o_all[i, g_lab[i]] - o_all[i, o_lab[i]] <= max(1e-10 * abs(o_all[i, o_lab[i]]), floor[i].min())
         for i in range(len(picked)))
+
+
+def test_serving_at_the_serving_shape_matches_the_oracle():
+    """The serving workload's shape: 1,024 resident centroids of support 32
+    (d = 32) and 128 distinct queries of support 4..64 arriving as a Poisson
+    stream at 10,000 per second; every served query's 1,024 distances and
+    its label against the oracle."""
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests selected but no GPU is visible")
+    import paper_1302_0435_amd as d2
+    from paper_1302_0435_amd import serve
+    Z = synth.make_centroids(5)
+    assert Z.n == 1024
+    Zd = d2.DeviceSet.from_ragged(Z, "cuda:0")
+    n_req = 128
+    q = synth.make_data(5, n=n_req)
+    pool = serve.QueryPool(q.offsets, q.points.astype(np.float64), q.weights.astype(np.float64))
+    arrivals = synth.arrivals(5, 10000.0, 0.05)[:n_req]
+    assert arrivals.size == n_req
+    req_idx = np.arange(n_req)                 # every request a distinct query
+    ex = serve.GpuExecutor(pool, req_idx, Zd, Z.n, slots=4, max_batch=64, keep_results=True,
+                           budget_bytes=64 << 20)
+    st = serve.Scheduler(ex, pool.sizes(), pool.d, Z.n, 64 << 20, 64, 4).run(arrivals)
+    assert np.all(~np.isnan(st.done_s))
+    assert all(ex.results[r][3] == 0 for r in range(n_req))
+    P = synth.RaggedSet(pool.offsets, pool.points, pool.weights)
+    o_lab, o_best, o_all, o_st, _ = oracle.assign(P, Z)
+    assert o_st.max() == 0
+    g_all = np.stack([ex.results[r][2] for r in range(n_req)])
+    g_lab = np.array([ex.results[r][0] for r in range(n_req)])
+    floor = np.array([[1e-14 * coupling_cost(*P.bag(r), *Z.bag(j)) for j in range(Z.n)]
+                      for r in range(n_req)])
+    assert_close(g_all, o_all, floor)
+    for r in range(n_req):
+        if g_lab[r] != o_lab[r]:
+            assert o_all[r, g_lab[r]] - o_all[r, o_lab[r]] <= max(1e-10 * abs(o_all[r, o_lab[r]]),
+                                                                  floor[r].min())
