@@ -42,3 +42,17 @@ def test_pivot_summary():
     assert s["hist"] == [2, 1, 1, 0, 1, 0, 0, 0, 0, 0]
     h = bench._pivot_summary(np.array([1, 2, 3, 8, 9, 16, 17, 64, 65, 128, 129, 256, 257, 9999]))["hist"]
     assert h == [0, 2, 1, 1, 2, 1, 1, 2, 2, 2]
+
+
+def test_fast_pair_tolerance_equals_the_per_pair_one():
+    """The moment form of the independent-coupling cost (used to check every
+    pair of a pairwise matrix) against the direct double sum."""
+    from tests.parity import pair_tolerance, pair_tolerance_fast
+    X = synth.make_data(4, n=120)
+    Z = synth.make_centroids(2)
+    Y = synth.make_data(2, n=60)
+    rng = np.random.default_rng(3)
+    p = np.stack([rng.integers(0, 120, 800), rng.integers(0, 120, 800)], 1)
+    np.testing.assert_allclose(pair_tolerance_fast(X, X, p), pair_tolerance(X, X, p), rtol=1e-12)
+    q = np.stack([rng.integers(0, 60, 300), rng.integers(0, 512, 300)], 1)
+    np.testing.assert_allclose(pair_tolerance_fast(Y, Z, q), pair_tolerance(Y, Z, q), rtol=1e-12)
