@@ -126,3 +126,34 @@ def test_triangle_inequality_on_pairwise_distances(d2):
     rhs = D[:, :, None] + D[None, :, :]         # D(i, j) + D(j, k)
     slack = rhs - lhs
     assert slack.min() >= -1e-9 * max(1.0, D.max())
+
+
+def test_entry_points_agree_bit_for_bit(d2):
+    """The same pair gives the same bits through d2_pairwise, d2_emd_batch
+    and d2_assign's full matrix when it is solved in the same orientation
+    (same pivot rules, whatever shape or schedule runs it)."""
+    rng = np.random.default_rng(95)
+    sizes = rng.choice([1, 5, 12, 16, 17, 30, 33, 50, 64], size=40)
+    X = synth.from_bags([(rng.normal(size=(int(t), 5)) + rng.uniform(-2, 2, size=5),
+                          rng.dirichlet(np.ones(int(t)))) for t in sizes])
+    h = d2.Handle(0)
+    Xd = d2.DeviceSet.from_ragged(X, DEV)
+    cond, st = d2.d2_pairwise(h, Xd)
+    _, _, full, st2 = d2.d2_assign(h, Xd, Xd, want_all=True)
+    torch.cuda.synchronize()
+    assert int(st.max().item()) == 0 and int(st2.max().item()) == 0
+    n = X.n
+    i, j = np.triu_indices(n, 1)
+    pairs = np.stack([i, j], 1).astype(np.int64)
+    batch = emd(d2, X, X, pairs)
+    np.testing.assert_array_equal(cond.cpu().numpy(), batch)
+    full = full.cpu().numpy()
+    np.testing.assert_array_equal(full[i, j], batch)
+    # the swapped pair: the larger support always takes the rows, so it is
+    # the same solve when the supports differ; with equal supports the rows
+    # are the first side, a different solve of the same LP
+    t = np.diff(X.offsets)
+    diff = t[i] != t[j]
+    assert diff.sum() > 0 and (~diff).sum() > 0
+    np.testing.assert_array_equal(full[j, i][diff], batch[diff])
+    assert_close(full[j, i][~diff], batch[~diff], pair_tolerance(X, X, pairs[~diff]))
